@@ -1,0 +1,247 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module only draws random numbers and evaluates boundary functions. It
+holds none of the Mosaic Flow arithmetic (no gather, no network, no sweep):
+the oracle and the GPU path each implement that on their own and both read
+the arrays produced here.
+
+Conventions used by every generator:
+
+* A domain of ``ux`` x ``uy`` units is a vertex-centred grid with 32 cells
+  per unit, i.e. ``(32*uy + 1)`` rows by ``(32*ux + 1)`` columns, row-major,
+  ``field[j, i]`` sitting at ``(x, y) = (i/32, j/32)`` in units.
+* The outer ring holds the Dirichlet data; the interior starts at zero.
+* SDNet parameters are one flat float32 vector laid out as
+  ``W1 (d x 130) | b1 | W2 (d x d) | b2 | W3 | b3 | W4 | b4 | w5 (d) | b5``,
+  every matrix row-major (out, in). Columns 0..127 of W1 act on the
+  boundary vector, column 128 on x and column 129 on y.
+
+Everything is rounded to float32 once and then treated as exact: the oracle
+upcasts those float32 values to float64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CELLS_PER_UNIT = 32
+N_BOUNDARY = 128
+
+
+def param_count(width: int, n_boundary: int = N_BOUNDARY) -> int:
+    d = width
+    return d * (n_boundary + 2) + d + 3 * (d * d + d) + d + 1
+
+
+def xavier_params(width: int, seed: int = 0, n_boundary: int = N_BOUNDARY) -> np.ndarray:
+    """Xavier-normal weights, zero biases, drawn layer by layer.
+
+    The draws come from ``numpy.random.default_rng(seed).standard_normal`` in
+    the order W1, W2, W3, W4, w5, each row-major (out, in), scaled by
+    sqrt(2 / (fan_in + fan_out)).
+    """
+    d = width
+    rng = np.random.default_rng(seed)
+    shapes = [(d, n_boundary + 2), (d, d), (d, d), (d, d), (1, d)]
+    mats = []
+    for out_f, in_f in shapes:
+        sigma = np.sqrt(2.0 / (in_f + out_f))
+        mats.append(rng.standard_normal((out_f, in_f)) * sigma)
+    parts = []
+    for li, m in enumerate(mats):
+        parts.append(m.reshape(-1))
+        nb = m.shape[0]
+        parts.append(np.zeros(nb))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == param_count(width, n_boundary)
+    return flat
+
+
+def random_params(width: int, seed: int, scale: float = 1.0,
+                  n_boundary: int = N_BOUNDARY) -> np.ndarray:
+    """Xavier-normal weights with non-zero normal biases (scale * N(0, 0.1)).
+
+    Used by tests so that every bias term is exercised.
+    """
+    flat = xavier_params(width, seed, n_boundary).astype(np.float64)
+    rng = np.random.default_rng(seed + 1000)
+    d = width
+    off = 0
+    sizes = [(d * (n_boundary + 2), d), (d * d, d), (d * d, d), (d * d, d), (d, 1)]
+    for wsz, bsz in sizes:
+        off += wsz
+        flat[off:off + bsz] = 0.1 * rng.standard_normal(bsz)
+        off += bsz
+    return (flat * scale).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# Outer-ring enumeration (input side only: which grid points carry data).
+# ----------------------------------------------------------------------------
+
+def ring_indices(ux: int, uy: int) -> tuple[np.ndarray, np.ndarray]:
+    """(j, i) index arrays of the outer ring, counter-clockwise from (0, 0)."""
+    nx, ny = CELLS_PER_UNIT * ux, CELLS_PER_UNIT * uy
+    ii, jj = [], []
+    ii += list(range(0, nx)); jj += [0] * nx              # bottom, left->right
+    ii += [nx] * ny; jj += list(range(0, ny))             # right, bottom->top
+    ii += list(range(nx, 0, -1)); jj += [ny] * nx         # top, right->left
+    ii += [0] * ny; jj += list(range(ny, 0, -1))          # left, top->bottom
+    return np.asarray(jj), np.asarray(ii)
+
+
+def _field_from_ring(ux: int, uy: int, values: np.ndarray) -> np.ndarray:
+    f = np.zeros((CELLS_PER_UNIT * uy + 1, CELLS_PER_UNIT * ux + 1), dtype=np.float64)
+    jj, ii = ring_indices(ux, uy)
+    f[jj, ii] = values
+    return f.astype(np.float32)
+
+
+def analytic_field(ux: int, uy: int, fn) -> np.ndarray:
+    """Ring = fn(x, y) evaluated in units (float64, then rounded); interior 0."""
+    jj, ii = ring_indices(ux, uy)
+    x = ii / CELLS_PER_UNIT
+    y = jj / CELLS_PER_UNIT
+    return _field_from_ring(ux, uy, fn(x, y))
+
+
+def x2_minus_y2_field(ux: int, uy: int) -> np.ndarray:
+    return analytic_field(ux, uy, lambda x, y: x * x - y * y)
+
+
+def full_analytic(ux: int, uy: int, fn) -> np.ndarray:
+    """fn evaluated at every grid vertex, float64 (for checks, not inputs)."""
+    ny, nx = CELLS_PER_UNIT * uy + 1, CELLS_PER_UNIT * ux + 1
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return fn(i / CELLS_PER_UNIT, j / CELLS_PER_UNIT)
+
+
+def _se_cholesky_sample(pts: np.ndarray, length: float, variance: float,
+                        z: np.ndarray, jitter: float = 1e-6) -> np.ndarray:
+    diff = pts[:, None, :] - pts[None, :, :]
+    r2 = np.sum(diff * diff, axis=-1)
+    k = variance * np.exp(-r2 / (2.0 * length * length))
+    k[np.diag_indices_from(k)] += jitter
+    chol = np.linalg.cholesky(k)
+    return chol @ z
+
+
+def gp_ring_values(ux: int, uy: int, length: float, seed: int = 0,
+                   variance: float = 1.0, rng: np.random.Generator | None = None) -> np.ndarray:
+    """Squared-exponential GP sample on the outer ring.
+
+    The covariance uses the Euclidean distance (in units) between ring
+    points, so the sample is continuous around the corners. The sample is
+    cholesky(K + 1e-6 I) @ z with z drawn from ``default_rng(seed)`` (or the
+    given generator) in ring order.
+    """
+    jj, ii = ring_indices(ux, uy)
+    pts = np.stack([ii / CELLS_PER_UNIT, jj / CELLS_PER_UNIT], axis=1)
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    z = rng.standard_normal(pts.shape[0])
+    return _se_cholesky_sample(pts, length, variance, z)
+
+
+def gp_field(ux: int, uy: int, length: float, seed: int = 0, variance: float = 1.0,
+             rng: np.random.Generator | None = None) -> np.ndarray:
+    vals = gp_ring_values(ux, uy, length, seed, variance, rng)
+    return _field_from_ring(ux, uy, vals)
+
+
+def expsin_field(ux: int, uy: int) -> np.ndarray:
+    """e^x * sin(y) on domain-normalised coordinates, min-max scaled to [0, 1].
+
+    x_hat = x / ux and y_hat = y / uy lie in [0, 1]; the ring values are then
+    scaled so that their minimum is 0 and maximum is 1.
+    """
+    jj, ii = ring_indices(ux, uy)
+    xh = ii / (CELLS_PER_UNIT * ux)
+    yh = jj / (CELLS_PER_UNIT * uy)
+    v = np.exp(xh) * np.sin(yh)
+    v = (v - v.min()) / (v.max() - v.min())
+    return _field_from_ring(ux, uy, v)
+
+
+def random_interior_field(ux: int, uy: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Uniform(-scale, scale) everywhere (ring included): a generic test state."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(-scale, scale, size=(CELLS_PER_UNIT * uy + 1, CELLS_PER_UNIT * ux + 1))
+    return f.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# Training batches: GP curves on the unit-square perimeter.
+# ----------------------------------------------------------------------------
+
+def unit_perimeter_nodes(n_per_side: int = 32) -> np.ndarray:
+    """128 perimeter nodes of the unit square, counter-clockwise from (0,0).
+
+    Side k of 4 holds n_per_side nodes and excludes its end corner:
+    bottom (s, 0), right (1, s), top (1 - s, 1), left (0, 1 - s) with
+    s = 0, 1/n, ..., (n-1)/n.
+    """
+    s = np.arange(n_per_side) / n_per_side
+    bottom = np.stack([s, np.zeros_like(s)], 1)
+    right = np.stack([np.ones_like(s), s], 1)
+    top = np.stack([1.0 - s, np.ones_like(s)], 1)
+    left = np.stack([np.zeros_like(s), 1.0 - s], 1)
+    return np.concatenate([bottom, right, top, left], 0)
+
+
+def gp_perimeter_batch(n_bc: int, length: float, seed: int, variance: float = 1.0) -> np.ndarray:
+    """[n_bc x 128] float32 GP samples on the unit-square perimeter nodes."""
+    pts = unit_perimeter_nodes()
+    diff = pts[:, None, :] - pts[None, :, :]
+    k = variance * np.exp(-np.sum(diff * diff, -1) / (2.0 * length * length))
+    k[np.diag_indices_from(k)] += 1e-6
+    chol = np.linalg.cholesky(k)
+    z = np.random.default_rng(seed).standard_normal((n_bc, pts.shape[0]))
+    return (z @ chol.T).astype(np.float32)
+
+
+def collocation_points(n_bc: int, n_pts: int, seed: int) -> np.ndarray:
+    """[n_bc x n_pts x 2] float32 points uniform in (0, 1)^2."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n_bc, n_pts, 2)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# Batched domains: sizes drawn from one stream, then per-domain GP data.
+# ----------------------------------------------------------------------------
+
+def batched_domains(n_domains: int = 48, lo: int = 4, hi: int = 48, length: float = 1.0,
+                    seed: int = 7) -> tuple[np.ndarray, list[np.ndarray]]:
+    """Sizes and GP ring data for a batch of independent domains.
+
+    One ``default_rng(seed)`` stream draws the (units_x, units_y) pairs, each
+    uniform on [lo, hi], then each domain's GP sample in domain order.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(lo, hi + 1, size=(n_domains, 2))
+    fields = [gp_field(int(ux), int(uy), length, rng=rng) for ux, uy in sizes]
+    return sizes, fields
+
+
+# ----------------------------------------------------------------------------
+# Named workloads.
+# ----------------------------------------------------------------------------
+
+WORKLOADS = {
+    "C1": dict(units=(2, 2), width=128, sweeps=50, data="x2-y2", prec="fp32"),
+    "C2": dict(units=(16, 16), width=256, sweeps=200, data="gp", length=2.0, seed=1, prec="fp32"),
+    "C3": dict(width=128, n_bc=1024, n_colloc=256, length=0.5, bc_seed=2, colloc_seed=3, steps=100),
+    "C4": dict(units=(64, 64), width=256, sweeps=500, data="expsin", prec="bf16"),
+    "C5": dict(n_domains=48, width=256, sweeps=20, length=1.0, seed=7, ckpt=5, prec="bf16"),
+}
+
+
+def workload_field(name: str) -> np.ndarray:
+    w = WORKLOADS[name]
+    ux, uy = w["units"]
+    if w["data"] == "x2-y2":
+        return x2_minus_y2_field(ux, uy)
+    if w["data"] == "gp":
+        return gp_field(ux, uy, w["length"], w["seed"])
+    if w["data"] == "expsin":
+        return expsin_field(ux, uy)
+    raise ValueError(name)

@@ -1,0 +1,63 @@
+"""Physics-informed SDNet training step in float64 (oracle).
+
+Alg. 1: a forward/backward pass over the data points, a second one over the
+collocation points, gradients summed, then one optimiser step (the allreduce
+of step 3 is the identity on one device).
+
+Loss:
+* data term: the network evaluated at the 128 boundary nodes of the unit
+  square must reproduce the boundary vector it was given,
+  L_data = mean_{b,k} (N(x_k, g_b) - g_{b,k})^2;
+* PDE term (Eq. 3): L_pde = mean_{b,j} (Laplacian N(x_{b,j}, g_b))^2 over the
+  collocation points.
+
+Gradients come from automatic differentiation (the paper obtains the
+second derivatives and the parameter gradient the same way, Sec. 3.4).
+Adam is the textbook update of Kingma and Ba with bias correction.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import sdnet
+
+
+def losses(theta: torch.Tensor, width: int, G: torch.Tensor, Xb: torch.Tensor,
+           Xc: torch.Tensor):
+    """(L_data, L_pde) as differentiable scalars.
+
+    G: [B, 128]; Xb: [128, 2] boundary node coordinates; Xc: [B, nc, 2].
+    """
+    layers = sdnet.unpack(theta, width)
+    u_b = sdnet.forward(layers, G, Xb)
+    l_data = torch.mean((u_b - G) ** 2)
+    _, _, _, lap = sdnet.derivatives(layers, G, Xc, create_graph=True)
+    l_pde = torch.mean(lap ** 2)
+    return l_data, l_pde
+
+
+def gradient(theta: torch.Tensor, width: int, G, Xb, Xc):
+    """Returns (L_data, L_pde, grad_data, grad_pde) in float64."""
+    th = theta.detach().clone().requires_grad_(True)
+    l_data, l_pde = losses(th, width, G, Xb, Xc)
+    (g_data,) = torch.autograd.grad(l_data, th)
+    (g_pde,) = torch.autograd.grad(l_pde, th)
+    return l_data.item(), l_pde.item(), g_data, g_pde
+
+
+def adam_update(theta, m, v, grad, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (step counts from 1). Returns new (theta, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    theta = theta - lr * mhat / (torch.sqrt(vhat) + eps)
+    return theta, m, v
+
+
+def train_step(theta, m, v, step: int, width: int, G, Xb, Xc, **adam):
+    """Alg. 1 then Adam: returns (theta, m, v, L_data, L_pde)."""
+    l_data, l_pde, g_data, g_pde = gradient(theta, width, G, Xb, Xc)
+    grad = g_data + g_pde
+    theta, m, v = adam_update(theta, m, v, grad, step, **adam)
+    return theta, m, v, l_data, l_pde
