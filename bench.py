@@ -1,0 +1,173 @@
+"""Throughput of the Mosaic Flow predictor on one MI355X.
+
+One step = one full pass of the hot path over one synthetic domain: the
+predictor loop of Alg. 2 (200 four-colour sweeps, CROSS targets) followed by
+the overlap-averaged assembly, on a 16 x 16 unit domain (513 x 513 grid,
+961 placements) with a width-256 SDNet (Xavier weights, seed 0) and GP
+boundary data (length scale 2, seed 1). The value is SDNet point
+evaluations per second over the whole step (sweeps + assembly), float32.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line. The "roofline" object reports the colour-phase kernel
+(the dominant kernel): algorithmic flops per launch over its average launch
+duration, timed with HIP events on the launch stream during the timed
+region. The "cpu_baseline" object times the float64 oracle on the host
+cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SDNet point-evals/s in MF sweep (BF16 vs FP32 @ stated L2 err); train steps/s"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2516.6
+CROSS_T = 61
+INTERIOR_T = 961
+
+
+def flops_per_point(width: int, T: int) -> float:
+    """Algorithmic flops of one SDNet evaluation in a phase with T targets per
+    placement: three d x d hidden layers (6 d^2), the coordinate term of the
+    first layer (4 d), the output layer (2 d), and the boundary projection
+    2 * 128 * d amortised over the placement's T points."""
+    d = width
+    return 6.0 * d * d + 6.0 * d + 2.0 * 128 * d / T
+
+
+def sweep_points(ux: int, uy: int, T: int) -> int:
+    return (2 * ux - 1) * (2 * uy - 1) * T
+
+
+def cpu_baseline(field, params, width, ux, uy, sample_sweeps):
+    import torch
+    from oracle import sweep as sw
+    torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), width)
+    u = torch.from_numpy(field.astype(np.float64))
+    t0 = time.perf_counter()
+    for _ in range(sample_sweeps):
+        u = sw.sweep(u, ux, uy, solver)
+    sw.assemble(u, ux, uy, solver)
+    dt = time.perf_counter() - t0
+    evals = sample_sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    return {"value": evals / dt, "unit": "point-evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample_sweeps} CROSS sweeps + 1 assembly of the same 16x16-unit, "
+                      f"width-{width} workload, float64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-sweeps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
+                                   "domain on a single device (see DESIGN.md for sharding)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import Context, MF_CROSS, MF_FP32, mf_solve
+
+    w = mi.WORKLOADS["C2"]
+    ux, uy = w["units"]
+    width = w["width"]
+    K = args.sweeps
+    field = mi.workload_field("C2")
+    params_np = mi.xavier_params(width, 0)
+
+    dev = torch.device("cuda:0")
+    ctx = Context(0)
+    params = torch.from_numpy(params_np).to(dev)
+    u0 = torch.from_numpy(field).to(dev)
+    u = u0.clone()
+    u_out = torch.empty_like(u)
+
+    def step():
+        u.copy_(u0)
+        mf_solve(ctx, params, u, (ux, uy), K, targets=MF_CROSS, prec=MF_FP32, u_out=u_out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_read()                      # drop anything recorded so far
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    launches, phase_ms, phase_rows = ctx.timing_read()
+
+    evals_per_step = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    value = evals_per_step * args.steps / dt
+    fpp = flops_per_point(width, CROSS_T)
+    achieved = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
+    avg_us = phase_ms * 1e3 / max(launches, 1)
+
+    # parity of the last step against stored oracle values (16x16, 200 sweeps)
+    parity = None
+    gpath = os.path.join(ROOT, "tests", "golden", "c2_fp32.npz")
+    if K == 200 and os.path.exists(gpath):
+        from oracle.sweep import skeleton_mask
+        g = np.load(gpath)
+        uh = u.cpu().numpy().astype(np.float64)
+        m = skeleton_mask(*field.shape).numpy()
+        e_s = np.linalg.norm(uh[m] - g["skel200"]) / np.linalg.norm(g["skel200"])
+        uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
+        e_o = np.linalg.norm(uo - g["u_out_sample"]) / np.linalg.norm(g["u_out_sample"])
+        parity = {"rel_l2_skeleton_vs_oracle": float(e_s), "rel_l2_u_out_vs_oracle": float(e_o)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2: plain Mosaic Flow, 16x16 units (513x513 grid, 961 "
+                               "placements), SDNet width 256, GP ring data (l=2, seed 1), "
+                               f"{K} CROSS sweeps + assembly",
+                   "units": [ux, uy], "width": width, "sweeps": K, "targets": "cross",
+                   "evals_per_step": evals_per_step},
+        "sweep_phase": {"launches": launches, "avg_launch_us": avg_us,
+                        "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": None,
+                     "kernel": "tile_kernel<256,R,CROSS,FP32> (colour phase)",
+                     "flops_per_point_eval": fpp},
+        "parity": parity,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(field, params_np, width, ux, uy, args.cpu_sample_sweeps)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

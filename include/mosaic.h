@@ -1,0 +1,220 @@
+/*
+ * mosaic.h -- C ABI of libmosaic: the Mosaic Flow sweep on one MI355X.
+ *
+ * Method: Feeney, Li, Bostanabad, Chandramowlishwaran, "Breaking Boundaries:
+ * Distributed Domain Decomposition with Scalable Physics-Informed Neural PDE
+ * Solvers" (SC'23, arXiv 2308.14258).
+ *
+ * Problem (Sec. 2.1, Eqs. 1-2): the 2-D Laplace equation with Dirichlet data
+ * on a rectangle of units_x x units_y unit squares. A pretrained subdomain
+ * network (SDNet, Sec. 2.4 and 3.2) maps the boundary values of a unit
+ * square, sampled at 128 points, plus a point (x, y) of that square to the
+ * solution there. The predictor (Sec. 4.1-4.2, Alg. 2) covers the domain
+ * with overlapping unit squares placed every half unit, and sweeps: each
+ * sweep runs four colour phases, and each phase gathers the boundary of every
+ * same-colour placement from the global field, evaluates SDNet at that
+ * placement's targets and writes the predictions back. A final assembly
+ * predicts every interior point of every placement and averages the overlaps.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Field: float32, row-major, u[j * pitch + i] is the vertex (x, y) =
+ *   (i / 32, j / 32) in units, 0 <= i <= 32 units_x, 0 <= j <= 32 units_y.
+ *   The outer ring holds the Dirichlet data and is never written.
+ * Placement (a, b), 0 <= a <= 2 units_x - 2, 0 <= b <= 2 units_y - 2, covers
+ *   columns 16a .. 16a+32 and rows 16b .. 16b+32; its colour is
+ *   (a mod 2) + 2 (b mod 2); a sweep runs colours 0, 1, 2, 3 in order.
+ * Boundary vector (128 values): counter-clockwise from the placement's local
+ *   (0, 0), 32 samples per side, each side excluding its end corner:
+ *   k < 32: (k, 0); k < 64: (32, k-32); k < 96: (96-k, 32); else (0, 128-k).
+ * Targets: MF_CROSS = the 61 interior points of the two centre lines (the
+ *   per-iteration set of Alg. 2), MF_INTERIOR = all 31 x 31 interior points.
+ *   SDNet sees local coordinates (i / 32, j / 32) in [0, 1].
+ * SDNet (mf_sdnet_desc): width d in {128, 256}, depth 4 tanh hidden layers,
+ *   scalar output. Parameters are one flat float32 vector
+ *     W1 (d x 130) | b1 (d) | W2 (d x d) | b2 | W3 | b3 | W4 | b4 | w5 (d) | b5
+ *   every matrix row-major (out, in); W1 columns 0..127 act on the boundary
+ *   vector, 128 on x and 129 on y. The first layer is evaluated in the
+ *   input-split form of Eq. 8: W1g g + b1 once per placement (or boundary
+ *   condition), plus W1x (x, y) per point.
+ * Precision: MF_FP32 computes every GEMM with float32 MFMA; MF_BF16 runs the
+ *   three hidden d x d GEMMs on bf16 MFMA with float32 accumulation. The
+ *   field, the boundary projection, tanh, the output layer and the overlap
+ *   averaging stay float32 in both.
+ *
+ * Memory and streams: every pointer argument marked "device" is device
+ * memory owned by the caller; "host" pointers are host memory. The library
+ * never frees caller memory and allocates no device memory in any call; the
+ * caller provides a workspace whose size mf_workspace_size / the *_ws_size
+ * queries return (256-byte aligned). All device work is enqueued on the
+ * given stream (a hipStream_t, NULL = default stream) and is asynchronous,
+ * except where an entry point says it synchronises.
+ *
+ * Errors: every function returns mf_status. Arguments are validated on the
+ * host before any device work; on failure nothing is enqueued and
+ * mf_last_error() returns a thread-local description. Nothing throws or
+ * aborts across this interface.
+ */
+#ifndef MOSAIC_H
+#define MOSAIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mf_status;
+enum {
+  MF_OK = 0,
+  MF_EINVAL = 1,         /* null/misaligned pointer, bad enum value          */
+  MF_ESHAPE = 2,         /* unsupported or inconsistent sizes                */
+  MF_ENOMEM = 3,         /* workspace smaller than required                  */
+  MF_EDEVICE = 4,        /* no usable GPU, or a HIP call failed              */
+  MF_ENONFINITE = 5,     /* delta test saw a NaN or infinity                 */
+  MF_ENOTCONVERGED = 6,  /* solve hit max_sweeps with eps > 0 (opt-in flag)  */
+  MF_EUNSUPPORTED = 7    /* valid request this build does not implement      */
+};
+
+enum { MF_FP32 = 0, MF_BF16 = 1 };                 /* precision           */
+enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
+enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
+enum { MF_TANH = 0 };                               /* activation          */
+enum { MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1 };        /* mf_solve flags      */
+
+typedef struct mf_sdnet_desc {
+  int32_t width;       /* d: 128 or 256                                    */
+  int32_t depth;       /* number of tanh hidden layers: 4                  */
+  int32_t n_boundary;  /* boundary samples: 128                            */
+  int32_t activation;  /* MF_TANH                                          */
+} mf_sdnet_desc;
+
+typedef struct mf_domain_desc {
+  int32_t units_x, units_y;  /* domain size in unit squares, each >= 1      */
+  int32_t cells_per_unit;    /* 32                                          */
+  int32_t stride;            /* placement stride in cells: 16               */
+  int64_t pitch;             /* row pitch of the field in floats            */
+  int64_t field_offset;      /* first element of this domain in the buffer  */
+} mf_domain_desc;
+
+typedef struct mf_adam {
+  float lr, beta1, beta2, eps;   /* textbook Adam (Kingma and Ba)           */
+} mf_adam;
+
+typedef struct mf_ctx mf_ctx;
+
+/* Context for one device. mf_ctx_create selects `device`, checks that it is
+ * a gfx950 GPU and returns MF_EDEVICE when no GPU is present. A context is
+ * used by one host thread at a time. */
+mf_status mf_ctx_create(int device, mf_ctx** out);
+void mf_ctx_destroy(mf_ctx* ctx);
+const char* mf_last_error(void);
+
+/* Kernel timing, a profiling aid. While enabled, every colour-phase launch
+ * of mf_sweep and mf_solve (not the assembly) is bracketed by two hipEvents
+ * recorded on the call's stream. mf_ctx_timing_read waits for those events
+ * and returns the number of timed launches (host, nullable), their summed
+ * duration in milliseconds (host, nullable) and the SDNet point evaluations
+ * they performed (host, nullable), then clears the record. */
+mf_status mf_ctx_timing(mf_ctx* ctx, int32_t enable);
+mf_status mf_ctx_timing_read(mf_ctx* ctx, int64_t* launches, double* total_ms, int64_t* rows);
+
+/* Number of float32 values in the flat parameter vector (see above); -1 on
+ * an invalid descriptor. Pure host function. */
+int64_t mf_param_count(const mf_sdnet_desc* desc);
+
+/* Workspace bytes needed by mf_sweep / mf_solve / mf_sweep_operator for this
+ * network, domain and precision. Pure host function. */
+mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom,
+                            int32_t n_domains, int32_t prec, size_t* bytes);
+
+/* One colour phase (colour = 0..3) or one full sweep (colour = -1) of the
+ * predictor (Sec. 4.1; the loop body of Alg. 2), updating the device field u
+ * in place at the chosen targets. All placements of a phase read the field
+ * as it was before the phase: same-colour placements never write a point
+ * that another same-colour placement reads, so the batch equals the
+ * sequential order. n_domains must be 1 (mode MF_ADDITIVE is reserved).
+ * params: device, mf_param_count floats. ws: device workspace. */
+mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
+                   float* u, const mf_domain_desc* dom, int32_t n_domains,
+                   int32_t colour, int32_t targets, int32_t mode, int32_t prec,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. 2 on one device: up to max_sweeps sweeps of u (in place), stopping
+ * early when eps > 0 and, at a sweep whose index is a multiple of
+ * check_every, the relative L2 change of the skeleton values (all grid
+ * points with i or j a multiple of 16, ring included) from the previous
+ * sweep drops below eps. Then, when u_out is not NULL, the final assembly
+ * writes u_out (device, same layout as u): every placement predicts its 961
+ * interior points from the final u and each interior point takes the mean
+ * over the placements covering it; u_out's ring is copied from u.
+ * sweeps_done (host, nullable) receives the number of sweeps run and
+ * last_delta (host, nullable) the last delta (NaN if never evaluated).
+ * Synchronises the stream when eps > 0 (one float pair read per check) and
+ * when sweeps_done or last_delta is requested; otherwise asynchronous.
+ * MF_ENONFINITE if a delta evaluates to NaN/inf with a nonzero reference. */
+mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
+                   float* u, const mf_domain_desc* dom, int32_t n_domains,
+                   int32_t targets, int32_t mode, int32_t prec,
+                   int32_t max_sweeps, float eps, int32_t check_every, int32_t flags,
+                   float* u_out, int32_t* sweeps_done, float* last_delta,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Check mode: the same sweep with the subdomain solver replaced by a linear
+ * operator, pred = Hop g, Hop a device float32 [T x 128] row-major matrix
+ * whose rows follow the target order (CROSS: the vertical centre line
+ * j = 1..31, then the horizontal line i = 1..31 without i = 16; INTERIOR:
+ * row by row, i fastest). With Hop = the exact 5-point subdomain solve this
+ * is classical alternating Schwarz (Sec. 2.3, Eq. 4). colour = -1 runs a
+ * full sweep; colour = 4 runs the overlap-averaged assembly into u_out
+ * (INTERIOR operator required). hop_rows must equal the number of targets
+ * (61 or 961); it is checked because the device size of Hop is not visible
+ * to the library. No workspace. */
+mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int32_t targets,
+                            float* u, float* u_out, const mf_domain_desc* dom, int32_t colour,
+                            void* stream);
+
+/* Workspace bytes for sdnet_forward with n_bc boundary conditions. */
+mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int32_t prec,
+                                size_t* bytes);
+
+/* N(x, g; theta) (Sec. 2.2) for n_bc boundary conditions G (device, [n_bc x
+ * 128]) at points X (device): shared [n_pts x 2] when x_per_bc = 0, or per
+ * condition [n_bc x n_pts x 2] when x_per_bc = 1. Writes U (device,
+ * [n_bc x n_pts]). When dU (device, [n_bc x n_pts x 2], nullable) or lapU
+ * (device, [n_bc x n_pts], nullable) is given, also writes the gradient and
+ * the Laplacian with respect to (x, y), propagated forward through the
+ * network (value, two first derivatives, Laplacian); that needs prec =
+ * MF_FP32. */
+mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
+                        const float* G, int64_t n_bc, const float* X, int64_t n_pts,
+                        int32_t x_per_bc, float* U, float* dU, float* lapU, int32_t prec,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for sdnet_train_step with B conditions and nc
+ * collocation points per condition. */
+mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nc, size_t* bytes);
+
+/* One physics-informed training iteration (Alg. 1 on one device, then Adam):
+ *   L_data = mean_{b,k} (N(Xb_k, G_b) - G_{b,k})^2   (boundary match)
+ *   L_pde  = mean_{b,j} (Laplacian N(Xc_{b,j}, G_b))^2  (Eq. 3)
+ * The gradient of L_data + L_pde is accumulated from the data pass and the
+ * collocation pass into one buffer; then one Adam step with bias correction
+ * (step counts from 1) updates params, m and v in place (all device,
+ * mf_param_count floats). G: device [B x 128]; Xb: device [128 x 2] boundary
+ * node coordinates; Xc: device [B x nc x 2]. loss_dev: device [2] receives
+ * (L_data, L_pde) at the incoming parameters. When grad_out (device,
+ * nullable) is given the gradient is written there and no update is made.
+ * prec must be MF_FP32. */
+mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params, float* m,
+                           float* v, int64_t step, const mf_adam* hp, const float* G,
+                           int64_t B, const float* Xb, const float* Xc, int64_t nc,
+                           float* loss_dev, float* grad_out, void* ws, size_t ws_bytes,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOSAIC_H */

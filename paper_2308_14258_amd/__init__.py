@@ -1,0 +1,10 @@
+"""Mosaic Flow on MI355X: the predictor sweep and SDNet training step as
+hand-written HIP kernels behind a C ABI (include/mosaic.h).
+
+The Python layer only marshals arguments: torch tensors provide device
+memory and the current stream; every step runs in libmosaic.so.
+"""
+from ._lib import (MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, MF_MULTIPLICATIVE,  # noqa: F401
+                   MosaicError, load)
+from .api import (Context, mf_solve, mf_sweep, mf_sweep_operator, sdnet_forward,  # noqa: F401
+                  sdnet_train_step)

@@ -1,0 +1,101 @@
+"""ctypes declarations of libmosaic's C ABI (include/mosaic.h).
+
+Loading fails loudly when the shared library has not been built: there is
+no fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmosaic.so")
+
+MF_OK, MF_EINVAL, MF_ESHAPE, MF_ENOMEM, MF_EDEVICE, MF_ENONFINITE, MF_ENOTCONVERGED, \
+    MF_EUNSUPPORTED = range(8)
+STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ESHAPE", 3: "MF_ENOMEM", 4: "MF_EDEVICE",
+                5: "MF_ENONFINITE", 6: "MF_ENOTCONVERGED", 7: "MF_EUNSUPPORTED"}
+MF_FP32, MF_BF16 = 0, 1
+MF_CROSS, MF_INTERIOR = 0, 1
+MF_MULTIPLICATIVE, MF_ADDITIVE = 0, 1
+MF_TANH = 0
+MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1
+
+
+class SdnetDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_boundary", ctypes.c_int32), ("activation", ctypes.c_int32)]
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [("units_x", ctypes.c_int32), ("units_y", ctypes.c_int32),
+                ("cells_per_unit", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("pitch", ctypes.c_int64), ("field_offset", ctypes.c_int64)]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+_c = ctypes
+_P = ctypes.c_void_p
+_F = ctypes.POINTER(ctypes.c_float)
+_SIG = {
+    "mf_ctx_create": (_c.c_int32, [_c.c_int, _c.POINTER(_P)]),
+    "mf_ctx_destroy": (None, [_P]),
+    "mf_last_error": (_c.c_char_p, []),
+    "mf_param_count": (_c.c_int64, [_c.POINTER(SdnetDesc)]),
+    "mf_ctx_timing": (_c.c_int32, [_P, _c.c_int32]),
+    "mf_ctx_timing_read": (_c.c_int32, [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
+                                        _c.POINTER(_c.c_int64)]),
+    "mf_workspace_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
+                                       _c.c_int32, _c.POINTER(_c.c_size_t)]),
+    "mf_sweep": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
+                              _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P, _c.c_size_t, _P]),
+    "mf_solve": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
+                              _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_float, _c.c_int32,
+                              _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),
+    "mf_sweep_operator": (_c.c_int32, [_P, _P, _c.c_int64, _c.c_int32, _P, _P, _c.POINTER(DomainDesc),
+                                       _c.c_int32, _P]),
+    "sdnet_forward_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int32,
+                                           _c.POINTER(_c.c_size_t)]),
+    "sdnet_forward": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,
+                                   _c.c_int32, _P, _P, _P, _c.c_int32, _P, _c.c_size_t, _P]),
+    "sdnet_train_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,
+                                         _c.POINTER(_c.c_size_t)]),
+    "sdnet_train_step": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _P, _c.c_int64,
+                                      _c.POINTER(Adam), _P, _c.c_int64, _P, _P, _c.c_int64, _P, _P,
+                                      _P, _c.c_size_t, _P]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libmosaic.so (built in-tree by paper_2308_14258_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2308_14258_amd.build` "
+            "(there is no non-HIP fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MosaicError(RuntimeError):
+    def __init__(self, status: int, where: str, text: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {text}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != MF_OK:
+        raise MosaicError(status, where, load().mf_last_error().decode())

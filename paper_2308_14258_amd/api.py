@@ -1,0 +1,208 @@
+"""Thin Python binding over libmosaic's C ABI.
+
+Each function has the name of the C entry point it calls and only marshals
+arguments: torch tensors supply device pointers (and the workspace), the
+current torch stream is passed as the HIP stream. No computation happens
+here.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
+                   check, load)
+
+
+def width_of(params: torch.Tensor) -> int:
+    n = params.numel()
+    for d in (128, 256):
+        if 3 * d * d + 135 * d + 1 == n:
+            return d
+    raise ValueError(f"parameter vector of {n} floats matches no supported width")
+
+
+def sdnet_desc(width: int) -> SdnetDesc:
+    return SdnetDesc(width, 4, 128, MF_TANH)
+
+
+def domain_desc(u: torch.Tensor, units) -> DomainDesc:
+    ux, uy = units
+    return DomainDesc(int(ux), int(uy), 32, 16, int(u.stride(0)), 0)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda_f32(t: torch.Tensor, name: str):
+    if not (t.is_cuda and t.dtype == torch.float32):
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+
+
+def _need_field(u: torch.Tensor, units):
+    _need_cuda_f32(u, "field")
+    ux, uy = units
+    if u.dim() != 2 or u.shape != (32 * uy + 1, 32 * ux + 1) or u.stride(1) != 1:
+        raise ValueError(f"field must be [{32 * uy + 1}, {32 * ux + 1}] with unit column stride")
+
+
+class Context:
+    """One mf_ctx plus a cached device workspace."""
+
+    def __init__(self, device: int = 0):
+        lib = load()
+        ptr = ctypes.c_void_p()
+        check(lib.mf_ctx_create(device, ctypes.byref(ptr)), "mf_ctx_create")
+        self.ptr = ptr
+        self.device = device
+        self._ws = None
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def timing(self, enable: bool) -> None:
+        check(load().mf_ctx_timing(self.ptr, 1 if enable else 0), "mf_ctx_timing")
+
+    def timing_read(self):
+        """(launches, total_ms, rows) of the timed colour-phase launches."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        rows = ctypes.c_int64()
+        check(load().mf_ctx_timing_read(self.ptr, ctypes.byref(n), ctypes.byref(ms),
+                                        ctypes.byref(rows)), "mf_ctx_timing_read")
+        return n.value, ms.value, rows.value
+
+    def close(self):
+        if self.ptr:
+            load().mf_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _sweep_ws(ctx: Context, width: int, dom: DomainDesc, prec: int) -> torch.Tensor:
+    n = ctypes.c_size_t()
+    check(load().mf_workspace_size(ctypes.byref(sdnet_desc(width)), ctypes.byref(dom), 1, prec,
+                                   ctypes.byref(n)), "mf_workspace_size")
+    return ctx.workspace(n.value)
+
+
+def mf_sweep(ctx: Context, params: torch.Tensor, u: torch.Tensor, units, colour: int = -1,
+             targets: int = MF_CROSS, prec: int = MF_FP32, mode: int = MF_MULTIPLICATIVE):
+    """One colour phase (0..3) or one sweep (-1) of u in place."""
+    _need_field(u, units)
+    _need_cuda_f32(params, "params")
+    width = width_of(params)
+    dom = domain_desc(u, units)
+    ws = _sweep_ws(ctx, width, dom, prec)
+    check(load().mf_sweep(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
+                          ctypes.byref(dom), 1, colour, targets, mode, prec, _ptr(ws), ws.numel(),
+                          _stream()), "mf_sweep")
+
+
+def mf_solve(ctx: Context, params: torch.Tensor, u: torch.Tensor, units, max_sweeps: int,
+             eps: float = 0.0, check_every: int = 1, targets: int = MF_CROSS,
+             prec: int = MF_FP32, u_out: torch.Tensor | None = None, flags: int = 0,
+             mode: int = MF_MULTIPLICATIVE, report: bool = False):
+    """Alg. 2 on one GPU; u is updated in place, u_out receives the assembly.
+    Returns (sweeps_done, last_delta) when report is True (synchronises)."""
+    _need_field(u, units)
+    _need_cuda_f32(params, "params")
+    if u_out is not None:
+        _need_field(u_out, units)
+        if u_out.stride(0) != u.stride(0):
+            raise ValueError("u_out must have the same pitch as u")
+    width = width_of(params)
+    dom = domain_desc(u, units)
+    ws = _sweep_ws(ctx, width, dom, prec)
+    done = ctypes.c_int32(-1)
+    last = ctypes.c_float(float("nan"))
+    check(load().mf_solve(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
+                          ctypes.byref(dom), 1, targets, mode, prec, max_sweeps, eps, check_every,
+                          flags, _ptr(u_out), ctypes.byref(done) if report else None,
+                          ctypes.byref(last) if report else None, _ptr(ws), ws.numel(),
+                          _stream()), "mf_solve")
+    return (done.value, last.value) if report else None
+
+
+def mf_sweep_operator(ctx: Context, Hop: torch.Tensor, u: torch.Tensor, units, colour: int = -1,
+                      targets: int = MF_CROSS, u_out: torch.Tensor | None = None):
+    """Sweep (colour -1), phase (0..3) or assembly (4) with a linear solver."""
+    _need_field(u, units)
+    _need_cuda_f32(Hop, "Hop")
+    if u_out is not None:
+        _need_field(u_out, units)
+    if Hop.dim() != 2 or Hop.shape[1] != 128:
+        raise ValueError("Hop must be [T, 128]")
+    dom = domain_desc(u, units)
+    Hop = Hop.contiguous()
+    check(load().mf_sweep_operator(ctx.ptr, _ptr(Hop), Hop.shape[0], targets, _ptr(u), _ptr(u_out),
+                                   ctypes.byref(dom), colour, _stream()), "mf_sweep_operator")
+
+
+def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.Tensor,
+                  prec: int = MF_FP32, derivatives: bool = False):
+    """U [n_bc, n_pts] (and dU [n_bc, n_pts, 2], lapU [n_bc, n_pts])."""
+    _need_cuda_f32(params, "params")
+    _need_cuda_f32(G, "G")
+    _need_cuda_f32(X, "X")
+    G = G.contiguous()
+    X = X.contiguous()
+    width = width_of(params)
+    n_bc = G.shape[0]
+    x_per_bc = 1 if X.dim() == 3 else 0
+    n_pts = X.shape[1] if x_per_bc else X.shape[0]
+    U = torch.empty(n_bc, n_pts, device=G.device, dtype=torch.float32)
+    dU = torch.empty(n_bc, n_pts, 2, device=G.device, dtype=torch.float32) if derivatives else None
+    lapU = torch.empty(n_bc, n_pts, device=G.device, dtype=torch.float32) if derivatives else None
+    n = ctypes.c_size_t()
+    lib = load()
+    check(lib.sdnet_forward_ws_size(ctypes.byref(sdnet_desc(width)), n_bc, prec, ctypes.byref(n)),
+          "sdnet_forward_ws_size")
+    ws = ctx.workspace(n.value)
+    check(lib.sdnet_forward(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G), n_bc,
+                            _ptr(X), n_pts, x_per_bc, _ptr(U), _ptr(dU), _ptr(lapU), prec, _ptr(ws),
+                            ws.numel(), _stream()), "sdnet_forward")
+    return (U, dU, lapU) if derivatives else U
+
+
+def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                     step: int, G: torch.Tensor, Xb: torch.Tensor, Xc: torch.Tensor,
+                     lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                     loss: torch.Tensor | None = None, grad_out: torch.Tensor | None = None):
+    """One Alg. 1 iteration + Adam. Returns the device loss tensor [2]."""
+    for t, name in ((params, "params"), (m, "m"), (v, "v"), (G, "G"), (Xb, "Xb"), (Xc, "Xc")):
+        _need_cuda_f32(t, name)
+    width = width_of(params)
+    B, nc = Xc.shape[0], Xc.shape[1]
+    if loss is None:
+        loss = torch.empty(2, device=G.device, dtype=torch.float32)
+    n = ctypes.c_size_t()
+    lib = load()
+    check(lib.sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nc, ctypes.byref(n)),
+          "sdnet_train_ws_size")
+    ws = ctx.workspace(n.value)
+    hp = Adam(lr, beta1, beta2, eps)
+    check(lib.sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(m),
+                               _ptr(v), step, ctypes.byref(hp), _ptr(G.contiguous()), B,
+                               _ptr(Xb.contiguous()), _ptr(Xc.contiguous()), nc, _ptr(loss),
+                               _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
+          "sdnet_train_step")
+    return loss
+
+
+__all__ = ["Context", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
+           "sdnet_train_step", "width_of", "sdnet_desc", "domain_desc", "_lib"]

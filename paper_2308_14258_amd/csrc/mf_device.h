@@ -1,0 +1,112 @@
+// Device helpers for the Mosaic Flow kernels (gfx950 / CDNA4).
+//
+// Geometry of the predictor (Sec. 4.1-4.2 of the paper): placements every 16
+// cells, 33 x 33 vertices each, four colours, a 128-sample boundary vector
+// running counter-clockwise, and the centre-cross / full-interior target
+// sets. The tanh used by every kernel is built from the identity
+// tanh|x| = (1 - e) / (1 + e), e = exp(-2|x|), with the odd Maclaurin series
+// of tanh near zero where that identity cancels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+constexpr int kS = 32;      // cells per unit = cells per subdomain side
+constexpr int kHalf = 16;   // placement stride in cells
+constexpr int kNB = 128;    // boundary samples per subdomain
+constexpr int kCross = 61;  // centre-cross targets
+constexpr int kInterior = 961;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Local (i, j) of boundary sample k (0..127), counter-clockwise from (0, 0).
+__device__ __forceinline__ void boundary_local(int k, int& i, int& j) {
+  const int side = k >> 5, m = k & 31;
+  switch (side) {
+    case 0: i = m; j = 0; break;
+    case 1: i = kS; j = m; break;
+    case 2: i = kS - m; j = kS; break;
+    default: i = 0; j = kS - m; break;
+  }
+}
+
+// Local (i, j) of target t. CROSS: vertical centre line j = 1..31 first, then
+// the horizontal line i = 1..31 without the centre. INTERIOR: row by row.
+template <int TMODE>
+__device__ __forceinline__ void target_local(int t, int& i, int& j) {
+  if (TMODE == 0) {
+    if (t < 31) { i = kHalf; j = t + 1; }
+    else { const int m = t - 31; i = m < 15 ? m + 1 : m + 2; j = kHalf; }
+  } else {
+    j = t / 31 + 1;
+    i = t - (j - 1) * 31 + 1;
+  }
+}
+
+template <int TMODE>
+constexpr int n_targets() { return TMODE == 0 ? kCross : kInterior; }
+
+// Placement q of colour c in a ux x uy domain -> (a, b). Colour (ca, cb)
+// holds the placements with a = ca mod 2, b = cb mod 2; there are ux - ca
+// of the former and uy - cb of the latter.
+__device__ __forceinline__ void placement_of(int q, int colour, int ux, int& a, int& b) {
+  const int ca = colour & 1, cb = colour >> 1;
+  const int na = ux - ca;
+  const int qa = q % na, qb = q / na;
+  a = ca + 2 * qa;
+  b = cb + 2 * qb;
+}
+
+// Number of placements whose interior covers grid index i along one axis of
+// n cells: one on stride lines and within half a unit of the ring, else two.
+__device__ __forceinline__ float cover_inv(int i, int n) {
+  return ((i & 15) == 0 || i < kHalf || i > n - kHalf) ? 1.0f : 0.5f;
+}
+
+// float32 tanh: odd series below 0.125, exp-based identity above.
+__device__ __forceinline__ float tanh_f32(float x) {
+  const float ax = fabsf(x);
+  const float x2 = x * x;
+  // x - x^3/3 + 2x^5/15 - 17x^7/315 + 62x^9/2835 (Maclaurin series of tanh)
+  float p = 62.0f / 2835.0f;
+  p = fmaf(p, x2, -17.0f / 315.0f);
+  p = fmaf(p, x2, 2.0f / 15.0f);
+  p = fmaf(p, x2, -1.0f / 3.0f);
+  p = fmaf(p, x2, 0.0f) * x + x;
+  // e = 2^(-2 log2(e) |x|) = exp(-2|x|)
+  const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * ax);
+  const float r = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+  return ax < 0.125f ? p : copysignf(r, x);
+}
+
+__device__ __forceinline__ floatx16 mfma32x32x2(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx16 mfma32x32x16_bf16(bf16x8 a, bf16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row of the 32x32 MFMA accumulator held by lane l in register v.
+__device__ __forceinline__ int acc_row(int lane, int v) {
+  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t x = __float_as_uint(f);
+  if ((x & 0x7f800000u) == 0x7f800000u) {          // inf or nan
+    return (uint16_t)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u));
+  }
+  x += 0x7fffu + ((x >> 16) & 1u);                  // round to nearest even
+  return (uint16_t)(x >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+}  // namespace mf

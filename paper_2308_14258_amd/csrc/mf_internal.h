@@ -1,0 +1,87 @@
+// Host-side internals shared by the libmosaic translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mosaic.h"
+
+namespace mf {
+
+// Set the thread-local error text and return the status.
+mf_status fail(mf_status s, const char* fmt, ...);
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Prepared network parameters inside a workspace (offsets in bytes).
+struct NetLayout {
+  int width = 0, prec = 0;
+  size_t w1gT = 0;   // float [128][d]: W1 boundary block, k-major
+  size_t w1x = 0;    // float [d][2]: W1 coordinate columns
+  size_t b1 = 0;     // float [d]
+  size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32 or bf16)
+  size_t bh = 0;     // float [3][d]
+  size_t w5 = 0;     // float [d]
+  size_t b5 = 0;     // float [1]
+  size_t end = 0;
+};
+NetLayout net_layout(int width, int prec, size_t base);
+
+// Device pointers into a prepared network.
+struct NetPtrs {
+  const float* w1gT;
+  const float* w1x;
+  const float* b1;
+  const void* wh;
+  const float* bh;
+  const float* w5;
+  const float* b5;
+};
+NetPtrs net_ptrs(const NetLayout& L, const void* ws);
+
+// Sweep workspace: prepared network, skeleton snapshot, delta partials.
+struct SweepLayout {
+  NetLayout net;
+  size_t skel = 0;     // float [n_skel]
+  size_t part = 0;     // float [2][kDeltaBlocks]
+  size_t dres = 0;     // float [2]
+  size_t total = 0;
+};
+constexpr int kDeltaBlocks = 512;
+int64_t skeleton_count(int ux, int uy);
+SweepLayout sweep_layout(int width, int prec, int ux, int uy);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_prepare_net(const float* params, int width, int prec, const NetLayout& L,
+                              void* ws, hipStream_t s);
+
+struct PhaseArgs {
+  const float* u_in;
+  float* u_out;
+  int64_t pitch;
+  int ux, uy, colour;
+};
+// One colour phase with SDNet. accumulate = assembly mode (u_out += pred / count).
+hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
+                        int tile_rows, const PhaseArgs& a, hipStream_t s);
+// Rows per tile picked for this phase size (CU count aware).
+int pick_tile_rows(int width, int prec, int targets, int64_t rows, int n_cu);
+
+hipError_t launch_assembly_init(const float* u, float* u_out, int64_t pitch, int ux, int uy,
+                                hipStream_t s);
+hipError_t launch_skeleton_snapshot(const float* u, int64_t pitch, int ux, int uy, float* skel,
+                                    hipStream_t s);
+hipError_t launch_delta(const float* u, int64_t pitch, int ux, int uy, const float* skel,
+                        float* part, float* dres, hipStream_t s);
+hipError_t launch_operator_phase(const float* Hop, int targets, bool accumulate,
+                                 const PhaseArgs& a, hipStream_t s);
+
+// sdnet_forward pieces.
+hipError_t launch_projection(const NetPtrs& net, int width, const float* G, int64_t n_bc,
+                             float* C, hipStream_t s);
+hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const float* C,
+                               const float* X, int64_t n_bc, int64_t n_pts, int x_per_bc,
+                               float* U, hipStream_t s);
+
+}  // namespace mf

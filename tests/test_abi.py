@@ -1,0 +1,161 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/mosaic.h, and rejects bad arguments on the host before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2308_14258_amd import _lib
+from paper_2308_14258_amd._lib import (MF_BF16, MF_CROSS, MF_EDEVICE, MF_EINVAL, MF_ENOMEM,
+                                       MF_INTERIOR,
+                                       MF_ESHAPE, MF_EUNSUPPORTED, MF_FP32, MF_OK, DomainDesc,
+                                       SdnetDesc)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mosaic.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return set(re.findall(r"^\s*(?:mf_status|void|int64_t|const char\*)\s+(\w+)\s*\(", txt, re.M))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert {"mf_sweep", "mf_solve", "sdnet_forward", "sdnet_train_step"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert names == set(_lib._SIG), names ^ set(_lib._SIG)
+
+
+def test_param_count(lib):
+    assert lib.mf_param_count(ctypes.byref(SdnetDesc(128, 4, 128, 0))) == 66433
+    assert lib.mf_param_count(ctypes.byref(SdnetDesc(256, 4, 128, 0))) == 231169
+    assert lib.mf_param_count(ctypes.byref(SdnetDesc(100, 4, 128, 0))) == -1
+    assert lib.mf_param_count(None) == -1
+
+
+def _dom(ux=2, uy=2, pitch=None, cpu=32, stride=16):
+    return DomainDesc(ux, uy, cpu, stride, pitch if pitch is not None else 32 * ux + 1, 0)
+
+
+def test_workspace_size(lib):
+    n = ctypes.c_size_t()
+    d = SdnetDesc(256, 4, 128, 0)
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_FP32,
+                                 ctypes.byref(n)) == MF_OK
+    fp32 = n.value
+    assert fp32 >= 3 * 256 * 256 * 4 + 32769 * 4
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_BF16,
+                                 ctypes.byref(n)) == MF_OK
+    assert n.value < fp32
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(0, 2)), 1, MF_FP32,
+                                 ctypes.byref(n)) == MF_ESHAPE
+    assert b"units" in lib.mf_last_error()
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(2, 2, cpu=16)), 1, MF_FP32,
+                                 ctypes.byref(n)) == MF_ESHAPE
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, 7,
+                                 ctypes.byref(n)) == MF_EINVAL
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, MF_FP32, None) == MF_EINVAL
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-GPU path")
+def test_ctx_create_without_gpu(lib):
+    p = ctypes.c_void_p()
+    assert lib.mf_ctx_create(0, ctypes.byref(p)) == MF_EDEVICE
+    assert not p.value
+    assert len(lib.mf_last_error()) > 0
+
+
+FAKE = 1 << 20       # a 256-byte aligned non-null address that is never dereferenced
+
+
+def _sweep(lib, *, ctx=None, desc=None, params=FAKE, u=FAKE, dom=None, nd=1, colour=-1,
+           targets=MF_CROSS, mode=0, prec=MF_FP32, ws=FAKE, ws_bytes=1 << 30):
+    desc = desc or SdnetDesc(128, 4, 128, 0)
+    dom = dom or _dom()
+    return lib.mf_sweep(ctx, ctypes.byref(desc), ctypes.c_void_p(params) if params else None,
+                        ctypes.c_void_p(u) if u else None, ctypes.byref(dom), nd, colour, targets,
+                        mode, prec, ctypes.c_void_p(ws) if ws else None, ws_bytes, None)
+
+
+def test_sweep_argument_errors(lib):
+    assert _sweep(lib) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # all else valid
+    assert _sweep(lib, params=0) == MF_EINVAL and b"params" in lib.mf_last_error()
+    assert _sweep(lib, u=FAKE + 2) == MF_EINVAL and b"aligned" in lib.mf_last_error()
+    assert _sweep(lib, desc=SdnetDesc(64, 4, 128, 0)) == MF_ESHAPE
+    assert _sweep(lib, desc=SdnetDesc(128, 3, 128, 0)) == MF_ESHAPE
+    assert _sweep(lib, desc=SdnetDesc(128, 4, 128, 5)) == MF_EINVAL
+    assert _sweep(lib, dom=_dom(2, 2, pitch=64)) == MF_ESHAPE and b"pitch" in lib.mf_last_error()
+    assert _sweep(lib, dom=_dom(2, 2, stride=8)) == MF_ESHAPE
+    assert _sweep(lib, nd=2) == MF_EUNSUPPORTED
+    assert _sweep(lib, colour=4) == MF_EINVAL
+    assert _sweep(lib, targets=3) == MF_EINVAL
+    assert _sweep(lib, mode=1) == MF_EUNSUPPORTED
+    assert _sweep(lib, prec=2) == MF_EINVAL
+    assert _sweep(lib, ws=0) == MF_EINVAL
+    assert _sweep(lib, ws=FAKE + 64) == MF_EINVAL
+    assert _sweep(lib, ws_bytes=1024) == MF_ENOMEM and b"needed" in lib.mf_last_error()
+
+
+def test_solve_argument_errors(lib):
+    d = SdnetDesc(128, 4, 128, 0)
+    dom = _dom()
+
+    def solve(max_sweeps=10, eps=0.0, check_every=1, flags=0, u_out=None, u=FAKE):
+        return lib.mf_solve(None, ctypes.byref(d), ctypes.c_void_p(FAKE), ctypes.c_void_p(u),
+                            ctypes.byref(dom), 1, MF_CROSS, 0, MF_FP32, max_sweeps, eps,
+                            check_every, flags, ctypes.c_void_p(u_out) if u_out else None, None,
+                            None, ctypes.c_void_p(FAKE), 1 << 30, None)
+
+    assert solve() == MF_EINVAL and b"ctx" in lib.mf_last_error()
+    assert solve(max_sweeps=-1) == MF_EINVAL
+    assert solve(eps=-1.0) == MF_EINVAL
+    assert solve(eps=float("nan")) == MF_EINVAL
+    assert solve(eps=1e-3, check_every=0) == MF_EINVAL
+    assert solve(flags=8) == MF_EINVAL
+    assert solve(u_out=FAKE) == MF_EINVAL and b"alias" in lib.mf_last_error()
+
+
+def test_forward_argument_errors(lib):
+    d = SdnetDesc(256, 4, 128, 0)
+    n = ctypes.c_size_t()
+    assert lib.sdnet_forward_ws_size(ctypes.byref(d), 1000, MF_FP32, ctypes.byref(n)) == MF_OK
+    assert n.value >= 1000 * 256 * 4
+    f = ctypes.c_void_p(FAKE)
+    assert lib.sdnet_forward(None, ctypes.byref(d), f, f, 10, f, 5, 0, f, None, None, MF_FP32, f,
+                             n.value, None) == MF_EINVAL
+    assert lib.sdnet_forward(None, ctypes.byref(d), f, f, -1, f, 5, 0, f, None, None, MF_FP32, f,
+                             n.value, None) == MF_ESHAPE
+    assert lib.sdnet_forward(None, ctypes.byref(d), f, f, 10, f, 5, 2, f, None, None, MF_FP32, f,
+                             n.value, None) == MF_EINVAL
+    assert lib.sdnet_forward(None, ctypes.byref(d), f, f, 10, f, 5, 0, f, None, None, MF_FP32, f,
+                             16, None) == MF_ENOMEM
+
+
+def test_operator_argument_errors(lib):
+    f = ctypes.c_void_p(FAKE)
+    dom = _dom()
+    op = lib.mf_sweep_operator
+    assert op(None, f, 61, MF_CROSS, f, None, ctypes.byref(dom), -1, None) == MF_EINVAL
+    assert b"ctx" in lib.mf_last_error()
+    assert op(None, f, 961, MF_CROSS, f, None, ctypes.byref(dom), -1, None) == MF_ESHAPE
+    assert op(None, f, 61, MF_INTERIOR, f, None, ctypes.byref(dom), -1, None) == MF_ESHAPE
+    assert op(None, f, 61, MF_CROSS, f, f, ctypes.byref(dom), 4, None) == MF_EINVAL
+    assert b"INTERIOR" in lib.mf_last_error()
+    assert op(None, None, 61, MF_CROSS, f, None, ctypes.byref(dom), -1, None) == MF_EINVAL
