@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-sweeps", type=int, default=20)
+    ap.add_argument("--mode", choices=["solve", "copy"], default="solve",
+                    help="copy: one plain device copy of --copy-mb MiB, the reference "
+                         "kernel for scaling HBM counters")
+    ap.add_argument("--copy-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
@@ -84,6 +88,16 @@ def main():
     import torch
     import mf_inputs as mi
     from paper_2308_14258_amd import Context, MF_CROSS, MF_FP32, mf_solve
+
+    if args.mode == "copy":
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
+        return
 
     w = mi.WORKLOADS["C2"]
     ux, uy = w["units"]

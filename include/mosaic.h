@@ -111,12 +111,21 @@ mf_status mf_ctx_create(int device, mf_ctx** out);
 void mf_ctx_destroy(mf_ctx* ctx);
 const char* mf_last_error(void);
 
+/* mf_solve replays its sweeps (when eps = 0) from hipGraphs captured on a
+ * stream owned by the context, joined to the caller's stream with events;
+ * enable = 0 switches to direct launches on the caller's stream. A graph
+ * holds the field and workspace addresses of the call that captured it and
+ * is replayed only by later calls with the same addresses, shape, width,
+ * precision and target set (at most 16 are cached per context). */
+mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
+
 /* Kernel timing, a profiling aid. While enabled, every colour-phase launch
  * of mf_sweep and mf_solve (not the assembly) is bracketed by two hipEvents
- * recorded on the call's stream. mf_ctx_timing_read waits for those events
- * and returns the number of timed launches (host, nullable), their summed
- * duration in milliseconds (host, nullable) and the SDNet point evaluations
- * they performed (host, nullable), then clears the record. */
+ * recorded on the stream it runs on; a replayed graph of several sweeps is
+ * bracketed as a whole. mf_ctx_timing_read waits for those events and
+ * returns the number of timed colour-phase launches (host, nullable), their
+ * summed duration in milliseconds (host, nullable) and the SDNet point
+ * evaluations they performed (host, nullable), then clears the record. */
 mf_status mf_ctx_timing(mf_ctx* ctx, int32_t enable);
 mf_status mf_ctx_timing_read(mf_ctx* ctx, int64_t* launches, double* total_ms, int64_t* rows);
 
@@ -175,9 +184,11 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
                             float* u, float* u_out, const mf_domain_desc* dom, int32_t colour,
                             void* stream);
 
-/* Workspace bytes for sdnet_forward with n_bc boundary conditions. */
-mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int32_t prec,
-                                size_t* bytes);
+/* Workspace bytes for sdnet_forward with n_bc boundary conditions and n_pts
+ * points per condition; derivatives != 0 when dU or lapU will be requested
+ * (then two float32 buffers of 4 n_bc n_pts d values are included). */
+mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int64_t n_pts,
+                                int32_t derivatives, int32_t prec, size_t* bytes);
 
 /* N(x, g; theta) (Sec. 2.2) for n_bc boundary conditions G (device, [n_bc x
  * 128]) at points X (device): shared [n_pts x 2] when x_per_bc = 0, or per

@@ -25,8 +25,4 @@ no blocking, fusion or reordering beyond what the definitions state:
 Every function states which passage it follows. Pins that tie the oracle to
 facts outside itself live in ``tests/test_oracle_*.py``.
 """
-import torch
-
-torch.set_default_dtype(torch.float64)
-
-from . import geometry, sdnet, sweep, fd, train, adjoint  # noqa: E402,F401
+from . import adjoint, fd, geometry, sdnet, sweep, train  # noqa: F401

@@ -47,6 +47,7 @@ _SIG = {
     "mf_last_error": (_c.c_char_p, []),
     "mf_param_count": (_c.c_int64, [_c.POINTER(SdnetDesc)]),
     "mf_ctx_timing": (_c.c_int32, [_P, _c.c_int32]),
+    "mf_ctx_graphs": (_c.c_int32, [_P, _c.c_int32]),
     "mf_ctx_timing_read": (_c.c_int32, [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
                                         _c.POINTER(_c.c_int64)]),
     "mf_workspace_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
@@ -58,8 +59,8 @@ _SIG = {
                               _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),
     "mf_sweep_operator": (_c.c_int32, [_P, _P, _c.c_int64, _c.c_int32, _P, _P, _c.POINTER(DomainDesc),
                                        _c.c_int32, _P]),
-    "sdnet_forward_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int32,
-                                           _c.POINTER(_c.c_size_t)]),
+    "sdnet_forward_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,
+                                           _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "sdnet_forward": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,
                                    _c.c_int32, _P, _P, _P, _c.c_int32, _P, _c.c_size_t, _P]),
     "sdnet_train_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,

@@ -69,6 +69,9 @@ class Context:
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
+    def graphs(self, enable: bool) -> None:
+        check(load().mf_ctx_graphs(self.ptr, 1 if enable else 0), "mf_ctx_graphs")
+
     def timing(self, enable: bool) -> None:
         check(load().mf_ctx_timing(self.ptr, 1 if enable else 0), "mf_ctx_timing")
 
@@ -170,7 +173,8 @@ def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.
     lapU = torch.empty(n_bc, n_pts, device=G.device, dtype=torch.float32) if derivatives else None
     n = ctypes.c_size_t()
     lib = load()
-    check(lib.sdnet_forward_ws_size(ctypes.byref(sdnet_desc(width)), n_bc, prec, ctypes.byref(n)),
+    check(lib.sdnet_forward_ws_size(ctypes.byref(sdnet_desc(width)), n_bc, n_pts,
+                                    1 if derivatives else 0, prec, ctypes.byref(n)),
           "sdnet_forward_ws_size")
     ws = ctx.workspace(n.value)
     check(lib.sdnet_forward(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G), n_bc,

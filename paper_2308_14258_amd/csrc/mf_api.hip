@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -66,6 +67,47 @@ SweepLayout sweep_layout(int width, int prec, int ux, int uy) {
   S.dres = o; o = align256(o + 2 * 4);
   S.total = o;
   return S;
+}
+
+TrainLayout train_layout(int width, int64_t B, int64_t nc) {
+  TrainLayout T;
+  T.net = net_layout(width, MF_FP32, 0);
+  const size_t d = (size_t)width;
+  const size_t SR = (size_t)std::max<int64_t>(4 * B * nc, B * 128);   // stream rows
+  const size_t chunks = (SR + 4095) / 4096;
+  const size_t P = (size_t)(d * 130 + d + 3 * (d * d + d) + d + 1);
+  size_t o = T.net.end;
+  T.whT = o; o = align256(o + 3 * d * d * 4);
+  T.C = o;   o = align256(o + (size_t)B * d * 4);
+  for (int l = 0; l < 4; ++l) { T.Z[l] = o; o = align256(o + SR * d * 4); }
+  for (int l = 0; l < 4; ++l) { T.Sv[l] = o; o = align256(o + SR * d * 4); }
+  for (int l = 0; l < 2; ++l) { T.Ab[l] = o; o = align256(o + SR * d * 4); }
+  T.wpart = o; o = align256(o + chunks * d * d * 4);
+  T.bpart = o; o = align256(o + chunks * d * 4);
+  for (int l = 0; l < 2; ++l) { T.opart[l] = o; o = align256(o + 2048 * (d + 2) * 4); }
+  for (int l = 0; l < 2; ++l) { T.l1[l] = o; o = align256(o + 3 * (size_t)B * d * 4); }
+  T.grad = o; o = align256(o + P * 4);
+  T.total = o;
+  return T;
+}
+
+TrainBuffers train_buffers(const TrainLayout& L, void* ws) {
+  char* b = static_cast<char*>(ws);
+  TrainBuffers t;
+  t.C = reinterpret_cast<float*>(b + L.C);
+  for (int l = 0; l < 4; ++l) {
+    t.Z[l] = reinterpret_cast<float*>(b + L.Z[l]);
+    t.Sv[l] = reinterpret_cast<float*>(b + L.Sv[l]);
+  }
+  for (int l = 0; l < 2; ++l) {
+    t.Ab[l] = reinterpret_cast<float*>(b + L.Ab[l]);
+    t.opart[l] = reinterpret_cast<float*>(b + L.opart[l]);
+    t.l1[l] = reinterpret_cast<float*>(b + L.l1[l]);
+  }
+  t.wpart = reinterpret_cast<float*>(b + L.wpart);
+  t.bpart = reinterpret_cast<float*>(b + L.bpart);
+  t.grad = reinterpret_cast<float*>(b + L.grad);
+  return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -136,12 +178,27 @@ static mf_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
 
 using namespace mf;
 
+// A captured run of `sweeps` consecutive sweeps (4 colour-phase launches
+// each) for one field / workspace / network configuration.
+struct SweepGraph {
+  const float* field;
+  const void* ws;
+  int64_t pitch;
+  int ux, uy, width, prec, targets, sweeps;
+  hipGraphExec_t exec;
+};
+
 struct mf_ctx {
   int device;
   int n_cu;
+  hipStream_t gstream = nullptr;     // graph launches (default priority)
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<SweepGraph> graphs;
+  bool use_graphs = true;
   bool timing = false;
   std::vector<hipEvent_t> events;   // pairs (start, stop) of timed launches
-  std::vector<int64_t> rows;        // point evaluations of each timed launch
+  std::vector<int64_t> rows;        // point evaluations of each timed record
+  std::vector<int64_t> nlaunch;     // colour-phase launches in each timed record
   size_t used = 0;                  // pairs recorded since the last read
 };
 
@@ -172,6 +229,12 @@ mf_status mf_ctx_create(int device, mf_ctx** out) {
   if (!c) return fail(MF_ENOMEM, "host allocation failed");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
+    mf_ctx_destroy(c);
+    return fail(MF_EDEVICE, "stream/event creation failed");
+  }
   *out = c;
   return ok();
 }
@@ -179,7 +242,17 @@ mf_status mf_ctx_create(int device, mf_ctx** out) {
 void mf_ctx_destroy(mf_ctx* ctx) {
   if (!ctx) return;
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  for (SweepGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
   delete ctx;
+}
+
+mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  ctx->use_graphs = enable != 0;
+  return ok();
 }
 
 mf_status mf_ctx_timing(mf_ctx* ctx, int32_t enable) {
@@ -191,15 +264,16 @@ mf_status mf_ctx_timing(mf_ctx* ctx, int32_t enable) {
 mf_status mf_ctx_timing_read(mf_ctx* ctx, int64_t* launches, double* total_ms, int64_t* rows) {
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   double ms = 0.0;
-  int64_t nrows = 0;
+  int64_t nrows = 0, nl = 0;
   for (size_t i = 0; i < ctx->used; ++i) {
     MF_HIP(hipEventSynchronize(ctx->events[2 * i + 1]));
     float t = 0.0f;
     MF_HIP(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]));
     ms += t;
     nrows += ctx->rows[i];
+    nl += ctx->nlaunch[i];
   }
-  if (launches) *launches = (int64_t)ctx->used;
+  if (launches) *launches = nl;
   if (total_ms) *total_ms = ms;
   if (rows) *rows = nrows;
   ctx->used = 0;
@@ -235,31 +309,111 @@ static mf_status sweep_common_checks(mf_ctx* ctx, const mf_sdnet_desc* desc, con
   return MF_OK;
 }
 
+static mf_status timing_begin(mf_ctx* ctx, hipStream_t s) {
+  if (ctx->events.size() < 2 * (ctx->used + 1)) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      MF_HIP(hipEventCreate(&e));
+      ctx->events.push_back(e);
+    }
+    ctx->rows.push_back(0);
+    ctx->nlaunch.push_back(0);
+  }
+  MF_HIP(hipEventRecord(ctx->events[2 * ctx->used], s));
+  return MF_OK;
+}
+
+static mf_status timing_end(mf_ctx* ctx, hipStream_t s, int64_t rows, int64_t launches) {
+  MF_HIP(hipEventRecord(ctx->events[2 * ctx->used + 1], s));
+  ctx->rows[ctx->used] = rows;
+  ctx->nlaunch[ctx->used] = launches;
+  ctx->used++;
+  return MF_OK;
+}
+
+static int64_t phase_rows(const mf_domain_desc* dom, int colour, int targets) {
+  const int64_t n_place = (int64_t)(dom->units_x - (colour & 1)) * (dom->units_y - (colour >> 1));
+  return n_place * (targets == MF_INTERIOR ? 961 : 61);
+}
+
 static mf_status run_phase(mf_ctx* ctx, const NetPtrs& net, int width, int prec, int targets,
                            bool accumulate, const float* u_in, float* u_out,
-                           const mf_domain_desc* dom, int colour, hipStream_t s) {
+                           const mf_domain_desc* dom, int colour, hipStream_t s,
+                           bool allow_timing = true) {
   PhaseArgs p{u_in, u_out, dom->pitch, dom->units_x, dom->units_y, colour};
   const int64_t n_place = (int64_t)(dom->units_x - (colour & 1)) * (dom->units_y - (colour >> 1));
   const int64_t rows = n_place * ((accumulate || targets == MF_INTERIOR) ? 961 : 61);
   const int R = pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
-  const bool timed = ctx->timing && !accumulate && rows > 0;
-  if (timed) {
-    if (ctx->events.size() < 2 * (ctx->used + 1)) {
-      for (int i = 0; i < 2; ++i) {
-        hipEvent_t e;
-        MF_HIP(hipEventCreate(&e));
-        ctx->events.push_back(e);
-      }
-      ctx->rows.push_back(0);
-    }
-    MF_HIP(hipEventRecord(ctx->events[2 * ctx->used], s));
-  }
+  const bool timed = allow_timing && ctx->timing && !accumulate && rows > 0;
+  if (timed) MF_TRY(timing_begin(ctx, s));
   MF_HIP(launch_phase(net, width, prec, targets, accumulate, R, p, s));
-  if (timed) {
-    MF_HIP(hipEventRecord(ctx->events[2 * ctx->used + 1], s));
-    ctx->rows[ctx->used] = rows;
-    ctx->used++;
+  if (timed) MF_TRY(timing_end(ctx, s, rows, 1));
+  return MF_OK;
+}
+
+// Cached graph of `sweeps` sweeps on ctx->gstream; captured on first use.
+static mf_status sweep_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_desc* desc, int prec,
+                             int targets, float* field, const mf_domain_desc* dom, const void* ws,
+                             int sweeps, hipGraphExec_t* out) {
+  for (const SweepGraph& g : ctx->graphs) {
+    if (g.field == field && g.ws == ws && g.pitch == dom->pitch && g.ux == dom->units_x &&
+        g.uy == dom->units_y && g.width == desc->width && g.prec == prec && g.targets == targets &&
+        g.sweeps == sweeps) {
+      *out = g.exec;
+      return MF_OK;
+    }
   }
+  if (ctx->graphs.size() >= 16) {   // bounded cache: drop the oldest entry
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  hipGraph_t graph = nullptr;
+  MF_HIP(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+  mf_status st = MF_OK;
+  for (int k = 0; k < sweeps && st == MF_OK; ++k)
+    for (int c = 0; c < 4 && st == MF_OK; ++c)
+      st = run_phase(ctx, net, desc->width, prec, targets, false, field, field, dom, c, ctx->gstream,
+                     false);
+  hipError_t e = hipStreamEndCapture(ctx->gstream, &graph);
+  if (st != MF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MF_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+  ctx->graphs.push_back(SweepGraph{field, ws, dom->pitch, dom->units_x, dom->units_y, desc->width, prec,
+                                   targets, sweeps, exec});
+  *out = exec;
+  return MF_OK;
+}
+
+// max_sweeps sweeps with no delta test, replayed from captured graphs of up
+// to kGraphSweeps sweeps on the context's stream, ordered after and before
+// the caller's stream by events.
+static constexpr int kGraphSweeps = 16;
+static mf_status run_sweeps_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_desc* desc, int prec,
+                                  int targets, float* field, const mf_domain_desc* dom, const void* ws,
+                                  int max_sweeps, hipStream_t s) {
+  const int full = max_sweeps / kGraphSweeps, rem = max_sweeps % kGraphSweeps;
+  hipGraphExec_t g_full = nullptr, g_rem = nullptr;
+  if (full > 0) MF_TRY(sweep_graph(ctx, net, desc, prec, targets, field, dom, ws, kGraphSweeps, &g_full));
+  if (rem > 0) MF_TRY(sweep_graph(ctx, net, desc, prec, targets, field, dom, ws, rem, &g_rem));
+  int64_t rows_sweep = 0;
+  for (int c = 0; c < 4; ++c) rows_sweep += phase_rows(dom, c, targets);
+  MF_HIP(hipEventRecord(ctx->fork, s));
+  MF_HIP(hipStreamWaitEvent(ctx->gstream, ctx->fork, 0));
+  for (int i = 0; i < full + (rem > 0 ? 1 : 0); ++i) {
+    const bool last_rem = i == full;
+    const int n = last_rem ? rem : kGraphSweeps;
+    if (ctx->timing) MF_TRY(timing_begin(ctx, ctx->gstream));
+    MF_HIP(hipGraphLaunch(last_rem ? g_rem : g_full, ctx->gstream));
+    if (ctx->timing) MF_TRY(timing_end(ctx, ctx->gstream, rows_sweep * n, 4 * (int64_t)n));
+  }
+  MF_HIP(hipEventRecord(ctx->join, ctx->gstream));
+  MF_HIP(hipStreamWaitEvent(s, ctx->join, 0));
   return MF_OK;
 }
 
@@ -309,7 +463,11 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   int done = 0;
   float last = NAN;
   bool converged = false;
-  for (int k = 1; k <= max_sweeps; ++k) {
+  if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0) {
+    MF_TRY(run_sweeps_graph(ctx, net, desc, prec, targets, field, dom, ws, max_sweeps, s));
+    done = max_sweeps;
+  }
+  for (int k = done + 1; k <= max_sweeps; ++k) {
     const bool check = eps > 0.0f && (k % check_every) == 0;
     if (check) MF_HIP(launch_skeleton_snapshot(field, dom->pitch, dom->units_x, dom->units_y, skel, s));
     for (int c = 0; c < 4; ++c)
@@ -389,23 +547,29 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
 // ---------------------------------------------------------------------------
 // sdnet_forward
 // ---------------------------------------------------------------------------
-static size_t forward_ws(int width, int prec, int64_t n_bc, NetLayout* Lout, size_t* c_off) {
+// Workspace of sdnet_forward: prepared network, projections C [n_bc][d] and,
+// for derivative outputs, two stream-row buffers [4 n_bc n_pts][d].
+static size_t forward_ws(int width, int prec, int64_t n_bc, int64_t n_pts, bool derivs,
+                         NetLayout* Lout, size_t* c_off, size_t* z_off) {
   NetLayout L = net_layout(width, prec, 0);
   size_t o = L.end;
   *c_off = o;
   o = align256(o + (size_t)n_bc * width * 4);
+  *z_off = o;
+  if (derivs) o = align256(o + 2 * (size_t)4 * n_bc * n_pts * width * 4);
   if (Lout) *Lout = L;
   return o;
 }
 
-mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int32_t prec, size_t* bytes) {
+mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int64_t n_pts,
+                                int32_t derivatives, int32_t prec, size_t* bytes) {
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
   MF_TRY(check_prec(prec));
-  if (n_bc < 0) return fail(MF_ESHAPE, "n_bc < 0");
-  size_t c_off;
-  *bytes = forward_ws(desc->width, prec, n_bc, nullptr, &c_off);
+  if (n_bc < 0 || n_pts < 0) return fail(MF_ESHAPE, "n_bc and n_pts must be >= 0");
+  size_t c_off, z_off;
+  *bytes = forward_ws(desc->width, prec, n_bc, n_pts, derivatives != 0, nullptr, &c_off, &z_off);
   return ok();
 }
 
@@ -417,15 +581,18 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
   if (n_bc < 0 || n_pts < 0) return fail(MF_ESHAPE, "n_bc and n_pts must be >= 0");
   if (x_per_bc != 0 && x_per_bc != 1) return fail(MF_EINVAL, "x_per_bc must be 0 or 1");
   if (n_bc * n_pts > (1LL << 40)) return fail(MF_ESHAPE, "too many rows");
-  if (dU || lapU) return fail(MF_EUNSUPPORTED, "derivative outputs are not implemented yet");
+  const bool derivs = dU || lapU;
+  if (derivs && prec != MF_FP32) return fail(MF_EUNSUPPORTED, "derivative outputs need MF_FP32");
   if (n_bc == 0 || n_pts == 0) return ctx ? ok() : fail(MF_EINVAL, "ctx is NULL");
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(G, "G"));
   MF_TRY(check_ptr(X, "X"));
   MF_TRY(check_ptr(U, "U"));
+  if (dU) MF_TRY(check_ptr(dU, "dU"));
+  if (lapU) MF_TRY(check_ptr(lapU, "lapU"));
   NetLayout L;
-  size_t c_off;
-  const size_t need = forward_ws(desc->width, prec, n_bc, &L, &c_off);
+  size_t c_off, z_off;
+  const size_t need = forward_ws(desc->width, prec, n_bc, n_pts, derivs, &L, &c_off, &z_off);
   MF_TRY(check_ws(ws, ws_bytes, need));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -434,7 +601,13 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
   const NetPtrs net = net_ptrs(L, ws);
   float* C = reinterpret_cast<float*>(static_cast<char*>(ws) + c_off);
   MF_HIP(launch_projection(net, desc->width, G, n_bc, C, s));
-  MF_HIP(launch_forward_rows(net, desc->width, prec, C, X, n_bc, n_pts, x_per_bc, U, s));
+  if (!derivs) {
+    MF_HIP(launch_forward_rows(net, desc->width, prec, C, X, n_bc, n_pts, x_per_bc, U, s));
+  } else {
+    float* Z0 = reinterpret_cast<float*>(static_cast<char*>(ws) + z_off);
+    float* Z1 = Z0 + (size_t)4 * n_bc * n_pts * desc->width;
+    MF_HIP(launch_forward_derivs(net, desc->width, C, X, x_per_bc, n_bc, n_pts, Z0, Z1, U, dU, lapU, s));
+  }
   return ok();
 }
 
@@ -442,17 +615,54 @@ mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nc, 
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
-  (void)B; (void)nc;
-  return fail(MF_EUNSUPPORTED, "training is not implemented yet");
+  if (B < 1 || nc < 1) return fail(MF_ESHAPE, "B and nc must be >= 1");
+  if (B * nc > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nc too large");
+  *bytes = train_layout(desc->width, B, nc).total;
+  return ok();
 }
 
 mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params, float* m, float* v,
                            int64_t step, const mf_adam* hp, const float* G, int64_t B, const float* Xb,
                            const float* Xc, int64_t nc, float* loss_dev, float* grad_out, void* ws,
                            size_t ws_bytes, void* stream) {
-  (void)ctx; (void)desc; (void)params; (void)m; (void)v; (void)step; (void)hp; (void)G; (void)B;
-  (void)Xb; (void)Xc; (void)nc; (void)loss_dev; (void)grad_out; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(MF_EUNSUPPORTED, "training is not implemented yet");
+  MF_TRY(check_desc(desc));
+  if (B < 1 || nc < 1) return fail(MF_ESHAPE, "B and nc must be >= 1");
+  if (B * nc > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nc too large");
+  MF_TRY(check_ptr(params, "params"));
+  MF_TRY(check_ptr(G, "G"));
+  MF_TRY(check_ptr(Xb, "Xb"));
+  MF_TRY(check_ptr(Xc, "Xc"));
+  MF_TRY(check_ptr(loss_dev, "loss_dev"));
+  if (grad_out) {
+    MF_TRY(check_ptr(grad_out, "grad_out"));
+  } else {
+    MF_TRY(check_ptr(m, "m"));
+    MF_TRY(check_ptr(v, "v"));
+    if (!hp) return fail(MF_EINVAL, "adam hyperparameters are NULL");
+    if (step < 1) return fail(MF_EINVAL, "step %lld < 1 (Adam counts from 1)", (long long)step);
+    if (!(hp->lr > 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) ||
+        !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->eps > 0.0f))
+      return fail(MF_EINVAL, "adam hyperparameters out of range");
+  }
+  const TrainLayout L = train_layout(desc->width, B, nc);
+  MF_TRY(check_ws(ws, ws_bytes, L.total));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, L.net, ws, s));
+  const NetPtrs net = net_ptrs(L.net, ws);
+  float* whT = reinterpret_cast<float*>(static_cast<char*>(ws) + L.whT);
+  MF_HIP(launch_prepare_wT(params, desc->width, whT, s));
+  const TrainBuffers tb = train_buffers(L, ws);
+  float* grad = grad_out ? grad_out : tb.grad;
+  MF_HIP(launch_train_grad(net, desc->width, whT, tb, G, B, Xb, Xc, nc, grad, loss_dev, s));
+  if (!grad_out) {
+    const double bc1 = 1.0 - pow((double)hp->beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)hp->beta2, (double)step);
+    MF_HIP(launch_adam(params, m, v, grad, mf_param_count(desc), hp->lr, hp->beta1, hp->beta2, hp->eps,
+                       (float)bc1, (float)bc2, s));
+  }
+  return ok();
 }
 
 }  // extern "C"

@@ -110,3 +110,35 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 }
 
 }  // namespace mf
+
+namespace mf {
+
+// One d x d layer on fp32 MFMA for a tile of 32*RB rows held in LDS (row
+// pitch LDH floats). The wave owning output columns [32 w, 32 w + 32)
+// passes `wsw` = prepared weights + w * (D/8) * 64 + lane (layout
+// [col block][k group][lane][4], see prepare_net_kernel). Inside each
+// 8-wide k group lane l feeds k = 8 kg + 4 (l >> 5) + e at MFMA step e to
+// both operands, so A and B are read as 16-byte vectors.
+template <int D, int RB, int LDH>
+__device__ __forceinline__ void mfma_layer_f32(const float* Hs, const floatx4* wsw,
+                                               floatx16 (&acc)[RB], int lane) {
+  const int arow = lane & 31, ahalf = lane >> 5;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[rb][v] = 0.0f;
+#pragma unroll 4
+  for (int kg = 0; kg < D / 8; ++kg) {
+    const floatx4 bv = wsw[kg * 64];
+    floatx4 av[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+      av[rb] = *reinterpret_cast<const floatx4*>(&Hs[(rb * 32 + arow) * LDH + kg * 8 + 4 * ahalf]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma32x32x2(av[rb][e], bv[e], acc[rb]);
+  }
+}
+
+}  // namespace mf

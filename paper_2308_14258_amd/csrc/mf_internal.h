@@ -84,4 +84,34 @@ hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const fl
                                const float* X, int64_t n_bc, int64_t n_pts, int x_per_bc,
                                float* U, hipStream_t s);
 
+// Training: device buffers carved from the workspace.
+struct TrainBuffers {
+  float* C;          // [B][d] boundary projections (b1 included)
+  float* Z[4];       // [SR][d] stream rows after layers 1..4 (z, z_x, z_y, z_L)
+  float* Sv[4];      // [SR][d] saved (z, a_x, a_y, a_L) of layers 1..4
+  float* Ab[2];      // [SR][d] ping-pong pre-activation adjoints
+  float* wpart;      // [n_chunks][d*d] weight-gradient partials
+  float* bpart;      // [n_chunks][d]
+  float* opart[2];   // [2048][d+2] output-layer partials (data, collocation)
+  float* l1[2];      // [3][B][d] first-layer sums (data, collocation)
+  float* grad;       // [P] gradient (used when the caller gives none)
+};
+struct TrainLayout {
+  NetLayout net;
+  size_t whT = 0, C = 0, Z[4] = {0, 0, 0, 0}, Sv[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
+  size_t wpart = 0, bpart = 0, opart[2] = {0, 0}, l1[2] = {0, 0}, grad = 0, total = 0;
+};
+TrainLayout train_layout(int width, int64_t B, int64_t nc);
+TrainBuffers train_buffers(const TrainLayout& L, void* ws);
+
+hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStream_t s);
+hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
+                             const float* G, int64_t B, const float* Xb, const float* Xc, int64_t nc,
+                             float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
+                                 int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
+                                 float* U, float* dU, float* lapU, hipStream_t s);
+
 }  // namespace mf

@@ -1,0 +1,610 @@
+// Physics-informed SDNet training step on gfx950 (Alg. 1 on one device).
+//
+// Derivatives with respect to the point (x, y) are propagated forward
+// through the network as four streams per point: value v, v_x, v_y and the
+// Laplacian v_L. An affine layer maps each stream with the same weights
+// (the bias enters the value stream only); tanh maps them by
+//   z = tanh a, s = 1 - z^2, z_x = s a_x, z_y = s a_y,
+//   z_L = s a_L - 2 z s (a_x^2 + a_y^2),
+// so the PDE residual (Eq. 3) is the output layer applied to the Laplacian
+// stream. The four streams of a point are stored as four consecutive rows;
+// in the 32x32 MFMA accumulator layout those are four consecutive registers
+// of one lane, so every tanh rule runs in registers in the GEMM epilogue.
+//
+// The reverse pass is written out by hand. For the tanh rules above, with
+// output adjoints (zb, zb_x, zb_y, zb_L):
+//   ab_L = s zb_L
+//   ab_x = s (zb_x - 4 z a_x zb_L)
+//   ab_y = s (zb_y - 4 z a_y zb_L)
+//   ab   = s zb - 2 z s (a_x zb_x + a_y zb_y)
+//          - zb_L (2 z s a_L + 2 s (1 - 3 z^2) (a_x^2 + a_y^2))
+// and an affine layer gives h-adjoints ab W and weight gradient
+// sum_rows ab^T h over all four streams (split-K partial sums, reduced in a
+// fixed order: the result is deterministic).
+//
+// Alg. 1 runs the data points (value stream only) and then the collocation
+// points (four streams); both accumulate into one gradient, then Adam.
+#include <algorithm>
+
+#include "mf_device.h"
+#include "mf_internal.h"
+
+namespace mf {
+
+constexpr int kChunk = 4096;       // stream rows per weight-gradient partial
+constexpr int kOutWaves = 2048;    // waves of the output-layer kernel
+
+// ---------------------------------------------------------------------------
+// W^T of each hidden layer in MFMA operand order (for h-adjoint = ab W).
+// ---------------------------------------------------------------------------
+__global__ void prepare_wT_kernel(const float* __restrict__ params, int d, float* __restrict__ whT) {
+  const int64_t off_w2 = (int64_t)d * 130 + d;
+  const int64_t lstride = (int64_t)d * d + d;
+  const int64_t dd = (int64_t)d * d;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 3 * dd;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(idx / dd);
+    const int64_t r = idx - l * dd;
+    const int e = r & 3, lane = (r >> 2) & 63;
+    const int64_t rest = r >> 8;
+    const int kg = (int)(rest % (d / 8)), cb = (int)(rest / (d / 8));
+    const int j = 32 * cb + (lane & 31);
+    const int k = 8 * kg + 4 * (lane >> 5) + e;
+    whT[idx] = params[off_w2 + l * lstride + (int64_t)k * d + j];   // (W^T)[j][k] = W[k][j]
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First layer: a = C[b] + x W1x[:,0] + y W1x[:,1]; streams for S = 4 use
+// a_x = W1x[:,0], a_y = W1x[:,1], a_L = 0.
+// ---------------------------------------------------------------------------
+template <int D, int S>
+__global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict__ C,
+                                                         const float* __restrict__ X, int x_per_bc,
+                                                         int64_t rows_per_bc, int64_t n_rows,
+                                                         const float* __restrict__ w1x,
+                                                         float* __restrict__ Z, float* __restrict__ Sv) {
+  const int64_t n = n_rows * D;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / D;
+    const int j = (int)(idx - r * D);
+    const int64_t b = r / rows_per_bc;
+    const float* xp = x_per_bc ? X + 2 * r : X + 2 * (r - b * rows_per_bc);
+    const float wx = w1x[2 * j], wy = w1x[2 * j + 1];
+    const float a = fmaf(xp[1], wy, fmaf(xp[0], wx, C[b * D + j]));
+    const float z = tanh_f32(a);
+    if constexpr (S == 1) {
+      Z[r * D + j] = z;
+    } else {
+      const float s = 1.0f - z * z;
+      const int64_t o = 4 * r * D + j;
+      Z[o] = z;
+      Z[o + D] = s * wx;
+      Z[o + 2 * D] = s * wy;
+      Z[o + 3 * D] = -2.0f * z * s * (wx * wx + wy * wy);
+      if (Sv) {
+        Sv[o] = z;
+        Sv[o + D] = wx;
+        Sv[o + 2 * D] = wy;
+        Sv[o + 3 * D] = 0.0f;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM over stream rows with a Taylor epilogue.
+//   MODE 0 (forward):  P = Zin W^T (+ b on the value stream) -> tanh rules ->
+//                      Zout (z streams) and Sv (z, a_x, a_y, a_L);
+//   MODE 1 (backward): Zb = Ain W -> reverse tanh rules with Sv -> Aout.
+// A tile is 64 stream rows x D columns; the tile is staged in LDS.
+// ---------------------------------------------------------------------------
+template <int D, int S, int MODE>
+__global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restrict__ Ain,
+                                                            const floatx4* __restrict__ wsw,
+                                                            const float* __restrict__ bias,
+                                                            const float* __restrict__ Sv_in,
+                                                            float* __restrict__ Out,
+                                                            float* __restrict__ Sv_out,
+                                                            int64_t n_srows) {
+  constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
+  __shared__ __align__(16) float Hs[R * LDH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+
+  for (int idx = tid; idx < R * D / 4; idx += NTH) {
+    const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+    floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(Ain + (row0 + r) * D)[c4];
+    *reinterpret_cast<floatx4*>(&Hs[r * LDH + 4 * c4]) = v;
+  }
+  __syncthreads();
+
+  floatx16 acc[RB];
+  mfma_layer_f32<D, RB, LDH>(Hs, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
+
+  const int j = wave * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const float bj = (MODE == 0) ? bias[j] : 0.0f;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int64_t sr = row0 + rb * 32 + 8 * m + 4 * h;   // first of 4 consecutive rows
+      if constexpr (S == 4) {
+        if (sr >= n_srows) continue;
+        const int64_t o = sr * D + j;
+        if constexpr (MODE == 0) {
+          const float a = acc[rb][4 * m] + bj, ax = acc[rb][4 * m + 1];
+          const float ay = acc[rb][4 * m + 2], aL = acc[rb][4 * m + 3];
+          const float z = tanh_f32(a), s = 1.0f - z * z;
+          Out[o] = z;
+          Out[o + D] = s * ax;
+          Out[o + 2 * D] = s * ay;
+          Out[o + 3 * D] = s * aL - 2.0f * z * s * (ax * ax + ay * ay);
+          if (Sv_out) {
+            Sv_out[o] = z;
+            Sv_out[o + D] = ax;
+            Sv_out[o + 2 * D] = ay;
+            Sv_out[o + 3 * D] = aL;
+          }
+        } else {
+          const float z = Sv_in[o], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
+          const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
+          const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
+          const float s = 1.0f - z * z, q = ax * ax + ay * ay;
+          Out[o] = s * zb - 2.0f * z * s * (ax * zbx + ay * zby) -
+                   zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
+          Out[o + D] = s * (zbx - 4.0f * z * ax * zbL);
+          Out[o + 2 * D] = s * (zby - 4.0f * z * ay * zbL);
+          Out[o + 3 * D] = s * zbL;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = sr + e;
+          if (row >= n_srows) continue;
+          const int64_t o = row * D + j;
+          if constexpr (MODE == 0) {
+            Out[o] = tanh_f32(acc[rb][4 * m + e] + bj);
+          } else {
+            const float z = Sv_in[o];
+            Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Output layer, loss and the seed of the reverse pass. One wave per point.
+//   S = 4 (collocation): residual u_L = w5 . z_L; ub_L = 2 u_L / n.
+//   S = 1 (data):        residual u - g; ub = 2 (u - g) / n.
+// Writes ab_4 = reverse tanh rules of zb_4 = w5 ub, and per-wave partial
+// sums of the w5 / b5 gradient and of the squared residual.
+// ---------------------------------------------------------------------------
+template <int D, int S>
+__global__ __launch_bounds__(256) void output_loss_kernel(const float* __restrict__ Z4,
+                                                          const float* __restrict__ Sv4,
+                                                          const float* __restrict__ w5,
+                                                          const float* __restrict__ b5,
+                                                          const float* __restrict__ target,
+                                                          int64_t n_rows, float inv_n,
+                                                          float* __restrict__ Ab,
+                                                          float* __restrict__ opart) {
+  constexpr int NJ = D / 64;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  float w5r[NJ], gw5[NJ];
+#pragma unroll
+  for (int t = 0; t < NJ; ++t) {
+    w5r[t] = w5[lane + 64 * t];
+    gw5[t] = 0.0f;
+  }
+  float gb5 = 0.0f, lsum = 0.0f;
+  for (int64_t r = gw; r < n_rows; r += kOutWaves) {
+    if constexpr (S == 4) {
+      const int64_t o = 4 * r * D;
+      float zL[NJ], p = 0.0f;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        zL[t] = Z4[o + 3 * D + lane + 64 * t];
+        p = fmaf(w5r[t], zL[t], p);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+      const float res = p;                      // Laplacian of the output
+      lsum = fmaf(res, res, lsum);
+      const float ubL = 2.0f * res * inv_n;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        const int j = lane + 64 * t;
+        gw5[t] = fmaf(ubL, zL[t], gw5[t]);
+        const float z = Sv4[o + j], ax = Sv4[o + D + j], ay = Sv4[o + 2 * D + j];
+        const float aL = Sv4[o + 3 * D + j];
+        const float zbL = w5r[t] * ubL;
+        const float s = 1.0f - z * z, q = ax * ax + ay * ay;
+        Ab[o + j] = -zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
+        Ab[o + D + j] = s * (-4.0f * z * ax * zbL);
+        Ab[o + 2 * D + j] = s * (-4.0f * z * ay * zbL);
+        Ab[o + 3 * D + j] = s * zbL;
+      }
+    } else {
+      const int64_t o = r * D;
+      float zv[NJ], p = 0.0f;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        zv[t] = Z4[o + lane + 64 * t];
+        p = fmaf(w5r[t], zv[t], p);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off);
+      const float res = p + b5[0] - target[r];
+      lsum = fmaf(res, res, lsum);
+      const float ub = 2.0f * res * inv_n;
+      gb5 += ub;
+#pragma unroll
+      for (int t = 0; t < NJ; ++t) {
+        gw5[t] = fmaf(ub, zv[t], gw5[t]);
+        Ab[o + lane + 64 * t] = (1.0f - zv[t] * zv[t]) * w5r[t] * ub;
+      }
+    }
+  }
+  float* op = opart + (int64_t)gw * (D + 2);
+#pragma unroll
+  for (int t = 0; t < NJ; ++t) op[lane + 64 * t] = gw5[t];
+  if (lane == 0) {
+    op[D] = gb5;
+    op[D + 1] = lsum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient partials: for a chunk of stream rows,
+//   P[j][k] = sum_r Ab[r][j] H[r][k],  pb[j] = sum_{value rows} Ab[r][j].
+// MFMA with A = Ab^T (32 x 2 slices down the rows), B = H; wave w owns the
+// output row block j in [32 w, 32 w + 32) and all column blocks.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(2 * D) void wgrad_kernel(const float* __restrict__ Ab,
+                                                      const float* __restrict__ H, int64_t n_srows,
+                                                      int S, float* __restrict__ wpart,
+                                                      float* __restrict__ bpart) {
+  constexpr int NKB = D / 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r_begin = (int64_t)blockIdx.x * kChunk;
+  const int64_t r_end = std::min<int64_t>(r_begin + kChunk, n_srows);
+  floatx16 acc[NKB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[kb][v] = 0.0f;
+  const int col = lane & 31, half = lane >> 5;
+  const int ja = wave * 32 + col;
+  constexpr int U = 8;   // row pairs per batch of loads
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += 2 * U) {
+    float av[U], bv[U][NKB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + 2 * u + half;
+      const bool ok = r < r_end;
+      av[u] = ok ? Ab[r * D + ja] : 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) bv[u][kb] = ok ? H[r * D + kb * 32 + col] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) acc[kb] = mfma32x32x2(av[u], bv[u][kb], acc[kb]);
+  }
+  float* P = wpart + (int64_t)blockIdx.x * D * D;
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int jrow = wave * 32 + acc_row(lane, v);
+      P[(int64_t)jrow * D + kb * 32 + col] = acc[kb][v];
+    }
+  if (tid < D) {
+    float s = 0.0f;
+    for (int64_t r = r_begin; r < r_end; r += S) s += Ab[r * D + tid];
+    bpart[(int64_t)blockIdx.x * D + tid] = s;
+  }
+}
+
+// out[i] (+)= scale * sum_p part[p * n + i], p in order.
+__global__ void reduce_parts_kernel(const float* __restrict__ part, int64_t n_parts, int64_t n,
+                                    int64_t stride, float* __restrict__ out, int accumulate) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int64_t p = 0; p < n_parts; ++p) s += part[p * stride + i];
+    out[i] = accumulate ? out[i] + s : s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First-layer reductions per boundary condition b:
+//   c[b][j]  = sum_rows ab,  cx[b][j] = sum_rows (ab x + ab_x),
+//   cy[b][j] = sum_rows (ab y + ab_y).
+// ---------------------------------------------------------------------------
+template <int D, int S>
+__global__ __launch_bounds__(D) void layer1_reduce_kernel(const float* __restrict__ Ab1,
+                                                          const float* __restrict__ X, int x_per_bc,
+                                                          int64_t rows_per_bc, int64_t B,
+                                                          float* __restrict__ out) {
+  const int64_t b = blockIdx.x;
+  const int j = threadIdx.x;
+  float c = 0.0f, cx = 0.0f, cy = 0.0f;
+  for (int64_t p = 0; p < rows_per_bc; ++p) {
+    const int64_t r = b * rows_per_bc + p;
+    const float* xp = x_per_bc ? X + 2 * r : X + 2 * p;
+    const float a = Ab1[S * r * D + j];
+    float ax = 0.0f, ay = 0.0f;
+    if constexpr (S == 4) {
+      ax = Ab1[(4 * r + 1) * D + j];
+      ay = Ab1[(4 * r + 2) * D + j];
+    }
+    c += a;
+    cx += fmaf(a, xp[0], ax);
+    cy += fmaf(a, xp[1], ay);
+  }
+  out[b * D + j] = c;
+  out[(B + b) * D + j] = cx;
+  out[(2 * B + b) * D + j] = cy;
+}
+
+// grad W1g[j][k] = sum_b (c0[b][j] + c1[b][j]) G[b][k]; b1, W1x from the sums.
+template <int D>
+__global__ __launch_bounds__(256) void layer1_grad_kernel(const float* __restrict__ l1a,
+                                                          const float* __restrict__ l1b,
+                                                          const float* __restrict__ G, int64_t B,
+                                                          float* __restrict__ grad) {
+  const int64_t off_b1 = (int64_t)D * 130;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < D * 128) {
+    const int j = t / 128, k = t % 128;
+    float s = 0.0f;
+    for (int64_t b = 0; b < B; ++b) s = fmaf(l1a[b * D + j] + l1b[b * D + j], G[b * 128 + k], s);
+    grad[(int64_t)j * 130 + k] = s;
+  } else if (t < D * 128 + D) {
+    const int j = t - D * 128;
+    float c = 0.0f, cx = 0.0f, cy = 0.0f;
+    for (int64_t b = 0; b < B; ++b) {
+      c += l1a[b * D + j] + l1b[b * D + j];
+      cx += l1a[(B + b) * D + j] + l1b[(B + b) * D + j];
+      cy += l1a[(2 * B + b) * D + j] + l1b[(2 * B + b) * D + j];
+    }
+    grad[(int64_t)j * 130 + 128] = cx;
+    grad[(int64_t)j * 130 + 129] = cy;
+    grad[off_b1 + j] = c;
+  }
+}
+
+// Output-layer gradient and the two losses from the per-wave partials.
+template <int D>
+__global__ __launch_bounds__(256) void output_grad_kernel(const float* __restrict__ op_data,
+                                                          const float* __restrict__ op_col,
+                                                          float inv_data, float inv_col,
+                                                          float* __restrict__ grad,
+                                                          float* __restrict__ loss) {
+  const int64_t off_w5 = (int64_t)D * 130 + D + 3 * ((int64_t)D * D + D);
+  const int t = threadIdx.x;
+  for (int j = t; j < D + 2; j += 256) {
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int w = 0; w < kOutWaves; ++w) {
+      s0 += op_data[(int64_t)w * (D + 2) + j];
+      s1 += op_col[(int64_t)w * (D + 2) + j];
+    }
+    if (j < D) grad[off_w5 + j] = s0 + s1;
+    else if (j == D) grad[off_w5 + D] = s0 + s1;
+    else {
+      loss[0] = s0 * inv_data;
+      loss[1] = s1 * inv_col;
+    }
+  }
+}
+
+__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
+                            float eps, float bc1, float bc2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mhat = mi / bc1, vhat = vi / bc2;
+    p[i] -= lr * mhat / (sqrtf(vhat) + eps);
+  }
+}
+
+// Forward-only output for sdnet_forward with derivatives: one wave per point.
+template <int D>
+__global__ __launch_bounds__(256) void forward_derivs_kernel(const float* __restrict__ Z4,
+                                                             const float* __restrict__ w5,
+                                                             const float* __restrict__ b5,
+                                                             int64_t n_rows, float* __restrict__ U,
+                                                             float* __restrict__ dU,
+                                                             float* __restrict__ lapU) {
+  constexpr int NJ = D / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t r = gw; r < n_rows; r += nw) {
+    float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+      const float w = w5[lane + 64 * t];
+#pragma unroll
+      for (int sgm = 0; sgm < 4; ++sgm) p[sgm] = fmaf(w, Z4[(4 * r + sgm) * D + lane + 64 * t], p[sgm]);
+    }
+#pragma unroll
+    for (int sgm = 0; sgm < 4; ++sgm)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) p[sgm] += __shfl_xor(p[sgm], off);
+    if (lane == 0) {
+      if (U) U[r] = p[0] + b5[0];
+      if (dU) {
+        dU[2 * r] = p[1];
+        dU[2 * r + 1] = p[2];
+      }
+      if (lapU) lapU[r] = p[3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side drivers
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n, int block, int cap = 8192) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, cap));
+}
+
+template <int D>
+static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const float* X, int x_per_bc,
+                                     int64_t rows_per_bc, int64_t n_rows, int S, float* const Z[4],
+                                     float* const Sv[4], hipStream_t s) {
+  const int64_t n_srows = S * n_rows;
+  if (S == 4)
+    hipLaunchKernelGGL((fwd_layer1_kernel<D, 4>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], Sv[0]);
+  else
+    hipLaunchKernelGGL((fwd_layer1_kernel<D, 1>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], Sv[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((n_srows + 63) / 64);
+  for (int l = 0; l < 3; ++l) {
+    const floatx4* w = static_cast<const floatx4*>(net.wh) + (size_t)l * D * D / 4;
+    if (S == 4)
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
+                         net.bh + l * D, nullptr, Z[l + 1], Sv[l + 1], n_srows);
+    else
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
+                         net.bh + l * D, nullptr, Z[l + 1], nullptr, n_srows);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int D>
+static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuffers& tb,
+                           const float* C, const float* X, int x_per_bc, int64_t rows_per_bc,
+                           int64_t B, int S, const float* target, float* grad, float* opart,
+                           float* l1out, bool accumulate, hipStream_t s) {
+  const int64_t n_rows = B * rows_per_bc;
+  const int64_t n_srows = S * n_rows;
+  float* const* Z = tb.Z;
+  float* const* Sv = (S == 4) ? tb.Sv : tb.Z;   // value-only rows: saved z = Z
+  hipError_t e = run_taylor_forward<D>(net, C, X, x_per_bc, rows_per_bc, n_rows, S, Z,
+                                       (S == 4) ? tb.Sv : tb.Z, s);
+  if (e != hipSuccess) return e;
+  const float inv_n = 1.0f / (float)n_rows;
+  if (S == 4)
+    hipLaunchKernelGGL((output_loss_kernel<D, 4>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
+                       net.w5, net.b5, target, n_rows, inv_n, tb.Ab[0], opart);
+  else
+    hipLaunchKernelGGL((output_loss_kernel<D, 1>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
+                       net.w5, net.b5, target, n_rows, inv_n, tb.Ab[0], opart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+
+  const int64_t off_w2 = (int64_t)D * 130 + D;
+  const int64_t lstride = (int64_t)D * D + D;
+  const int64_t n_chunks = (n_srows + kChunk - 1) / kChunk;
+  int cur = 0;
+  for (int l = 2; l >= 0; --l) {           // hidden layer l+2, input Z[l]
+    float* Ab = tb.Ab[cur];
+    hipLaunchKernelGGL((wgrad_kernel<D>), dim3((unsigned)n_chunks), dim3(2 * D), 0, s, Ab, Z[l],
+                       n_srows, S, tb.wpart, tb.bpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    float* gW = grad + off_w2 + l * lstride;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256)), dim3(256), 0, s,
+                       tb.wpart, n_chunks, (int64_t)D * D, (int64_t)D * D, gW, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, tb.bpart, n_chunks, (int64_t)D,
+                       (int64_t)D, gW + (int64_t)D * D, accumulate ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
+    const unsigned blocks = (unsigned)((n_srows + 63) / 64);
+    if (S == 4)
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab, wT,
+                         nullptr, Sv[l], tb.Ab[cur ^ 1], nullptr, n_srows);
+    else
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab, wT,
+                         nullptr, Sv[l], tb.Ab[cur ^ 1], nullptr, n_srows);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    cur ^= 1;
+  }
+  if (S == 4)
+    hipLaunchKernelGGL((layer1_reduce_kernel<D, 4>), dim3((unsigned)B), dim3(D), 0, s, tb.Ab[cur], X,
+                       x_per_bc, rows_per_bc, B, l1out);
+  else
+    hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)B), dim3(D), 0, s, tb.Ab[cur], X,
+                       x_per_bc, rows_per_bc, B, l1out);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStream_t s) {
+  hipLaunchKernelGGL(prepare_wT_kernel, dim3(256), dim3(256), 0, s, params, width, whT);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t train_step_d(const NetPtrs& net, const float* whT, const TrainBuffers& tb,
+                               const float* G, int64_t B, const float* Xb, const float* Xc,
+                               int64_t nc, float* grad, float* loss, hipStream_t s) {
+  hipError_t e = launch_projection(net, D, G, B, tb.C, s);
+  if (e != hipSuccess) return e;
+  // Alg. 1 step 1: data points (the 128 boundary nodes), value stream only.
+  e = run_pass<D>(net, whT, tb, tb.C, Xb, 0, 128, B, 1, G, grad, tb.opart[0], tb.l1[0], false, s);
+  if (e != hipSuccess) return e;
+  // Alg. 1 step 2: collocation points, four streams; accumulate.
+  e = run_pass<D>(net, whT, tb, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((layer1_grad_kernel<D>), dim3((D * 128 + D + 255) / 256), dim3(256), 0, s,
+                     tb.l1[0], tb.l1[1], G, B, grad);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((output_grad_kernel<D>), dim3(1), dim3(256), 0, s, tb.opart[0], tb.opart[1],
+                     1.0f / (float)(B * 128), 1.0f / (float)(B * nc), grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
+                             const float* G, int64_t B, const float* Xb, const float* Xc, int64_t nc,
+                             float* grad, float* loss, hipStream_t s) {
+  return width == 256 ? train_step_d<256>(net, whT, tb, G, B, Xb, Xc, nc, grad, loss, s)
+                      : train_step_d<128>(net, whT, tb, G, B, Xb, Xc, nc, grad, loss, s);
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                       float b2, float eps, float bc1, float bc2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, p, m, v, g, n, lr, b1,
+                     b2, eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
+                                 int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
+                                 float* U, float* dU, float* lapU, hipStream_t s) {
+  float* Z[4] = {Z0, Z1, Z0, Z1};
+  float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
+  const int64_t n_rows = n_bc * n_pts;
+  hipError_t e = width == 256
+                     ? run_taylor_forward<256>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, s)
+                     : run_taylor_forward<128>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, s);
+  if (e != hipSuccess) return e;
+  const int blocks = grid_for(n_rows, 4, 4096);
+  if (width == 256)
+    hipLaunchKernelGGL((forward_derivs_kernel<256>), dim3(blocks), dim3(256), 0, s, Z1, net.w5, net.b5,
+                       n_rows, U, dU, lapU);
+  else
+    hipLaunchKernelGGL((forward_derivs_kernel<128>), dim3(blocks), dim3(256), 0, s, Z1, net.w5, net.b5,
+                       n_rows, U, dU, lapU);
+  return hipGetLastError();
+}
+
+}  // namespace mf

@@ -5,6 +5,8 @@ seeded inputs of ``mf_inputs``; nothing is read from the HIP path.
 
     python tests/golden/make_golden.py [name ...]
 
+c3_train.npz -- the training workload: full-batch gradient at the initial
+    parameters and the loss curve of 100 Adam steps.
 c2_fp32.npz -- 16 x 16 units, width 256, GP ring data (length 2, seed 1),
     Xavier weights seed 0, 200 CROSS sweeps then the assembly. Holds the
     skeleton after 20 and 200 sweeps and u_out at 8192 sampled interior
@@ -58,7 +60,37 @@ def c2():
     print(f"c2: done in {time.time() - t0:.0f} s", flush=True)
 
 
-JOBS = {"c2": c2}
+def c3():
+    """1024 GP boundary conditions (l = 0.5, seed 2) x 256 collocation points
+    (seed 3), width 128, Xavier seed 0: the full-batch gradient at the initial
+    parameters and the (L_data, L_pde) curve of 100 Adam steps (lr 1e-3)."""
+    from oracle import train
+    w = mi.WORKLOADS["C3"]
+    G32 = mi.gp_perimeter_batch(w["n_bc"], w["length"], w["bc_seed"])
+    Xc32 = mi.collocation_points(w["n_bc"], w["n_colloc"], w["colloc_seed"])
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes())
+    G = torch.from_numpy(G32.astype(np.float64))
+    Xc = torch.from_numpy(Xc32.astype(np.float64))
+    th0 = mi.xavier_params(w["width"], 0)
+    th = torch.from_numpy(th0.astype(np.float64))
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    t0 = time.time()
+    ld, lp, gd, gp = train.gradient(th, w["width"], G, Xb, Xc)
+    grad0 = (gd + gp).numpy()
+    curve = []
+    for step in range(1, w["steps"] + 1):
+        th, m, v, ld, lp = train.train_step(th, m, v, step, w["width"], G, Xb, Xc)
+        curve.append((ld, lp))
+        if step % 5 == 0:
+            print(f"c3: step {step} L_data {ld:.6e} L_pde {lp:.6e} ({time.time() - t0:.0f} s)",
+                  flush=True)
+    np.savez_compressed(os.path.join(HERE, "c3_train.npz"), grad0=grad0, curve=np.array(curve),
+                        G_sha=_sha(G32), Xc_sha=_sha(Xc32), params_sha=_sha(th0))
+    print(f"c3: done in {time.time() - t0:.0f} s", flush=True)
+
+
+JOBS = {"c2": c2, "c3": c3}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)

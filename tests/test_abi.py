@@ -135,7 +135,7 @@ def test_solve_argument_errors(lib):
 def test_forward_argument_errors(lib):
     d = SdnetDesc(256, 4, 128, 0)
     n = ctypes.c_size_t()
-    assert lib.sdnet_forward_ws_size(ctypes.byref(d), 1000, MF_FP32, ctypes.byref(n)) == MF_OK
+    assert lib.sdnet_forward_ws_size(ctypes.byref(d), 1000, 7, 0, MF_FP32, ctypes.byref(n)) == MF_OK
     assert n.value >= 1000 * 256 * 4
     f = ctypes.c_void_p(FAKE)
     assert lib.sdnet_forward(None, ctypes.byref(d), f, f, 10, f, 5, 0, f, None, None, MF_FP32, f,

@@ -62,6 +62,6 @@ def test_forward_bf16_error(ctx, width):
 
 def test_forward_empty(ctx):
     params = torch.from_numpy(mi.xavier_params(128, 0)).cuda()
-    U = sdnet_forward(ctx, params, torch.zeros(0, 128, device="cuda"),
-                      torch.zeros(5, 2, device="cuda"))
+    U = sdnet_forward(ctx, params, torch.zeros(0, 128, device="cuda", dtype=torch.float32),
+                      torch.zeros(5, 2, device="cuda", dtype=torch.float32))
     assert U.shape == (0, 5)

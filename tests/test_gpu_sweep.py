@@ -18,7 +18,6 @@ from paper_2308_14258_amd import mf_solve, mf_sweep, mf_sweep_operator
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-torch.set_default_dtype(torch.float64)
 
 
 @pytest.fixture(scope="module")
@@ -278,3 +277,18 @@ def test_bf16_solve_c2_error(ctx):
     e_out = rel_l2(u_out.cpu().numpy()[g["sample_j"], g["sample_i"]], g["u_out_sample"])
     print(f"C2 bf16 rel L2 vs oracle: skeleton {e_skel:.3e} u_out {e_out:.3e}", flush=True)
     assert e_skel <= 2e-2 and e_out <= 2e-2
+
+
+def test_graph_replay_equals_direct_launches(ctx):
+    print("case: graph replay vs direct launches", flush=True)
+    params = dev(mi.random_params(256, seed=12))
+    f = mi.gp_field(3, 4, 1.0, seed=6)
+    a = dev(f)
+    b = dev(f)
+    ctx.graphs(False)
+    mf_solve(ctx, params, a, (3, 4), 37)
+    ctx.graphs(True)
+    mf_solve(ctx, params, b, (3, 4), 37)
+    mf_solve(ctx, params, b, (3, 4), 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

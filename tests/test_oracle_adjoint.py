@@ -10,7 +10,6 @@ import torch
 import mf_inputs as mi
 from oracle import adjoint, fd, sweep as sw
 
-torch.set_default_dtype(torch.float64)
 
 
 def _J(u0, ux, uy, solver, K):

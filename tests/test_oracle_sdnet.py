@@ -5,7 +5,6 @@ import torch
 import mf_inputs as mi
 from oracle import sdnet
 
-torch.set_default_dtype(torch.float64)
 
 
 def _theta(width, seed=5):

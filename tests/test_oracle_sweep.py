@@ -14,7 +14,6 @@ import torch
 import mf_inputs as mi
 from oracle import fd, geometry as geo, sdnet, sweep as sw
 
-torch.set_default_dtype(torch.float64)
 
 HARMONIC = {
     "x2-y2": lambda x, y: x * x - y * y,

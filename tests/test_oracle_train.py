@@ -12,7 +12,6 @@ import torch
 import mf_inputs as mi
 from oracle import train
 
-torch.set_default_dtype(torch.float64)
 
 D = 32
 
@@ -76,8 +75,8 @@ def test_adam_matches_torch_optim():
     th = torch.from_numpy(rng.standard_normal(50))
     p = torch.nn.Parameter(th.clone())
     opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
-    m = torch.zeros(50)
-    v = torch.zeros(50)
+    m = torch.zeros(50, dtype=torch.float64)
+    v = torch.zeros(50, dtype=torch.float64)
     x = th.clone()
     for step in range(1, 8):
         g = torch.from_numpy(rng.standard_normal(50))
