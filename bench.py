@@ -78,6 +78,11 @@ def main():
                     help="copy: one plain device copy of --copy-mb MiB, the reference "
                          "kernel for scaling HBM counters")
     ap.add_argument("--copy-mb", type=int, default=512)
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the 64x64-unit BF16-vs-FP32 comparison")
+    ap.add_argument("--bf16-sweeps", type=int, default=500)
+    ap.add_argument("--only-bf16", action="store_true",
+                    help="run only the 64x64-unit comparison (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
@@ -97,6 +102,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
+        return
+
+    if args.only_bf16:
+        ctx = Context(0)
+        print(json.dumps({"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)}), flush=True)
+        ctx.close()
         return
 
     w = mi.WORKLOADS["C2"]
@@ -177,10 +188,55 @@ def main():
                      "flops_per_point_eval": fpp},
         "parity": parity,
     }
+    if not args.no_bf16:
+        out["bf16_vs_fp32"] = bf16_comparison(ctx, args.bf16_sweeps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(field, params_np, width, ux, uy, args.cpu_sample_sweeps)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def bf16_comparison(ctx, sweeps):
+    """64 x 64 units (2049^2 grid, 16,129 placements), width 256, e^x sin y
+    ring data: the same solve in FP32 and with BF16 hidden GEMMs, one timed
+    run each after a short warm-up; error of BF16 against the FP32 run."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, mf_solve
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    width = w["width"]
+    field = torch.from_numpy(mi.workload_field("C4")).cuda()
+    params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
+    res = {"workload": f"C4: 64x64 units, width {width}, e^x sin y scaled, {sweeps} CROSS sweeps "
+                       "+ assembly"}
+    outs = {}
+    evals = sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+        u = field.clone()
+        u_out = torch.empty_like(u)
+        mf_solve(ctx, params, u, (ux, uy), 2, targets=MF_CROSS, prec=prec)   # warm-up + capture
+        u.copy_(field)
+        ctx.timing_read()
+        ctx.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mf_solve(ctx, params, u, (ux, uy), sweeps, targets=MF_CROSS, prec=prec, u_out=u_out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.timing(False)
+        launches, ms, rows = ctx.timing_read()
+        fpp = flops_per_point(width, CROSS_T)
+        peak = PEAK_FP32_MFMA_TFLOPS if prec == MF_FP32 else PEAK_BF16_MFMA_TFLOPS
+        ach = rows * fpp / (ms * 1e-3) / 1e12
+        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt,
+                     "phase_avg_us": ms * 1e3 / max(launches, 1),
+                     "phase_tflops": ach, "phase_frac_of_mfma_peak": ach / peak}
+        outs[name] = u_out.double()
+    d = outs["bf16"][1:-1, 1:-1] - outs["fp32"][1:-1, 1:-1]
+    res["rel_l2_bf16_vs_fp32_u_out"] = float(d.norm() / outs["fp32"][1:-1, 1:-1].norm())
+    res["speedup_bf16_over_fp32"] = res["bf16"]["point_evals_per_s"] / res["fp32"]["point_evals_per_s"]
+    return res
 
 
 if __name__ == "__main__":

@@ -99,7 +99,8 @@ typedef struct mf_domain_desc {
 } mf_domain_desc;
 
 typedef struct mf_adam {
-  float lr, beta1, beta2, eps;   /* textbook Adam (Kingma and Ba)           */
+  double lr, beta1, beta2, eps;  /* textbook Adam (Kingma and Ba); double so
+                                    that 1 - beta is formed before rounding */
 } mf_adam;
 
 typedef struct mf_ctx mf_ctx;
@@ -118,6 +119,23 @@ const char* mf_last_error(void);
  * is replayed only by later calls with the same addresses, shape, width,
  * precision and target set (at most 16 are cached per context). */
 mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
+
+/* Tile height (rows of (placement, target) pairs per workgroup) of the
+ * colour-phase kernel for one precision: 32 or 64 for MF_FP32, 64, 128 or
+ * 256 for MF_BF16; 0 restores the automatic choice (a tuned value from
+ * mf_autotune, else a rule based on the phase size and the CU count). */
+mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
+
+/* Autotuner: for this network, domain, target set and precision, time
+ * `trials` sweeps (after one warm-up sweep) of every available tile height
+ * with hipEvents on `stream` and keep the fastest in the context for later
+ * mf_sweep / mf_solve calls on the same configuration. The sweeps run on u
+ * itself (it advances by (trials + 1) x candidates sweeps); pass a scratch
+ * copy to keep the field. rows_out (host, nullable) receives the choice.
+ * Synchronises the stream. */
+mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                      const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
+                      int32_t trials, void* ws, size_t ws_bytes, void* stream, int32_t* rows_out);
 
 /* Kernel timing, a profiling aid. While enabled, every colour-phase launch
  * of mf_sweep and mf_solve (not the assembly) is bracketed by two hipEvents

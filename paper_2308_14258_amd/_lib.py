@@ -34,8 +34,8 @@ class DomainDesc(ctypes.Structure):
 
 
 class Adam(ctypes.Structure):
-    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
 _c = ctypes
@@ -48,6 +48,10 @@ _SIG = {
     "mf_param_count": (_c.c_int64, [_c.POINTER(SdnetDesc)]),
     "mf_ctx_timing": (_c.c_int32, [_P, _c.c_int32]),
     "mf_ctx_graphs": (_c.c_int32, [_P, _c.c_int32]),
+    "mf_ctx_tile_rows": (_c.c_int32, [_P, _c.c_int32, _c.c_int32]),
+    "mf_autotune": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
+                                 _c.c_int32, _c.c_int32, _c.c_int32, _P, _c.c_size_t, _P,
+                                 _c.POINTER(_c.c_int32)]),
     "mf_ctx_timing_read": (_c.c_int32, [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
                                         _c.POINTER(_c.c_int64)]),
     "mf_workspace_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,

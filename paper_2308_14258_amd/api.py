@@ -69,6 +69,10 @@ class Context:
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
+    def tile_rows(self, prec: int, rows: int) -> None:
+        """Force the colour-phase tile height for one precision (0 = automatic)."""
+        check(load().mf_ctx_tile_rows(self.ptr, prec, rows), "mf_ctx_tile_rows")
+
     def graphs(self, enable: bool) -> None:
         check(load().mf_ctx_graphs(self.ptr, 1 if enable else 0), "mf_ctx_graphs")
 
@@ -96,45 +100,113 @@ class Context:
             pass
 
 
-def _sweep_ws(ctx: Context, width: int, dom: DomainDesc, prec: int) -> torch.Tensor:
+def _sweep_ws(ctx: Context, width: int, dom, prec: int, n_domains: int = 1) -> torch.Tensor:
     n = ctypes.c_size_t()
-    check(load().mf_workspace_size(ctypes.byref(sdnet_desc(width)), ctypes.byref(dom), 1, prec,
+    check(load().mf_workspace_size(ctypes.byref(sdnet_desc(width)), _dom_arg(dom), n_domains, prec,
                                    ctypes.byref(n)), "mf_workspace_size")
     return ctx.workspace(n.value)
 
 
-def mf_sweep(ctx: Context, params: torch.Tensor, u: torch.Tensor, units, colour: int = -1,
-             targets: int = MF_CROSS, prec: int = MF_FP32, mode: int = MF_MULTIPLICATIVE):
-    """One colour phase (0..3) or one sweep (-1) of u in place."""
+def _dom_arg(dom):
+    return dom if isinstance(dom, ctypes.Array) else ctypes.byref(dom)
+
+
+class Batch:
+    """Independent domains packed into one flat float32 device buffer.
+
+    ``fields`` are [32 uy + 1, 32 ux + 1] arrays; each domain is stored
+    row-major with its own pitch (the row length) at its offset.
+    """
+
+    def __init__(self, fields, device="cuda:0"):
+        self.units = []
+        offs = []
+        off = 0
+        for f in fields:
+            ny, nx = f.shape
+            self.units.append(((nx - 1) // 32, (ny - 1) // 32))
+            offs.append(off)
+            off += ny * nx
+        self.offsets = offs
+        self.buf = torch.empty(off, dtype=torch.float32, device=device)
+        for f, o in zip(fields, offs):
+            t = torch.as_tensor(f, dtype=torch.float32)
+            self.buf[o:o + t.numel()].copy_(t.reshape(-1))
+        arr = (DomainDesc * len(fields))()
+        for i, ((ux, uy), o) in enumerate(zip(self.units, offs)):
+            arr[i] = DomainDesc(ux, uy, 32, 16, 32 * ux + 1, o)
+        self.descs = arr
+
+    def __len__(self):
+        return len(self.units)
+
+    def field(self, i, buf=None):
+        ux, uy = self.units[i]
+        ny, nx = 32 * uy + 1, 32 * ux + 1
+        b = self.buf if buf is None else buf
+        return b[self.offsets[i]:self.offsets[i] + ny * nx].view(ny, nx)
+
+
+def _field_and_domains(u, units):
+    """(device pointer owner, domain descriptor(s), count) for a single 2-D
+    field with units (ux, uy), or a Batch."""
+    if isinstance(u, Batch):
+        return u.buf, u.descs, len(u)
     _need_field(u, units)
+    return u, domain_desc(u, units), 1
+
+
+def mf_sweep(ctx: Context, params: torch.Tensor, u, units=None, colour: int = -1,
+             targets: int = MF_CROSS, prec: int = MF_FP32, mode: int = MF_MULTIPLICATIVE):
+    """One colour phase (0..3) or one sweep (-1) of u in place (u: a 2-D
+    field with units (ux, uy), or a Batch of domains)."""
     _need_cuda_f32(params, "params")
+    buf, dom, nd = _field_and_domains(u, units)
     width = width_of(params)
-    dom = domain_desc(u, units)
-    ws = _sweep_ws(ctx, width, dom, prec)
-    check(load().mf_sweep(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
-                          ctypes.byref(dom), 1, colour, targets, mode, prec, _ptr(ws), ws.numel(),
+    ws = _sweep_ws(ctx, width, dom, prec, nd)
+    check(load().mf_sweep(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+                          _dom_arg(dom), nd, colour, targets, mode, prec, _ptr(ws), ws.numel(),
                           _stream()), "mf_sweep")
 
 
-def mf_solve(ctx: Context, params: torch.Tensor, u: torch.Tensor, units, max_sweeps: int,
-             eps: float = 0.0, check_every: int = 1, targets: int = MF_CROSS,
-             prec: int = MF_FP32, u_out: torch.Tensor | None = None, flags: int = 0,
-             mode: int = MF_MULTIPLICATIVE, report: bool = False):
-    """Alg. 2 on one GPU; u is updated in place, u_out receives the assembly.
-    Returns (sweeps_done, last_delta) when report is True (synchronises)."""
+def mf_autotune(ctx: Context, params: torch.Tensor, u: torch.Tensor, units,
+                targets: int = MF_CROSS, prec: int = MF_FP32, trials: int = 3) -> int:
+    """Time every tile height on u (which advances) and keep the fastest."""
     _need_field(u, units)
     _need_cuda_f32(params, "params")
-    if u_out is not None:
-        _need_field(u_out, units)
-        if u_out.stride(0) != u.stride(0):
-            raise ValueError("u_out must have the same pitch as u")
     width = width_of(params)
     dom = domain_desc(u, units)
     ws = _sweep_ws(ctx, width, dom, prec)
+    rows = ctypes.c_int32(0)
+    check(load().mf_autotune(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
+                             ctypes.byref(dom), 1, targets, prec, trials, _ptr(ws), ws.numel(),
+                             _stream(), ctypes.byref(rows)), "mf_autotune")
+    return rows.value
+
+
+def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
+             eps: float = 0.0, check_every: int = 1, targets: int = MF_CROSS,
+             prec: int = MF_FP32, u_out=None, flags: int = 0,
+             mode: int = MF_MULTIPLICATIVE, report: bool = False):
+    """Alg. 2 on one GPU; u is updated in place, u_out receives the assembly.
+    u is a 2-D field with units (ux, uy), or a Batch (then units is ignored
+    and u_out, if given, is a flat buffer laid out like u.buf).
+    Returns (sweeps_done, last_delta) when report is True (synchronises)."""
+    _need_cuda_f32(params, "params")
+    buf, dom, nd = _field_and_domains(u, units)
+    if u_out is not None:
+        if nd == 1:
+            _need_field(u_out, units)
+            if u_out.stride(0) != u.stride(0):
+                raise ValueError("u_out must have the same pitch as u")
+        elif u_out.numel() != buf.numel():
+            raise ValueError("u_out must match the batch buffer")
+    width = width_of(params)
+    ws = _sweep_ws(ctx, width, dom, prec, nd)
     done = ctypes.c_int32(-1)
     last = ctypes.c_float(float("nan"))
-    check(load().mf_solve(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
-                          ctypes.byref(dom), 1, targets, mode, prec, max_sweeps, eps, check_every,
+    check(load().mf_solve(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+                          _dom_arg(dom), nd, targets, mode, prec, max_sweeps, eps, check_every,
                           flags, _ptr(u_out), ctypes.byref(done) if report else None,
                           ctypes.byref(last) if report else None, _ptr(ws), ws.numel(),
                           _stream()), "mf_solve")
@@ -208,5 +280,5 @@ def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: tor
     return loss
 
 
-__all__ = ["Context", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
+__all__ = ["Batch", "Context", "mf_autotune", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
            "sdnet_train_step", "width_of", "sdnet_desc", "domain_desc", "_lib"]

@@ -6,7 +6,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "mf_internal.h"
@@ -58,13 +60,17 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws) {
   return p;
 }
 
-SweepLayout sweep_layout(int width, int prec, int ux, int uy) {
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains) {
   SweepLayout S;
   S.net = net_layout(width, prec, 0);
   size_t o = S.net.end;
-  S.skel = o; o = align256(o + (size_t)skeleton_count(ux, uy) * 4);
-  S.part = o; o = align256(o + 2 * (size_t)kDeltaBlocks * 4);
-  S.dres = o; o = align256(o + 2 * 4);
+  int64_t n_skel = 0;
+  for (int d = 0; d < n_domains; ++d) n_skel += skeleton_count(dom[d].units_x, dom[d].units_y);
+  S.skel = o; o = align256(o + (size_t)n_skel * 4);
+  S.part = o; o = align256(o + 2 * (size_t)kDeltaBlocks * n_domains * 4);
+  S.dres = o; o = align256(o + 2 * (size_t)n_domains * 4);
+  S.table = o;
+  o = align256(o + (size_t)n_domains * sizeof(DomEntry) + 2 * 4 * ((size_t)n_domains + 1) * 4);
   S.total = o;
   return S;
 }
@@ -110,6 +116,18 @@ TrainBuffers train_buffers(const TrainLayout& L, void* ws) {
   return t;
 }
 
+#define MF_TRY(expr)                 \
+  do {                               \
+    mf_status _s = (expr);           \
+    if (_s != MF_OK) return _s;      \
+  } while (0)
+
+#define MF_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) return fail(MF_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 // validation helpers
 // ---------------------------------------------------------------------------
@@ -126,25 +144,46 @@ static mf_status check_desc(const mf_sdnet_desc* d) {
   return MF_OK;
 }
 
+static bool valid_tile_rows(int prec, int rows) {
+  return prec == MF_FP32 ? (rows == 32 || rows == 64) : (rows == 64 || rows == 128 || rows == 256);
+}
+
 static mf_status check_prec(int prec) {
   if (prec != MF_FP32 && prec != MF_BF16) return fail(MF_EINVAL, "precision %d unknown", prec);
   return MF_OK;
 }
 
+static mf_status check_one_domain(const mf_domain_desc* dom, int d) {
+  if (dom->units_x < 1 || dom->units_y < 1)
+    return fail(MF_ESHAPE, "domain %d: units %d x %d: each must be >= 1", d, dom->units_x, dom->units_y);
+  if (dom->units_x > 4096 || dom->units_y > 4096)
+    return fail(MF_ESHAPE, "domain %d: units %d x %d exceed 4096", d, dom->units_x, dom->units_y);
+  if (dom->cells_per_unit != 32) return fail(MF_ESHAPE, "domain %d: cells_per_unit must be 32", d);
+  if (dom->stride != 16) return fail(MF_ESHAPE, "domain %d: placement stride must be 16 cells", d);
+  const int64_t nx = 32LL * dom->units_x + 1, ny = 32LL * dom->units_y + 1;
+  if (dom->pitch < nx)
+    return fail(MF_ESHAPE, "domain %d: pitch %lld < row length %lld", d, (long long)dom->pitch, (long long)nx);
+  if (dom->field_offset < 0) return fail(MF_ESHAPE, "domain %d: field_offset must be >= 0", d);
+  if ((ny - 1) * dom->pitch + nx > (1LL << 40)) return fail(MF_ESHAPE, "domain %d: field too large", d);
+  return MF_OK;
+}
+
+// One domain, or a batch of 2..4096 independent domains in one packed
+// buffer whose element ranges must not overlap (their phases run
+// concurrently).
 static mf_status check_domain(const mf_domain_desc* dom, int n_domains) {
   if (!dom) return fail(MF_EINVAL, "domain descriptor is NULL");
-  if (n_domains != 1)
-    return fail(MF_EUNSUPPORTED, "n_domains = %d: only single-domain sweeps are implemented", n_domains);
-  if (dom->units_x < 1 || dom->units_y < 1)
-    return fail(MF_ESHAPE, "domain units %d x %d: each must be >= 1", dom->units_x, dom->units_y);
-  if (dom->units_x > 4096 || dom->units_y > 4096)
-    return fail(MF_ESHAPE, "domain units %d x %d exceed 4096", dom->units_x, dom->units_y);
-  if (dom->cells_per_unit != 32) return fail(MF_ESHAPE, "cells_per_unit must be 32");
-  if (dom->stride != 16) return fail(MF_ESHAPE, "placement stride must be 16 cells");
-  const int64_t nx = 32LL * dom->units_x + 1, ny = 32LL * dom->units_y + 1;
-  if (dom->pitch < nx) return fail(MF_ESHAPE, "pitch %lld < row length %lld", (long long)dom->pitch, (long long)nx);
-  if (dom->field_offset < 0) return fail(MF_ESHAPE, "field_offset must be >= 0");
-  if ((ny - 1) * dom->pitch + nx > (1LL << 40)) return fail(MF_ESHAPE, "field too large");
+  if (n_domains < 1 || n_domains > 4096)
+    return fail(MF_ESHAPE, "n_domains = %d not in 1..4096", n_domains);
+  std::vector<std::pair<int64_t, int64_t>> ext;
+  for (int d = 0; d < n_domains; ++d) {
+    MF_TRY(check_one_domain(&dom[d], d));
+    const int64_t nx = 32LL * dom[d].units_x + 1, ny = 32LL * dom[d].units_y + 1;
+    ext.emplace_back(dom[d].field_offset, dom[d].field_offset + (ny - 1) * dom[d].pitch + nx);
+  }
+  std::sort(ext.begin(), ext.end());
+  for (size_t i = 1; i < ext.size(); ++i)
+    if (ext[i].first < ext[i - 1].second) return fail(MF_EINVAL, "domains overlap in the field buffer");
   return MF_OK;
 }
 
@@ -162,18 +201,6 @@ static mf_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
   return MF_OK;
 }
 
-#define MF_TRY(expr)                 \
-  do {                               \
-    mf_status _s = (expr);           \
-    if (_s != MF_OK) return _s;      \
-  } while (0)
-
-#define MF_HIP(expr)                                                                   \
-  do {                                                                                 \
-    hipError_t _e = (expr);                                                            \
-    if (_e != hipSuccess) return fail(MF_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
-  } while (0)
-
 }  // namespace mf
 
 using namespace mf;
@@ -185,12 +212,20 @@ struct SweepGraph {
   const void* ws;
   int64_t pitch;
   int ux, uy, width, prec, targets, sweeps;
+  uint64_t key;
   hipGraphExec_t exec;
+};
+
+// Tile height chosen by mf_autotune for one phase configuration.
+struct TuneEntry {
+  int width, prec, targets, ux, uy, rows;
 };
 
 struct mf_ctx {
   int device;
   int n_cu;
+  int force_rows[2] = {0, 0};         // per precision; 0 = automatic
+  std::vector<TuneEntry> tuned;
   hipStream_t gstream = nullptr;     // graph launches (default priority)
   hipEvent_t fork = nullptr, join = nullptr;
   std::vector<SweepGraph> graphs;
@@ -249,6 +284,17 @@ void mf_ctx_destroy(mf_ctx* ctx) {
   delete ctx;
 }
 
+mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows) {
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_TRY(check_prec(prec));
+  if (rows != 0 && !valid_tile_rows(prec, rows))
+    return fail(MF_EINVAL, "tile rows %d not available for precision %d", rows, prec);
+  ctx->force_rows[prec] = rows;
+  for (SweepGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);   // captured shapes change
+  ctx->graphs.clear();
+  return ok();
+}
+
 mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   ctx->use_graphs = enable != 0;
@@ -287,14 +333,14 @@ mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom
   MF_TRY(check_desc(desc));
   MF_TRY(check_prec(prec));
   MF_TRY(check_domain(dom, n_domains));
-  *bytes = sweep_layout(desc->width, prec, dom->units_x, dom->units_y).total;
+  *bytes = sweep_layout(desc->width, prec, dom, n_domains).total;
   return ok();
 }
 
-static mf_status sweep_common_checks(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
-                                     float* u, const mf_domain_desc* dom, int32_t n_domains,
-                                     int32_t targets, int32_t mode, int32_t prec, void* ws,
-                                     size_t ws_bytes, SweepLayout* L) {
+static mf_status sweep_common_checks(const mf_sdnet_desc* desc, const float* params, float* u,
+                                     const mf_domain_desc* dom, int32_t n_domains, int32_t targets,
+                                     int32_t mode, int32_t prec, void* ws, size_t ws_bytes,
+                                     SweepLayout* L) {
   MF_TRY(check_desc(desc));
   MF_TRY(check_prec(prec));
   MF_TRY(check_domain(dom, n_domains));
@@ -303,9 +349,8 @@ static mf_status sweep_common_checks(mf_ctx* ctx, const mf_sdnet_desc* desc, con
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
   if (mode == MF_ADDITIVE) return fail(MF_EUNSUPPORTED, "additive sweeps are not implemented");
-  *L = sweep_layout(desc->width, prec, dom->units_x, dom->units_y);
+  *L = sweep_layout(desc->width, prec, dom, n_domains);
   MF_TRY(check_ws(ws, ws_bytes, L->total));
-  (void)ctx;
   return MF_OK;
 }
 
@@ -336,28 +381,114 @@ static int64_t phase_rows(const mf_domain_desc* dom, int colour, int targets) {
   return n_place * (targets == MF_INTERIOR ? 961 : 61);
 }
 
-static mf_status run_phase(mf_ctx* ctx, const NetPtrs& net, int width, int prec, int targets,
-                           bool accumulate, const float* u_in, float* u_out,
-                           const mf_domain_desc* dom, int colour, hipStream_t s,
-                           bool allow_timing = true) {
-  PhaseArgs p{u_in, u_out, dom->pitch, dom->units_x, dom->units_y, colour};
-  const int64_t n_place = (int64_t)(dom->units_x - (colour & 1)) * (dom->units_y - (colour >> 1));
-  const int64_t rows = n_place * ((accumulate || targets == MF_INTERIOR) ? 961 : 61);
-  const int R = pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
-  const bool timed = allow_timing && ctx->timing && !accumulate && rows > 0;
+// Everything a colour phase needs: one domain, or a batch whose domain table
+// and per-colour tile prefixes were uploaded into the workspace.
+struct Plan {
+  int nd = 1;
+  const mf_domain_desc* dom = nullptr;   // host descriptors
+  float* u = nullptr;                    // caller's buffer (offsets are relative to it)
+  int width = 0, prec = 0, targets = 0;
+  NetPtrs net{};
+  const void* ws = nullptr;
+  const DomEntry* d_doms = nullptr;
+  const int32_t* d_tb[2] = {nullptr, nullptr};   // [4][nd + 1]: sweep targets, assembly
+  int R[2] = {0, 0};                              // tile rows (batched)
+  int64_t n_tiles[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  int64_t rows[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  uint64_t key = 0;                               // identifies the domain list
+};
+
+static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, const mf_domain_desc* dom,
+                         int nd, int64_t rows) {
+  if (ctx->force_rows[prec]) return ctx->force_rows[prec];
+  if (nd == 1)
+    for (const TuneEntry& t : ctx->tuned)
+      if (t.width == width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
+          t.uy == dom->units_y)
+        return t.rows;
+  return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
+}
+
+static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int targets, float* u,
+                           const mf_domain_desc* dom, int nd, void* ws, const SweepLayout& L,
+                           hipStream_t s, Plan* P) {
+  P->nd = nd;
+  P->dom = dom;
+  P->u = u;
+  P->width = desc->width;
+  P->prec = prec;
+  P->targets = targets;
+  P->net = net_ptrs(L.net, ws);
+  P->ws = ws;
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 4; ++c)
+      for (int d = 0; d < nd; ++d) P->rows[a][c] += phase_rows(&dom[d], c, a ? MF_INTERIOR : targets);
+  uint64_t h = 1469598103934665603ull;                  // FNV-1a over the descriptors
+  const unsigned char* bytes = reinterpret_cast<const unsigned char*>(dom);
+  for (size_t i = 0; i < (size_t)nd * sizeof(mf_domain_desc); ++i) h = (h ^ bytes[i]) * 1099511628211ull;
+  P->key = h;
+  if (nd == 1) return MF_OK;
+  std::vector<char> host((size_t)nd * sizeof(DomEntry) + 2 * 4 * ((size_t)nd + 1) * 4);
+  DomEntry* he = reinterpret_cast<DomEntry*>(host.data());
+  int32_t* htb = reinterpret_cast<int32_t*>(host.data() + (size_t)nd * sizeof(DomEntry));
+  for (int d = 0; d < nd; ++d)
+    he[d] = DomEntry{dom[d].field_offset, dom[d].pitch, dom[d].units_x, dom[d].units_y};
+  for (int a = 0; a < 2; ++a) {
+    const int tg = a ? MF_INTERIOR : targets;
+    P->R[a] = tile_rows_for(ctx, desc->width, prec, tg, dom, nd, P->rows[a][0]);
+    for (int c = 0; c < 4; ++c) {
+      int32_t* tb = htb + (a * 4 + c) * (nd + 1);
+      int64_t acc = 0;
+      for (int d = 0; d < nd; ++d) {
+        tb[d] = (int32_t)acc;
+        acc += (phase_rows(&dom[d], c, tg) + P->R[a] - 1) / P->R[a];
+      }
+      if (acc > INT32_MAX) return fail(MF_ESHAPE, "batch has too many tiles");
+      tb[nd] = (int32_t)acc;
+      P->n_tiles[a][c] = acc;
+    }
+  }
+  char* dst = static_cast<char*>(ws) + L.table;
+  MF_HIP(hipMemcpyAsync(dst, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  P->d_doms = reinterpret_cast<const DomEntry*>(dst);
+  P->d_tb[0] = reinterpret_cast<const int32_t*>(dst + (size_t)nd * sizeof(DomEntry));
+  P->d_tb[1] = P->d_tb[0] + 4 * (nd + 1);
+  return MF_OK;
+}
+
+// One colour phase of the plan: sweep (into u) or assembly accumulation
+// (into out). Timed when the context's timing is on and allow_timing is set.
+static mf_status run_colour(mf_ctx* ctx, const Plan& P, int colour, bool accumulate, float* out,
+                            hipStream_t s, bool allow_timing = true) {
+  const int a = accumulate ? 1 : 0;
+  const int64_t rows = P.rows[a][colour];
+  if (rows == 0) return MF_OK;
+  const bool timed = allow_timing && ctx->timing && !accumulate;
   if (timed) MF_TRY(timing_begin(ctx, s));
-  MF_HIP(launch_phase(net, width, prec, targets, accumulate, R, p, s));
+  float* dst = accumulate ? out : P.u;
+  if (P.nd == 1) {
+    const mf_domain_desc* dom = P.dom;
+    PhaseArgs p{P.u + dom->field_offset, dst + dom->field_offset, dom->pitch, dom->units_x,
+                dom->units_y, colour};
+    const int R = tile_rows_for(ctx, P.width, P.prec, accumulate ? MF_INTERIOR : P.targets, dom, 1, rows);
+    MF_HIP(launch_phase(P.net, P.width, P.prec, P.targets, accumulate, R, p, s));
+  } else {
+    MF_HIP(launch_phase_multi(P.net, P.width, P.prec, P.targets, accumulate, P.R[a], P.u, dst, P.d_doms,
+                              P.d_tb[a] + colour * (P.nd + 1), P.nd, P.n_tiles[a][colour], colour,
+                              ctx->n_cu, s));
+  }
   if (timed) MF_TRY(timing_end(ctx, s, rows, 1));
   return MF_OK;
 }
 
 // Cached graph of `sweeps` sweeps on ctx->gstream; captured on first use.
-static mf_status sweep_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_desc* desc, int prec,
-                             int targets, float* field, const mf_domain_desc* dom, const void* ws,
-                             int sweeps, hipGraphExec_t* out) {
+static mf_status sweep_graph(mf_ctx* ctx, const Plan& P, int sweeps, hipGraphExec_t* out) {
+  const int64_t pitch = P.nd == 1 ? P.dom->pitch : 0;
+  const int ux = P.nd == 1 ? P.dom->units_x : -P.nd;
+  const int uy = P.nd == 1 ? P.dom->units_y : (int)(P.key & 0x7fffffff);
   for (const SweepGraph& g : ctx->graphs) {
-    if (g.field == field && g.ws == ws && g.pitch == dom->pitch && g.ux == dom->units_x &&
-        g.uy == dom->units_y && g.width == desc->width && g.prec == prec && g.targets == targets &&
+    if (g.field == P.u && g.ws == P.ws && g.pitch == pitch && g.ux == ux && g.uy == uy &&
+        g.key == P.key && g.width == P.width && g.prec == P.prec && g.targets == P.targets &&
         g.sweeps == sweeps) {
       *out = g.exec;
       return MF_OK;
@@ -371,9 +502,7 @@ static mf_status sweep_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_des
   MF_HIP(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
   mf_status st = MF_OK;
   for (int k = 0; k < sweeps && st == MF_OK; ++k)
-    for (int c = 0; c < 4 && st == MF_OK; ++c)
-      st = run_phase(ctx, net, desc->width, prec, targets, false, field, field, dom, c, ctx->gstream,
-                     false);
+    for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, ctx->gstream, false);
   hipError_t e = hipStreamEndCapture(ctx->gstream, &graph);
   if (st != MF_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -384,8 +513,7 @@ static mf_status sweep_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_des
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(MF_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-  ctx->graphs.push_back(SweepGraph{field, ws, dom->pitch, dom->units_x, dom->units_y, desc->width, prec,
-                                   targets, sweeps, exec});
+  ctx->graphs.push_back(SweepGraph{P.u, P.ws, pitch, ux, uy, P.width, P.prec, P.targets, sweeps, P.key, exec});
   *out = exec;
   return MF_OK;
 }
@@ -394,15 +522,17 @@ static mf_status sweep_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_des
 // to kGraphSweeps sweeps on the context's stream, ordered after and before
 // the caller's stream by events.
 static constexpr int kGraphSweeps = 16;
-static mf_status run_sweeps_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdnet_desc* desc, int prec,
-                                  int targets, float* field, const mf_domain_desc* dom, const void* ws,
-                                  int max_sweeps, hipStream_t s) {
+static mf_status run_sweeps_graph(mf_ctx* ctx, const Plan& P, int max_sweeps, hipStream_t s) {
   const int full = max_sweeps / kGraphSweeps, rem = max_sweeps % kGraphSweeps;
   hipGraphExec_t g_full = nullptr, g_rem = nullptr;
-  if (full > 0) MF_TRY(sweep_graph(ctx, net, desc, prec, targets, field, dom, ws, kGraphSweeps, &g_full));
-  if (rem > 0) MF_TRY(sweep_graph(ctx, net, desc, prec, targets, field, dom, ws, rem, &g_rem));
+  if (full > 0) MF_TRY(sweep_graph(ctx, P, kGraphSweeps, &g_full));
+  if (rem > 0) MF_TRY(sweep_graph(ctx, P, rem, &g_rem));
   int64_t rows_sweep = 0;
-  for (int c = 0; c < 4; ++c) rows_sweep += phase_rows(dom, c, targets);
+  int launches_sweep = 0;
+  for (int c = 0; c < 4; ++c) {
+    rows_sweep += P.rows[0][c];
+    launches_sweep += P.rows[0][c] > 0 ? 1 : 0;
+  }
   MF_HIP(hipEventRecord(ctx->fork, s));
   MF_HIP(hipStreamWaitEvent(ctx->gstream, ctx->fork, 0));
   for (int i = 0; i < full + (rem > 0 ? 1 : 0); ++i) {
@@ -410,7 +540,7 @@ static mf_status run_sweeps_graph(mf_ctx* ctx, const NetPtrs& net, const mf_sdne
     const int n = last_rem ? rem : kGraphSweeps;
     if (ctx->timing) MF_TRY(timing_begin(ctx, ctx->gstream));
     MF_HIP(hipGraphLaunch(last_rem ? g_rem : g_full, ctx->gstream));
-    if (ctx->timing) MF_TRY(timing_end(ctx, ctx->gstream, rows_sweep * n, 4 * (int64_t)n));
+    if (ctx->timing) MF_TRY(timing_end(ctx, ctx->gstream, rows_sweep * n, (int64_t)launches_sweep * n));
   }
   MF_HIP(hipEventRecord(ctx->join, ctx->gstream));
   MF_HIP(hipStreamWaitEvent(s, ctx->join, 0));
@@ -421,17 +551,119 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
                    const mf_domain_desc* dom, int32_t n_domains, int32_t colour, int32_t targets,
                    int32_t mode, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
   SweepLayout L;
-  MF_TRY(sweep_common_checks(ctx, desc, params, u, dom, n_domains, targets, mode, prec, ws, ws_bytes, &L));
+  MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, mode, prec, ws, ws_bytes, &L));
   if (colour < -1 || colour > 3) return fail(MF_EINVAL, "colour %d not in -1..3", colour);
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  float* field = u + dom->field_offset;
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
-  const NetPtrs net = net_ptrs(L.net, ws);
+  Plan P;
+  MF_TRY(make_plan(ctx, desc, prec, targets, u, dom, n_domains, ws, L, s, &P));
   for (int c = (colour < 0 ? 0 : colour); c <= (colour < 0 ? 3 : colour); ++c)
-    MF_TRY(run_phase(ctx, net, desc->width, prec, targets, false, field, field, dom, c, s));
+    MF_TRY(run_colour(ctx, P, c, false, nullptr, s));
   return ok();
+}
+
+mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                      const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
+                      int32_t trials, void* ws, size_t ws_bytes, void* stream, int32_t* rows_out) {
+  SweepLayout L;
+  MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, MF_MULTIPLICATIVE, prec, ws,
+                             ws_bytes, &L));
+  if (n_domains != 1) return fail(MF_EUNSUPPORTED, "autotune takes one domain");
+  if (trials < 1 || trials > 1000) return fail(MF_EINVAL, "trials %d not in 1..1000", trials);
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
+  const int cands_fp32[] = {32, 64};
+  const int cands_bf16[] = {64, 128, 256};
+  const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
+  const int n_cands = prec == MF_FP32 ? 2 : 3;
+  const int saved_force = ctx->force_rows[prec];
+  const bool saved_timing = ctx->timing;
+  ctx->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MF_HIP(hipEventCreate(&e0));
+  MF_HIP(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.0f;
+  mf_status st = MF_OK;
+  for (int ci = 0; ci < n_cands && st == MF_OK; ++ci) {
+    ctx->force_rows[prec] = cands[ci];
+    Plan P;
+    st = make_plan(ctx, desc, prec, targets, u, dom, 1, ws, L, s, &P);
+    for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, s);   // warm-up
+    if (st != MF_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MF_EDEVICE, "event record failed"); break; }
+    for (int k = 0; k < trials && st == MF_OK; ++k)
+      for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, s);
+    if (st != MF_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(MF_EDEVICE, "event timing failed");
+      break;
+    }
+    if (best == 0 || ms < best_ms) {
+      best = cands[ci];
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->force_rows[prec] = saved_force;
+  ctx->timing = saved_timing;
+  if (st != MF_OK) return st;
+  bool found = false;
+  for (TuneEntry& t : ctx->tuned)
+    if (t.width == desc->width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
+        t.uy == dom->units_y) {
+      t.rows = best;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back(TuneEntry{desc->width, prec, targets, dom->units_x, dom->units_y, best});
+  for (SweepGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+  if (rows_out) *rows_out = best;
+  return ok();
+}
+
+// delta over all domains' skeletons: per-domain partial sums, summed on the host.
+static mf_status delta_snapshot(const Plan& P, const SweepLayout& L, void* ws, hipStream_t s) {
+  char* wsb = static_cast<char*>(ws);
+  float* skel = reinterpret_cast<float*>(wsb + L.skel);
+  for (int d = 0; d < P.nd; ++d) {
+    const mf_domain_desc& D = P.dom[d];
+    MF_HIP(launch_skeleton_snapshot(P.u + D.field_offset, D.pitch, D.units_x, D.units_y, skel, s));
+    skel += skeleton_count(D.units_x, D.units_y);
+  }
+  return MF_OK;
+}
+
+static mf_status delta_eval(const Plan& P, const SweepLayout& L, void* ws, hipStream_t s, float* num,
+                            float* den) {
+  char* wsb = static_cast<char*>(ws);
+  const float* skel = reinterpret_cast<const float*>(wsb + L.skel);
+  float* part = reinterpret_cast<float*>(wsb + L.part);
+  float* dres = reinterpret_cast<float*>(wsb + L.dres);
+  for (int d = 0; d < P.nd; ++d) {
+    const mf_domain_desc& D = P.dom[d];
+    MF_HIP(launch_delta(P.u + D.field_offset, D.pitch, D.units_x, D.units_y, skel,
+                        part + (size_t)2 * kDeltaBlocks * d, dres + 2 * d, s));
+    skel += skeleton_count(D.units_x, D.units_y);
+  }
+  std::vector<float> h(2 * (size_t)P.nd);
+  MF_HIP(hipMemcpyAsync(h.data(), dres, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  MF_HIP(hipStreamSynchronize(s));
+  double sn = 0.0, sd = 0.0;
+  for (int d = 0; d < P.nd; ++d) {
+    sn += h[2 * d];
+    sd += h[2 * d + 1];
+  }
+  *num = (float)sn;
+  *den = (float)sd;
+  return MF_OK;
 }
 
 mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
@@ -440,7 +672,7 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
                    float* u_out, int32_t* sweeps_done, float* last_delta, void* ws, size_t ws_bytes,
                    void* stream) {
   SweepLayout L;
-  MF_TRY(sweep_common_checks(ctx, desc, params, u, dom, n_domains, targets, mode, prec, ws, ws_bytes, &L));
+  MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, mode, prec, ws, ws_bytes, &L));
   if (max_sweeps < 0) return fail(MF_EINVAL, "max_sweeps %d < 0", max_sweeps);
   if (!(eps >= 0.0f) || isinf(eps)) return fail(MF_EINVAL, "eps must be finite and >= 0");
   if (eps > 0.0f && check_every < 1) return fail(MF_EINVAL, "check_every %d < 1", check_every);
@@ -452,38 +684,30 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  float* field = u + dom->field_offset;
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
-  const NetPtrs net = net_ptrs(L.net, ws);
-  char* wsb = static_cast<char*>(ws);
-  float* skel = reinterpret_cast<float*>(wsb + L.skel);
-  float* part = reinterpret_cast<float*>(wsb + L.part);
-  float* dres = reinterpret_cast<float*>(wsb + L.dres);
+  Plan P;
+  MF_TRY(make_plan(ctx, desc, prec, targets, u, dom, n_domains, ws, L, s, &P));
 
   int done = 0;
   float last = NAN;
   bool converged = false;
   if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0) {
-    MF_TRY(run_sweeps_graph(ctx, net, desc, prec, targets, field, dom, ws, max_sweeps, s));
+    MF_TRY(run_sweeps_graph(ctx, P, max_sweeps, s));
     done = max_sweeps;
   }
   for (int k = done + 1; k <= max_sweeps; ++k) {
     const bool check = eps > 0.0f && (k % check_every) == 0;
-    if (check) MF_HIP(launch_skeleton_snapshot(field, dom->pitch, dom->units_x, dom->units_y, skel, s));
-    for (int c = 0; c < 4; ++c)
-      MF_TRY(run_phase(ctx, net, desc->width, prec, targets, false, field, field, dom, c, s));
+    if (check) MF_TRY(delta_snapshot(P, L, ws, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, false, nullptr, s));
     done = k;
     if (check) {
-      MF_HIP(launch_delta(field, dom->pitch, dom->units_x, dom->units_y, skel, part, dres, s));
-      float h[2];
-      MF_HIP(hipMemcpyAsync(h, dres, sizeof(h), hipMemcpyDeviceToHost, s));
-      MF_HIP(hipStreamSynchronize(s));
-      if (h[1] == 0.0f) {
+      float num = 0.0f, den = 0.0f;
+      MF_TRY(delta_eval(P, L, ws, s, &num, &den));
+      if (den == 0.0f) {
         last = INFINITY;
       } else {
-        last = sqrtf(h[0]) / sqrtf(h[1]);
-        if (!isfinite(last))
-          return fail(MF_ENONFINITE, "delta is not finite after sweep %d", k);
+        last = sqrtf(num) / sqrtf(den);
+        if (!isfinite(last)) return fail(MF_ENONFINITE, "delta is not finite after sweep %d", k);
       }
       if (last < eps) {
         converged = true;
@@ -492,10 +716,10 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
     }
   }
   if (u_out) {
-    float* out = u_out + dom->field_offset;
-    MF_HIP(launch_assembly_init(field, out, dom->pitch, dom->units_x, dom->units_y, s));
-    for (int c = 0; c < 4; ++c)
-      MF_TRY(run_phase(ctx, net, desc->width, prec, MF_INTERIOR, true, field, out, dom, c, s));
+    for (int d = 0; d < n_domains; ++d)
+      MF_HIP(launch_assembly_init(u + dom[d].field_offset, u_out + dom[d].field_offset, dom[d].pitch,
+                                  dom[d].units_x, dom[d].units_y, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, true, u_out, s));
   }
   if (sweeps_done || last_delta) MF_HIP(hipStreamSynchronize(s));
   if (sweeps_done) *sweeps_done = done;
@@ -640,8 +864,8 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
     MF_TRY(check_ptr(v, "v"));
     if (!hp) return fail(MF_EINVAL, "adam hyperparameters are NULL");
     if (step < 1) return fail(MF_EINVAL, "step %lld < 1 (Adam counts from 1)", (long long)step);
-    if (!(hp->lr > 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) ||
-        !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->eps > 0.0f))
+    if (!(hp->lr > 0.0) || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) ||
+        !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) || !(hp->eps > 0.0))
       return fail(MF_EINVAL, "adam hyperparameters out of range");
   }
   const TrainLayout L = train_layout(desc->width, B, nc);
@@ -656,12 +880,9 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
   const TrainBuffers tb = train_buffers(L, ws);
   float* grad = grad_out ? grad_out : tb.grad;
   MF_HIP(launch_train_grad(net, desc->width, whT, tb, G, B, Xb, Xc, nc, grad, loss_dev, s));
-  if (!grad_out) {
-    const double bc1 = 1.0 - pow((double)hp->beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)hp->beta2, (double)step);
+  if (!grad_out)
     MF_HIP(launch_adam(params, m, v, grad, mf_param_count(desc), hp->lr, hp->beta1, hp->beta2, hp->eps,
-                       (float)bc1, (float)bc2, s));
-  }
+                       step, s));
   return ok();
 }
 

@@ -43,14 +43,14 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws);
 // Sweep workspace: prepared network, skeleton snapshot, delta partials.
 struct SweepLayout {
   NetLayout net;
-  size_t skel = 0;     // float [n_skel]
-  size_t part = 0;     // float [2][kDeltaBlocks]
-  size_t dres = 0;     // float [2]
+  size_t skel = 0;     // float [sum of n_skel over domains]
+  size_t part = 0;     // float [n_domains][2][kDeltaBlocks]
+  size_t dres = 0;     // float [n_domains][2]
+  size_t table = 0;    // batched domains: DomEntry [n] + int32 tile prefixes [2][4][n + 1]
   size_t total = 0;
 };
 constexpr int kDeltaBlocks = 512;
 int64_t skeleton_count(int ux, int uy);
-SweepLayout sweep_layout(int width, int prec, int ux, int uy);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_prepare_net(const float* params, int width, int prec, const NetLayout& L,
@@ -76,6 +76,18 @@ hipError_t launch_delta(const float* u, int64_t pitch, int ux, int uy, const flo
                         float* part, float* dres, hipStream_t s);
 hipError_t launch_operator_phase(const float* Hop, int targets, bool accumulate,
                                  const PhaseArgs& a, hipStream_t s);
+
+// One domain of a batch, as the batched colour-phase kernel reads it.
+struct DomEntry {
+  int64_t offset;   // first element of the domain in the packed field
+  int64_t pitch;    // row pitch in floats
+  int32_t ux, uy;   // units
+};
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains);
+hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
+                              int tile_rows, const float* field_in, float* field_out,
+                              const DomEntry* doms, const int32_t* tile_begin, int n_domains,
+                              int64_t n_tiles, int colour, int n_cu, hipStream_t s);
 
 // sdnet_forward pieces.
 hipError_t launch_projection(const NetPtrs& net, int width, const float* G, int64_t n_bc,
@@ -108,8 +120,8 @@ hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStre
 hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
                              const float* G, int64_t B, const float* Xb, const float* Xc, int64_t nc,
                              float* grad, float* loss, hipStream_t s);
-hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
-                       float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
+                       double b2, double eps, int64_t step, hipStream_t s);
 hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s);

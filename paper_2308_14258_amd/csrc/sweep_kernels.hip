@@ -128,8 +128,55 @@ __device__ __forceinline__ float h_load(const typename HType<PREC>::T* p) {
   if constexpr (PREC == 0) return *p; else return bf16_to_f32(*p);
 }
 
+// Three hidden layers with bf16 operands and float32 accumulation. Each wave
+// owns 32 output columns and keeps its slice of the layer's weights in
+// registers (D/16 bf16x8 operands); it walks the tile's 32-row blocks with
+// one barrier per block, so the tanh epilogue of block rb-1 (written back
+// in place: every wave has finished reading those rows once it passed the
+// previous barrier) overlaps the MFMAs of block rb.
+template <int D, int R>
+__device__ __forceinline__ void hidden_layers_bf16(uint16_t* Hs, const u32x4* wh, const float* bh,
+                                                   int lane, int wave) {
+  constexpr int RB = R / 32, KG = D / 16, LDH = D + 8;
+  const int arow = lane & 31, ahalf = lane >> 5;
+  const int j = wave * 32 + arow;
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    bf16x8 breg[KG];
+    const u32x4* wsw = wh + (size_t)l * (D * D / 8) + (size_t)wave * KG * 64 + lane;
+#pragma unroll
+    for (int kg = 0; kg < KG; ++kg) breg[kg] = __builtin_bit_cast(bf16x8, wsw[kg * 64]);
+    const float bj = bh[l * D + j];
+    floatx16 prev;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) prev[v] = 0.0f;
+#pragma unroll 1
+    for (int rb = 0; rb <= RB; ++rb) {
+      floatx16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      if (rb < RB) {
+        const uint16_t* ap = Hs + (rb * 32 + arow) * LDH + 8 * ahalf;
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg)
+          acc = mfma32x32x16_bf16(
+              __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + kg * 16)), breg[kg], acc);
+      }
+      if (rb > 0) {
+        uint16_t* op = Hs + ((rb - 1) * 32) * LDH + j;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          op[acc_row(lane, v) * LDH] = f32_to_bf16_rne(tanh_fast(prev[v] + bj));
+      }
+      prev = acc;
+      __syncthreads();
+    }
+  }
+}
+
+// One tile: rows [row0, row0 + R) of the phase described by A.
 template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
-__global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
+__device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0) {
   constexpr int NTH = 2 * D;                 // one wave per 32 output columns
   constexpr int RB = R / 32;                 // 32-row MFMA blocks per tile
   constexpr int T = n_targets<TMODE>();
@@ -139,15 +186,14 @@ __global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
 
   __shared__ __align__(16) HT Hs[R * LDH];
   __shared__ float gs[NPMAX * kNB];
-  __shared__ float cs[2 * NPMAX * D];
+  __shared__ float cs[NPMAX * D];
   __shared__ int r_slot[R];
   __shared__ float r_x[R], r_y[R], r_w[R];
   __shared__ int64_t r_addr[R];
-  __shared__ int64_t r_bc[R];
+  __shared__ int64_t r_bc[SRC == SRC_C ? R : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
   const NetPtrs& net = A.net;
 
   // -- rows of this tile -----------------------------------------------------
@@ -204,8 +250,15 @@ __global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
 #pragma unroll
       for (int s = 0; s < NPMAX; ++s) acc[s] = fmaf(w, gs[s * kNB + k], acc[s]);
     }
+    if (half == 0) {
 #pragma unroll
-    for (int s = 0; s < NPMAX; ++s) cs[(half * NPMAX + s) * D + n] = acc[s];
+      for (int s = 0; s < NPMAX; ++s) cs[s * D + n] = acc[s];
+    }
+    __syncthreads();
+    if (half == 1) {
+#pragma unroll
+      for (int s = 0; s < NPMAX; ++s) cs[s * D + n] += acc[s];
+    }
   }
   __syncthreads();
 
@@ -217,8 +270,7 @@ __global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
     for (int r = tid / D; r < R; r += 2) {
       float c;
       if constexpr (SRC == SRC_GATHER) {
-        const int s = r_slot[r];
-        c = cs[s * D + n] + cs[(NPMAX + s) * D + n] + bb;
+        c = cs[r_slot[r] * D + n] + bb;
       } else {
         c = A.C[r_bc[r] * D + n];
       }
@@ -229,54 +281,27 @@ __global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
   __syncthreads();
 
   // -- hidden layers on MFMA --------------------------------------------------
-  const int arow = lane & 31, ahalf = lane >> 5;
-  for (int l = 0; l < 3; ++l) {
-    floatx16 acc[RB];
+  if constexpr (PREC == 1) {
+    hidden_layers_bf16<D, R>(Hs, static_cast<const u32x4*>(net.wh), net.bh, lane, wave);
+  } else {
+    const int arow = lane & 31;
+    for (int l = 0; l < 3; ++l) {
+      floatx16 acc[RB];
+      mfma_layer_f32<D, RB, LDH>(Hs, static_cast<const floatx4*>(net.wh) + (size_t)l * (D * D / 4) +
+                                         (size_t)wave * (D / 8) * 64 + lane,
+                                 acc, lane);
+      __syncthreads();   // every wave has finished reading this layer's input
+      const int j = wave * 32 + arow;
+      const float bj = net.bh[l * D + j];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[rb][v] = 0.0f;
-
-    if constexpr (PREC == 0) {
-      const floatx4* wsw = static_cast<const floatx4*>(net.wh) + (size_t)l * (D * D / 4) +
-                           (size_t)wave * (D / 8) * 64 + lane;
-#pragma unroll 4
-      for (int kg = 0; kg < D / 8; ++kg) {
-        const floatx4 bv = wsw[kg * 64];
-        floatx4 av[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          av[rb] = *reinterpret_cast<const floatx4*>(&Hs[(rb * 32 + arow) * LDH + kg * 8 + 4 * ahalf]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) acc[rb] = mfma32x32x2(av[rb][e], bv[e], acc[rb]);
-      }
-    } else {
-      const u32x4* wsw = static_cast<const u32x4*>(net.wh) + (size_t)l * (D * D / 8) +
-                         (size_t)wave * (D / 16) * 64 + lane;
-#pragma unroll 4
-      for (int kg = 0; kg < D / 16; ++kg) {
-        const bf16x8 bv = __builtin_bit_cast(bf16x8, wsw[kg * 64]);
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const bf16x8 av = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const u32x4*>(&Hs[(rb * 32 + arow) * LDH + kg * 16 + 8 * ahalf]));
-          acc[rb] = mfma32x32x16_bf16(av, bv, acc[rb]);
+        for (int v = 0; v < 16; ++v) {
+          const int i = rb * 32 + acc_row(lane, v);
+          Hs[i * LDH + j] = tanh_f32(acc[rb][v] + bj);
         }
-      }
+      __syncthreads();
     }
-    __syncthreads();   // every wave has finished reading this layer's input
-    const int j = wave * 32 + arow;
-    const float bj = net.bh[l * D + j];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int i = rb * 32 + acc_row(lane, v);
-        h_store<PREC>(&Hs[i * LDH + j], tanh_f32(acc[rb][v] + bj));
-      }
-    __syncthreads();
   }
 
   // -- output layer and store -------------------------------------------------
@@ -300,6 +325,103 @@ __global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
 }
 
 template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
+__global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
+  tile_body<D, R, TMODE, PREC, SRC, OUT>(A, (int64_t)blockIdx.x * R);
+}
+
+// Batched independent domains in one persistent launch per colour: block b
+// takes tiles b, b + gridDim.x, ...; tile t belongs to the domain d with
+// tile_begin[d] <= t < tile_begin[d + 1] and covers rows
+// [(t - tile_begin[d]) R, ... + R) of that domain's phase.
+struct MultiArgs {
+  TileArgs base;             // network; colour
+  const float* field_in;     // packed fields (domain offsets are relative to these)
+  float* field_out;
+  const DomEntry* doms;      // [n_domains]
+  const int32_t* tile_begin; // [n_domains + 1] for this colour and target set
+  int n_domains;
+  int64_t n_tiles;
+};
+
+template <int D, int R, int TMODE, int PREC, int OUT>
+__global__ __launch_bounds__(2 * D) void tile_kernel_multi(MultiArgs M) {
+  constexpr int T = n_targets<TMODE>();
+  const int ca = M.base.colour & 1, cb = M.base.colour >> 1;
+  for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
+    int lo = 0, hi = M.n_domains - 1;       // last d with tile_begin[d] <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (M.tile_begin[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const DomEntry e = M.doms[lo];
+    TileArgs A = M.base;
+    A.u_in = M.field_in + e.offset;
+    A.u_out = M.field_out + e.offset;
+    A.pitch = e.pitch;
+    A.ux = e.ux;
+    A.uy = e.uy;
+    A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
+    tile_body<D, R, TMODE, PREC, SRC_GATHER, OUT>(A, (t - M.tile_begin[lo]) * R);
+    __syncthreads();   // the next tile reuses the LDS
+  }
+}
+
+template <int D, int R, int TMODE, int PREC, int OUT>
+static hipError_t launch_multi(const MultiArgs& m, int n_cu, hipStream_t s) {
+  if (m.n_tiles == 0) return hipSuccess;
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<D, R, TMODE, PREC, OUT>,
+                                                     2 * D, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    per_cu = nb;
+  }
+  const int64_t grid = std::min<int64_t>(m.n_tiles, (int64_t)per_cu * n_cu);
+  hipLaunchKernelGGL((tile_kernel_multi<D, R, TMODE, PREC, OUT>), dim3((unsigned)grid), dim3(2 * D), 0,
+                     s, m);
+  return hipGetLastError();
+}
+
+template <int D, int R, int PREC>
+static hipError_t dispatch_multi(const MultiArgs& m, int targets, bool accumulate, int n_cu,
+                                 hipStream_t s) {
+  if (accumulate) return launch_multi<D, R, 1, PREC, OUT_ACCUM>(m, n_cu, s);
+  if (targets == MF_CROSS) return launch_multi<D, R, 0, PREC, OUT_STORE>(m, n_cu, s);
+  return launch_multi<D, R, 1, PREC, OUT_STORE>(m, n_cu, s);
+}
+
+hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
+                              int tile_rows, const float* field_in, float* field_out,
+                              const DomEntry* doms, const int32_t* tile_begin, int n_domains,
+                              int64_t n_tiles, int colour, int n_cu, hipStream_t s) {
+  MultiArgs m{};
+  m.base.net = net;
+  m.base.colour = colour;
+  m.field_in = field_in;
+  m.field_out = field_out;
+  m.doms = doms;
+  m.tile_begin = tile_begin;
+  m.n_domains = n_domains;
+  m.n_tiles = n_tiles;
+  if (prec == MF_BF16) {
+    if (width == 256) {
+      if (tile_rows == 256) return dispatch_multi<256, 256, 1>(m, targets, accumulate, n_cu, s);
+      if (tile_rows == 128) return dispatch_multi<256, 128, 1>(m, targets, accumulate, n_cu, s);
+      return dispatch_multi<256, 64, 1>(m, targets, accumulate, n_cu, s);
+    }
+    if (tile_rows == 256) return dispatch_multi<128, 256, 1>(m, targets, accumulate, n_cu, s);
+    if (tile_rows == 128) return dispatch_multi<128, 128, 1>(m, targets, accumulate, n_cu, s);
+    return dispatch_multi<128, 64, 1>(m, targets, accumulate, n_cu, s);
+  }
+  if (width == 256)
+    return tile_rows == 64 ? dispatch_multi<256, 64, 0>(m, targets, accumulate, n_cu, s)
+                           : dispatch_multi<256, 32, 0>(m, targets, accumulate, n_cu, s);
+  return tile_rows == 64 ? dispatch_multi<128, 64, 0>(m, targets, accumulate, n_cu, s)
+                         : dispatch_multi<128, 32, 0>(m, targets, accumulate, n_cu, s);
+}
+
+template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
 static hipError_t launch_tile(const TileArgs& a, hipStream_t s) {
   const int64_t blocks = (a.total_rows + R - 1) / R;
   if (blocks == 0) return hipSuccess;
@@ -315,19 +437,17 @@ static hipError_t dispatch_phase(const TileArgs& a, int targets, bool accumulate
   return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_STORE>(a, s);
 }
 
-template <int D, int R>
-static hipError_t dispatch_phase_prec(const TileArgs& a, int prec, int targets, bool acc,
-                                      hipStream_t s) {
-  return prec == MF_FP32 ? dispatch_phase<D, R, 0>(a, targets, acc, s)
-                         : dispatch_phase<D, R, 1>(a, targets, acc, s);
-}
-
 static int64_t colour_count(int ux, int uy, int colour) {
   return (int64_t)(ux - (colour & 1)) * (uy - (colour >> 1));
 }
 
 int pick_tile_rows(int width, int prec, int targets, int64_t rows, int n_cu) {
-  (void)width; (void)prec; (void)targets;
+  (void)width; (void)targets;
+  if (prec == MF_BF16) {
+    if (rows >= (int64_t)256 * 3 * n_cu) return 256;
+    if (rows >= (int64_t)128 * 2 * n_cu) return 128;
+    return 64;
+  }
   return rows >= (int64_t)64 * 2 * n_cu ? 64 : 32;
 }
 
@@ -344,12 +464,21 @@ hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bo
   const int T = (accumulate || targets == MF_INTERIOR) ? kInterior : kCross;
   a.total_rows = colour_count(p.ux, p.uy, p.colour) * T;
   if (a.total_rows == 0) return hipSuccess;
-  if (width == 256) {
-    return tile_rows == 64 ? dispatch_phase_prec<256, 64>(a, prec, targets, accumulate, s)
-                           : dispatch_phase_prec<256, 32>(a, prec, targets, accumulate, s);
+  if (prec == MF_BF16) {
+    if (width == 256) {
+      if (tile_rows == 256) return dispatch_phase<256, 256, 1>(a, targets, accumulate, s);
+      if (tile_rows == 128) return dispatch_phase<256, 128, 1>(a, targets, accumulate, s);
+      return dispatch_phase<256, 64, 1>(a, targets, accumulate, s);
+    }
+    if (tile_rows == 256) return dispatch_phase<128, 256, 1>(a, targets, accumulate, s);
+    if (tile_rows == 128) return dispatch_phase<128, 128, 1>(a, targets, accumulate, s);
+    return dispatch_phase<128, 64, 1>(a, targets, accumulate, s);
   }
-  return tile_rows == 64 ? dispatch_phase_prec<128, 64>(a, prec, targets, accumulate, s)
-                         : dispatch_phase_prec<128, 32>(a, prec, targets, accumulate, s);
+  if (width == 256)
+    return tile_rows == 64 ? dispatch_phase<256, 64, 0>(a, targets, accumulate, s)
+                           : dispatch_phase<256, 32, 0>(a, targets, accumulate, s);
+  return tile_rows == 64 ? dispatch_phase<128, 64, 0>(a, targets, accumulate, s)
+                         : dispatch_phase<128, 32, 0>(a, targets, accumulate, s);
 }
 
 // ---------------------------------------------------------------------------

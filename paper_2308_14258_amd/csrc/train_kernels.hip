@@ -24,6 +24,8 @@
 //
 // Alg. 1 runs the data points (value stream only) and then the collocation
 // points (four streams); both accumulate into one gradient, then Adam.
+#include <math.h>
+
 #include <algorithm>
 
 #include "mf_device.h"
@@ -407,14 +409,16 @@ __global__ __launch_bounds__(256) void output_grad_kernel(const float* __restric
   }
 }
 
+// Adam with bias correction; omb1 = 1 - beta1 and omb2 = 1 - beta2 are
+// formed in double on the host.
 __global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                            const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
-                            float eps, float bc1, float bc2) {
+                            const float* __restrict__ g, int64_t n, float lr, float b1, float omb1,
+                            float b2, float omb2, float eps, float bc1, float bc2) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     const float mhat = mi / bc1, vhat = vi / bc2;
@@ -580,10 +584,12 @@ hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, co
                       : train_step_d<128>(net, whT, tb, G, B, Xb, Xc, nc, grad, loss, s);
 }
 
-hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1,
-                       float b2, float eps, float bc1, float bc2, hipStream_t s) {
-  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, p, m, v, g, n, lr, b1,
-                     b2, eps, bc1, bc2);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
+                       double b2, double eps, int64_t step, hipStream_t s) {
+  const double bc1 = 1.0 - pow(b1, (double)step), bc2 = 1.0 - pow(b2, (double)step);
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, p, m, v, g, n,
+                     (float)lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps,
+                     (float)bc1, (float)bc2);
   return hipGetLastError();
 }
 

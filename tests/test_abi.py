@@ -103,7 +103,17 @@ def test_sweep_argument_errors(lib):
     assert _sweep(lib, desc=SdnetDesc(128, 4, 128, 5)) == MF_EINVAL
     assert _sweep(lib, dom=_dom(2, 2, pitch=64)) == MF_ESHAPE and b"pitch" in lib.mf_last_error()
     assert _sweep(lib, dom=_dom(2, 2, stride=8)) == MF_ESHAPE
-    assert _sweep(lib, nd=2) == MF_EUNSUPPORTED
+    assert _sweep(lib, nd=0) == MF_ESHAPE
+    two = (DomainDesc * 2)(_dom(), _dom())             # same offsets: overlapping
+    assert lib.mf_sweep(None, ctypes.byref(SdnetDesc(128, 4, 128, 0)), ctypes.c_void_p(FAKE),
+                        ctypes.c_void_p(FAKE), two, 2, -1, MF_CROSS, 0, MF_FP32,
+                        ctypes.c_void_p(FAKE), 1 << 30, None) == MF_EINVAL
+    assert b"overlap" in lib.mf_last_error()
+    two[1].field_offset = 65 * 65
+    assert lib.mf_sweep(None, ctypes.byref(SdnetDesc(128, 4, 128, 0)), ctypes.c_void_p(FAKE),
+                        ctypes.c_void_p(FAKE), two, 2, -1, MF_CROSS, 0, MF_FP32,
+                        ctypes.c_void_p(FAKE), 1 << 30, None) == MF_EINVAL
+    assert b"ctx" in lib.mf_last_error()               # a valid batch gets as far as the ctx
     assert _sweep(lib, colour=4) == MF_EINVAL
     assert _sweep(lib, targets=3) == MF_EINVAL
     assert _sweep(lib, mode=1) == MF_EUNSUPPORTED

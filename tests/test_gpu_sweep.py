@@ -292,3 +292,45 @@ def test_graph_replay_equals_direct_launches(ctx):
     mf_solve(ctx, params, b, (3, 4), 0)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_BF16, 64),
+                                       (MF_BF16, 128), (MF_BF16, 256)])
+@pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
+def test_every_tile_height(ctx, prec, rows, targets):
+    print(f"case: tile rows {rows} prec {prec} targets {targets}", flush=True)
+    params = mi.random_params(256, seed=31)
+    f = mi.random_interior_field(6, 5, seed=4)
+    u = dev(f)
+    ctx.tile_rows(prec, rows)
+    try:
+        mf_sweep(ctx, dev(params), u, (6, 5), -1, targets, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.tile_rows(prec, 0)
+    kind = "cross" if targets == MF_CROSS else "interior"
+    want = sw.sweep(torch.from_numpy(f.astype(np.float64)), 6, 5, oracle_solver(params, 256), kind)
+    ny, nx = f.shape
+    m = skel_interior_mask(ny, nx) if targets == MF_CROSS else interior_mask(ny, nx)
+    err = rel_l2(u.cpu().numpy(), want.numpy(), m)
+    print(f"tile rows {rows} prec {prec} targets {targets}: rel L2 {err:.3e}", flush=True)
+    assert err <= (1e-5 if prec == MF_FP32 else 2e-2)
+    np.testing.assert_array_equal(u.cpu().numpy()[~m], f[~m])
+
+
+def test_autotune_picks_a_candidate_and_is_used(ctx):
+    print("case: autotune", flush=True)
+    from paper_2308_14258_amd import mf_autotune
+    params = dev(mi.xavier_params(256, 0))
+    f = mi.gp_field(8, 8, 1.0, seed=2)
+    scratch = dev(f)
+    best = mf_autotune(ctx, params, scratch, (8, 8), MF_CROSS, MF_BF16, trials=2)
+    assert best in (64, 128, 256)
+    a = dev(f)
+    mf_solve(ctx, params, a, (8, 8), 5, prec=MF_BF16)
+    ctx.tile_rows(MF_BF16, best)
+    b = dev(f)
+    mf_solve(ctx, params, b, (8, 8), 5, prec=MF_BF16)
+    ctx.tile_rows(MF_BF16, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
