@@ -202,6 +202,29 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
                             float* u, float* u_out, const mf_domain_desc* dom, int32_t colour,
                             void* stream);
 
+/* Workspace bytes for mf_solve_adjoint. */
+mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
+                             int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes);
+
+/* Sensitivity of the assembled solution to the initial field, float32.
+ * Forward: K multiplicative sweeps of u0 (device, read only; not modified)
+ * then the overlap-averaged assembly into u_out (device, same layout as u0;
+ * nullable) and J = sum over interior grid points of u_out^2 (device [1],
+ * nullable; summed over the domains of a batch). Reverse: writes
+ * u0_bar = dJ/du0 (device, same layout as u0, grid points only) through the
+ * assembly and every colour phase in reverse order, recomputing field
+ * states from checkpoints taken every ckpt_every sweeps. Its values on the
+ * outer ring are dJ/dg, the sensitivity to the Dirichlet data. Each phase
+ * is reversed by reading and zeroing the target adjoints, re-running the
+ * network forward from the stored field, the hand-written value-stream
+ * reverse pass, gb = W1g^T sum_t ab1 (Eq. 8), and a deterministic scatter-
+ * add of gb onto the placement boundaries in four sub-colours. Batches
+ * (n_domains > 1) are processed domain by domain. Asynchronous. */
+mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
+                           const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
+                           int32_t ckpt_every, float* u_out, float* J, float* u0_bar, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* Workspace bytes for sdnet_forward with n_bc boundary conditions and n_pts
  * points per condition; derivatives != 0 when dU or lapU will be requested
  * (then two float32 buffers of 4 n_bc n_pts d values are included). */

@@ -63,6 +63,11 @@ _SIG = {
                               _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),
     "mf_sweep_operator": (_c.c_int32, [_P, _P, _c.c_int64, _c.c_int32, _P, _P, _c.POINTER(DomainDesc),
                                        _c.c_int32, _P]),
+    "mf_adjoint_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
+                                        _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
+    "mf_solve_adjoint": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc),
+                                      _c.c_int32, _c.c_int32,
+                                      _c.c_int32, _c.c_int32, _P, _P, _P, _P, _c.c_size_t, _P]),
     "sdnet_forward_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,
                                            _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "sdnet_forward": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,

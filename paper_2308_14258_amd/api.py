@@ -213,6 +213,30 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
     return (done.value, last.value) if report else None
 
 
+def mf_solve_adjoint(ctx: Context, params: torch.Tensor, u0, units, K: int, ckpt_every: int = 5,
+                     targets: int = MF_CROSS, u_out=None, J: torch.Tensor | None = None,
+                     u0_bar=None):
+    """d J / d u0 for J = sum of squared interior values of the assembly
+    after K sweeps. u0 is a 2-D field (units (ux, uy)) or a Batch (then
+    u_out / u0_bar are flat buffers like u0.buf). Returns (u0_bar, J)."""
+    _need_cuda_f32(params, "params")
+    buf, dom, nd = _field_and_domains(u0, units)
+    width = width_of(params)
+    if u0_bar is None:
+        u0_bar = torch.zeros_like(buf)
+    if J is None:
+        J = torch.zeros(1, dtype=torch.float32, device=buf.device)
+    n = ctypes.c_size_t()
+    lib = load()
+    check(lib.mf_adjoint_ws_size(ctypes.byref(sdnet_desc(width)), _dom_arg(dom), nd, targets, K,
+                                 ckpt_every, ctypes.byref(n)), "mf_adjoint_ws_size")
+    ws = ctx.workspace(n.value)
+    check(lib.mf_solve_adjoint(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+                               _dom_arg(dom), nd, targets, K, ckpt_every, _ptr(u_out), _ptr(J),
+                               _ptr(u0_bar), _ptr(ws), ws.numel(), _stream()), "mf_solve_adjoint")
+    return u0_bar, J
+
+
 def mf_sweep_operator(ctx: Context, Hop: torch.Tensor, u: torch.Tensor, units, colour: int = -1,
                       targets: int = MF_CROSS, u_out: torch.Tensor | None = None):
     """Sweep (colour -1), phase (0..3) or assembly (4) with a linear solver."""
@@ -280,5 +304,5 @@ def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: tor
     return loss
 
 
-__all__ = ["Batch", "Context", "mf_autotune", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
+__all__ = ["Batch", "Context", "mf_autotune", "mf_solve_adjoint", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
            "sdnet_train_step", "width_of", "sdnet_desc", "domain_desc", "_lib"]

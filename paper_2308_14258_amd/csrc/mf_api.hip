@@ -769,6 +769,166 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
 }
 
 // ---------------------------------------------------------------------------
+// mf_solve_adjoint
+// ---------------------------------------------------------------------------
+static constexpr int64_t kAdjRows = 262144;   // (placement, target) rows per chunk
+
+struct AdjLayout {
+  NetLayout net;
+  size_t whT = 0, X_cross = 0, X_interior = 0, G = 0, C = 0, ubp = 0, Z[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
+  size_t csum = 0, gb = 0, part = 0, field = 0, ckpt = 0, states = 0, uout = 0, total = 0;
+  size_t fsize = 0;   // floats per field copy (largest domain)
+  int n_ckpt = 0;
+};
+
+static int64_t field_extent(const mf_domain_desc& d) {
+  return (32LL * d.units_y) * d.pitch + 32LL * d.units_x + 1;
+}
+
+static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, int K, int ckpt_every) {
+  AdjLayout A;
+  A.net = net_layout(width, MF_FP32, 0);
+  const size_t d = (size_t)width;
+  const size_t max_q = (size_t)(kAdjRows / 61);
+  int64_t fs = 0;
+  for (int i = 0; i < nd; ++i) fs = std::max<int64_t>(fs, field_extent(dom[i]));
+  A.fsize = (size_t)fs;
+  A.n_ckpt = K > 0 ? (K + ckpt_every - 1) / ckpt_every : 0;
+  size_t o = A.net.end;
+  A.whT = o; o = align256(o + 3 * d * d * 4);
+  A.X_cross = o; o = align256(o + 61 * 2 * 4);
+  A.X_interior = o; o = align256(o + 961 * 2 * 4);
+  A.G = o; o = align256(o + max_q * 128 * 4);
+  A.C = o; o = align256(o + max_q * d * 4);
+  A.ubp = o; o = align256(o + (size_t)kAdjRows * 4);
+  for (int l = 0; l < 4; ++l) { A.Z[l] = o; o = align256(o + (size_t)kAdjRows * d * 4); }
+  for (int l = 0; l < 2; ++l) { A.Ab[l] = o; o = align256(o + (size_t)kAdjRows * d * 4); }
+  A.csum = o; o = align256(o + 3 * max_q * d * 4);
+  A.gb = o; o = align256(o + max_q * 128 * 4);
+  A.part = o; o = align256(o + 1024 * 4);
+  A.field = o; o = align256(o + A.fsize * 4);
+  A.ckpt = o; o = align256(o + (size_t)A.n_ckpt * A.fsize * 4);
+  A.states = o; o = align256(o + 4 * (size_t)ckpt_every * A.fsize * 4);
+  A.uout = o; o = align256(o + A.fsize * 4);
+  A.total = o;
+  return A;
+}
+
+static mf_status adjoint_checks(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int targets,
+                                int K, int ckpt_every) {
+  MF_TRY(check_desc(desc));
+  MF_TRY(check_domain(dom, nd));
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  if (K < 0) return fail(MF_EINVAL, "K %d < 0", K);
+  if (ckpt_every < 1 || ckpt_every > 1000) return fail(MF_EINVAL, "ckpt_every %d not in 1..1000", ckpt_every);
+  return MF_OK;
+}
+
+mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
+                             int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes) {
+  MF_TRY(check_ptr(bytes, "bytes", 1));
+  *bytes = 0;
+  MF_TRY(adjoint_checks(desc, dom, n_domains, targets, K, ckpt_every));
+  *bytes = adjoint_layout(desc->width, dom, n_domains, K, ckpt_every).total;
+  return ok();
+}
+
+static Plan single_plan(const mf_sdnet_desc* desc, int targets, float* field, const mf_domain_desc* dom1,
+                        const NetPtrs& net, const void* ws) {
+  Plan P;
+  P.nd = 1;
+  P.dom = dom1;
+  P.u = field;
+  P.width = desc->width;
+  P.prec = MF_FP32;
+  P.targets = targets;
+  P.net = net;
+  P.ws = ws;
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 4; ++c) P.rows[a][c] = phase_rows(dom1, c, a ? MF_INTERIOR : targets);
+  return P;
+}
+
+mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
+                           const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
+                           int32_t ckpt_every, float* u_out, float* J, float* u0_bar, void* ws,
+                           size_t ws_bytes, void* stream) {
+  MF_TRY(adjoint_checks(desc, dom, n_domains, targets, K, ckpt_every));
+  MF_TRY(check_ptr(params, "params"));
+  MF_TRY(check_ptr(u0, "u0"));
+  MF_TRY(check_ptr(u0_bar, "u0_bar"));
+  if (u_out) MF_TRY(check_ptr(u_out, "u_out"));
+  if (J) MF_TRY(check_ptr(J, "J"));
+  if (u0_bar == u0 || (u_out && (u_out == u0 || u_out == u0_bar)))
+    return fail(MF_EINVAL, "u0, u_out and u0_bar must be distinct buffers");
+  const AdjLayout A = adjoint_layout(desc->width, dom, n_domains, K, ckpt_every);
+  MF_TRY(check_ws(ws, ws_bytes, A.total));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  char* b = static_cast<char*>(ws);
+  MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, A.net, ws, s));
+  const NetPtrs net = net_ptrs(A.net, ws);
+  float* whT = reinterpret_cast<float*>(b + A.whT);
+  MF_HIP(launch_prepare_wT(params, desc->width, whT, s));
+  AdjointBuffers ab;
+  ab.X_cross = reinterpret_cast<float*>(b + A.X_cross);
+  ab.X_interior = reinterpret_cast<float*>(b + A.X_interior);
+  ab.G = reinterpret_cast<float*>(b + A.G);
+  ab.C = reinterpret_cast<float*>(b + A.C);
+  ab.ubp = reinterpret_cast<float*>(b + A.ubp);
+  for (int l = 0; l < 4; ++l) ab.Z[l] = reinterpret_cast<float*>(b + A.Z[l]);
+  for (int l = 0; l < 2; ++l) ab.Ab[l] = reinterpret_cast<float*>(b + A.Ab[l]);
+  ab.csum = reinterpret_cast<float*>(b + A.csum);
+  ab.gb = reinterpret_cast<float*>(b + A.gb);
+  ab.max_rows = kAdjRows;
+  MF_HIP(launch_target_coords(ab.X_cross, ab.X_interior, s));
+  float* part = reinterpret_cast<float*>(b + A.part);
+  float* F = reinterpret_cast<float*>(b + A.field);
+  float* ckpt = reinterpret_cast<float*>(b + A.ckpt);
+  float* states = reinterpret_cast<float*>(b + A.states);
+
+  for (int d = 0; d < n_domains; ++d) {
+    const mf_domain_desc& D = dom[d];
+    const size_t ext = (size_t)field_extent(D);
+    const mf_domain_desc D1{D.units_x, D.units_y, 32, 16, D.pitch, 0};
+    const Plan P = single_plan(desc, targets, F, &D1, net, ws);
+    float* uo = u_out ? u_out + D.field_offset : reinterpret_cast<float*>(b + A.uout);
+    float* ub = u0_bar + D.field_offset;
+    // forward with checkpoints
+    MF_HIP(hipMemcpyAsync(F, u0 + D.field_offset, ext * 4, hipMemcpyDeviceToDevice, s));
+    for (int i = 0; i < A.n_ckpt; ++i) {
+      MF_HIP(hipMemcpyAsync(ckpt + (size_t)i * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
+      const int n_s = std::min(ckpt_every, K - i * ckpt_every);
+      for (int k = 0; k < n_s; ++k)
+        for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, false, nullptr, s, false));
+    }
+    MF_HIP(launch_assembly_init(F, uo, D.pitch, D.units_x, D.units_y, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, true, uo, s, false));
+    if (J) MF_HIP(launch_interior_sumsq(uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
+    // reverse: assembly, then the sweeps segment by segment
+    MF_HIP(launch_fill2d(ub, D.pitch, D.units_x, D.units_y, 0.0f, s));
+    for (int c = 3; c >= 0; --c)
+      MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, F, uo, ub, D.pitch, D.units_x, D.units_y, c,
+                                   targets, true, s));
+    for (int i = A.n_ckpt - 1; i >= 0; --i) {
+      const int n_s = std::min(ckpt_every, K - i * ckpt_every);
+      MF_HIP(hipMemcpyAsync(F, ckpt + (size_t)i * A.fsize, ext * 4, hipMemcpyDeviceToDevice, s));
+      for (int k = 0; k < n_s; ++k)
+        for (int c = 0; c < 4; ++c) {
+          MF_HIP(hipMemcpyAsync(states + (size_t)(4 * k + c) * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
+          MF_TRY(run_colour(ctx, P, c, false, nullptr, s, false));
+        }
+      for (int k = n_s - 1; k >= 0; --k)
+        for (int c = 3; c >= 0; --c)
+          MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, states + (size_t)(4 * k + c) * A.fsize,
+                                       nullptr, ub, D.pitch, D.units_x, D.units_y, c, targets, false, s));
+    }
+  }
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
 // sdnet_forward
 // ---------------------------------------------------------------------------
 // Workspace of sdnet_forward: prepared network, projections C [n_bc][d] and,

@@ -126,4 +126,31 @@ hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, 
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s);
 
+// Adjoint of the sweep: device buffers carved from the workspace.
+struct AdjointBuffers {
+  float* X_cross;     // [61][2] target coordinates
+  float* X_interior;  // [961][2]
+  float* G;           // [max_q][128] boundary vectors of a chunk
+  float* C;           // [max_q][d]
+  float* ubp;         // [max_rows] target adjoints
+  float* Z[4];        // [max_rows][d] activations of layers 1..4
+  float* Ab[2];       // [max_rows][d] pre-activation adjoints
+  float* csum;        // [3][max_q][d] first-layer sums
+  float* gb;          // [max_q][128] boundary adjoints
+  int64_t max_rows;
+};
+hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
+                                int64_t n_bc, float* const Z[4], hipStream_t s);
+hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Ab[2],
+                                 int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
+                                 hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill2d(float* p, int64_t pitch, int ux, int uy, float v, hipStream_t s);
+hipError_t launch_target_coords(float* X_cross, float* X_interior, hipStream_t s);
+hipError_t launch_interior_sumsq(const float* u, int64_t pitch, int ux, int uy, float* part, float* out,
+                                 int accumulate, hipStream_t s);
+hipError_t launch_adjoint_colour(const NetPtrs& net, int width, const float* whT, const AdjointBuffers& ab,
+                                 const float* u_before, const float* u_out, float* ub, int64_t pitch, int ux,
+                                 int uy, int colour, int targets, bool assembly, hipStream_t s);
+
 }  // namespace mf

@@ -593,6 +593,42 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, 
   return hipGetLastError();
 }
 
+// Value stream only: first layer from C [n_bc][D] and shared points X [T][2],
+// then the three hidden layers; Z[l] receives layer l+1's activations.
+hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
+                                int64_t n_bc, float* const Z[4], hipStream_t s) {
+  float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
+  return width == 256 ? run_taylor_forward<256>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, s)
+                      : run_taylor_forward<128>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, s);
+}
+
+// Value-stream reverse pass from ab4 in Ab[0] down to ab1, then per-condition
+// sums c[b][j] = sum_t ab1 (first of the three [n_bc][D] blocks of csum).
+template <int D>
+static hipError_t value_backward_d(const float* whT, float* const Z[4], float* const Ab[2], int64_t n_rows,
+                                   const float* X, int64_t n_bc, int64_t T, float* csum, hipStream_t s) {
+  int cur = 0;
+  const unsigned blocks = (unsigned)((n_rows + 63) / 64);
+  for (int l = 2; l >= 0; --l) {
+    const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
+    hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT, nullptr,
+                       Z[l], Ab[cur ^ 1], nullptr, n_rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)n_bc), dim3(D), 0, s, Ab[cur], X, 0, T, n_bc,
+                     csum);
+  return hipGetLastError();
+}
+
+hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Ab[2],
+                                 int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
+                                 hipStream_t s) {
+  return width == 256 ? value_backward_d<256>(whT, Z, Ab, n_rows, X, n_bc, T, csum, s)
+                      : value_backward_d<128>(whT, Z, Ab, n_rows, X, n_bc, T, csum, s);
+}
+
 hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s) {

@@ -1,0 +1,90 @@
+"""GPU parity of mf_solve_adjoint (dJ/du0, J = sum of squared interior
+values of the assembly after K sweeps) against the float64 oracle's
+autograd gradient and against float64 finite differences of the oracle's
+J, through the C ABI. Bar: relative 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+import mf_inputs as mi
+from oracle import adjoint, sweep as sw
+from paper_2308_14258_amd import MF_CROSS, MF_INTERIOR, Batch, Context, mf_solve_adjoint
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("units,K,ce,targets", [((2, 2), 3, 2, MF_CROSS), ((1, 2), 2, 5, MF_INTERIOR),
+                                                ((3, 2), 5, 2, MF_CROSS), ((2, 1), 0, 1, MF_CROSS)])
+def test_adjoint_matches_oracle(ctx, units, K, ce, targets):
+    print(f"case: adjoint units={units} K={K} ckpt={ce} targets={targets}", flush=True)
+    ux, uy = units
+    width = 128
+    params = mi.random_params(width, seed=41)
+    f = mi.gp_field(ux, uy, 0.6, seed=ux * 10 + uy)
+    u0 = torch.from_numpy(f).cuda()
+    u_out = torch.empty_like(u0)
+    ub, J = mf_solve_adjoint(ctx, torch.from_numpy(params).cuda(), u0, units, K, ce, targets,
+                             u_out=u_out)
+    torch.cuda.synchronize()
+    kind = "cross" if targets == MF_CROSS else "interior"
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), width)
+    Jo, go = adjoint.solve_adjoint(torch.from_numpy(f.astype(np.float64)), ux, uy, solver, K, kind)
+    got = ub.cpu().numpy().astype(np.float64)
+    err = _rel(got, go.numpy())
+    print(f"adjoint rel L2 {err:.3e}, J {J.item():.6e} vs {Jo:.6e}", flush=True)
+    assert err <= 1e-4
+    assert abs(J.item() - Jo) <= 1e-5 * abs(Jo)
+    # u0 is not modified
+    np.testing.assert_array_equal(u0.cpu().numpy(), f)
+
+
+def test_adjoint_directional_fd(ctx):
+    """<dJ/du0, v> against central differences of the float64 oracle's J."""
+    print("case: adjoint vs FD", flush=True)
+    width = 128
+    params = mi.random_params(width, seed=43)
+    f = mi.gp_field(2, 2, 0.6, seed=5)
+    ub, _ = mf_solve_adjoint(ctx, torch.from_numpy(params).cuda(), torch.from_numpy(f).cuda(), (2, 2), 3, 2)
+    g = ub.cpu().numpy().astype(np.float64)
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), width)
+
+    def J(u):
+        for _ in range(3):
+            u = sw.sweep(u, 2, 2, solver)
+        return adjoint.objective(sw.assemble(u, 2, 2, solver)).item()
+
+    rng = np.random.default_rng(0)
+    f64 = torch.from_numpy(f.astype(np.float64))
+    for _ in range(4):
+        v = rng.standard_normal(f.shape)
+        h = 1e-5
+        fd = (J(f64 + h * torch.from_numpy(v)) - J(f64 - h * torch.from_numpy(v))) / (2 * h)
+        an = float(np.sum(g * v))
+        assert abs(fd - an) <= 1e-4 * max(abs(fd), 1e-3 * np.linalg.norm(g)), (fd, an)
+
+
+def test_adjoint_batch_equals_single(ctx):
+    print("case: adjoint batch", flush=True)
+    sizes, fields = mi.batched_domains(3, 1, 3, 1.0, seed=2)
+    params = torch.from_numpy(mi.random_params(256, seed=3)).cuda()
+    batch = Batch(fields)
+    ub, J = mf_solve_adjoint(ctx, params, batch, None, 4, 2)
+    total = 0.0
+    for i, f in enumerate(fields):
+        ux, uy = (int(v) for v in sizes[i])
+        ubi, Ji = mf_solve_adjoint(ctx, params, torch.from_numpy(f).cuda(), (ux, uy), 4, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.field(i, ub), ubi), i
+        total += Ji.item()
+    assert abs(J.item() - total) <= 1e-6 * abs(total)
