@@ -239,25 +239,38 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       gs[idx] = A.u_in[(int64_t)(kHalf * b + bj) * A.pitch + kHalf * a + bi];
     }
     __syncthreads();
-    const int n = tid & (D - 1), half = tid / D;
-    float acc[NPMAX];
+    // Thread t owns 4 consecutive columns (group t % (D/4)) and a 16-wide
+    // slice of k (t / (D/4)); its 16 float4 weight loads are independent, so
+    // they are in flight together. The 8 k-slice partials go to LDS scratch
+    // that aliases the activation tile (not in use yet) and are then summed.
+    constexpr int NG = D / 4, KSL = NTH / NG, KPS = kNB / KSL;
+    static_assert(KSL * KPS == kNB, "projection split");
+    static_assert((size_t)KSL * NPMAX * D * sizeof(float) <= sizeof(HT) * R * LDH, "projection scratch");
+    const int n4 = tid % NG, ks = tid / NG;
+    floatx4 w[KPS];
 #pragma unroll
-    for (int s = 0; s < NPMAX; ++s) acc[s] = 0.0f;
-    const float* wcol = net.w1gT + n;
-#pragma unroll 8
-    for (int k = half * 64; k < half * 64 + 64; ++k) {
-      const float w = wcol[k * D];
+    for (int i = 0; i < KPS; ++i)
+      w[i] = *reinterpret_cast<const floatx4*>(net.w1gT + (ks * KPS + i) * D + 4 * n4);
+    float* part = reinterpret_cast<float*>(Hs);
+    for (int s = 0; s < np; ++s) {
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int s = 0; s < NPMAX; ++s) acc[s] = fmaf(w, gs[s * kNB + k], acc[s]);
-    }
-    if (half == 0) {
-#pragma unroll
-      for (int s = 0; s < NPMAX; ++s) cs[s * D + n] = acc[s];
+      for (int i = 0; i < KPS; ++i) {
+        const float g = gs[s * kNB + ks * KPS + i];
+        acc[0] = fmaf(w[i][0], g, acc[0]);
+        acc[1] = fmaf(w[i][1], g, acc[1]);
+        acc[2] = fmaf(w[i][2], g, acc[2]);
+        acc[3] = fmaf(w[i][3], g, acc[3]);
+      }
+      *reinterpret_cast<floatx4*>(&part[(ks * NPMAX + s) * D + 4 * n4]) = acc;
     }
     __syncthreads();
-    if (half == 1) {
+    for (int idx = tid; idx < np * D; idx += NTH) {
+      const int s = idx / D, n = idx - s * D;
+      float c = 0.0f;
 #pragma unroll
-      for (int s = 0; s < NPMAX; ++s) cs[s * D + n] += acc[s];
+      for (int k = 0; k < KSL; ++k) c += part[(k * NPMAX + s) * D + n];
+      cs[idx] = c;
     }
   }
   __syncthreads();
@@ -275,7 +288,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
         c = A.C[r_bc[r] * D + n];
       }
       const float pre = fmaf(r_y[r], wy, fmaf(r_x[r], wx, c));
-      h_store<PREC>(&Hs[r * LDH + n], tanh_f32(pre));
+      h_store<PREC>(&Hs[r * LDH + n], tanh_fast(pre));
     }
   }
   __syncthreads();
@@ -298,7 +311,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int i = rb * 32 + acc_row(lane, v);
-          Hs[i * LDH + j] = tanh_f32(acc[rb][v] + bj);
+          Hs[i * LDH + j] = tanh_fast(acc[rb][v] + bj);
         }
       __syncthreads();
     }
