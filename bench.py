@@ -83,6 +83,12 @@ def main():
     ap.add_argument("--bf16-sweeps", type=int, default=500)
     ap.add_argument("--only-bf16", action="store_true",
                     help="run only the 64x64-unit comparison (for counter collection)")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--c5", action="store_true",
+                    help="also time the 48-domain batch (BF16 sweeps + FP32 adjoint); its GP "
+                         "inputs take about a minute to generate on the host")
+    ap.add_argument("--only-c5", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
@@ -104,9 +110,11 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
         return
 
-    if args.only_bf16:
+    if args.only_bf16 or args.only_c5:
         ctx = Context(0)
-        print(json.dumps({"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)}), flush=True)
+        out = {"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)} if args.only_bf16 else \
+            {"batched": batched_measurement(ctx)}
+        print(json.dumps(out), flush=True)
         ctx.close()
         return
 
@@ -190,10 +198,84 @@ def main():
     }
     if not args.no_bf16:
         out["bf16_vs_fp32"] = bf16_comparison(ctx, args.bf16_sweeps)
+    if not args.no_train:
+        out["train"] = train_measurement(ctx, args.train_steps)
+    if args.c5:
+        out["batched"] = batched_measurement(ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(field, params_np, width, ux, uy, args.cpu_sample_sweeps)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def train_measurement(ctx, steps):
+    """Physics-informed training step (Alg. 1 + Adam): 1024 GP boundary
+    conditions x (128 boundary + 256 collocation points), width 128, fp32.
+    Algorithmic flops per step count the forward Taylor streams (4 streams of
+    3 hidden d x d GEMMs per collocation point, 1 for a data point) and twice
+    that for the reverse pass (input adjoints + weight gradients)."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import sdnet_train_step
+    w = mi.WORKLOADS["C3"]
+    d = w["width"]
+    G = torch.from_numpy(mi.gp_perimeter_batch(w["n_bc"], w["length"], w["bc_seed"])).cuda()
+    Xc = torch.from_numpy(mi.collocation_points(w["n_bc"], w["n_colloc"], w["colloc_seed"])).cuda()
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes().astype(np.float32)).cuda()
+    p = torch.from_numpy(mi.xavier_params(d, 0)).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    for k in range(2):
+        sdnet_train_step(ctx, p, m, v, k + 1, G, Xb, Xc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        loss = sdnet_train_step(ctx, p, m, v, k + 3, G, Xb, Xc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rows = w["n_bc"] * (4 * w["n_colloc"] + 128)
+    flops = 3 * (3 * 2.0 * d * d * rows)
+    return {"workload": "C3: 1024 conditions x (128 + 256) points, width 128, Adam",
+            "steps_per_s": steps / dt, "ms_per_step": dt * 1e3 / steps,
+            "gemm_tflops": flops * steps / dt / 1e12,
+            "frac_of_fp32_mfma_peak": flops * steps / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+            "last_loss": [float(x) for x in loss.cpu()]}
+
+
+def batched_measurement(ctx):
+    """48 independent domains (4..48 units per side, seed 7), width 256: 20
+    BF16 sweeps + assembly in one persistent launch per colour, and the FP32
+    adjoint of J = sum u_out^2 through 20 sweeps with checkpoints every 5."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_BF16, MF_CROSS, Batch, mf_solve, mf_solve_adjoint
+    w = mi.WORKLOADS["C5"]
+    t0 = time.perf_counter()
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    gen_s = time.perf_counter() - t0
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    batch = Batch(fields)
+    base = batch.buf.clone()
+    out = torch.empty_like(batch.buf)
+    K = w["sweeps"]
+    mf_solve(ctx, params, batch, None, 2, prec=MF_BF16)
+    batch.buf.copy_(base)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mf_solve(ctx, params, batch, None, K, prec=MF_BF16, u_out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    placements = int(sum((2 * ux - 1) * (2 * uy - 1) for ux, uy in sizes))
+    evals = K * placements * CROSS_T + placements * INTERIOR_T
+    t0 = time.perf_counter()
+    ub, J = mf_solve_adjoint(ctx, params, Batch(fields), None, K, w["ckpt"])
+    torch.cuda.synchronize()
+    dta = time.perf_counter() - t0
+    return {"workload": f"C5: 48 domains, {placements} placements, width 256, {K} sweeps",
+            "input_generation_s": gen_s,
+            "bf16_solve": {"s": dt, "point_evals_per_s": evals / dt},
+            "fp32_adjoint": {"s": dta, "J": float(J.item()),
+                             "grad_norm": float(ub.double().norm().item())}}
 
 
 def bf16_comparison(ctx, sweeps):

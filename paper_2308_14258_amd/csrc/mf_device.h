@@ -103,13 +103,18 @@ __device__ __forceinline__ int acc_row(int lane, int v) {
   return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
 }
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t x = __float_as_uint(f);
-  if ((x & 0x7f800000u) == 0x7f800000u) {          // inf or nan
-    return (uint16_t)((x >> 16) | ((x & 0xffffu) ? 0x40u : 0u));
-  }
-  x += 0x7fffu + ((x >> 16) & 1u);                  // round to nearest even
-  return (uint16_t)(x >> 16);
+// float -> bf16, round to nearest even, by the hardware converter
+// (v_cvt_pk_bf16_f32 converts two values per instruction).
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bf16_pair(float a, float b, uint16_t& ha, uint16_t& hb) {
+  const bf16x2 p = {(__bf16)a, (__bf16)b};
+  const uint32_t u = __builtin_bit_cast(uint32_t, p);
+  ha = (uint16_t)(u & 0xffffu);
+  hb = (uint16_t)(u >> 16);
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {

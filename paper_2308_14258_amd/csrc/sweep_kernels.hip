@@ -77,8 +77,7 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
       const int kg = (int)(rest % (d / 16)), cb = (int)(rest / (d / 16));
       j = 32 * cb + (lane & 31);
       k = 16 * kg + 8 * (lane >> 5) + e;
-      static_cast<uint16_t*>(wh)[idx] =
-          f32_to_bf16_rne(params[off_w2 + l * lstride + (int64_t)j * d + k]);
+      static_cast<uint16_t*>(wh)[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)j * d + k]);
     }
   }
 }
@@ -121,7 +120,7 @@ template <> struct HType<1> { typedef uint16_t T; };
 
 template <int PREC>
 __device__ __forceinline__ void h_store(typename HType<PREC>::T* p, float v) {
-  if constexpr (PREC == 0) *p = v; else *p = f32_to_bf16_rne(v);
+  if constexpr (PREC == 0) *p = v; else *p = bf16_bits(v);
 }
 template <int PREC>
 __device__ __forceinline__ float h_load(const typename HType<PREC>::T* p) {
@@ -165,8 +164,12 @@ __device__ __forceinline__ void hidden_layers_bf16(uint16_t* Hs, const u32x4* wh
       if (rb > 0) {
         uint16_t* op = Hs + ((rb - 1) * 32) * LDH + j;
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          op[acc_row(lane, v) * LDH] = f32_to_bf16_rne(tanh_fast(prev[v] + bj));
+        for (int v = 0; v < 16; v += 2) {
+          uint16_t h0, h1;
+          bf16_pair(tanh_fast(prev[v] + bj), tanh_fast(prev[v + 1] + bj), h0, h1);
+          op[acc_row(lane, v) * LDH] = h0;
+          op[acc_row(lane, v + 1) * LDH] = h1;
+        }
       }
       prev = acc;
       __syncthreads();
@@ -318,20 +321,24 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
   }
 
   // -- output layer and store -------------------------------------------------
+  // Eight threads per row, whatever the tile height, so a row's dot product
+  // is summed in the same order for every tile shape.
   {
-    constexpr int TPR = NTH / R;   // threads per row, a power of two <= 64
-    const int r = tid / TPR, part = tid % TPR;
-    float s = 0.0f;
-    for (int n = part; n < D; n += TPR) s = fmaf(h_load<PREC>(&Hs[r * LDH + n]), net.w5[n], s);
+    constexpr int TPR = 8;
+    const int part = tid % TPR;
+    for (int r = tid / TPR; r < R; r += NTH / TPR) {
+      float s = 0.0f;
+      for (int n = part; n < D; n += TPR) s = fmaf(h_load<PREC>(&Hs[r * LDH + n]), net.w5[n], s);
 #pragma unroll
-    for (int o = TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (part == 0) {
-      const int64_t addr = r_addr[r];
-      if (addr >= 0) {
-        const float val = s + net.b5[0];
-        if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
-        else if constexpr (OUT == OUT_ACCUM) A.u_out[addr] += val * r_w[r];
-        else A.U[addr] = val;
+      for (int o = TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      if (part == 0) {
+        const int64_t addr = r_addr[r];
+        if (addr >= 0) {
+          const float val = s + net.b5[0];
+          if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
+          else if constexpr (OUT == OUT_ACCUM) A.u_out[addr] += val * r_w[r];
+          else A.U[addr] = val;
+        }
       }
     }
   }

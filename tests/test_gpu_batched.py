@@ -38,11 +38,9 @@ def test_batch_equals_one_by_one(ctx, prec, targets):
         ux, uy = sizes[i]
         u = torch.from_numpy(f).cuda()
         uo = torch.empty_like(u)
-        ctx.tile_rows(prec, 64)            # same tile height as the batch uses here
-        try:
-            mf_solve(ctx, params, u, (int(ux), int(uy)), 6, targets=targets, prec=prec, u_out=uo)
-        finally:
-            ctx.tile_rows(prec, 0)
+        # the single domain may get another tile height than the batch; results
+        # do not depend on it
+        mf_solve(ctx, params, u, (int(ux), int(uy)), 6, targets=targets, prec=prec, u_out=uo)
         got = batch.field(i)
         torch.cuda.synchronize()
         assert torch.equal(got, u), i
