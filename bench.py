@@ -98,7 +98,7 @@ def main():
 
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import Context, MF_CROSS, MF_FP32, mf_solve
+    from paper_2308_14258_amd import Context, MF_CROSS, MF_FP32, mf_autotune, mf_solve
 
     if args.mode == "copy":
         n = args.copy_mb * (1 << 20) // 4
@@ -131,6 +131,9 @@ def main():
     u0 = torch.from_numpy(field).to(dev)
     u = u0.clone()
     u_out = torch.empty_like(u)
+
+    # tile height chosen by the autotuner on a scratch copy (outside the timed region)
+    tile_rows = mf_autotune(ctx, params, u0.clone(), (ux, uy), MF_CROSS, MF_FP32, trials=3)
 
     def step():
         u.copy_(u0)
@@ -186,7 +189,7 @@ def main():
                                "placements), SDNet width 256, GP ring data (l=2, seed 1), "
                                f"{K} CROSS sweeps + assembly",
                    "units": [ux, uy], "width": width, "sweeps": K, "targets": "cross",
-                   "evals_per_step": evals_per_step},
+                   "evals_per_step": evals_per_step, "tile_rows": tile_rows},
         "sweep_phase": {"launches": launches, "avg_launch_us": avg_us,
                         "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
@@ -294,7 +297,9 @@ def bf16_comparison(ctx, sweeps):
                        "+ assembly"}
     outs = {}
     evals = sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    from paper_2308_14258_amd import mf_autotune
     for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+        rows = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, prec, trials=2)
         u = field.clone()
         u_out = torch.empty_like(u)
         mf_solve(ctx, params, u, (ux, uy), 2, targets=MF_CROSS, prec=prec)   # warm-up + capture
@@ -311,7 +316,7 @@ def bf16_comparison(ctx, sweeps):
         fpp = flops_per_point(width, CROSS_T)
         peak = PEAK_FP32_MFMA_TFLOPS if prec == MF_FP32 else PEAK_BF16_MFMA_TFLOPS
         ach = rows * fpp / (ms * 1e-3) / 1e12
-        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt,
+        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt, "tile_rows": rows,
                      "phase_avg_us": ms * 1e3 / max(launches, 1),
                      "phase_tflops": ach, "phase_frac_of_mfma_peak": ach / peak}
         outs[name] = u_out.double()

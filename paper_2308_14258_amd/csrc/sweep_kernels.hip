@@ -178,6 +178,50 @@ __device__ __forceinline__ void hidden_layers_bf16(uint16_t* Hs, const u32x4* wh
 }
 
 // One tile: rows [row0, row0 + R) of the phase described by A.
+// The same pipeline with float32 operands: each wave holds its 32-column
+// weight slice as D/8 float4 MFMA operands (128 VGPRs at d = 256) for the
+// whole layer, so the k loop issues LDS reads and MFMAs only.
+template <int D, int R>
+__device__ __forceinline__ void hidden_layers_f32(float* Hs, const floatx4* wh, const float* bh, int lane,
+                                                  int wave) {
+  constexpr int RB = R / 32, KG = D / 8, LDH = D + 4;
+  const int arow = lane & 31, ahalf = lane >> 5;
+  const int j = wave * 32 + arow;
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    floatx4 breg[KG];
+    const floatx4* wsw = wh + (size_t)l * (D * D / 4) + (size_t)wave * KG * 64 + lane;
+#pragma unroll
+    for (int kg = 0; kg < KG; ++kg) breg[kg] = wsw[kg * 64];
+    const float bj = bh[l * D + j];
+    floatx16 prev;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) prev[v] = 0.0f;
+#pragma unroll 1
+    for (int rb = 0; rb <= RB; ++rb) {
+      floatx16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      if (rb < RB) {
+        const float* ap = Hs + (rb * 32 + arow) * LDH + 4 * ahalf;
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg) {
+          const floatx4 av = *reinterpret_cast<const floatx4*>(ap + kg * 8);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc = mfma32x32x2(av[e], breg[kg][e], acc);
+        }
+      }
+      if (rb > 0) {
+        float* op = Hs + ((rb - 1) * 32) * LDH + j;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) op[acc_row(lane, v) * LDH] = tanh_fast(prev[v] + bj);
+      }
+      prev = acc;
+      __syncthreads();
+    }
+  }
+}
+
 template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
 __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0) {
   constexpr int NTH = 2 * D;                 // one wave per 32 output columns
@@ -299,6 +343,8 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
   // -- hidden layers on MFMA --------------------------------------------------
   if constexpr (PREC == 1) {
     hidden_layers_bf16<D, R>(Hs, static_cast<const u32x4*>(net.wh), net.bh, lane, wave);
+  } else if constexpr (R >= 64) {
+    hidden_layers_f32<D, R>(Hs, static_cast<const floatx4*>(net.wh), net.bh, lane, wave);
   } else {
     const int arow = lane & 31;
     for (int l = 0; l < 3; ++l) {
