@@ -34,6 +34,25 @@ PEAK_BF16_MFMA_TFLOPS = 2516.6
 CROSS_T = 61
 INTERIOR_T = 961
 
+# HBM traffic of the colour-phase kernel per launch on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
+# what the same counters read for a plain 512 MiB device copy (FETCH_SIZE
+# reads half the copied bytes on this part: factor 2.0; WRITE_SIZE: 1.0). It is
+# reported only while the kernel sources hash to the value the counters were
+# taken with; otherwise "traffic" is null. Summary: profiles/*_traffic.md.
+MEASURED_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None}
+KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
+                  "paper_2308_14258_amd/csrc/mf_device.h")
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def flops_per_point(width: int, T: int) -> float:
     """Algorithmic flops of one SDNet evaluation in a phase with T targets per
@@ -194,7 +213,10 @@ def main():
                         "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": None,
+                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
+                                 if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha()
+                                 else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
                      "kernel": "tile_kernel<256,R,CROSS,FP32> (colour phase)",
                      "flops_per_point_eval": fpp},
         "parity": parity,
