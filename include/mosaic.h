@@ -161,7 +161,12 @@ mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom
  * in place at the chosen targets. All placements of a phase read the field
  * as it was before the phase: same-colour placements never write a point
  * that another same-colour placement reads, so the batch equals the
- * sequential order. n_domains must be 1 (mode MF_ADDITIVE is reserved).
+ * sequential order. mode MF_ADDITIVE replaces the four ordered phases by the
+ * parallel (Lions-type, Sec. 2.3) form: every placement reads the field
+ * before the sweep and each target point takes the mean of the predictions
+ * covering it (colour must then be -1). n_domains > 1 runs a batch of
+ * independent domains packed in one buffer (dom is an array; their element
+ * ranges must not overlap) with one launch per colour for the whole batch.
  * params: device, mf_param_count floats. ws: device workspace. */
 mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
                    float* u, const mf_domain_desc* dom, int32_t n_domains,

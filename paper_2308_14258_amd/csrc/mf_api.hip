@@ -71,6 +71,12 @@ SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_d
   S.dres = o; o = align256(o + 2 * (size_t)n_domains * 4);
   S.table = o;
   o = align256(o + (size_t)n_domains * sizeof(DomEntry) + 2 * 4 * ((size_t)n_domains + 1) * 4);
+  int64_t span = 0;
+  for (int d = 0; d < n_domains; ++d)
+    span = std::max<int64_t>(span, dom[d].field_offset + (32LL * dom[d].units_y) * dom[d].pitch +
+                                       32LL * dom[d].units_x + 1);
+  S.anext = o;
+  o = align256(o + (size_t)span * 4);
   S.total = o;
   return S;
 }
@@ -211,7 +217,7 @@ struct SweepGraph {
   const float* field;
   const void* ws;
   int64_t pitch;
-  int ux, uy, width, prec, targets, sweeps;
+  int ux, uy, width, prec, targets, mode, sweeps;
   uint64_t key;
   hipGraphExec_t exec;
 };
@@ -348,7 +354,6 @@ static mf_status sweep_common_checks(const mf_sdnet_desc* desc, const float* par
   MF_TRY(check_ptr(u, "u"));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
-  if (mode == MF_ADDITIVE) return fail(MF_EUNSUPPORTED, "additive sweeps are not implemented");
   *L = sweep_layout(desc->width, prec, dom, n_domains);
   MF_TRY(check_ws(ws, ws_bytes, L->total));
   return MF_OK;
@@ -387,9 +392,10 @@ struct Plan {
   int nd = 1;
   const mf_domain_desc* dom = nullptr;   // host descriptors
   float* u = nullptr;                    // caller's buffer (offsets are relative to it)
-  int width = 0, prec = 0, targets = 0;
+  int width = 0, prec = 0, targets = 0, mode = MF_MULTIPLICATIVE;
   NetPtrs net{};
   const void* ws = nullptr;
+  float* anext = nullptr;                         // additive: the next field
   const DomEntry* d_doms = nullptr;
   const int32_t* d_tb[2] = {nullptr, nullptr};   // [4][nd + 1]: sweep targets, assembly
   int R[2] = {0, 0};                              // tile rows (batched)
@@ -409,10 +415,12 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
   return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
 }
 
-static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int targets, float* u,
-                           const mf_domain_desc* dom, int nd, void* ws, const SweepLayout& L,
+static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int targets, int mode,
+                           float* u, const mf_domain_desc* dom, int nd, void* ws, const SweepLayout& L,
                            hipStream_t s, Plan* P) {
   P->nd = nd;
+  P->mode = mode;
+  P->anext = reinterpret_cast<float*>(static_cast<char*>(ws) + L.anext);
   P->dom = dom;
   P->u = u;
   P->width = desc->width;
@@ -456,28 +464,51 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
   return MF_OK;
 }
 
-// One colour phase of the plan: sweep (into u) or assembly accumulation
-// (into out). Timed when the context's timing is on and allow_timing is set.
-static mf_status run_colour(mf_ctx* ctx, const Plan& P, int colour, bool accumulate, float* out,
-                            hipStream_t s, bool allow_timing = true) {
-  const int a = accumulate ? 1 : 0;
+// One colour phase of the plan:
+//   PH_SWEEP     predictions stored into u at the plan's targets;
+//   PH_ASSEMBLY  INTERIOR predictions / cover count accumulated into out;
+//   PH_ADDITIVE  predictions at the plan's targets / cover count accumulated into out.
+// Sweep and additive phases are timed when the context's timing is on.
+enum { PH_SWEEP = 0, PH_ASSEMBLY = 1, PH_ADDITIVE = 2 };
+static mf_status run_colour(mf_ctx* ctx, const Plan& P, int colour, int kind, float* out, hipStream_t s,
+                            bool allow_timing = true) {
+  const int a = kind == PH_ASSEMBLY ? 1 : 0;
+  const int tg = kind == PH_ASSEMBLY ? MF_INTERIOR : P.targets;
+  const bool acc = kind != PH_SWEEP;
   const int64_t rows = P.rows[a][colour];
   if (rows == 0) return MF_OK;
-  const bool timed = allow_timing && ctx->timing && !accumulate;
+  const bool timed = allow_timing && ctx->timing && kind != PH_ASSEMBLY;
   if (timed) MF_TRY(timing_begin(ctx, s));
-  float* dst = accumulate ? out : P.u;
+  float* dst = acc ? out : P.u;
   if (P.nd == 1) {
     const mf_domain_desc* dom = P.dom;
     PhaseArgs p{P.u + dom->field_offset, dst + dom->field_offset, dom->pitch, dom->units_x,
                 dom->units_y, colour};
-    const int R = tile_rows_for(ctx, P.width, P.prec, accumulate ? MF_INTERIOR : P.targets, dom, 1, rows);
-    MF_HIP(launch_phase(P.net, P.width, P.prec, P.targets, accumulate, R, p, s));
+    const int R = tile_rows_for(ctx, P.width, P.prec, tg, dom, 1, rows);
+    MF_HIP(launch_phase(P.net, P.width, P.prec, tg, acc, R, p, s));
   } else {
-    MF_HIP(launch_phase_multi(P.net, P.width, P.prec, P.targets, accumulate, P.R[a], P.u, dst, P.d_doms,
+    MF_HIP(launch_phase_multi(P.net, P.width, P.prec, tg, acc, P.R[a], P.u, dst, P.d_doms,
                               P.d_tb[a] + colour * (P.nd + 1), P.nd, P.n_tiles[a][colour], colour,
                               ctx->n_cu, s));
   }
   if (timed) MF_TRY(timing_end(ctx, s, rows, 1));
+  return MF_OK;
+}
+
+// One sweep of the plan: the four colour phases in order (multiplicative),
+// or the additive form (all placements read u; targets take the mean).
+static mf_status run_sweep(mf_ctx* ctx, const Plan& P, hipStream_t s, bool allow_timing = true) {
+  if (P.mode == MF_MULTIPLICATIVE) {
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, allow_timing));
+    return MF_OK;
+  }
+  for (int d = 0; d < P.nd; ++d)
+    MF_HIP(launch_additive_init(P.u + P.dom[d].field_offset, P.anext + P.dom[d].field_offset, P.dom[d].pitch,
+                                P.dom[d].units_x, P.dom[d].units_y, P.targets, s));
+  for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ADDITIVE, P.anext, s, allow_timing));
+  for (int d = 0; d < P.nd; ++d)
+    MF_HIP(launch_additive_copy(P.anext + P.dom[d].field_offset, P.u + P.dom[d].field_offset, P.dom[d].pitch,
+                                P.dom[d].units_x, P.dom[d].units_y, P.targets, s));
   return MF_OK;
 }
 
@@ -489,7 +520,7 @@ static mf_status sweep_graph(mf_ctx* ctx, const Plan& P, int sweeps, hipGraphExe
   for (const SweepGraph& g : ctx->graphs) {
     if (g.field == P.u && g.ws == P.ws && g.pitch == pitch && g.ux == ux && g.uy == uy &&
         g.key == P.key && g.width == P.width && g.prec == P.prec && g.targets == P.targets &&
-        g.sweeps == sweeps) {
+        g.mode == P.mode && g.sweeps == sweeps) {
       *out = g.exec;
       return MF_OK;
     }
@@ -501,8 +532,7 @@ static mf_status sweep_graph(mf_ctx* ctx, const Plan& P, int sweeps, hipGraphExe
   hipGraph_t graph = nullptr;
   MF_HIP(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
   mf_status st = MF_OK;
-  for (int k = 0; k < sweeps && st == MF_OK; ++k)
-    for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, ctx->gstream, false);
+  for (int k = 0; k < sweeps && st == MF_OK; ++k) st = run_sweep(ctx, P, ctx->gstream, false);
   hipError_t e = hipStreamEndCapture(ctx->gstream, &graph);
   if (st != MF_OK) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -513,7 +543,8 @@ static mf_status sweep_graph(mf_ctx* ctx, const Plan& P, int sweeps, hipGraphExe
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(MF_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-  ctx->graphs.push_back(SweepGraph{P.u, P.ws, pitch, ux, uy, P.width, P.prec, P.targets, sweeps, P.key, exec});
+  ctx->graphs.push_back(SweepGraph{P.u, P.ws, pitch, ux, uy, P.width, P.prec, P.targets, P.mode, sweeps,
+                                   P.key, exec});
   *out = exec;
   return MF_OK;
 }
@@ -553,14 +584,19 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   SweepLayout L;
   MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, mode, prec, ws, ws_bytes, &L));
   if (colour < -1 || colour > 3) return fail(MF_EINVAL, "colour %d not in -1..3", colour);
+  if (mode == MF_ADDITIVE && colour != -1)
+    return fail(MF_EINVAL, "an additive sweep has no single colour phase (colour must be -1)");
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   Plan P;
-  MF_TRY(make_plan(ctx, desc, prec, targets, u, dom, n_domains, ws, L, s, &P));
-  for (int c = (colour < 0 ? 0 : colour); c <= (colour < 0 ? 3 : colour); ++c)
-    MF_TRY(run_colour(ctx, P, c, false, nullptr, s));
+  MF_TRY(make_plan(ctx, desc, prec, targets, mode, u, dom, n_domains, ws, L, s, &P));
+  if (colour < 0) {
+    MF_TRY(run_sweep(ctx, P, s));
+  } else {
+    MF_TRY(run_colour(ctx, P, colour, PH_SWEEP, nullptr, s));
+  }
   return ok();
 }
 
@@ -592,12 +628,11 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   for (int ci = 0; ci < n_cands && st == MF_OK; ++ci) {
     ctx->force_rows[prec] = cands[ci];
     Plan P;
-    st = make_plan(ctx, desc, prec, targets, u, dom, 1, ws, L, s, &P);
-    for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, s);   // warm-up
+    st = make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, 1, ws, L, s, &P);
+    if (st == MF_OK) st = run_sweep(ctx, P, s);   // warm-up
     if (st != MF_OK) break;
     if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MF_EDEVICE, "event record failed"); break; }
-    for (int k = 0; k < trials && st == MF_OK; ++k)
-      for (int c = 0; c < 4 && st == MF_OK; ++c) st = run_colour(ctx, P, c, false, nullptr, s);
+    for (int k = 0; k < trials && st == MF_OK; ++k) st = run_sweep(ctx, P, s);
     if (st != MF_OK) break;
     float ms = 0.0f;
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -686,7 +721,7 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   Plan P;
-  MF_TRY(make_plan(ctx, desc, prec, targets, u, dom, n_domains, ws, L, s, &P));
+  MF_TRY(make_plan(ctx, desc, prec, targets, mode, u, dom, n_domains, ws, L, s, &P));
 
   int done = 0;
   float last = NAN;
@@ -698,7 +733,7 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   for (int k = done + 1; k <= max_sweeps; ++k) {
     const bool check = eps > 0.0f && (k % check_every) == 0;
     if (check) MF_TRY(delta_snapshot(P, L, ws, s));
-    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, false, nullptr, s));
+    MF_TRY(run_sweep(ctx, P, s));
     done = k;
     if (check) {
       float num = 0.0f, den = 0.0f;
@@ -719,7 +754,7 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
     for (int d = 0; d < n_domains; ++d)
       MF_HIP(launch_assembly_init(u + dom[d].field_offset, u_out + dom[d].field_offset, dom[d].pitch,
                                   dom[d].units_x, dom[d].units_y, s));
-    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, true, u_out, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ASSEMBLY, u_out, s));
   }
   if (sweeps_done || last_delta) MF_HIP(hipStreamSynchronize(s));
   if (sweeps_done) *sweeps_done = done;
@@ -901,10 +936,10 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
       MF_HIP(hipMemcpyAsync(ckpt + (size_t)i * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
       const int n_s = std::min(ckpt_every, K - i * ckpt_every);
       for (int k = 0; k < n_s; ++k)
-        for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, false, nullptr, s, false));
+        for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
     }
     MF_HIP(launch_assembly_init(F, uo, D.pitch, D.units_x, D.units_y, s));
-    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, true, uo, s, false));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ASSEMBLY, uo, s, false));
     if (J) MF_HIP(launch_interior_sumsq(uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
     // reverse: assembly, then the sweeps segment by segment
     MF_HIP(launch_fill2d(ub, D.pitch, D.units_x, D.units_y, 0.0f, s));
@@ -917,7 +952,7 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
       for (int k = 0; k < n_s; ++k)
         for (int c = 0; c < 4; ++c) {
           MF_HIP(hipMemcpyAsync(states + (size_t)(4 * k + c) * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
-          MF_TRY(run_colour(ctx, P, c, false, nullptr, s, false));
+          MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
         }
       for (int k = n_s - 1; k >= 0; --k)
         for (int c = 3; c >= 0; --c)

@@ -47,6 +47,7 @@ struct SweepLayout {
   size_t part = 0;     // float [n_domains][2][kDeltaBlocks]
   size_t dres = 0;     // float [n_domains][2]
   size_t table = 0;    // batched domains: DomEntry [n] + int32 tile prefixes [2][4][n + 1]
+  size_t anext = 0;    // additive sweeps: the next field, laid out like the caller's buffer
   size_t total = 0;
 };
 constexpr int kDeltaBlocks = 512;
@@ -69,6 +70,10 @@ hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bo
 int pick_tile_rows(int width, int prec, int targets, int64_t rows, int n_cu);
 
 hipError_t launch_assembly_init(const float* u, float* u_out, int64_t pitch, int ux, int uy,
+                                hipStream_t s);
+hipError_t launch_additive_init(const float* u, float* un, int64_t pitch, int ux, int uy, int targets,
+                                hipStream_t s);
+hipError_t launch_additive_copy(const float* un, float* u, int64_t pitch, int ux, int uy, int targets,
                                 hipStream_t s);
 hipError_t launch_skeleton_snapshot(const float* u, int64_t pitch, int ux, int uy, float* skel,
                                     hipStream_t s);

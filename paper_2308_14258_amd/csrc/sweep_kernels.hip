@@ -452,7 +452,9 @@ static hipError_t launch_multi(const MultiArgs& m, int n_cu, hipStream_t s) {
 template <int D, int R, int PREC>
 static hipError_t dispatch_multi(const MultiArgs& m, int targets, bool accumulate, int n_cu,
                                  hipStream_t s) {
-  if (accumulate) return launch_multi<D, R, 1, PREC, OUT_ACCUM>(m, n_cu, s);
+  if (accumulate)
+    return targets == MF_CROSS ? launch_multi<D, R, 0, PREC, OUT_ACCUM>(m, n_cu, s)
+                               : launch_multi<D, R, 1, PREC, OUT_ACCUM>(m, n_cu, s);
   if (targets == MF_CROSS) return launch_multi<D, R, 0, PREC, OUT_STORE>(m, n_cu, s);
   return launch_multi<D, R, 1, PREC, OUT_STORE>(m, n_cu, s);
 }
@@ -498,7 +500,9 @@ static hipError_t launch_tile(const TileArgs& a, hipStream_t s) {
 
 template <int D, int R, int PREC>
 static hipError_t dispatch_phase(const TileArgs& a, int targets, bool accumulate, hipStream_t s) {
-  if (accumulate) return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_ACCUM>(a, s);
+  if (accumulate)
+    return targets == MF_CROSS ? launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_ACCUM>(a, s)
+                               : launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_ACCUM>(a, s);
   if (targets == MF_CROSS) return launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_STORE>(a, s);
   return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_STORE>(a, s);
 }
@@ -527,7 +531,7 @@ hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bo
   a.ux = p.ux;
   a.uy = p.uy;
   a.colour = p.colour;
-  const int T = (accumulate || targets == MF_INTERIOR) ? kInterior : kCross;
+  const int T = targets == MF_INTERIOR ? kInterior : kCross;
   a.total_rows = colour_count(p.ux, p.uy, p.colour) * T;
   if (a.total_rows == 0) return hipSuccess;
   if (prec == MF_BF16) {
@@ -629,6 +633,61 @@ hipError_t launch_assembly_init(const float* u, float* u_out, int64_t pitch, int
   const int64_t n = (int64_t)nx * ny;
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(assembly_init_kernel, dim3(blocks), dim3(256), 0, s, u, u_out, pitch, nx, ny);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Additive (parallel Schwarz) sweep: every placement reads the old field u and
+// the targets of the new field take the mean of the predictions covering
+// them. A target point is covered 1 / (cover_inv(i) cover_inv(j)) times for
+// either target set, so the colour phases accumulate pred * cover_inv^2 into
+// un, which starts as u with its target points zeroed; then the targets are
+// copied back into u.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool is_target_point(int i, int j, int nx, int ny, int interior) {
+  const bool inner = i > 0 && j > 0 && i < nx - 1 && j < ny - 1;
+  return inner && (interior || (i & 15) == 0 || (j & 15) == 0);
+}
+
+__global__ void additive_init_kernel(const float* __restrict__ u, float* __restrict__ un, int64_t pitch,
+                                     int nx, int ny, int interior) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nx), i = (int)(idx - (int64_t)j * nx);
+    const int64_t o = (int64_t)j * pitch + i;
+    un[o] = is_target_point(i, j, nx, ny, interior) ? 0.0f : u[o];
+  }
+}
+
+__global__ void additive_copy_kernel(const float* __restrict__ un, float* __restrict__ u, int64_t pitch,
+                                     int nx, int ny, int interior) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nx), i = (int)(idx - (int64_t)j * nx);
+    if (is_target_point(i, j, nx, ny, interior)) {
+      const int64_t o = (int64_t)j * pitch + i;
+      u[o] = un[o];
+    }
+  }
+}
+
+hipError_t launch_additive_init(const float* u, float* un, int64_t pitch, int ux, int uy, int targets,
+                                hipStream_t s) {
+  const int nx = kS * ux + 1, ny = kS * uy + 1;
+  const int blocks = (int)std::min<int64_t>(((int64_t)nx * ny + 255) / 256, 4096);
+  hipLaunchKernelGGL(additive_init_kernel, dim3(blocks), dim3(256), 0, s, u, un, pitch, nx, ny,
+                     targets == MF_INTERIOR ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_additive_copy(const float* un, float* u, int64_t pitch, int ux, int uy, int targets,
+                                hipStream_t s) {
+  const int nx = kS * ux + 1, ny = kS * uy + 1;
+  const int blocks = (int)std::min<int64_t>(((int64_t)nx * ny + 255) / 256, 4096);
+  hipLaunchKernelGGL(additive_copy_kernel, dim3(blocks), dim3(256), 0, s, un, u, pitch, nx, ny,
+                     targets == MF_INTERIOR ? 1 : 0);
   return hipGetLastError();
 }
 

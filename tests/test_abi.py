@@ -116,7 +116,9 @@ def test_sweep_argument_errors(lib):
     assert b"ctx" in lib.mf_last_error()               # a valid batch gets as far as the ctx
     assert _sweep(lib, colour=4) == MF_EINVAL
     assert _sweep(lib, targets=3) == MF_EINVAL
-    assert _sweep(lib, mode=1) == MF_EUNSUPPORTED
+    assert _sweep(lib, mode=1) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # additive is valid
+    assert _sweep(lib, mode=1, colour=2) == MF_EINVAL and b"additive" in lib.mf_last_error()
+    assert _sweep(lib, mode=2) == MF_EINVAL
     assert _sweep(lib, prec=2) == MF_EINVAL
     assert _sweep(lib, ws=0) == MF_EINVAL
     assert _sweep(lib, ws=FAKE + 64) == MF_EINVAL

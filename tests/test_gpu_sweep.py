@@ -334,3 +334,36 @@ def test_autotune_picks_a_candidate_and_is_used(ctx):
     ctx.tile_rows(MF_BF16, 0)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("units,width,targets", [((2, 2), 128, MF_CROSS), ((3, 2), 256, MF_CROSS),
+                                                 ((2, 3), 128, MF_INTERIOR), ((1, 1), 256, MF_INTERIOR)])
+def test_additive_sweep_matches_oracle(ctx, units, width, targets):
+    print(f"case: additive sweep units={units} width={width} targets={targets}", flush=True)
+    from paper_2308_14258_amd import MF_ADDITIVE
+    ux, uy = units
+    params = mi.random_params(width, seed=17)
+    f = mi.random_interior_field(ux, uy, seed=3)
+    u = dev(f)
+    mf_sweep(ctx, dev(params), u, units, -1, targets, MF_FP32, mode=MF_ADDITIVE)
+    kind = "cross" if targets == MF_CROSS else "interior"
+    want = sw.sweep_additive(torch.from_numpy(f.astype(np.float64)), ux, uy,
+                             oracle_solver(params, width), kind)
+    ny, nx = f.shape
+    m = skel_interior_mask(ny, nx) if targets == MF_CROSS else interior_mask(ny, nx)
+    assert rel_l2(u.cpu().numpy(), want.numpy(), m) <= 1e-5
+    np.testing.assert_array_equal(u.cpu().numpy()[~m], f[~m])
+
+
+def test_additive_solve_c1(ctx):
+    print("case: additive solve C1", flush=True)
+    from paper_2308_14258_amd import MF_ADDITIVE
+    params = mi.xavier_params(128, 0)
+    f = mi.workload_field("C1")
+    u = dev(f)
+    u_out = torch.empty_like(u)
+    mf_solve(ctx, dev(params), u, (2, 2), 20, u_out=u_out, mode=MF_ADDITIVE)
+    uK, uo, _, _ = sw.solve(torch.from_numpy(f.astype(np.float64)), 2, 2, oracle_solver(params, 128), 20,
+                            mode="additive")
+    assert rel_l2(u.cpu().numpy(), uK.numpy(), skel_interior_mask(65, 65)) <= 1e-5
+    assert rel_l2(u_out.cpu().numpy(), uo.numpy(), interior_mask(65, 65)) <= 1e-5
