@@ -75,3 +75,18 @@ def test_batch_delta_and_sweep(ctx):
         mf_sweep(ctx, params, b)
     torch.cuda.synchronize()
     assert torch.equal(a.buf, b.buf)
+
+
+def test_batch_additive_equals_one_by_one(ctx):
+    print("case: batch additive vs single", flush=True)
+    from paper_2308_14258_amd import MF_ADDITIVE
+    sizes, fields = _fields(seed=5, n=4, lo=1, hi=4)
+    params = torch.from_numpy(mi.random_params(128, seed=8)).cuda()
+    batch = Batch(fields)
+    mf_solve(ctx, params, batch, None, 5, mode=MF_ADDITIVE)
+    for i, f in enumerate(fields):
+        ux, uy = (int(v) for v in sizes[i])
+        u = torch.from_numpy(f).cuda()
+        mf_solve(ctx, params, u, (ux, uy), 5, mode=MF_ADDITIVE)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.field(i), u), i
