@@ -152,6 +152,21 @@ def assemble(u: torch.Tensor, ux: int, uy: int, solver) -> torch.Tensor:
     return _average_into(u, plist, tgts, pred)
 
 
+def assemble_at(u: torch.Tensor, ux: int, uy: int, solver, points) -> torch.Tensor:
+    """The assembly (Alg. 2, final phase) at chosen interior grid points only:
+    for each (j, i), the mean of SDNet's predictions there over every
+    placement whose interior contains the point."""
+    vals = []
+    for (j, i) in points:
+        preds = []
+        for (a, b) in geo.placements(ux, uy):
+            ti, tj = i - geo.HALF * a, j - geo.HALF * b
+            if 0 < ti < geo.S and 0 < tj < geo.S:
+                preds.append(solver(gather(u, [(a, b)]), [(ti, tj)])[0, 0])
+        vals.append(torch.stack(preds).mean())
+    return torch.stack(vals)
+
+
 def solve(u0: torch.Tensor, ux: int, uy: int, solver, max_sweeps: int, eps: float = 0.0,
           check_every: int = 1, kind: str = "cross", mode: str = "multiplicative",
           trajectory: list | None = None, assemble_out: bool = True):

@@ -151,7 +151,10 @@ static mf_status check_desc(const mf_sdnet_desc* d) {
 }
 
 static bool valid_tile_rows(int prec, int rows) {
-  return prec == MF_FP32 ? (rows == 32 || rows == 64) : (rows == 64 || rows == 128 || rows == 256);
+  if (prec == MF_FP32) return rows == 32 || rows == 64;
+  const int r = rows & ~MF_TILE_WIDE;
+  if (rows & MF_TILE_WIDE) return r == 128 || r == 256;
+  return r == 64 || r == 128 || r == 256;
 }
 
 static mf_status check_prec(int prec) {
@@ -449,7 +452,8 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
       int64_t acc = 0;
       for (int d = 0; d < nd; ++d) {
         tb[d] = (int32_t)acc;
-        acc += (phase_rows(&dom[d], c, tg) + P->R[a] - 1) / P->R[a];
+        const int rows_per_tile = P->R[a] & ~MF_TILE_WIDE;
+        acc += (phase_rows(&dom[d], c, tg) + rows_per_tile - 1) / rows_per_tile;
       }
       if (acc > INT32_MAX) return fail(MF_ESHAPE, "batch has too many tiles");
       tb[nd] = (int32_t)acc;
@@ -613,9 +617,9 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   const int cands_fp32[] = {32, 64};
-  const int cands_bf16[] = {64, 128, 256};
+  const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE};
   const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
-  const int n_cands = prec == MF_FP32 ? 2 : 3;
+  const int n_cands = prec == MF_FP32 ? 2 : 5;
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;

@@ -133,51 +133,63 @@ __device__ __forceinline__ float h_load(const typename HType<PREC>::T* p) {
 // one barrier per block, so the tanh epilogue of block rb-1 (written back
 // in place: every wave has finished reading those rows once it passed the
 // previous barrier) overlaps the MFMAs of block rb.
-template <int D, int R>
+template <int D, int R, int CPW>
 __device__ __forceinline__ void hidden_layers_bf16(uint16_t* Hs, const u32x4* wh, const float* bh,
                                                    int lane, int wave) {
-  constexpr int RB = R / 32, KG = D / 16, LDH = D + 8;
+  constexpr int RB = R / 32, KG = D / 16, LDH = D + 8, NCB = CPW / 32;
   const int arow = lane & 31, ahalf = lane >> 5;
-  const int j = wave * 32 + arow;
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
-    bf16x8 breg[KG];
-    const u32x4* wsw = wh + (size_t)l * (D * D / 8) + (size_t)wave * KG * 64 + lane;
+    bf16x8 breg[NCB][KG];
+    float bj[NCB];
 #pragma unroll
-    for (int kg = 0; kg < KG; ++kg) breg[kg] = __builtin_bit_cast(bf16x8, wsw[kg * 64]);
-    const float bj = bh[l * D + j];
-    floatx16 prev;
+    for (int cb = 0; cb < NCB; ++cb) {
+      const u32x4* wsw = wh + (size_t)l * (D * D / 8) + (size_t)(wave * NCB + cb) * KG * 64 + lane;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) prev[v] = 0.0f;
+      for (int kg = 0; kg < KG; ++kg) breg[cb][kg] = __builtin_bit_cast(bf16x8, wsw[kg * 64]);
+      bj[cb] = bh[l * D + (wave * NCB + cb) * 32 + arow];
+    }
+    floatx16 prev[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) prev[cb][v] = 0.0f;
 #pragma unroll 1
     for (int rb = 0; rb <= RB; ++rb) {
-      floatx16 acc;
+      floatx16 acc[NCB];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
       if (rb < RB) {
         const uint16_t* ap = Hs + (rb * 32 + arow) * LDH + 8 * ahalf;
 #pragma unroll
-        for (int kg = 0; kg < KG; ++kg)
-          acc = mfma32x32x16_bf16(
-              __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + kg * 16)), breg[kg], acc);
-      }
-      if (rb > 0) {
-        uint16_t* op = Hs + ((rb - 1) * 32) * LDH + j;
+        for (int kg = 0; kg < KG; ++kg) {
+          const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + kg * 16));
 #pragma unroll
-        for (int v = 0; v < 16; v += 2) {
-          uint16_t h0, h1;
-          bf16_pair(tanh_fast(prev[v] + bj), tanh_fast(prev[v + 1] + bj), h0, h1);
-          op[acc_row(lane, v) * LDH] = h0;
-          op[acc_row(lane, v + 1) * LDH] = h1;
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma32x32x16_bf16(av, breg[cb][kg], acc[cb]);
         }
       }
-      prev = acc;
+      if (rb > 0) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          uint16_t* op = Hs + ((rb - 1) * 32) * LDH + (wave * NCB + cb) * 32 + arow;
+#pragma unroll
+          for (int v = 0; v < 16; v += 2) {
+            uint16_t h0, h1;
+            bf16_pair(tanh_fast(prev[cb][v] + bj[cb]), tanh_fast(prev[cb][v + 1] + bj[cb]), h0, h1);
+            op[acc_row(lane, v) * LDH] = h0;
+            op[acc_row(lane, v + 1) * LDH] = h1;
+          }
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) prev[cb] = acc[cb];
       __syncthreads();
     }
   }
 }
 
-// One tile: rows [row0, row0 + R) of the phase described by A.
 // The same pipeline with float32 operands: each wave holds its 32-column
 // weight slice as D/8 float4 MFMA operands (128 VGPRs at d = 256) for the
 // whole layer, so the k loop issues LDS reads and MFMAs only.
@@ -222,9 +234,10 @@ __device__ __forceinline__ void hidden_layers_f32(float* Hs, const floatx4* wh, 
   }
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
+template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
 __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0) {
-  constexpr int NTH = 2 * D;                 // one wave per 32 output columns
+  static_assert(CPW == 32 || (CPW == 64 && PREC == 1), "64 columns per wave: bf16 only");
+  constexpr int NTH = (D / CPW) * 64;        // one wave per CPW output columns
   constexpr int RB = R / 32;                 // 32-row MFMA blocks per tile
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = SRC == SRC_GATHER ? (R - 1) / T + 2 : 1;
@@ -251,7 +264,8 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
     q0 = row0 / T;
     np = (int)(last / T - q0 + 1);
   }
-  if (tid < R) {
+  for (int rt = tid; rt < R; rt += NTH) {
+    const int tid = rt;
     const int64_t row = row0 + tid;
     const bool valid = row < A.total_rows;
     const int64_t rr = valid ? row : A.total_rows - 1;
@@ -327,7 +341,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
     const int n = tid & (D - 1);
     const float wx = net.w1x[2 * n], wy = net.w1x[2 * n + 1];
     const float bb = net.b1[n];
-    for (int r = tid / D; r < R; r += 2) {
+    for (int r = tid / D; r < R; r += NTH / D) {
       float c;
       if constexpr (SRC == SRC_GATHER) {
         c = cs[r_slot[r] * D + n] + bb;
@@ -342,7 +356,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
 
   // -- hidden layers on MFMA --------------------------------------------------
   if constexpr (PREC == 1) {
-    hidden_layers_bf16<D, R>(Hs, static_cast<const u32x4*>(net.wh), net.bh, lane, wave);
+    hidden_layers_bf16<D, R, CPW>(Hs, static_cast<const u32x4*>(net.wh), net.bh, lane, wave);
   } else if constexpr (R >= 64) {
     hidden_layers_f32<D, R>(Hs, static_cast<const floatx4*>(net.wh), net.bh, lane, wave);
   } else {
@@ -390,9 +404,9 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
   }
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
-__global__ __launch_bounds__(2 * D) void tile_kernel(TileArgs A) {
-  tile_body<D, R, TMODE, PREC, SRC, OUT>(A, (int64_t)blockIdx.x * R);
+template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
+__global__ __launch_bounds__((D / CPW) * 64) void tile_kernel(TileArgs A) {
+  tile_body<D, R, TMODE, PREC, SRC, OUT, CPW>(A, (int64_t)blockIdx.x * R);
 }
 
 // Batched independent domains in one persistent launch per colour: block b
@@ -409,8 +423,8 @@ struct MultiArgs {
   int64_t n_tiles;
 };
 
-template <int D, int R, int TMODE, int PREC, int OUT>
-__global__ __launch_bounds__(2 * D) void tile_kernel_multi(MultiArgs M) {
+template <int D, int R, int TMODE, int PREC, int OUT, int CPW = 32>
+__global__ __launch_bounds__((D / CPW) * 64) void tile_kernel_multi(MultiArgs M) {
   constexpr int T = n_targets<TMODE>();
   const int ca = M.base.colour & 1, cb = M.base.colour >> 1;
   for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
@@ -427,36 +441,37 @@ __global__ __launch_bounds__(2 * D) void tile_kernel_multi(MultiArgs M) {
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    tile_body<D, R, TMODE, PREC, SRC_GATHER, OUT>(A, (t - M.tile_begin[lo]) * R);
+    tile_body<D, R, TMODE, PREC, SRC_GATHER, OUT, CPW>(A, (t - M.tile_begin[lo]) * R);
     __syncthreads();   // the next tile reuses the LDS
   }
 }
 
-template <int D, int R, int TMODE, int PREC, int OUT>
+template <int D, int R, int TMODE, int PREC, int OUT, int CPW = 32>
 static hipError_t launch_multi(const MultiArgs& m, int n_cu, hipStream_t s) {
   if (m.n_tiles == 0) return hipSuccess;
+  constexpr int NTH = (D / CPW) * 64;
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<D, R, TMODE, PREC, OUT>,
-                                                     2 * D, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<D, R, TMODE, PREC, OUT, CPW>,
+                                                     NTH, 0) != hipSuccess || nb < 1)
       nb = 1;
     per_cu = nb;
   }
   const int64_t grid = std::min<int64_t>(m.n_tiles, (int64_t)per_cu * n_cu);
-  hipLaunchKernelGGL((tile_kernel_multi<D, R, TMODE, PREC, OUT>), dim3((unsigned)grid), dim3(2 * D), 0,
+  hipLaunchKernelGGL((tile_kernel_multi<D, R, TMODE, PREC, OUT, CPW>), dim3((unsigned)grid), dim3(NTH), 0,
                      s, m);
   return hipGetLastError();
 }
 
-template <int D, int R, int PREC>
+template <int D, int R, int PREC, int CPW = 32>
 static hipError_t dispatch_multi(const MultiArgs& m, int targets, bool accumulate, int n_cu,
                                  hipStream_t s) {
   if (accumulate)
-    return targets == MF_CROSS ? launch_multi<D, R, 0, PREC, OUT_ACCUM>(m, n_cu, s)
-                               : launch_multi<D, R, 1, PREC, OUT_ACCUM>(m, n_cu, s);
-  if (targets == MF_CROSS) return launch_multi<D, R, 0, PREC, OUT_STORE>(m, n_cu, s);
-  return launch_multi<D, R, 1, PREC, OUT_STORE>(m, n_cu, s);
+    return targets == MF_CROSS ? launch_multi<D, R, 0, PREC, OUT_ACCUM, CPW>(m, n_cu, s)
+                               : launch_multi<D, R, 1, PREC, OUT_ACCUM, CPW>(m, n_cu, s);
+  if (targets == MF_CROSS) return launch_multi<D, R, 0, PREC, OUT_STORE, CPW>(m, n_cu, s);
+  return launch_multi<D, R, 1, PREC, OUT_STORE, CPW>(m, n_cu, s);
 }
 
 hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
@@ -472,6 +487,14 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
   m.tile_begin = tile_begin;
   m.n_domains = n_domains;
   m.n_tiles = n_tiles;
+  if (prec == MF_BF16 && (tile_rows & MF_TILE_WIDE)) {
+    const int r = tile_rows & ~MF_TILE_WIDE;
+    if (width == 256)
+      return r == 256 ? dispatch_multi<256, 256, 1, 64>(m, targets, accumulate, n_cu, s)
+                      : dispatch_multi<256, 128, 1, 64>(m, targets, accumulate, n_cu, s);
+    return r == 256 ? dispatch_multi<128, 256, 1, 64>(m, targets, accumulate, n_cu, s)
+                    : dispatch_multi<128, 128, 1, 64>(m, targets, accumulate, n_cu, s);
+  }
   if (prec == MF_BF16) {
     if (width == 256) {
       if (tile_rows == 256) return dispatch_multi<256, 256, 1>(m, targets, accumulate, n_cu, s);
@@ -489,22 +512,22 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
                          : dispatch_multi<128, 32, 0>(m, targets, accumulate, n_cu, s);
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT>
+template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
 static hipError_t launch_tile(const TileArgs& a, hipStream_t s) {
   const int64_t blocks = (a.total_rows + R - 1) / R;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((tile_kernel<D, R, TMODE, PREC, SRC, OUT>), dim3((unsigned)blocks),
-                     dim3(2 * D), 0, s, a);
+  hipLaunchKernelGGL((tile_kernel<D, R, TMODE, PREC, SRC, OUT, CPW>), dim3((unsigned)blocks),
+                     dim3((D / CPW) * 64), 0, s, a);
   return hipGetLastError();
 }
 
-template <int D, int R, int PREC>
+template <int D, int R, int PREC, int CPW = 32>
 static hipError_t dispatch_phase(const TileArgs& a, int targets, bool accumulate, hipStream_t s) {
   if (accumulate)
-    return targets == MF_CROSS ? launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_ACCUM>(a, s)
-                               : launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_ACCUM>(a, s);
-  if (targets == MF_CROSS) return launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_STORE>(a, s);
-  return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_STORE>(a, s);
+    return targets == MF_CROSS ? launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_ACCUM, CPW>(a, s)
+                               : launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_ACCUM, CPW>(a, s);
+  if (targets == MF_CROSS) return launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_STORE, CPW>(a, s);
+  return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_STORE, CPW>(a, s);
 }
 
 static int64_t colour_count(int ux, int uy, int colour) {
@@ -534,6 +557,14 @@ hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bo
   const int T = targets == MF_INTERIOR ? kInterior : kCross;
   a.total_rows = colour_count(p.ux, p.uy, p.colour) * T;
   if (a.total_rows == 0) return hipSuccess;
+  if (prec == MF_BF16 && (tile_rows & MF_TILE_WIDE)) {
+    const int r = tile_rows & ~MF_TILE_WIDE;
+    if (width == 256)
+      return r == 256 ? dispatch_phase<256, 256, 1, 64>(a, targets, accumulate, s)
+                      : dispatch_phase<256, 128, 1, 64>(a, targets, accumulate, s);
+    return r == 256 ? dispatch_phase<128, 256, 1, 64>(a, targets, accumulate, s)
+                    : dispatch_phase<128, 128, 1, 64>(a, targets, accumulate, s);
+  }
   if (prec == MF_BF16) {
     if (width == 256) {
       if (tile_rows == 256) return dispatch_phase<256, 256, 1>(a, targets, accumulate, s);

@@ -7,6 +7,8 @@ seeded inputs of ``mf_inputs``; nothing is read from the HIP path.
 
 c3_train.npz -- the training workload: full-batch gradient at the initial
     parameters and the loss curve of 100 Adam steps.
+c4_fp64.npz -- 64 x 64 units, 500 sweeps: sampled skeleton values and
+    sampled assembly points.
 c2_fp32.npz -- 16 x 16 units, width 256, GP ring data (length 2, seed 1),
     Xavier weights seed 0, 200 CROSS sweeps then the assembly. Holds the
     skeleton after 20 and 200 sweeps and u_out at 8192 sampled interior
@@ -90,7 +92,42 @@ def c3():
     print(f"c3: done in {time.time() - t0:.0f} s", flush=True)
 
 
-JOBS = {"c2": c2, "c3": c3}
+def c4():
+    """64 x 64 units (2049^2 grid), width 256, e^x sin y ring data, Xavier
+    seed 0, 500 CROSS sweeps: 32768 sampled skeleton values after 20 and 500
+    sweeps and the assembly at 2048 sampled interior points (seed 321)."""
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    field = mi.workload_field("C4")
+    params = mi.xavier_params(w["width"], seed=0)
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), w["width"])
+    u = torch.from_numpy(field.astype(np.float64))
+    mask = sw.skeleton_mask(*field.shape).numpy()
+    sj, si = np.nonzero(mask)
+    rng = np.random.default_rng(321)
+    pick = rng.choice(sj.size, 32768, replace=False)
+    sj, si = sj[pick], si[pick]
+    t0 = time.time()
+    skel20 = None
+    for k in range(1, w["sweeps"] + 1):
+        u = sw.sweep(u, ux, uy, solver)
+        if k == 20:
+            skel20 = u.numpy()[sj, si].copy()
+        if k % 10 == 0:
+            print(f"c4: sweep {k} ({time.time() - t0:.0f} s)", flush=True)
+    skel500 = u.numpy()[sj, si].copy()
+    ny, nx = field.shape
+    aj = rng.integers(1, ny - 1, 2048)
+    ai = rng.integers(1, nx - 1, 2048)
+    u_out = sw.assemble_at(u, ux, uy, solver, list(zip(aj.tolist(), ai.tolist()))).numpy()
+    np.savez_compressed(os.path.join(HERE, "c4_fp64.npz"), skel_j=sj.astype(np.int32),
+                        skel_i=si.astype(np.int32), skel20=skel20, skel500=skel500,
+                        sample_j=aj.astype(np.int32), sample_i=ai.astype(np.int32),
+                        u_out_sample=u_out, field_sha=_sha(field), params_sha=_sha(params))
+    print(f"c4: done in {time.time() - t0:.0f} s", flush=True)
+
+
+JOBS = {"c2": c2, "c3": c3, "c4": c4}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)

@@ -295,7 +295,8 @@ def test_graph_replay_equals_direct_launches(ctx):
 
 
 @pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_BF16, 64),
-                                       (MF_BF16, 128), (MF_BF16, 256)])
+                                       (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
+                                       (MF_BF16, 256 | (1 << 16))])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
 def test_every_tile_height(ctx, prec, rows, targets):
     print(f"case: tile rows {rows} prec {prec} targets {targets}", flush=True)

@@ -201,3 +201,15 @@ def test_assembly_average_of_equal_predictions():
     out = sw.assemble(exact, 3, 2, fd.operator_solver())
     assert torch.max(torch.abs(out - exact)) <= 1e-13
     assert torch.equal(out[0], f[0])
+
+
+def test_assemble_at_matches_full_assembly():
+    d = 16
+    th = torch.from_numpy(mi.random_params(d, 12).astype(np.float64))
+    solver = sw.sdnet_solver(th, d)
+    u = _field(mi.random_interior_field(3, 2, seed=4))
+    full = sw.assemble(u, 3, 2, solver)
+    pts = [(1, 1), (16, 16), (17, 40), (32, 33), (63, 95), (20, 48)]
+    part = sw.assemble_at(u, 3, 2, solver, pts)
+    want = torch.stack([full[j, i] for (j, i) in pts])
+    assert torch.max(torch.abs(part - want)) <= 1e-13
