@@ -9,6 +9,11 @@ c3_train.npz -- the training workload: full-batch gradient at the initial
     parameters and the loss curve of 100 Adam steps.
 c4_fp64.npz -- 64 x 64 units, 500 sweeps: sampled skeleton values and
     sampled assembly points.
+c4_one_sweep.npz -- the same 64 x 64-unit problem after ONE sweep from the
+    initial field: the skeleton at the c4 sample points and the assembly of
+    that state at the c4 assembly points (a full-size check of the sweep map
+    that does not pass through the early transient, where an untrained
+    network amplifies float32 rounding differences by orders of magnitude).
 c2_fp32.npz -- 16 x 16 units, width 256, GP ring data (length 2, seed 1),
     Xavier weights seed 0, 200 CROSS sweeps then the assembly. Holds the
     skeleton after 20 and 200 sweeps and u_out at 8192 sampled interior
@@ -127,7 +132,26 @@ def c4():
     print(f"c4: done in {time.time() - t0:.0f} s", flush=True)
 
 
-JOBS = {"c2": c2, "c3": c3, "c4": c4}
+def c4_one():
+    """One sweep of the 64 x 64-unit workload from its initial field, sampled
+    at the c4 points (which it reads from c4_fp64.npz, itself oracle output)."""
+    g = np.load(os.path.join(HERE, "c4_fp64.npz"))
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    field = mi.workload_field("C4")
+    params = mi.xavier_params(w["width"], seed=0)
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), w["width"])
+    t0 = time.time()
+    u1 = sw.sweep(torch.from_numpy(field.astype(np.float64)), ux, uy, solver)
+    skel1 = u1.numpy()[g["skel_j"], g["skel_i"]].copy()
+    pts = list(zip(g["sample_j"].tolist(), g["sample_i"].tolist()))
+    out1 = sw.assemble_at(u1, ux, uy, solver, pts).numpy()
+    np.savez_compressed(os.path.join(HERE, "c4_one_sweep.npz"), skel1=skel1, u_out_sample=out1,
+                        field_sha=_sha(field), params_sha=_sha(params))
+    print(f"c4_one: done in {time.time() - t0:.0f} s", flush=True)
+
+
+JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)
