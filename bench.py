@@ -34,13 +34,14 @@ PEAK_BF16_MFMA_TFLOPS = 2516.6
 CROSS_T = 61
 INTERIOR_T = 961
 
-# HBM traffic of the colour-phase kernel per launch on this workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
-# what the same counters read for a plain 512 MiB device copy (FETCH_SIZE
-# reads half the copied bytes on this part: factor 2.0; WRITE_SIZE: 1.0). It is
-# reported only while the kernel sources hash to the value the counters were
-# taken with; otherwise "traffic" is null. Summary: profiles/*_traffic.md.
-MEASURED_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None}
+# HBM traffic of the colour-phase kernel per launch on this workload, by tile
+# shape, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per
+# dispatch) scaled by what the same counters read for a plain 512 MiB device
+# copy (FETCH_SIZE reads half the copied bytes on this part: factor 2.0;
+# WRITE_SIZE: 1.0). It is reported only while the kernel sources hash to the
+# value the counters were taken with; otherwise "traffic" is null. Summary:
+# profiles/*_traffic.md.
+MEASURED_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": {}}
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
 
@@ -108,6 +109,7 @@ def main():
                     help="also time the 48-domain batch (BF16 sweeps + FP32 adjoint); its GP "
                          "inputs take about a minute to generate on the host")
     ap.add_argument("--only-c5", action="store_true")
+    ap.add_argument("--only-train", action="store_true", help="only the training-step measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
@@ -129,10 +131,14 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
         return
 
-    if args.only_bf16 or args.only_c5:
+    if args.only_bf16 or args.only_c5 or args.only_train:
         ctx = Context(0)
-        out = {"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)} if args.only_bf16 else \
-            {"batched": batched_measurement(ctx)}
+        if args.only_bf16:
+            out = {"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)}
+        elif args.only_c5:
+            out = {"batched": batched_measurement(ctx)}
+        else:
+            out = {"train": train_measurement(ctx, args.train_steps)}
         print(json.dumps(out), flush=True)
         ctx.close()
         return
@@ -208,12 +214,12 @@ def main():
                                "placements), SDNet width 256, GP ring data (l=2, seed 1), "
                                f"{K} CROSS sweeps + assembly",
                    "units": [ux, uy], "width": width, "sweeps": K, "targets": "cross",
-                   "evals_per_step": evals_per_step, "tile_rows": tile_rows},
+                   "evals_per_step": evals_per_step, "tile_shape": tile_shape_name(tile_rows)},
         "sweep_phase": {"launches": launches, "avg_launch_us": avg_us,
                         "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
+                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"].get(tile_shape_name(tile_rows))
                                  if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha()
                                  else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
@@ -303,6 +309,16 @@ def batched_measurement(ctx):
                              "grad_norm": float(ub.double().norm().item())}}
 
 
+def tile_shape_name(code):
+    """Readable tile shape: height plus the MF_TILE_WIDE / MF_TILE_STREAM flags."""
+    name = str(code & 0xFFFF)
+    if code & (1 << 16):
+        name += "|wide"
+    if code & (1 << 17):
+        name += "|stream"
+    return name
+
+
 def bf16_comparison(ctx, sweeps):
     """64 x 64 units (2049^2 grid, 16,129 placements), width 256, e^x sin y
     ring data: the same solve in FP32 and with BF16 hidden GEMMs, one timed
@@ -321,7 +337,7 @@ def bf16_comparison(ctx, sweeps):
     evals = sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
     from paper_2308_14258_amd import mf_autotune
     for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
-        rows = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, prec, trials=2)
+        shape = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, prec, trials=2)
         u = field.clone()
         u_out = torch.empty_like(u)
         mf_solve(ctx, params, u, (ux, uy), 2, targets=MF_CROSS, prec=prec)   # warm-up + capture
@@ -338,7 +354,7 @@ def bf16_comparison(ctx, sweeps):
         fpp = flops_per_point(width, CROSS_T)
         peak = PEAK_FP32_MFMA_TFLOPS if prec == MF_FP32 else PEAK_BF16_MFMA_TFLOPS
         ach = rows * fpp / (ms * 1e-3) / 1e12
-        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt, "tile_rows": rows,
+        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt, "tile_shape": tile_shape_name(shape),
                      "phase_avg_us": ms * 1e3 / max(launches, 1),
                      "phase_tflops": ach, "phase_frac_of_mfma_peak": ach / peak}
         outs[name] = u_out.double()

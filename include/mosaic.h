@@ -82,7 +82,7 @@ enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
 enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
 enum { MF_TANH = 0 };                               /* activation          */
 enum { MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1 };        /* mf_solve flags      */
-enum { MF_TILE_WIDE = 1 << 16 };                    /* tile-shape flag     */
+enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17 }; /* tile-shape flags */
 
 typedef struct mf_sdnet_desc {
   int32_t width;       /* d: 128 or 256                                    */
@@ -123,11 +123,14 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
 
 /* Tile shape of the colour-phase kernel for one precision: the tile height
  * (rows of (placement, target) pairs per workgroup) is 32 or 64 for MF_FP32
- * and 64, 128 or 256 for MF_BF16; for MF_BF16 heights 128 and 256 may be
- * or-ed with MF_TILE_WIDE (each wave then owns 64 output columns instead of
- * 32, halving the LDS reads of the activations). 0 restores the automatic
- * choice (a tuned value from mf_autotune, else a rule based on the phase
- * size and the CU count). */
+ * and 64, 128 or 256 for MF_BF16. Height 32 in fp32 streams the hidden
+ * weights from L2; height 64 keeps each wave's slice of them in registers,
+ * or streams them when or-ed with MF_TILE_STREAM (fewer registers, two
+ * workgroups per CU). For MF_BF16 heights 128 and 256 may be or-ed with
+ * MF_TILE_WIDE (each wave then owns 64 output columns instead of 32, halving
+ * the LDS reads of the activations). 0 restores the automatic choice (a
+ * tuned value from mf_autotune, else a rule based on the phase size and the
+ * CU count). */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
 /* Autotuner: for this network, domain, target set and precision, time

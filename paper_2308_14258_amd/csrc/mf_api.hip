@@ -42,7 +42,7 @@ NetLayout net_layout(int width, int prec, size_t base) {
   L.wh = o;   o = align256(o + 3 * d * d * (prec == MF_FP32 ? 4 : 2));
   L.bh = o;   o = align256(o + 3 * d * 4);
   L.w5 = o;   o = align256(o + d * 4);
-  L.b5 = o;   o = align256(o + 4);
+  L.b5 = o;   o = align256(o + 8);
   L.end = o;
   return L;
 }
@@ -151,7 +151,8 @@ static mf_status check_desc(const mf_sdnet_desc* d) {
 }
 
 static bool valid_tile_rows(int prec, int rows) {
-  if (prec == MF_FP32) return rows == 32 || rows == 64;
+  if (prec == MF_FP32) return rows == 32 || rows == 64 || rows == (64 | MF_TILE_STREAM);
+  if (rows & MF_TILE_STREAM) return false;
   const int r = rows & ~MF_TILE_WIDE;
   if (rows & MF_TILE_WIDE) return r == 128 || r == 256;
   return r == 64 || r == 128 || r == 256;
@@ -452,7 +453,7 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
       int64_t acc = 0;
       for (int d = 0; d < nd; ++d) {
         tb[d] = (int32_t)acc;
-        const int rows_per_tile = P->R[a] & ~MF_TILE_WIDE;
+        const int rows_per_tile = P->R[a] & 0xffff;
         acc += (phase_rows(&dom[d], c, tg) + rows_per_tile - 1) / rows_per_tile;
       }
       if (acc > INT32_MAX) return fail(MF_ESHAPE, "batch has too many tiles");
@@ -616,10 +617,10 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
-  const int cands_fp32[] = {32, 64};
+  const int cands_fp32[] = {32, 64, 64 | MF_TILE_STREAM};
   const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE};
   const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
-  const int n_cands = prec == MF_FP32 ? 2 : 5;
+  const int n_cands = prec == MF_FP32 ? 3 : 5;
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;

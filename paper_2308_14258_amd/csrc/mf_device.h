@@ -90,6 +90,14 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
+// tanh(x + b) with kb = 2 log2(e) b precomputed: the bias folds into the
+// exponent, exp(2 (x + b)) = 2^(2 log2(e) x + kb).
+constexpr float kTwoLog2e = 2.8853900817779268f;
+__device__ __forceinline__ float tanh_biased(float x, float kb) {
+  const float e = __builtin_amdgcn_exp2f(fmaf(x, kTwoLog2e, kb));
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
+}
+
 __device__ __forceinline__ floatx16 mfma32x32x2(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }

@@ -23,7 +23,7 @@ struct NetLayout {
   size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32 or bf16)
   size_t bh = 0;     // float [3][d]
   size_t w5 = 0;     // float [d]
-  size_t b5 = 0;     // float [1]
+  size_t b5 = 0;     // float [2]: b5, b5 + sum(w5)
   size_t end = 0;
 };
 NetLayout net_layout(int width, int prec, size_t base);

@@ -57,7 +57,14 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
     w5[n] = params[off_w5 + n];
     for (int l = 0; l < 3; ++l) bh[l * d + n] = params[off_w2 + l * lstride + (int64_t)d * d + n];
   }
-  if (tid == 0) b5[0] = params[off_b5];
+  if (tid == 0) {
+    // b5 and, for the sweep kernel's output layer, b5 + sum(w5) (summed in
+    // index order)
+    float sw = params[off_b5];
+    for (int n = 0; n < d; ++n) sw += params[off_w5 + n];
+    b5[0] = params[off_b5];
+    b5[1] = sw;
+  }
 
   const int64_t dd = (int64_t)d * d;
   for (int64_t idx = tid; idx < 3 * dd; idx += nthr) {
@@ -118,143 +125,285 @@ struct TileArgs {
 template <int PREC> struct HType { typedef float T; };
 template <> struct HType<1> { typedef uint16_t T; };
 
+// MFMA on one k group of a d x d layer. The prepared weights are the A
+// operand (rows = output units j) and the activations the B operand (columns
+// = points i), so a lane's accumulator registers 4g .. 4g + 3 hold four
+// consecutive units of one point: the epilogue converts and stores them as
+// one 16-byte (fp32) or 8-byte (bf16) vector. Inside a k group lane l feeds
+// the same k indices to both operands (fp32: k = 4 (l >> 5) + e at step e;
+// bf16: k = 8 (l >> 5) + e), which is what the prepared layout holds.
+template <int PREC> struct Mma;
+template <> struct Mma<0> {
+  typedef floatx4 T;
+  static constexpr int K = 8;
+  template <int N>
+  static __device__ __forceinline__ void run(const T& w, const T (&h)[N], floatx16 (&c)[N]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int n = 0; n < N; ++n) c[n] = mfma32x32x2(w[e], h[n][e], c[n]);
+  }
+};
+template <> struct Mma<1> {
+  typedef bf16x8 T;
+  static constexpr int K = 16;
+  template <int N>
+  static __device__ __forceinline__ void run(const T& w, const T (&h)[N], floatx16 (&c)[N]) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) c[n] = mfma32x32x16_bf16(w, h[n], c[n]);
+  }
+};
+
 template <int PREC>
-__device__ __forceinline__ void h_store(typename HType<PREC>::T* p, float v) {
-  if constexpr (PREC == 0) *p = v; else *p = bf16_bits(v);
-}
-template <int PREC>
-__device__ __forceinline__ float h_load(const typename HType<PREC>::T* p) {
-  if constexpr (PREC == 0) return *p; else return bf16_to_f32(*p);
+__device__ __forceinline__ typename Mma<PREC>::T load_op(const void* p) {
+  return __builtin_bit_cast(typename Mma<PREC>::T, *static_cast<const u32x4*>(p));
 }
 
-// Three hidden layers with bf16 operands and float32 accumulation. Each wave
-// owns 32 output columns and keeps its slice of the layer's weights in
-// registers (D/16 bf16x8 operands); it walks the tile's 32-row blocks with
-// one barrier per block, so the tanh epilogue of block rb-1 (written back
-// in place: every wave has finished reading those rows once it passed the
-// previous barrier) overlaps the MFMAs of block rb.
-template <int D, int R, int CPW>
-__device__ __forceinline__ void hidden_layers_bf16(uint16_t* Hs, const u32x4* wh, const float* bh,
-                                                   int lane, int wave) {
-  constexpr int RB = R / 32, KG = D / 16, LDH = D + 8, NCB = CPW / 32;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Four consecutive activations of one row.
+template <int PREC>
+__device__ __forceinline__ void store4(typename HType<PREC>::T* p, float a, float b, float c, float d) {
+  if constexpr (PREC == 0) {
+    *reinterpret_cast<floatx4*>(p) = floatx4{a, b, c, d};
+  } else {
+    const bf16x2 lo = {(__bf16)a, (__bf16)b}, hi = {(__bf16)c, (__bf16)d};
+    *reinterpret_cast<u32x2*>(p) = u32x2{__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)};
+  }
+}
+
+// Activations are stored multiplied by k = 2 log2(e): a layer's accumulator
+// then holds k z (its bias is stored as k b too), and
+//   k tanh(z) = k - 2 k / (1 + 2^(k z)),
+// one exp2, one reciprocal and one fma; the scale costs nothing.
+__device__ __forceinline__ float rsig_exp2(float kz) {   // 1 / (1 + e^(2z))
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(kz));
+}
+__device__ __forceinline__ float ktanh_exp2(float kz) {
+  return fmaf(-2.0f * kTwoLog2e, rsig_exp2(kz), kTwoLog2e);
+}
+
+// Accumulator of one 32 x 32 block initialised with the (scaled) bias of its
+// units; `b` points at unit col0 + 4 (lane >> 5).
+__device__ __forceinline__ floatx16 bias_acc(const float* b) {
+  floatx16 a;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(b + 8 * g);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[4 * g + e] = v[e];
+  }
+  return a;
+}
+
+// k tanh of one finished block, written to the activation rows in place.
+template <int PREC>
+__device__ __forceinline__ void store_tanh(typename HType<PREC>::T* p, const floatx16& acc) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    store4<PREC>(p + 8 * g, ktanh_exp2(acc[4 * g]), ktanh_exp2(acc[4 * g + 1]), ktanh_exp2(acc[4 * g + 2]),
+                 ktanh_exp2(acc[4 * g + 3]));
+}
+
+// Output layer folded into the last hidden layer: with tanh z = 1 - 2 r,
+// w5 . tanh(z) = sum(w5) + sum(-2 w5 r); here the second sum over the lane's
+// 16 units (`w` holds -2 w5 at unit col0 + 4 (lane >> 5)).
+__device__ __forceinline__ float dot_tanh(const floatx16& acc, const float* w) {
+  float s = 0.0f;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const floatx4 v = *reinterpret_cast<const floatx4*>(w + 8 * g);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s = fmaf(v[e], rsig_exp2(acc[4 * g + e]), s);
+  }
+  return s;
+}
+
+// Partial output of one 32-column block for the 32 points of a row block:
+// the two half-waves hold the two halves of the block's units.
+__device__ __forceinline__ void put_partial(float* po, float s, int lane) {
+  s += __shfl_xor(s, 32);
+  if (lane < 32) po[lane] = s;
+}
+
+// The wave's CPW-column slice of hidden layer l's prepared weights: D/KK
+// MFMA operands per 32 columns. The layer offset is opaque to the optimiser,
+// which would otherwise hoist the loads of all three layers (and, in the
+// persistent kernel, out of the tile loop) and run out of registers.
+template <int D, int PREC, int CPW>
+__device__ __forceinline__ const u32x4* wslice(const u32x4* wh, int l, int wave, int lane, int cb) {
+  constexpr int KG = D / Mma<PREC>::K, NCB = CPW / 32;
+  constexpr int LAYER = D * D / (PREC == 0 ? 4 : 8);   // u32x4 per prepared layer
+  int lofs = l * LAYER;
+  asm volatile("" : "+s"(lofs));
+  return wh + lofs + (wave * NCB + cb) * KG * 64 + lane;
+}
+
+template <int D, int PREC, int CPW>
+__device__ __forceinline__ void load_wslice(typename Mma<PREC>::T (&wreg)[CPW / 32][D / Mma<PREC>::K],
+                                            const u32x4* wh, int l, int wave, int lane) {
+#pragma unroll
+  for (int cb = 0; cb < CPW / 32; ++cb) {
+    const u32x4* wsw = wslice<D, PREC, CPW>(wh, l, wave, lane, cb);
+#pragma unroll
+    for (int kg = 0; kg < D / Mma<PREC>::K; ++kg)
+      wreg[cb][kg] = __builtin_bit_cast(typename Mma<PREC>::T, wsw[kg * 64]);
+  }
+}
+
+// One hidden layer with the wave's weight slice in registers (`wreg`, loaded
+// by the caller). The wave walks the tile's 32-row blocks with one barrier
+// per block; the row-block loop is unrolled, so the tanh epilogue of block
+// rb - 1 (written back in place: every wave has finished reading those rows
+// once it passed the previous barrier) sits in the same basic block as the
+// MFMAs of block rb and the scheduler overlaps them. LAST: the output
+// layer's dot products instead of activations, no writes to the tile and so
+// no barriers.
+template <int D, int R, int PREC, int CPW, bool LAST>
+__device__ __forceinline__ void layer_wreg(typename HType<PREC>::T* Hs,
+                                           typename Mma<PREC>::T (&wreg)[CPW / 32][D / Mma<PREC>::K],
+                                           const u32x4* wh, int l, const float* nb, float* po, int lane,
+                                           int wave) {
+  typedef Mma<PREC> M;
+  typedef typename M::T OT;
+  constexpr int KK = M::K, KG = D / KK, RB = R / 32, NCB = CPW / 32;
+  constexpr int LDH = PREC == 0 ? D + 4 : D + 8;
   const int arow = lane & 31, ahalf = lane >> 5;
-#pragma unroll 1
-  for (int l = 0; l < 3; ++l) {
-    bf16x8 breg[NCB][KG];
-    float bj[NCB];
+  floatx16 acc[2][NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const u32x4* wsw = wh + (size_t)l * (D * D / 8) + (size_t)(wave * NCB + cb) * KG * 64 + lane;
+  for (int rb = 0; rb <= RB; ++rb) {
+    floatx16(&cur)[NCB] = acc[rb & 1];
+    floatx16(&prv)[NCB] = acc[(rb + 1) & 1];
+    if (rb < RB) {
 #pragma unroll
-      for (int kg = 0; kg < KG; ++kg) breg[cb][kg] = __builtin_bit_cast(bf16x8, wsw[kg * 64]);
-      bj[cb] = bh[l * D + (wave * NCB + cb) * 32 + arow];
-    }
-    floatx16 prev[NCB];
+      for (int cb = 0; cb < NCB; ++cb) cur[cb] = bias_acc(nb + l * D + (wave * NCB + cb) * 32 + 4 * ahalf);
+      const typename HType<PREC>::T* ap = Hs + (rb * 32 + arow) * LDH + (KK / 2) * ahalf;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) prev[cb][v] = 0.0f;
-#pragma unroll 1
-    for (int rb = 0; rb <= RB; ++rb) {
-      floatx16 acc[NCB];
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
-      if (rb < RB) {
-        const uint16_t* ap = Hs + (rb * 32 + arow) * LDH + 8 * ahalf;
-#pragma unroll
-        for (int kg = 0; kg < KG; ++kg) {
-          const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(ap + kg * 16));
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma32x32x16_bf16(av, breg[cb][kg], acc[cb]);
-        }
-      }
-      if (rb > 0) {
+      for (int kg = 0; kg < KG; ++kg) {
+        const OT h[1] = {load_op<PREC>(ap + kg * KK)};
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-          uint16_t* op = Hs + ((rb - 1) * 32) * LDH + (wave * NCB + cb) * 32 + arow;
-#pragma unroll
-          for (int v = 0; v < 16; v += 2) {
-            uint16_t h0, h1;
-            bf16_pair(tanh_fast(prev[cb][v] + bj[cb]), tanh_fast(prev[cb][v + 1] + bj[cb]), h0, h1);
-            op[acc_row(lane, v) * LDH] = h0;
-            op[acc_row(lane, v + 1) * LDH] = h1;
-          }
+          floatx16 c1[1] = {cur[cb]};
+          M::template run<1>(wreg[cb][kg], h, c1);
+          cur[cb] = c1[0];
         }
       }
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) prev[cb] = acc[cb];
-      __syncthreads();
     }
+    // after the last block's MFMAs (and the barrier that ends them, which
+    // the scheduler does not cross) the next layer's weights are loaded into
+    // the same registers, in flight during the last epilogue
+
+    if (rb > 0) {
+      const int row = (rb - 1) * 32;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int col = (wave * NCB + cb) * 32;
+        if constexpr (!LAST) store_tanh<PREC>(Hs + (row + arow) * LDH + col + 4 * ahalf, prv[cb]);
+        else put_partial(po + (col / 32) * R + row, dot_tanh(prv[cb], nb + 3 * D + col + 4 * ahalf), lane);
+      }
+    }
+    if constexpr (!LAST) __syncthreads();
   }
 }
 
-// The same pipeline with float32 operands: each wave holds its 32-column
-// weight slice as D/8 float4 MFMA operands (128 VGPRs at d = 256) for the
-// whole layer, so the k loop issues LDS reads and MFMAs only.
-template <int D, int R>
-__device__ __forceinline__ void hidden_layers_f32(float* Hs, const floatx4* wh, const float* bh, int lane,
+// The three hidden layers and the output layer's dot products. `nb` (LDS)
+// holds k times the biases of the three hidden layers and then -2 w5; `po` (LDS,
+// [D / 32][R]) receives per-32-column partial outputs, summed by the caller
+// in a fixed order, so a row's result does not depend on the tile shape.
+// WREG: register-resident weights (layer_wreg). Otherwise (fp32 only) the
+// weights stream from L2 per k group and serve all row blocks of the tile;
+// fewer registers, so more workgroups per CU.
+template <int D, int R, int PREC, int CPW, bool WREG>
+__device__ __forceinline__ void hidden_and_output(typename HType<PREC>::T* Hs,
+                                                  typename Mma<PREC>::T (&wreg)[CPW / 32][D / Mma<PREC>::K],
+                                                  const u32x4* wh, const float* nb, float* po, int lane,
                                                   int wave) {
-  constexpr int RB = R / 32, KG = D / 8, LDH = D + 4;
-  const int arow = lane & 31, ahalf = lane >> 5;
-  const int j = wave * 32 + arow;
+  if constexpr (WREG) {
+    // wreg holds layer 0 on entry (loaded by the caller ahead of the first
+    // layer, so those loads overlap its tanh work)
 #pragma unroll 1
-  for (int l = 0; l < 3; ++l) {
-    floatx4 breg[KG];
-    const floatx4* wsw = wh + (size_t)l * (D * D / 4) + (size_t)wave * KG * 64 + lane;
-#pragma unroll
-    for (int kg = 0; kg < KG; ++kg) breg[kg] = wsw[kg * 64];
-    const float bj = bh[l * D + j];
-    floatx16 prev;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) prev[v] = 0.0f;
+    for (int l = 0; l < 2; ++l) {
+      if (l > 0) load_wslice<D, PREC, CPW>(wreg, wh, l, wave, lane);
+      layer_wreg<D, R, PREC, CPW, false>(Hs, wreg, wh, l, nb, po, lane, wave);
+    }
+    load_wslice<D, PREC, CPW>(wreg, wh, 2, wave, lane);
+    layer_wreg<D, R, PREC, CPW, true>(Hs, wreg, wh, 2, nb, po, lane, wave);
+  } else {
+    typedef Mma<PREC> M;
+    typedef typename M::T OT;
+    constexpr int KK = M::K, KG = D / KK, RB = R / 32;
+    constexpr int LDH = PREC == 0 ? D + 4 : D + 8;
+    constexpr int LAYER = D * D / (PREC == 0 ? 4 : 8);
+    static_assert(PREC == 0 && CPW == 32, "streamed weights: fp32, 32 columns per wave");
+    const int arow = lane & 31, ahalf = lane >> 5;
+    const int col = wave * 32;
 #pragma unroll 1
-    for (int rb = 0; rb <= RB; ++rb) {
-      floatx16 acc;
+    for (int l = 0; l < 3; ++l) {
+      floatx16 acc[RB];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-      if (rb < RB) {
-        const float* ap = Hs + (rb * 32 + arow) * LDH + 4 * ahalf;
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = bias_acc(nb + l * D + col + 4 * ahalf);
+      const u32x4* wsw = wh + l * LAYER + wave * KG * 64 + lane;
+#pragma unroll 4
+      for (int kg = 0; kg < KG; ++kg) {
+        const OT w = __builtin_bit_cast(OT, wsw[kg * 64]);
+        OT h[RB];
 #pragma unroll
-        for (int kg = 0; kg < KG; ++kg) {
-          const floatx4 av = *reinterpret_cast<const floatx4*>(ap + kg * 8);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc = mfma32x32x2(av[e], breg[kg][e], acc);
-        }
+        for (int rb = 0; rb < RB; ++rb) h[rb] = load_op<PREC>(Hs + (rb * 32 + arow) * LDH + kg * KK + (KK / 2) * ahalf);
+        M::template run<RB>(w, h, acc);
       }
-      if (rb > 0) {
-        float* op = Hs + ((rb - 1) * 32) * LDH + j;
+      if (l < 2) {
+        __syncthreads();   // every wave has finished reading this layer's input
 #pragma unroll
-        for (int v = 0; v < 16; ++v) op[acc_row(lane, v) * LDH] = tanh_fast(prev[v] + bj);
+        for (int rb = 0; rb < RB; ++rb) store_tanh<PREC>(Hs + (rb * 32 + arow) * LDH + col + 4 * ahalf, acc[rb]);
+        __syncthreads();
+      } else {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          put_partial(po + wave * R + rb * 32, dot_tanh(acc[rb], nb + 3 * D + col + 4 * ahalf), lane);
       }
-      prev = acc;
-      __syncthreads();
     }
   }
+  __syncthreads();   // partial outputs complete
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
+template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32, bool WREG = true>
 __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0) {
   static_assert(CPW == 32 || (CPW == 64 && PREC == 1), "64 columns per wave: bf16 only");
   constexpr int NTH = (D / CPW) * 64;        // one wave per CPW output columns
-  constexpr int RB = R / 32;                 // 32-row MFMA blocks per tile
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = SRC == SRC_GATHER ? (R - 1) / T + 2 : 1;
   constexpr int LDH = PREC == 0 ? D + 4 : D + 8;   // padded row (elements)
+  constexpr int NCOLB = D / 32;
+  constexpr int SCR = NPMAX * (kNB + D) > NCOLB * R ? NPMAX * (kNB + D) : NCOLB * R;
   typedef typename HType<PREC>::T HT;
 
   __shared__ __align__(16) HT Hs[R * LDH];
-  __shared__ float gs[NPMAX * kNB];
-  __shared__ float cs[NPMAX * D];
-  __shared__ int r_slot[R];
-  __shared__ float r_x[R], r_y[R], r_w[R];
+  __shared__ __align__(16) float scr[SCR];   // boundary values + projections, later partial outputs
+  __shared__ __align__(16) floatx4 r_info[R];   // x, y, placement slot (bits), cover weight
+  __shared__ __align__(16) float nb[4 * D];   // k b2, k b3, k b4, -2 w5
   __shared__ int64_t r_addr[R];
   __shared__ int64_t r_bc[SRC == SRC_C ? R : 1];
+  float* gs = scr;
+  float* cs = scr + NPMAX * kNB;
+  float* po = scr;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const NetPtrs& net = A.net;
+  // The network pointers, offset by an opaque zero: in the persistent kernel
+  // the optimiser would otherwise hoist every tile-invariant weight load
+  // (projection, first layer, hidden layers) out of the tile loop and run
+  // out of registers.
+  int zero = 0;
+  asm volatile("" : "+s"(zero));
+  NetPtrs net = A.net;
+  net.w1gT += zero;
+  net.w1x += zero;
+  net.b1 += zero;
+  net.bh += zero;
+  net.w5 += zero;
+  net.wh = static_cast<const u32x4*>(net.wh) + zero;
+
+  for (int i = tid; i < 4 * D; i += NTH) nb[i] = i < 3 * D ? kTwoLog2e * net.bh[i] : -2.0f * net.w5[i - 3 * D];
 
   // -- rows of this tile -----------------------------------------------------
   int64_t q0 = 0;
@@ -265,8 +414,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
     np = (int)(last / T - q0 + 1);
   }
   for (int rt = tid; rt < R; rt += NTH) {
-    const int tid = rt;
-    const int64_t row = row0 + tid;
+    const int64_t row = row0 + rt;
     const bool valid = row < A.total_rows;
     const int64_t rr = valid ? row : A.total_rows - 1;
     if constexpr (SRC == SRC_GATHER) {
@@ -275,23 +423,30 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       placement_of(q, A.colour, A.ux, a, b);
       target_local<TMODE>(t, ti, tj);
       const int gi = kHalf * a + ti, gj = kHalf * b + tj;
-      r_slot[tid] = (int)(q - q0);
-      r_x[tid] = ti * (1.0f / kS);
-      r_y[tid] = tj * (1.0f / kS);
-      r_w[tid] = cover_inv(gi, kS * A.ux) * cover_inv(gj, kS * A.uy);
-      r_addr[tid] = valid ? (int64_t)gj * A.pitch + gi : -1;
+      r_info[rt] = floatx4{ti * (1.0f / kS), tj * (1.0f / kS), __int_as_float((int)(q - q0)),
+                           cover_inv(gi, kS * A.ux) * cover_inv(gj, kS * A.uy)};
+      r_addr[rt] = valid ? (int64_t)gj * A.pitch + gi : -1;
     } else {
       const int64_t bc = rr / A.n_pts, pt = rr - bc * A.n_pts;
       const float* xp = A.x_per_bc ? A.X + 2 * rr : A.X + 2 * pt;
-      r_x[tid] = xp[0];
-      r_y[tid] = xp[1];
-      r_bc[tid] = bc;
-      r_addr[tid] = valid ? rr : -1;
+      r_info[rt] = floatx4{xp[0], xp[1], 0.0f, 1.0f};
+      r_bc[rt] = bc;
+      r_addr[rt] = valid ? rr : -1;
     }
   }
 
   // -- gather + boundary projection (once per placement) --------------------
+  // Thread t owns 4 consecutive columns (group t % (D/4)) and a 16-wide slice
+  // of k (t / (D/4)); its 16 float4 loads of W1g^T are independent and are
+  // issued before the gather, so both latencies overlap.
+  constexpr int NG = D / 4, KSL = NTH / NG, KPS = kNB / KSL;
+  static_assert(KSL * KPS == kNB, "projection split");
+  floatx4 w[KPS];
+  const int n4 = tid % NG, ks = tid / NG;
   if constexpr (SRC == SRC_GATHER) {
+#pragma unroll
+    for (int i = 0; i < KPS; ++i)
+      w[i] = *reinterpret_cast<const floatx4*>(net.w1gT + (ks * KPS + i) * D + 4 * n4);
     for (int idx = tid; idx < np * kNB; idx += NTH) {
       const int s = idx >> 7, k = idx & 127;
       int a, b, bi, bj;
@@ -300,18 +455,10 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       gs[idx] = A.u_in[(int64_t)(kHalf * b + bj) * A.pitch + kHalf * a + bi];
     }
     __syncthreads();
-    // Thread t owns 4 consecutive columns (group t % (D/4)) and a 16-wide
-    // slice of k (t / (D/4)); its 16 float4 weight loads are independent, so
-    // they are in flight together. The 8 k-slice partials go to LDS scratch
-    // that aliases the activation tile (not in use yet) and are then summed.
-    constexpr int NG = D / 4, KSL = NTH / NG, KPS = kNB / KSL;
-    static_assert(KSL * KPS == kNB, "projection split");
+    // The k-slice partials go to LDS scratch that aliases the activation tile
+    // (not in use yet) and are then summed; the stored projection carries b1
+    // and the factor 2 log2(e) of the tanh.
     static_assert((size_t)KSL * NPMAX * D * sizeof(float) <= sizeof(HT) * R * LDH, "projection scratch");
-    const int n4 = tid % NG, ks = tid / NG;
-    floatx4 w[KPS];
-#pragma unroll
-    for (int i = 0; i < KPS; ++i)
-      w[i] = *reinterpret_cast<const floatx4*>(net.w1gT + (ks * KPS + i) * D + 4 * n4);
     float* part = reinterpret_cast<float*>(Hs);
     for (int s = 0; s < np; ++s) {
       floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -331,82 +478,75 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       float c = 0.0f;
 #pragma unroll
       for (int k = 0; k < KSL; ++k) c += part[(k * NPMAX + s) * D + n];
-      cs[idx] = c;
+      cs[idx] = kTwoLog2e * (c + net.b1[n]);
     }
   }
   __syncthreads();
 
-  // -- first layer: tanh(projection + W1x (x, y)) ---------------------------
+  // the first hidden layer's weights are in flight during the first layer
+  typename Mma<PREC>::T wreg[CPW / 32][D / Mma<PREC>::K];
+  if constexpr (WREG) load_wslice<D, PREC, CPW>(wreg, static_cast<const u32x4*>(net.wh), 0, wave, lane);
+
+  // -- first layer: tanh(projection + W1x (x, y)), four columns per thread --
   {
-    const int n = tid & (D - 1);
-    const float wx = net.w1x[2 * n], wy = net.w1x[2 * n + 1];
-    const float bb = net.b1[n];
-    for (int r = tid / D; r < R; r += NTH / D) {
-      float c;
+    constexpr int RL = NTH / NG;   // rows in flight; thread: columns 4 n4 .. 4 n4 + 3
+    const int rl = tid / NG;
+    floatx4 wx, wy;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      wx[e] = kTwoLog2e * net.w1x[2 * (4 * n4 + e)];
+      wy[e] = kTwoLog2e * net.w1x[2 * (4 * n4 + e) + 1];
+    }
+    for (int r = rl; r < R; r += RL) {
+      const floatx4 ri = r_info[r];
+      floatx4 c;
       if constexpr (SRC == SRC_GATHER) {
-        c = cs[r_slot[r] * D + n] + bb;
+        c = *reinterpret_cast<const floatx4*>(&cs[__float_as_int(ri[2]) * D + 4 * n4]);
       } else {
-        c = A.C[r_bc[r] * D + n];
+        c = kTwoLog2e * *reinterpret_cast<const floatx4*>(A.C + r_bc[r] * D + 4 * n4);
       }
-      const float pre = fmaf(r_y[r], wy, fmaf(r_x[r], wx, c));
-      h_store<PREC>(&Hs[r * LDH + n], tanh_fast(pre));
+      float t[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[e] = ktanh_exp2(fmaf(ri[1], wy[e], fmaf(ri[0], wx[e], c[e])));
+      store4<PREC>(&Hs[r * LDH + 4 * n4], t[0], t[1], t[2], t[3]);
     }
   }
   __syncthreads();
 
-  // -- hidden layers on MFMA --------------------------------------------------
-  if constexpr (PREC == 1) {
-    hidden_layers_bf16<D, R, CPW>(Hs, static_cast<const u32x4*>(net.wh), net.bh, lane, wave);
-  } else if constexpr (R >= 64) {
-    hidden_layers_f32<D, R>(Hs, static_cast<const floatx4*>(net.wh), net.bh, lane, wave);
-  } else {
-    const int arow = lane & 31;
-    for (int l = 0; l < 3; ++l) {
-      floatx16 acc[RB];
-      mfma_layer_f32<D, RB, LDH>(Hs, static_cast<const floatx4*>(net.wh) + (size_t)l * (D * D / 4) +
-                                         (size_t)wave * (D / 8) * 64 + lane,
-                                 acc, lane);
-      __syncthreads();   // every wave has finished reading this layer's input
-      const int j = wave * 32 + arow;
-      const float bj = net.bh[l * D + j];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int i = rb * 32 + acc_row(lane, v);
-          Hs[i * LDH + j] = tanh_fast(acc[rb][v] + bj);
-        }
-      __syncthreads();
-    }
-  }
+  // -- hidden layers on MFMA, output layer in the last epilogue -----------------
+  hidden_and_output<D, R, PREC, CPW, WREG>(Hs, wreg, static_cast<const u32x4*>(net.wh), nb, po, lane, wave);
 
-  // -- output layer and store -------------------------------------------------
-  // Eight threads per row, whatever the tile height, so a row's dot product
-  // is summed in the same order for every tile shape.
-  {
-    constexpr int TPR = 8;
-    const int part = tid % TPR;
-    for (int r = tid / TPR; r < R; r += NTH / TPR) {
+  // -- sum of the per-column-block partials (fixed order) and store -----------
+  for (int r = tid; r < R; r += NTH) {
+    const int64_t addr = r_addr[r];
+    if (addr >= 0) {
       float s = 0.0f;
-      for (int n = part; n < D; n += TPR) s = fmaf(h_load<PREC>(&Hs[r * LDH + n]), net.w5[n], s);
 #pragma unroll
-      for (int o = TPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      if (part == 0) {
-        const int64_t addr = r_addr[r];
-        if (addr >= 0) {
-          const float val = s + net.b5[0];
-          if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
-          else if constexpr (OUT == OUT_ACCUM) A.u_out[addr] += val * r_w[r];
-          else A.U[addr] = val;
-        }
-      }
+      for (int c = 0; c < NCOLB; ++c) s += po[c * R + r];
+      const float val = s + net.b5[1];
+      if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
+      else if constexpr (OUT == OUT_ACCUM) A.u_out[addr] += val * r_info[r][3];
+      else A.U[addr] = val;
     }
   }
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
-__global__ __launch_bounds__((D / CPW) * 64) void tile_kernel(TileArgs A) {
-  tile_body<D, R, TMODE, PREC, SRC, OUT, CPW>(A, (int64_t)blockIdx.x * R);
+// A tile shape: width, tile height, precision, output columns per wave and
+// whether the hidden weights live in registers (else streamed from L2).
+template <int D_, int R_, int PREC_, int CPW_, bool WREG_>
+struct Shape {
+  static constexpr int D = D_, R = R_, PREC = PREC_, CPW = CPW_;
+  static constexpr bool WREG = WREG_;
+  static constexpr int NTH = (D / CPW) * 64;
+  // waves per SIMD the register budget is sized for (HIP's second launch
+  // bound): two 8-wave workgroups per CU, i.e. 128 VGPRs, where the LDS tile
+  // allows it
+  static constexpr int MINW = ((PREC == 1 && CPW == 32 && R <= 128) || (PREC == 0 && !WREG)) ? 2 * NTH / 256 : 1;
+};
+
+template <class S, int TMODE, int SRC, int OUT>
+__global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
+  tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (int64_t)blockIdx.x * S::R);
 }
 
 // Batched independent domains in one persistent launch per colour: block b
@@ -423,8 +563,8 @@ struct MultiArgs {
   int64_t n_tiles;
 };
 
-template <int D, int R, int TMODE, int PREC, int OUT, int CPW = 32>
-__global__ __launch_bounds__((D / CPW) * 64) void tile_kernel_multi(MultiArgs M) {
+template <class S, int TMODE, int OUT>
+__global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M) {
   constexpr int T = n_targets<TMODE>();
   const int ca = M.base.colour & 1, cb = M.base.colour >> 1;
   for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
@@ -441,37 +581,48 @@ __global__ __launch_bounds__((D / CPW) * 64) void tile_kernel_multi(MultiArgs M)
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    tile_body<D, R, TMODE, PREC, SRC_GATHER, OUT, CPW>(A, (t - M.tile_begin[lo]) * R);
+    tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
     __syncthreads();   // the next tile reuses the LDS
   }
 }
 
-template <int D, int R, int TMODE, int PREC, int OUT, int CPW = 32>
+// Tile shapes by (width, precision, tile code): fp32 32 (streamed weights),
+// 64 (register weights), 64 | MF_TILE_STREAM (streamed); bf16 64, 128, 256,
+// and 128 or 256 | MF_TILE_WIDE (64 columns per wave). The caller has
+// validated the code.
+template <int D, class F>
+static hipError_t with_shape_d(int prec, int code, F&& f) {
+  const int r = code & 0xffff;
+  if (prec == MF_BF16) {
+    if (code & MF_TILE_WIDE) return r == 256 ? f(Shape<D, 256, 1, 64, true>{}) : f(Shape<D, 128, 1, 64, true>{});
+    if (r == 256) return f(Shape<D, 256, 1, 32, true>{});
+    if (r == 128) return f(Shape<D, 128, 1, 32, true>{});
+    return f(Shape<D, 64, 1, 32, true>{});
+  }
+  if (r == 64) return (code & MF_TILE_STREAM) ? f(Shape<D, 64, 0, 32, false>{}) : f(Shape<D, 64, 0, 32, true>{});
+  return f(Shape<D, 32, 0, 32, false>{});
+}
+
+template <class F>
+static hipError_t with_shape(int width, int prec, int code, F&& f) {
+  return width == 256 ? with_shape_d<256>(prec, code, f) : with_shape_d<128>(prec, code, f);
+}
+
+template <class S, int TMODE, int OUT>
 static hipError_t launch_multi(const MultiArgs& m, int n_cu, hipStream_t s) {
   if (m.n_tiles == 0) return hipSuccess;
-  constexpr int NTH = (D / CPW) * 64;
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<D, R, TMODE, PREC, OUT, CPW>,
-                                                     NTH, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<S, TMODE, OUT>, S::NTH, 0) !=
+            hipSuccess ||
+        nb < 1)
       nb = 1;
     per_cu = nb;
   }
   const int64_t grid = std::min<int64_t>(m.n_tiles, (int64_t)per_cu * n_cu);
-  hipLaunchKernelGGL((tile_kernel_multi<D, R, TMODE, PREC, OUT, CPW>), dim3((unsigned)grid), dim3(NTH), 0,
-                     s, m);
+  hipLaunchKernelGGL((tile_kernel_multi<S, TMODE, OUT>), dim3((unsigned)grid), dim3(S::NTH), 0, s, m);
   return hipGetLastError();
-}
-
-template <int D, int R, int PREC, int CPW = 32>
-static hipError_t dispatch_multi(const MultiArgs& m, int targets, bool accumulate, int n_cu,
-                                 hipStream_t s) {
-  if (accumulate)
-    return targets == MF_CROSS ? launch_multi<D, R, 0, PREC, OUT_ACCUM, CPW>(m, n_cu, s)
-                               : launch_multi<D, R, 1, PREC, OUT_ACCUM, CPW>(m, n_cu, s);
-  if (targets == MF_CROSS) return launch_multi<D, R, 0, PREC, OUT_STORE, CPW>(m, n_cu, s);
-  return launch_multi<D, R, 1, PREC, OUT_STORE, CPW>(m, n_cu, s);
 }
 
 hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
@@ -487,47 +638,20 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
   m.tile_begin = tile_begin;
   m.n_domains = n_domains;
   m.n_tiles = n_tiles;
-  if (prec == MF_BF16 && (tile_rows & MF_TILE_WIDE)) {
-    const int r = tile_rows & ~MF_TILE_WIDE;
-    if (width == 256)
-      return r == 256 ? dispatch_multi<256, 256, 1, 64>(m, targets, accumulate, n_cu, s)
-                      : dispatch_multi<256, 128, 1, 64>(m, targets, accumulate, n_cu, s);
-    return r == 256 ? dispatch_multi<128, 256, 1, 64>(m, targets, accumulate, n_cu, s)
-                    : dispatch_multi<128, 128, 1, 64>(m, targets, accumulate, n_cu, s);
-  }
-  if (prec == MF_BF16) {
-    if (width == 256) {
-      if (tile_rows == 256) return dispatch_multi<256, 256, 1>(m, targets, accumulate, n_cu, s);
-      if (tile_rows == 128) return dispatch_multi<256, 128, 1>(m, targets, accumulate, n_cu, s);
-      return dispatch_multi<256, 64, 1>(m, targets, accumulate, n_cu, s);
-    }
-    if (tile_rows == 256) return dispatch_multi<128, 256, 1>(m, targets, accumulate, n_cu, s);
-    if (tile_rows == 128) return dispatch_multi<128, 128, 1>(m, targets, accumulate, n_cu, s);
-    return dispatch_multi<128, 64, 1>(m, targets, accumulate, n_cu, s);
-  }
-  if (width == 256)
-    return tile_rows == 64 ? dispatch_multi<256, 64, 0>(m, targets, accumulate, n_cu, s)
-                           : dispatch_multi<256, 32, 0>(m, targets, accumulate, n_cu, s);
-  return tile_rows == 64 ? dispatch_multi<128, 64, 0>(m, targets, accumulate, n_cu, s)
-                         : dispatch_multi<128, 32, 0>(m, targets, accumulate, n_cu, s);
+  return with_shape(width, prec, tile_rows, [&](auto sh) {
+    typedef decltype(sh) S;
+    if (accumulate)
+      return targets == MF_CROSS ? launch_multi<S, 0, OUT_ACCUM>(m, n_cu, s) : launch_multi<S, 1, OUT_ACCUM>(m, n_cu, s);
+    return targets == MF_CROSS ? launch_multi<S, 0, OUT_STORE>(m, n_cu, s) : launch_multi<S, 1, OUT_STORE>(m, n_cu, s);
+  });
 }
 
-template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32>
+template <class S, int TMODE, int SRC, int OUT>
 static hipError_t launch_tile(const TileArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.total_rows + R - 1) / R;
+  const int64_t blocks = (a.total_rows + S::R - 1) / S::R;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((tile_kernel<D, R, TMODE, PREC, SRC, OUT, CPW>), dim3((unsigned)blocks),
-                     dim3((D / CPW) * 64), 0, s, a);
+  hipLaunchKernelGGL((tile_kernel<S, TMODE, SRC, OUT>), dim3((unsigned)blocks), dim3(S::NTH), 0, s, a);
   return hipGetLastError();
-}
-
-template <int D, int R, int PREC, int CPW = 32>
-static hipError_t dispatch_phase(const TileArgs& a, int targets, bool accumulate, hipStream_t s) {
-  if (accumulate)
-    return targets == MF_CROSS ? launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_ACCUM, CPW>(a, s)
-                               : launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_ACCUM, CPW>(a, s);
-  if (targets == MF_CROSS) return launch_tile<D, R, 0, PREC, SRC_GATHER, OUT_STORE, CPW>(a, s);
-  return launch_tile<D, R, 1, PREC, SRC_GATHER, OUT_STORE, CPW>(a, s);
 }
 
 static int64_t colour_count(int ux, int uy, int colour) {
@@ -557,29 +681,14 @@ hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bo
   const int T = targets == MF_INTERIOR ? kInterior : kCross;
   a.total_rows = colour_count(p.ux, p.uy, p.colour) * T;
   if (a.total_rows == 0) return hipSuccess;
-  if (prec == MF_BF16 && (tile_rows & MF_TILE_WIDE)) {
-    const int r = tile_rows & ~MF_TILE_WIDE;
-    if (width == 256)
-      return r == 256 ? dispatch_phase<256, 256, 1, 64>(a, targets, accumulate, s)
-                      : dispatch_phase<256, 128, 1, 64>(a, targets, accumulate, s);
-    return r == 256 ? dispatch_phase<128, 256, 1, 64>(a, targets, accumulate, s)
-                    : dispatch_phase<128, 128, 1, 64>(a, targets, accumulate, s);
-  }
-  if (prec == MF_BF16) {
-    if (width == 256) {
-      if (tile_rows == 256) return dispatch_phase<256, 256, 1>(a, targets, accumulate, s);
-      if (tile_rows == 128) return dispatch_phase<256, 128, 1>(a, targets, accumulate, s);
-      return dispatch_phase<256, 64, 1>(a, targets, accumulate, s);
-    }
-    if (tile_rows == 256) return dispatch_phase<128, 256, 1>(a, targets, accumulate, s);
-    if (tile_rows == 128) return dispatch_phase<128, 128, 1>(a, targets, accumulate, s);
-    return dispatch_phase<128, 64, 1>(a, targets, accumulate, s);
-  }
-  if (width == 256)
-    return tile_rows == 64 ? dispatch_phase<256, 64, 0>(a, targets, accumulate, s)
-                           : dispatch_phase<256, 32, 0>(a, targets, accumulate, s);
-  return tile_rows == 64 ? dispatch_phase<128, 64, 0>(a, targets, accumulate, s)
-                         : dispatch_phase<128, 32, 0>(a, targets, accumulate, s);
+  return with_shape(width, prec, tile_rows, [&](auto sh) {
+    typedef decltype(sh) S;
+    if (accumulate)
+      return targets == MF_CROSS ? launch_tile<S, 0, SRC_GATHER, OUT_ACCUM>(a, s)
+                                 : launch_tile<S, 1, SRC_GATHER, OUT_ACCUM>(a, s);
+    return targets == MF_CROSS ? launch_tile<S, 0, SRC_GATHER, OUT_STORE>(a, s)
+                               : launch_tile<S, 1, SRC_GATHER, OUT_STORE>(a, s);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -635,11 +744,7 @@ hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const fl
   a.U = U;
   a.total_rows = n_bc * n_pts;
   if (a.total_rows == 0) return hipSuccess;
-  if (width == 256)
-    return prec == MF_FP32 ? launch_tile<256, 64, 0, 0, SRC_C, OUT_LINEAR>(a, s)
-                           : launch_tile<256, 64, 0, 1, SRC_C, OUT_LINEAR>(a, s);
-  return prec == MF_FP32 ? launch_tile<128, 64, 0, 0, SRC_C, OUT_LINEAR>(a, s)
-                         : launch_tile<128, 64, 0, 1, SRC_C, OUT_LINEAR>(a, s);
+  return with_shape(width, prec, 64, [&](auto sh) { return launch_tile<decltype(sh), 0, SRC_C, OUT_LINEAR>(a, s); });
 }
 
 // ---------------------------------------------------------------------------

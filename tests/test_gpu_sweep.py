@@ -279,6 +279,47 @@ def test_bf16_solve_c2_error(ctx):
     assert e_skel <= 2e-2 and e_out <= 2e-2
 
 
+@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2)])
+def test_solve_c4_full_size_golden(ctx, prec, tol):
+    """64 x 64 units (2049^2 grid, 16,129 placements), width 256: the
+    benchmark's BF16-vs-FP32 workload at full size, in the launch
+    configuration the benchmark uses (autotuned tile shape, graphs), against
+    oracle values at 32768 sampled skeleton points and 2048 assembly points:
+    after one sweep (the sweep map itself) and after 500 sweeps (the end
+    state). After 20 sweeps the untrained network's iteration is in a
+    transient that amplifies float32 rounding by about 1e5 on this domain, so
+    that comparison is reported, not bounded."""
+    print(f"case: mf_solve C4 (64x64, d=256) prec {prec} vs golden", flush=True)
+    from paper_2308_14258_amd import mf_autotune
+    g = np.load(os.path.join(HERE, "golden", "c4_fp64.npz"))
+    g1 = np.load(os.path.join(HERE, "golden", "c4_one_sweep.npz"))
+    w = mi.WORKLOADS["C4"]
+    params = mi.xavier_params(w["width"], 0)
+    f = mi.workload_field("C4")
+    p = dev(params)
+    sj, si = g["skel_j"], g["skel_i"]
+    aj, ai = g["sample_j"], g["sample_i"]
+    mf_autotune(ctx, p, dev(f), (64, 64), MF_CROSS, prec, trials=1)
+    u = dev(f)
+    u_out = torch.empty_like(u)
+    mf_solve(ctx, p, u, (64, 64), 1, prec=prec, u_out=u_out)
+    torch.cuda.synchronize()
+    err1 = rel_l2(u.cpu().numpy()[sj, si], g1["skel1"])
+    err1_out = rel_l2(u_out.cpu().numpy()[aj, ai], g1["u_out_sample"])
+    mf_solve(ctx, p, u, (64, 64), 19, prec=prec)
+    torch.cuda.synchronize()
+    err20 = rel_l2(u.cpu().numpy()[sj, si], g["skel20"])
+    mf_solve(ctx, p, u, (64, 64), w["sweeps"] - 20, prec=prec, u_out=u_out)
+    torch.cuda.synchronize()
+    err500 = rel_l2(u.cpu().numpy()[sj, si], g["skel500"])
+    err_out = rel_l2(u_out.cpu().numpy()[aj, ai], g["u_out_sample"])
+    print(f"C4 prec {prec} rel L2 vs oracle: sweep 1 skeleton {err1:.3e} u_out {err1_out:.3e}; "
+          f"skeleton@20 {err20:.3e} (reported); skeleton@500 {err500:.3e} u_out {err_out:.3e}",
+          flush=True)
+    assert err1 <= tol and err1_out <= tol
+    assert err500 <= tol and err_out <= tol
+
+
 def test_graph_replay_equals_direct_launches(ctx):
     print("case: graph replay vs direct launches", flush=True)
     params = dev(mi.random_params(256, seed=12))
@@ -294,7 +335,7 @@ def test_graph_replay_equals_direct_launches(ctx):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_BF16, 64),
+@pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_FP32, 64 | (1 << 17)), (MF_BF16, 64),
                                        (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
                                        (MF_BF16, 256 | (1 << 16))])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
@@ -326,7 +367,7 @@ def test_autotune_picks_a_candidate_and_is_used(ctx):
     f = mi.gp_field(8, 8, 1.0, seed=2)
     scratch = dev(f)
     best = mf_autotune(ctx, params, scratch, (8, 8), MF_CROSS, MF_BF16, trials=2)
-    assert best in (64, 128, 256)
+    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16))
     a = dev(f)
     mf_solve(ctx, params, a, (8, 8), 5, prec=MF_BF16)
     ctx.tile_rows(MF_BF16, best)
