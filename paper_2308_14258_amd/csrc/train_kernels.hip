@@ -266,64 +266,102 @@ __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restric
 // ---------------------------------------------------------------------------
 // Weight-gradient partials: for a chunk of stream rows,
 //   P[j][k] = sum_r Ab[r][j] H[r][k],  pb[j] = sum_{value rows} Ab[r][j].
-// MFMA with A = Ab^T (32 x 2 slices down the rows), B = H; wave w owns the
-// output row block j in [32 w, 32 w + 32) and all column blocks.
+// MFMA with A = Ab^T (32 x 2 slices down the rows), B = H. Sixteen waves
+// per workgroup: wave w owns output row block jb = w / WPJ and KBW column
+// blocks starting at (w % WPJ) KBW, so the whole D x D partial of a chunk
+// is computed by one workgroup with enough waves to keep the loads in
+// flight (the rows a wave reads are shared with its neighbours through L1).
 // ---------------------------------------------------------------------------
+constexpr int kWgradWaves = 16;
+
 template <int D>
-__global__ __launch_bounds__(2 * D) void wgrad_kernel(const float* __restrict__ Ab,
-                                                      const float* __restrict__ H, int64_t n_srows,
-                                                      int S, float* __restrict__ wpart,
-                                                      float* __restrict__ bpart) {
-  constexpr int NKB = D / 32;
+__global__ __launch_bounds__(64 * kWgradWaves) void wgrad_kernel(const float* __restrict__ Ab,
+                                                                 const float* __restrict__ H, int64_t n_srows,
+                                                                 int S, float* __restrict__ wpart,
+                                                                 float* __restrict__ bpart) {
+  constexpr int NB = D / 32;                 // 32-wide blocks per side
+  constexpr int WPJ = kWgradWaves / NB;      // waves per output row block
+  constexpr int KBW = NB / WPJ;              // column blocks per wave
+  static_assert(WPJ * KBW == NB && WPJ * NB == kWgradWaves, "wave split");
+  constexpr int NTH = 64 * kWgradWaves;
+  constexpr int BG = NTH / D;                // row groups of the bias partial
+  __shared__ float bsh[BG][D];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jb = wave / WPJ, kb0 = (wave % WPJ) * KBW;
   const int64_t r_begin = (int64_t)blockIdx.x * kChunk;
   const int64_t r_end = std::min<int64_t>(r_begin + kChunk, n_srows);
-  floatx16 acc[NKB];
+  floatx16 acc[KBW];
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
+  for (int q = 0; q < KBW; ++q)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[kb][v] = 0.0f;
+    for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
   const int col = lane & 31, half = lane >> 5;
-  const int ja = wave * 32 + col;
+  const int ja = jb * 32 + col;
   constexpr int U = 8;   // row pairs per batch of loads
   for (int64_t r0 = r_begin; r0 < r_end; r0 += 2 * U) {
-    float av[U], bv[U][NKB];
+    float av[U], bv[U][KBW];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t r = r0 + 2 * u + half;
       const bool ok = r < r_end;
       av[u] = ok ? Ab[r * D + ja] : 0.0f;
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) bv[u][kb] = ok ? H[r * D + kb * 32 + col] : 0.0f;
+      for (int q = 0; q < KBW; ++q) bv[u][q] = ok ? H[r * D + (kb0 + q) * 32 + col] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) acc[kb] = mfma32x32x2(av[u], bv[u][kb], acc[kb]);
+      for (int q = 0; q < KBW; ++q) acc[q] = mfma32x32x2(av[u], bv[u][q], acc[q]);
   }
   float* P = wpart + (int64_t)blockIdx.x * D * D;
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
+  for (int q = 0; q < KBW; ++q)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int jrow = wave * 32 + acc_row(lane, v);
-      P[(int64_t)jrow * D + kb * 32 + col] = acc[kb][v];
+      const int jrow = jb * 32 + acc_row(lane, v);
+      P[(int64_t)jrow * D + (kb0 + q) * 32 + col] = acc[q][v];
     }
+  // bias partial: row group g sums the value rows r_begin + g S, + BG S, ...
+  {
+    const int j = tid % D, g = tid / D;
+    float sb = 0.0f;
+    for (int64_t r = r_begin + (int64_t)g * S; r < r_end; r += (int64_t)BG * S) sb += Ab[r * D + j];
+    bsh[g][j] = sb;
+  }
+  __syncthreads();
   if (tid < D) {
-    float s = 0.0f;
-    for (int64_t r = r_begin; r < r_end; r += S) s += Ab[r * D + tid];
-    bpart[(int64_t)blockIdx.x * D + tid] = s;
+    float sb = 0.0f;
+#pragma unroll
+    for (int g = 0; g < BG; ++g) sb += bsh[g][tid];
+    bpart[(int64_t)blockIdx.x * D + tid] = sb;
   }
 }
 
-// out[i] (+)= scale * sum_p part[p * n + i], p in order.
-__global__ void reduce_parts_kernel(const float* __restrict__ part, int64_t n_parts, int64_t n,
-                                    int64_t stride, float* __restrict__ out, int accumulate) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+// out[i] (+)= sum_p part[p * stride + i]. Eight threads per element each sum
+// the partials p = g, g + 8, ... and the eight sums are added in g order, so
+// the result does not depend on the launch shape.
+constexpr int kReduceGroups = 8;
+
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restrict__ part, int64_t n_parts,
+                                                           int64_t n, int64_t stride, float* __restrict__ out,
+                                                           int accumulate) {
+  constexpr int EPB = 256 / kReduceGroups;   // elements per block
+  __shared__ float sh[kReduceGroups][EPB];
+  const int e = threadIdx.x % EPB, g = threadIdx.x / EPB;
+  for (int64_t i0 = (int64_t)blockIdx.x * EPB; i0 < n; i0 += (int64_t)gridDim.x * EPB) {
+    const int64_t i = i0 + e;
     float s = 0.0f;
-    for (int64_t p = 0; p < n_parts; ++p) s += part[p * stride + i];
-    out[i] = accumulate ? out[i] + s : s;
+    if (i < n)
+      for (int64_t p = g; p < n_parts; p += kReduceGroups) s += part[p * stride + i];
+    sh[g][e] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+      float t = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kReduceGroups; ++q) t += sh[q][e];
+      out[i] = accumulate ? out[i] + t : t;
+    }
+    __syncthreads();
   }
 }
 
@@ -523,11 +561,11 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
   int cur = 0;
   for (int l = 2; l >= 0; --l) {           // hidden layer l+2, input Z[l]
     float* Ab = tb.Ab[cur];
-    hipLaunchKernelGGL((wgrad_kernel<D>), dim3((unsigned)n_chunks), dim3(2 * D), 0, s, Ab, Z[l],
+    hipLaunchKernelGGL((wgrad_kernel<D>), dim3((unsigned)n_chunks), dim3(64 * kWgradWaves), 0, s, Ab, Z[l],
                        n_srows, S, tb.wpart, tb.bpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float* gW = grad + off_w2 + l * lstride;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256 / kReduceGroups)), dim3(256), 0, s,
                        tb.wpart, n_chunks, (int64_t)D * D, (int64_t)D * D, gW, accumulate ? 1 : 0);
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, tb.bpart, n_chunks, (int64_t)D,
                        (int64_t)D, gW + (int64_t)D * D, accumulate ? 1 : 0);
