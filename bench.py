@@ -41,7 +41,12 @@ INTERIOR_T = 961
 # WRITE_SIZE: 1.0). It is reported only while the kernel sources hash to the
 # value the counters were taken with; otherwise "traffic" is null. Summary:
 # profiles/*_traffic.md.
-MEASURED_TRAFFIC = {"sources_sha256": None, "bytes_per_launch": {}}
+MEASURED_TRAFFIC = {
+    "sources_sha256": "de645fc376b73af5225b841cb073616fe71ad442fa8e9c6ea5d2d415be7f01ce",
+    "bytes_per_launch": {"64": (5147.8 * 2.0 + 261.9) * 1024,
+                         "64|stream": (5099.4 * 2.0 + 261.9) * 1024,
+                         "32": (6006.5 * 2.0 + 268.6) * 1024},
+}
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
 
