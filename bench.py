@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SDNet point-evals/s in MF sweep (BF16 vs FP32 @ stated L2 err); train steps/s"
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2516.6
+PEAK_HBM_BYTES_PER_S = 8.0e12
 CROSS_T = 61
 INTERIOR_T = 961
 
@@ -202,6 +203,8 @@ def main():
         e_o = np.linalg.norm(uo - g["u_out_sample"]) / np.linalg.norm(g["u_out_sample"])
         parity = {"rel_l2_skeleton_vs_oracle": float(e_s), "rel_l2_u_out_vs_oracle": float(e_o)}
 
+    traffic = (MEASURED_TRAFFIC["bytes_per_launch"].get(tile_shape_name(tile_rows))
+               if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha() else None)
     out = {
         "metric": METRIC,
         "value": value,
@@ -224,10 +227,10 @@ def main():
                         "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": (MEASURED_TRAFFIC["bytes_per_launch"].get(tile_shape_name(tile_rows))
-                                 if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha()
-                                 else None),
+                     "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+                     "hbm_gbps": traffic / (avg_us * 1e3) if traffic else None,
+                     "hbm_frac": traffic / (avg_us * 1e-6) / PEAK_HBM_BYTES_PER_S if traffic else None,
                      "kernel": "tile_kernel<256,R,CROSS,FP32> (colour phase)",
                      "flops_per_point_eval": fpp},
         "parity": parity,
@@ -339,6 +342,7 @@ def bf16_comparison(ctx, sweeps):
     res = {"workload": f"C4: 64x64 units, width {width}, e^x sin y scaled, {sweeps} CROSS sweeps "
                        "+ assembly"}
     outs = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "c4_fp64.npz")   # oracle values, 500 sweeps
     evals = sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
     from paper_2308_14258_amd import mf_autotune
     for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
@@ -362,6 +366,14 @@ def bf16_comparison(ctx, sweeps):
         res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt, "tile_shape": tile_shape_name(shape),
                      "phase_avg_us": ms * 1e3 / max(launches, 1),
                      "phase_tflops": ach, "phase_frac_of_mfma_peak": ach / peak}
+        if sweeps == w["sweeps"] and os.path.exists(gpath):
+            g = np.load(gpath)
+            sk = u.cpu().numpy().astype(np.float64)[g["skel_j"], g["skel_i"]]
+            uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
+            res[name]["rel_l2_skeleton_vs_oracle"] = float(np.linalg.norm(sk - g["skel500"]) /
+                                                           np.linalg.norm(g["skel500"]))
+            res[name]["rel_l2_u_out_vs_oracle"] = float(np.linalg.norm(uo - g["u_out_sample"]) /
+                                                        np.linalg.norm(g["u_out_sample"]))
         outs[name] = u_out.double()
     d = outs["bf16"][1:-1, 1:-1] - outs["fp32"][1:-1, 1:-1]
     res["rel_l2_bf16_vs_fp32_u_out"] = float(d.norm() / outs["fp32"][1:-1, 1:-1].norm())

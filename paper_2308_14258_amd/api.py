@@ -304,5 +304,61 @@ def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: tor
     return loss
 
 
-__all__ = ["Batch", "Context", "mf_autotune", "mf_solve_adjoint", "mf_sweep", "mf_solve", "mf_sweep_operator", "sdnet_forward",
-           "sdnet_train_step", "width_of", "sdnet_desc", "domain_desc", "_lib"]
+def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.Tensor,
+                    Xc: torch.Tensor, loss: torch.Tensor | None = None,
+                    grad_out: torch.Tensor | None = None):
+    """(L_data, L_pde) of Alg. 1 at `params` and the gradient of
+    L_data + L_pde from the library's hand-written reverse pass, with no
+    parameter update (sdnet_train_step with grad_out). Returns (loss [2],
+    grad), both device tensors."""
+    for t, name in ((params, "params"), (G, "G"), (Xb, "Xb"), (Xc, "Xc")):
+        _need_cuda_f32(t, name)
+    width = width_of(params)
+    B, nc = Xc.shape[0], Xc.shape[1]
+    if loss is None:
+        loss = torch.empty(2, device=G.device, dtype=torch.float32)
+    if grad_out is None:
+        grad_out = torch.empty_like(params)
+    _need_cuda_f32(grad_out, "grad_out")
+    n = ctypes.c_size_t()
+    lib = load()
+    check(lib.sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nc, ctypes.byref(n)),
+          "sdnet_train_ws_size")
+    ws = ctx.workspace(n.value)
+    check(lib.sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), None, None, 1,
+                               None, _ptr(G.contiguous()), B, _ptr(Xb.contiguous()),
+                               _ptr(Xc.contiguous()), nc, _ptr(loss), _ptr(grad_out), _ptr(ws),
+                               ws.numel(), _stream()),
+          "sdnet_train_step")
+    return loss, grad_out
+
+
+class PhysicsLoss(torch.autograd.Function):
+    """L = L_data + L_pde (Alg. 1: boundary match plus the squared Laplacian
+    residual of Eq. 3) as a differentiable function of the flat parameter
+    vector. The forward and the backward are one call of the library's
+    training kernels (Taylor-mode forward, hand-written reverse pass); the
+    backward returns the saved gradient scaled by the incoming one, so the
+    loss composes with torch optimisers and other loss terms."""
+
+    @staticmethod
+    def forward(fctx, params, G, Xb, Xc, mf_ctx):
+        loss, grad = sdnet_loss_grad(mf_ctx, params.detach(), G, Xb, Xc)
+        fctx.save_for_backward(grad)
+        return loss.sum()
+
+    @staticmethod
+    def backward(fctx, g):
+        (grad,) = fctx.saved_tensors
+        return g * grad, None, None, None, None
+
+
+def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.Tensor,
+                 Xc: torch.Tensor) -> torch.Tensor:
+    """Scalar L_data + L_pde whose .backward() runs the hand-written reverse pass."""
+    return PhysicsLoss.apply(params, G, Xb, Xc, ctx)
+
+
+__all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep", "mf_solve",
+           "mf_sweep_operator", "physics_loss", "sdnet_forward", "sdnet_loss_grad", "sdnet_train_step",
+           "width_of", "sdnet_desc", "domain_desc", "_lib"]

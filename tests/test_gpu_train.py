@@ -17,7 +17,7 @@ import torch
 
 import mf_inputs as mi
 from oracle import sdnet, train
-from paper_2308_14258_amd import Context, sdnet_forward, sdnet_train_step
+from paper_2308_14258_amd import Context, physics_loss, sdnet_forward, sdnet_loss_grad, sdnet_train_step
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -176,3 +176,50 @@ def test_forward_derivatives(ctx, width, per_bc):
     errs = (rel(U, u), rel(dU[..., 0], ux), rel(dU[..., 1], uy), rel(lapU, lap))
     print(f"forward derivative rel L2 (u, ux, uy, lap): {errs}", flush=True)
     assert errs[0] <= 1e-5 and errs[1] <= 1e-5 and errs[2] <= 1e-5 and errs[3] <= 1e-4
+
+
+def test_autograd_function_gives_the_library_gradient(ctx):
+    """physics_loss(...).backward() (torch.autograd.Function around the
+    hand-written reverse pass) puts exactly the library's gradient into
+    params.grad, scaled by the incoming gradient, and the value is
+    L_data + L_pde; the gradient matches the float64 oracle."""
+    print("case: autograd Function width=128 B=4 nc=8", flush=True)
+    width = 128
+    params = mi.random_params(width, seed=23)
+    G, Xb, Xc = _batch(4, 8, seed=11)
+    Gd, Xbd, Xcd = _d(G), _d(Xb), _d(Xc)
+    p = _d(params).requires_grad_(True)
+    L = physics_loss(ctx, p, Gd, Xbd, Xcd)
+    (3.0 * L).backward()
+    loss, grad = sdnet_loss_grad(ctx, _d(params), Gd, Xbd, Xcd)
+    torch.cuda.synchronize()
+    assert torch.equal(p.grad, 3.0 * grad)
+    assert abs(L.item() - loss.sum().item()) <= 1e-6 * abs(loss.sum().item())
+    ld, lp, gd, gp = train.gradient(_t64(params), width, _t64(G), _t64(Xb), _t64(Xc))
+    want = (gd + gp).numpy()
+    got = grad.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"autograd Function gradient rel L2 vs oracle {err:.3e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_torch_adam_on_the_autograd_loss_tracks_the_fused_step(ctx):
+    """Three steps of torch.optim.Adam driven by physics_loss follow the
+    library's fused Adam step (sdnet_train_step) to float32 rounding."""
+    print("case: torch Adam vs fused Adam, 3 steps", flush=True)
+    width = 128
+    params = mi.random_params(width, seed=29)
+    G, Xb, Xc = _batch(4, 8, seed=13)
+    Gd, Xbd, Xcd = _d(G), _d(Xb), _d(Xc)
+    p = _d(params).requires_grad_(True)
+    opt = torch.optim.Adam([p], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    q, m, v = _d(params), torch.zeros_like(p), torch.zeros_like(p)
+    for k in range(1, 4):
+        opt.zero_grad()
+        physics_loss(ctx, p, Gd, Xbd, Xcd).backward()
+        opt.step()
+        sdnet_train_step(ctx, q, m, v, k, Gd, Xbd, Xcd, lr=1e-3)
+    torch.cuda.synchronize()
+    d = (p.detach() - q).norm() / (_d(params) - q).norm()
+    print(f"torch Adam vs fused: relative difference of the update {d.item():.3e}", flush=True)
+    assert d.item() <= 1e-4
