@@ -86,7 +86,7 @@ TrainLayout train_layout(int width, int64_t B, int64_t nc) {
   T.net = net_layout(width, MF_FP32, 0);
   const size_t d = (size_t)width;
   const size_t SR = (size_t)std::max<int64_t>(4 * B * nc, B * 128);   // stream rows
-  const size_t chunks = (SR + 4095) / 4096;
+  const size_t chunks = kBwdGroups;   // weight-gradient partials: one per reverse-kernel workgroup
   const size_t P = (size_t)(d * 130 + d + 3 * (d * d + d) + d + 1);
   size_t o = T.net.end;
   T.whT = o; o = align256(o + 3 * d * d * 4);

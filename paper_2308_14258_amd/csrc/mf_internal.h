@@ -102,13 +102,17 @@ hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const fl
                                float* U, hipStream_t s);
 
 // Training: device buffers carved from the workspace.
+// Upper bound of the fused reverse kernel's persistent grid = number of
+// weight-gradient partials in the training workspace.
+constexpr int kBwdGroups = 512;
+
 struct TrainBuffers {
   float* C;          // [B][d] boundary projections (b1 included)
   float* Z[4];       // [SR][d] stream rows after layers 1..4 (z, z_x, z_y, z_L)
   float* Sv[4];      // [SR][d] saved (z, a_x, a_y, a_L) of layers 1..4
   float* Ab[2];      // [SR][d] ping-pong pre-activation adjoints
-  float* wpart;      // [n_chunks][d*d] weight-gradient partials
-  float* bpart;      // [n_chunks][d]
+  float* wpart;      // [kBwdGroups][d*d] weight-gradient partials
+  float* bpart;      // [kBwdGroups][d]
   float* opart[2];   // [2048][d+2] output-layer partials (data, collocation)
   float* l1[2];      // [3][B][d] first-layer sums (data, collocation)
   float* grad;       // [P] gradient (used when the caller gives none)

@@ -33,7 +33,6 @@
 
 namespace mf {
 
-constexpr int kChunk = 4096;       // stream rows per weight-gradient partial
 constexpr int kOutWaves = 2048;    // waves of the output-layer kernel
 
 // ---------------------------------------------------------------------------
@@ -181,6 +180,118 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Reverse pass of one hidden layer fused with its weight gradient. A
+// persistent grid: workgroup b takes the 64-row tiles b, b + gridDim.x, ...
+// For each tile the pre-activation adjoints Ab and the layer inputs H are
+// staged in LDS once and serve both products:
+//   (i)  the input adjoint Ab W (MFMA, weights streamed as in the forward)
+//        with the reverse tanh rules of the previous layer -> Out;
+//   (ii) the weight gradient P[j][k] += sum_r Ab[r][j] H[r][k], held in
+//        MFMA accumulators across the workgroup's tiles (wave w owns rows
+//        j in [32 w, 32 w + 32) and all column blocks), and the bias
+//        gradient sum over value rows of Ab.
+// Each workgroup writes one partial; the partials are summed in workgroup
+// order, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+
+template <int D, int S>
+__device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t row0, int j, int h,
+                                             const float* __restrict__ Sv_in, float* __restrict__ Out,
+                                             int64_t n_srows) {
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int64_t sr = row0 + rb * 32 + 8 * m + 4 * h;   // first of 4 consecutive rows
+      if constexpr (S == 4) {
+        if (sr >= n_srows) continue;
+        const int64_t o = sr * D + j;
+        const float z = Sv_in[o], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
+        const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
+        const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
+        const float s = 1.0f - z * z, q = ax * ax + ay * ay;
+        Out[o] = s * zb - 2.0f * z * s * (ax * zbx + ay * zby) -
+                 zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
+        Out[o + D] = s * (zbx - 4.0f * z * ax * zbL);
+        Out[o + 2 * D] = s * (zby - 4.0f * z * ay * zbL);
+        Out[o + 3 * D] = s * zbL;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = sr + e;
+          if (row >= n_srows) continue;
+          const int64_t o = row * D + j;
+          const float z = Sv_in[o];
+          Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
+        }
+      }
+    }
+  }
+}
+
+template <int D, int S>
+__global__ __launch_bounds__(2 * D) void taylor_bwd_kernel(const float* __restrict__ Ab,
+                                                           const float* __restrict__ H,
+                                                           const floatx4* __restrict__ wsw,
+                                                           const float* __restrict__ Sv_in,
+                                                           float* __restrict__ Out, int64_t n_srows,
+                                                           float* __restrict__ wpart,
+                                                           float* __restrict__ bpart) {
+  constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D, NKB = D / 32;
+  __shared__ __align__(16) float HA[R * LDH];
+  __shared__ __align__(16) float HH[R * LDH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, h = lane >> 5;
+  const int j = wave * 32 + col;
+  floatx16 accw[NKB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) accw[kb][v] = 0.0f;
+  float bsum = 0.0f;
+  const int64_t n_tiles = (n_srows + R - 1) / R;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t row0 = t * R;
+    for (int idx = tid; idx < R * D / 4; idx += NTH) {
+      const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+      floatx4 va = {0.0f, 0.0f, 0.0f, 0.0f}, vh = va;
+      if (row0 + r < n_srows) {
+        va = reinterpret_cast<const floatx4*>(Ab + (row0 + r) * D)[c4];
+        vh = reinterpret_cast<const floatx4*>(H + (row0 + r) * D)[c4];
+      }
+      *reinterpret_cast<floatx4*>(&HA[r * LDH + 4 * c4]) = va;
+      *reinterpret_cast<floatx4*>(&HH[r * LDH + 4 * c4]) = vh;
+    }
+    __syncthreads();
+    // (i) input adjoint and reverse rules
+    floatx16 acc[RB];
+    mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
+    bwd_epilogue<D, S>(acc, row0, j, h, Sv_in, Out, n_srows);
+    // (ii) weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
+    // at MFMA step e to both operands
+#pragma unroll 2
+    for (int g = 0; g < R / 8; ++g) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = 8 * g + 4 * h + e;
+        const float a = HA[r * LDH + j];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) accw[kb] = mfma32x32x2(a, HH[r * LDH + kb * 32 + col], accw[kb]);
+      }
+    }
+    if (tid < D)
+      for (int r = 0; r < R; r += S) bsum += HA[r * LDH + tid];   // value rows (zero beyond the end)
+    __syncthreads();   // the next tile overwrites the LDS
+  }
+  float* P = wpart + (int64_t)blockIdx.x * D * D;
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) P[(int64_t)(wave * 32 + acc_row(lane, v)) * D + kb * 32 + col] = accw[kb][v];
+  if (tid < D) bpart[(int64_t)blockIdx.x * D + tid] = bsum;
+}
+
+// ---------------------------------------------------------------------------
 // Output layer, loss and the seed of the reverse pass. One wave per point.
 //   S = 4 (collocation): residual u_L = w5 . z_L; ub_L = 2 u_L / n.
 //   S = 1 (data):        residual u - g; ub = 2 (u - g) / n.
@@ -260,80 +371,6 @@ __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restric
   if (lane == 0) {
     op[D] = gb5;
     op[D + 1] = lsum;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Weight-gradient partials: for a chunk of stream rows,
-//   P[j][k] = sum_r Ab[r][j] H[r][k],  pb[j] = sum_{value rows} Ab[r][j].
-// MFMA with A = Ab^T (32 x 2 slices down the rows), B = H. Sixteen waves
-// per workgroup: wave w owns output row block jb = w / WPJ and KBW column
-// blocks starting at (w % WPJ) KBW, so the whole D x D partial of a chunk
-// is computed by one workgroup with enough waves to keep the loads in
-// flight (the rows a wave reads are shared with its neighbours through L1).
-// ---------------------------------------------------------------------------
-constexpr int kWgradWaves = 16;
-
-template <int D>
-__global__ __launch_bounds__(64 * kWgradWaves) void wgrad_kernel(const float* __restrict__ Ab,
-                                                                 const float* __restrict__ H, int64_t n_srows,
-                                                                 int S, float* __restrict__ wpart,
-                                                                 float* __restrict__ bpart) {
-  constexpr int NB = D / 32;                 // 32-wide blocks per side
-  constexpr int WPJ = kWgradWaves / NB;      // waves per output row block
-  constexpr int KBW = NB / WPJ;              // column blocks per wave
-  static_assert(WPJ * KBW == NB && WPJ * NB == kWgradWaves, "wave split");
-  constexpr int NTH = 64 * kWgradWaves;
-  constexpr int BG = NTH / D;                // row groups of the bias partial
-  __shared__ float bsh[BG][D];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int jb = wave / WPJ, kb0 = (wave % WPJ) * KBW;
-  const int64_t r_begin = (int64_t)blockIdx.x * kChunk;
-  const int64_t r_end = std::min<int64_t>(r_begin + kChunk, n_srows);
-  floatx16 acc[KBW];
-#pragma unroll
-  for (int q = 0; q < KBW; ++q)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
-  const int col = lane & 31, half = lane >> 5;
-  const int ja = jb * 32 + col;
-  constexpr int U = 8;   // row pairs per batch of loads
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += 2 * U) {
-    float av[U], bv[U][KBW];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t r = r0 + 2 * u + half;
-      const bool ok = r < r_end;
-      av[u] = ok ? Ab[r * D + ja] : 0.0f;
-#pragma unroll
-      for (int q = 0; q < KBW; ++q) bv[u][q] = ok ? H[r * D + (kb0 + q) * 32 + col] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < KBW; ++q) acc[q] = mfma32x32x2(av[u], bv[u][q], acc[q]);
-  }
-  float* P = wpart + (int64_t)blockIdx.x * D * D;
-#pragma unroll
-  for (int q = 0; q < KBW; ++q)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int jrow = jb * 32 + acc_row(lane, v);
-      P[(int64_t)jrow * D + (kb0 + q) * 32 + col] = acc[q][v];
-    }
-  // bias partial: row group g sums the value rows r_begin + g S, + BG S, ...
-  {
-    const int j = tid % D, g = tid / D;
-    float sb = 0.0f;
-    for (int64_t r = r_begin + (int64_t)g * S; r < r_end; r += (int64_t)BG * S) sb += Ab[r * D + j];
-    bsh[g][j] = sb;
-  }
-  __syncthreads();
-  if (tid < D) {
-    float sb = 0.0f;
-#pragma unroll
-    for (int g = 0; g < BG; ++g) sb += bsh[g][tid];
-    bpart[(int64_t)blockIdx.x * D + tid] = sb;
   }
 }
 
@@ -557,27 +594,24 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
 
   const int64_t off_w2 = (int64_t)D * 130 + D;
   const int64_t lstride = (int64_t)D * D + D;
-  const int64_t n_chunks = (n_srows + kChunk - 1) / kChunk;
+  const int64_t n_tiles = (n_srows + 63) / 64;
+  const int64_t groups = std::min<int64_t>(n_tiles, kBwdGroups);
   int cur = 0;
   for (int l = 2; l >= 0; --l) {           // hidden layer l+2, input Z[l]
     float* Ab = tb.Ab[cur];
-    hipLaunchKernelGGL((wgrad_kernel<D>), dim3((unsigned)n_chunks), dim3(64 * kWgradWaves), 0, s, Ab, Z[l],
-                       n_srows, S, tb.wpart, tb.bpart);
+    const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
+    if (S == 4)
+      hipLaunchKernelGGL((taylor_bwd_kernel<D, 4>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l], wT,
+                         Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+    else
+      hipLaunchKernelGGL((taylor_bwd_kernel<D, 1>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l], wT,
+                         Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float* gW = grad + off_w2 + l * lstride;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256 / kReduceGroups)), dim3(256), 0, s,
-                       tb.wpart, n_chunks, (int64_t)D * D, (int64_t)D * D, gW, accumulate ? 1 : 0);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, tb.bpart, n_chunks, (int64_t)D,
+                       tb.wpart, groups, (int64_t)D * D, (int64_t)D * D, gW, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, tb.bpart, groups, (int64_t)D,
                        (int64_t)D, gW + (int64_t)D * D, accumulate ? 1 : 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
-    const unsigned blocks = (unsigned)((n_srows + 63) / 64);
-    if (S == 4)
-      hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab, wT,
-                         nullptr, Sv[l], tb.Ab[cur ^ 1], nullptr, n_srows);
-    else
-      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab, wT,
-                         nullptr, Sv[l], tb.Ab[cur ^ 1], nullptr, n_srows);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
