@@ -85,7 +85,6 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
       Z[o + 2 * D] = s * wy;
       Z[o + 3 * D] = -2.0f * z * s * (wx * wx + wy * wy);
       if (Sv) {
-        Sv[o] = z;
         Sv[o + D] = wx;
         Sv[o + 2 * D] = wy;
         Sv[o + 3 * D] = 0.0f;
@@ -97,8 +96,10 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 // GEMM over stream rows with a Taylor epilogue.
 //   MODE 0 (forward):  P = Zin W^T (+ b on the value stream) -> tanh rules ->
-//                      Zout (z streams) and Sv (z, a_x, a_y, a_L);
-//   MODE 1 (backward): Zb = Ain W -> reverse tanh rules with Sv -> Aout.
+//                      Zout (z streams) and Sv (a_x, a_y, a_L in the rows of
+//                      the derivative streams; z is Zout's value row);
+//   MODE 1 (backward, value stream only): Zb = Ain W -> Aout = (1 - z^2) Zb.
+// The four-stream backward is the fused taylor_bwd_kernel below.
 // A tile is 64 stream rows x D columns; the tile is staged in LDS.
 // ---------------------------------------------------------------------------
 template <int D, int S, int MODE>
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
                                                             float* __restrict__ Out,
                                                             float* __restrict__ Sv_out,
                                                             int64_t n_srows) {
+  static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_kernel");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
   __shared__ __align__(16) float Hs[R * LDH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -144,22 +146,11 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
           Out[o + D] = s * ax;
           Out[o + 2 * D] = s * ay;
           Out[o + 3 * D] = s * aL - 2.0f * z * s * (ax * ax + ay * ay);
-          if (Sv_out) {
-            Sv_out[o] = z;
+          if (Sv_out) {   // z itself is the value row of Out
             Sv_out[o + D] = ax;
             Sv_out[o + 2 * D] = ay;
             Sv_out[o + 3 * D] = aL;
           }
-        } else {
-          const float z = Sv_in[o], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
-          const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
-          const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
-          const float s = 1.0f - z * z, q = ax * ax + ay * ay;
-          Out[o] = s * zb - 2.0f * z * s * (ax * zbx + ay * zby) -
-                   zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
-          Out[o + D] = s * (zbx - 4.0f * z * ax * zbL);
-          Out[o + 2 * D] = s * (zby - 4.0f * z * ay * zbL);
-          Out[o + 3 * D] = s * zbL;
         }
       } else {
 #pragma unroll
@@ -194,19 +185,23 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
 // order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 
-template <int D, int S>
+// Reverse tanh rules of the previous layer applied to Zb = Ab W (acc). z is
+// that layer's output, i.e. the value rows of the layer-input tile `HH`
+// (LDS, row pitch LDH); a_x, a_y, a_L come from the saved streams Sv_in.
+template <int D, int S, int LDH>
 __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t row0, int j, int h,
-                                             const float* __restrict__ Sv_in, float* __restrict__ Out,
-                                             int64_t n_srows) {
+                                             const float* HH, const float* __restrict__ Sv_in,
+                                             float* __restrict__ Out, int64_t n_srows) {
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int64_t sr = row0 + rb * 32 + 8 * m + 4 * h;   // first of 4 consecutive rows
+      const int lr = rb * 32 + 8 * m + 4 * h;                // first of 4 consecutive rows in the tile
+      const int64_t sr = row0 + lr;
       if constexpr (S == 4) {
         if (sr >= n_srows) continue;
         const int64_t o = sr * D + j;
-        const float z = Sv_in[o], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
+        const float z = HH[lr * LDH + j], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
         const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
         const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
         const float s = 1.0f - z * z, q = ax * ax + ay * ay;
@@ -220,9 +215,8 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
         for (int e = 0; e < 4; ++e) {
           const int64_t row = sr + e;
           if (row >= n_srows) continue;
-          const int64_t o = row * D + j;
-          const float z = Sv_in[o];
-          Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
+          const float z = HH[(lr + e) * LDH + j];
+          Out[row * D + j] = (1.0f - z * z) * acc[rb][4 * m + e];
         }
       }
     }
@@ -250,23 +244,38 @@ __global__ __launch_bounds__(2 * D) void taylor_bwd_kernel(const float* __restri
     for (int v = 0; v < 16; ++v) accw[kb][v] = 0.0f;
   float bsum = 0.0f;
   const int64_t n_tiles = (n_srows + R - 1) / R;
+  // the next tile's adjoint rows are loaded into registers while this one
+  // computes (the input rows follow with the LDS stores)
+  constexpr int PER = R * D / 4 / NTH;   // float4 per thread per array
+  floatx4 pa[PER];
+  auto fetch = [&](int64_t t) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = tid + i * NTH;
+      const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+      const int64_t row = t * R + r;
+      pa[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      if (t < n_tiles && row < n_srows) pa[i] = reinterpret_cast<const floatx4*>(Ab + row * D)[c4];
+    }
+  };
+  fetch(blockIdx.x);
   for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
     const int64_t row0 = t * R;
-    for (int idx = tid; idx < R * D / 4; idx += NTH) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = tid + i * NTH;
       const int r = idx / (D / 4), c4 = idx - r * (D / 4);
-      floatx4 va = {0.0f, 0.0f, 0.0f, 0.0f}, vh = va;
-      if (row0 + r < n_srows) {
-        va = reinterpret_cast<const floatx4*>(Ab + (row0 + r) * D)[c4];
-        vh = reinterpret_cast<const floatx4*>(H + (row0 + r) * D)[c4];
-      }
-      *reinterpret_cast<floatx4*>(&HA[r * LDH + 4 * c4]) = va;
+      floatx4 vh = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (row0 + r < n_srows) vh = reinterpret_cast<const floatx4*>(H + (row0 + r) * D)[c4];
+      *reinterpret_cast<floatx4*>(&HA[r * LDH + 4 * c4]) = pa[i];
       *reinterpret_cast<floatx4*>(&HH[r * LDH + 4 * c4]) = vh;
     }
     __syncthreads();
+    fetch(t + gridDim.x);
     // (i) input adjoint and reverse rules
     floatx16 acc[RB];
     mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
-    bwd_epilogue<D, S>(acc, row0, j, h, Sv_in, Out, n_srows);
+    bwd_epilogue<D, S, LDH>(acc, row0, j, h, HH, Sv_in, Out, n_srows);
     // (ii) weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
     // at MFMA step e to both operands
 #pragma unroll 2
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restric
       for (int t = 0; t < NJ; ++t) {
         const int j = lane + 64 * t;
         gw5[t] = fmaf(ubL, zL[t], gw5[t]);
-        const float z = Sv4[o + j], ax = Sv4[o + D + j], ay = Sv4[o + 2 * D + j];
+        const float z = Z4[o + j], ax = Sv4[o + D + j], ay = Sv4[o + 2 * D + j];
         const float aL = Sv4[o + 3 * D + j];
         const float zbL = w5r[t] * ubL;
         const float s = 1.0f - z * z, q = ax * ax + ay * ay;
@@ -388,8 +397,10 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restri
   for (int64_t i0 = (int64_t)blockIdx.x * EPB; i0 < n; i0 += (int64_t)gridDim.x * EPB) {
     const int64_t i = i0 + e;
     float s = 0.0f;
-    if (i < n)
+    if (i < n) {
+#pragma unroll 8
       for (int64_t p = g; p < n_parts; p += kReduceGroups) s += part[p * stride + i];
+    }
     sh[g][e] = s;
     __syncthreads();
     if (g == 0 && i < n) {
@@ -434,52 +445,112 @@ __global__ __launch_bounds__(D) void layer1_reduce_kernel(const float* __restric
 }
 
 // grad W1g[j][k] = sum_b (c0[b][j] + c1[b][j]) G[b][k]; b1, W1x from the sums.
+// Workgroup g < D/8 owns rows j in [8 g, 8 g + 8) and all 128 k, with the
+// conditions b staged through LDS in chunks of 64 (each (j, k) is summed
+// over b in ascending order); the last workgroup forms b1 and W1x.
+constexpr int kL1Rows = 8, kL1Chunk = 64;
+
 template <int D>
 __global__ __launch_bounds__(256) void layer1_grad_kernel(const float* __restrict__ l1a,
                                                           const float* __restrict__ l1b,
                                                           const float* __restrict__ G, int64_t B,
                                                           float* __restrict__ grad) {
   const int64_t off_b1 = (int64_t)D * 130;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < D * 128) {
-    const int j = t / 128, k = t % 128;
-    float s = 0.0f;
-    for (int64_t b = 0; b < B; ++b) s = fmaf(l1a[b * D + j] + l1b[b * D + j], G[b * 128 + k], s);
-    grad[(int64_t)j * 130 + k] = s;
-  } else if (t < D * 128 + D) {
-    const int j = t - D * 128;
+  if (blockIdx.x == D / kL1Rows) {
+    // 256 / D threads per j, each summing every (256 / D)-th condition; the
+    // partial sums are added in thread order
+    constexpr int TPJ = 256 / D;
+    __shared__ float red[3][256];
+    const int j = threadIdx.x % D, q = threadIdx.x / D;
     float c = 0.0f, cx = 0.0f, cy = 0.0f;
-    for (int64_t b = 0; b < B; ++b) {
+#pragma unroll 8
+    for (int64_t b = q; b < B; b += TPJ) {
       c += l1a[b * D + j] + l1b[b * D + j];
       cx += l1a[(B + b) * D + j] + l1b[(B + b) * D + j];
       cy += l1a[(2 * B + b) * D + j] + l1b[(2 * B + b) * D + j];
     }
-    grad[(int64_t)j * 130 + 128] = cx;
-    grad[(int64_t)j * 130 + 129] = cy;
-    grad[off_b1 + j] = c;
+    red[0][threadIdx.x] = c;
+    red[1][threadIdx.x] = cx;
+    red[2][threadIdx.x] = cy;
+    __syncthreads();
+    if (q == 0) {
+      c = cx = cy = 0.0f;
+#pragma unroll
+      for (int u = 0; u < TPJ; ++u) {
+        c += red[0][u * D + j];
+        cx += red[1][u * D + j];
+        cy += red[2][u * D + j];
+      }
+      grad[(int64_t)j * 130 + 128] = cx;
+      grad[(int64_t)j * 130 + 129] = cy;
+      grad[off_b1 + j] = c;
+    }
+    return;
   }
+  __shared__ float gs[kL1Chunk][128];
+  __shared__ float ls[kL1Chunk][kL1Rows];
+  const int j0 = blockIdx.x * kL1Rows;
+  const int k = threadIdx.x & 127, js = threadIdx.x >> 7;   // rows j0 + js + 2 i, i < 4
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t b0 = 0; b0 < B; b0 += kL1Chunk) {
+    for (int idx = threadIdx.x; idx < kL1Chunk * 128; idx += 256) {
+      const int bb = idx >> 7, kk = idx & 127;
+      gs[bb][kk] = (b0 + bb < B) ? G[(b0 + bb) * 128 + kk] : 0.0f;
+    }
+    for (int idx = threadIdx.x; idx < kL1Chunk * kL1Rows; idx += 256) {
+      const int bb = idx / kL1Rows, jj = idx - bb * kL1Rows;
+      const int64_t b = b0 + bb;
+      ls[bb][jj] = (b < B) ? l1a[b * D + j0 + jj] + l1b[b * D + j0 + jj] : 0.0f;
+    }
+    __syncthreads();
+    const int nb = (int)std::min<int64_t>(kL1Chunk, B - b0);
+    for (int bb = 0; bb < nb; ++bb) {
+      const float g = gs[bb][k];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = fmaf(ls[bb][js + 2 * i], g, acc[i]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) grad[(int64_t)(j0 + js + 2 * i) * 130 + k] = acc[i];
 }
 
-// Output-layer gradient and the two losses from the per-wave partials.
+// Output-layer gradient and the two losses from the per-wave partials:
+// eight threads per element each sum every eighth wave's partial, and the
+// eight sums are added in order.
 template <int D>
 __global__ __launch_bounds__(256) void output_grad_kernel(const float* __restrict__ op_data,
                                                           const float* __restrict__ op_col,
                                                           float inv_data, float inv_col,
                                                           float* __restrict__ grad,
                                                           float* __restrict__ loss) {
+  constexpr int EPB = 256 / kReduceGroups;
+  __shared__ float sh[2][kReduceGroups][EPB];
   const int64_t off_w5 = (int64_t)D * 130 + D + 3 * ((int64_t)D * D + D);
-  const int t = threadIdx.x;
-  for (int j = t; j < D + 2; j += 256) {
-    float s0 = 0.0f, s1 = 0.0f;
-    for (int w = 0; w < kOutWaves; ++w) {
+  const int e = threadIdx.x % EPB, g = threadIdx.x / EPB;
+  const int j = blockIdx.x * EPB + e;
+  float s0 = 0.0f, s1 = 0.0f;
+  if (j < D + 2) {
+#pragma unroll 8
+    for (int w = g; w < kOutWaves; w += kReduceGroups) {
       s0 += op_data[(int64_t)w * (D + 2) + j];
       s1 += op_col[(int64_t)w * (D + 2) + j];
     }
-    if (j < D) grad[off_w5 + j] = s0 + s1;
-    else if (j == D) grad[off_w5 + D] = s0 + s1;
+  }
+  sh[0][g][e] = s0;
+  sh[1][g][e] = s1;
+  __syncthreads();
+  if (g == 0 && j < D + 2) {
+    float t0 = 0.0f, t1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kReduceGroups; ++q) {
+      t0 += sh[0][q][e];
+      t1 += sh[1][q][e];
+    }
+    if (j <= D) grad[off_w5 + j] = t0 + t1;
     else {
-      loss[0] = s0 * inv_data;
-      loss[1] = s1 * inv_col;
+      loss[0] = t0 * inv_data;
+      loss[1] = t1 * inv_col;
     }
   }
 }
@@ -641,10 +712,11 @@ static hipError_t train_step_d(const NetPtrs& net, const float* whT, const Train
   // Alg. 1 step 2: collocation points, four streams; accumulate.
   e = run_pass<D>(net, whT, tb, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((layer1_grad_kernel<D>), dim3((D * 128 + D + 255) / 256), dim3(256), 0, s,
-                     tb.l1[0], tb.l1[1], G, B, grad);
+  hipLaunchKernelGGL((layer1_grad_kernel<D>), dim3(D / kL1Rows + 1), dim3(256), 0, s, tb.l1[0], tb.l1[1], G, B,
+                     grad);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((output_grad_kernel<D>), dim3(1), dim3(256), 0, s, tb.opart[0], tb.opart[1],
+  hipLaunchKernelGGL((output_grad_kernel<D>), dim3((D + 2 + 256 / kReduceGroups - 1) / (256 / kReduceGroups)),
+                     dim3(256), 0, s, tb.opart[0], tb.opart[1],
                      1.0f / (float)(B * 128), 1.0f / (float)(B * nc), grad, loss);
   return hipGetLastError();
 }
