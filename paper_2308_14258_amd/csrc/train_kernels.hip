@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
 //                      Zout (z streams) and Sv (a_x, a_y, a_L in the rows of
 //                      the derivative streams; z is Zout's value row);
 //   MODE 1 (backward, value stream only): Zb = Ain W -> Aout = (1 - z^2) Zb.
-// The four-stream backward is the fused taylor_bwd_kernel below.
+// The four-stream backward is the fused taylor_bwd_split_kernel /
+// taylor_bwd_seq_kernel below.
 // A tile is 64 stream rows x D columns; the tile is staged in LDS.
 // ---------------------------------------------------------------------------
 template <int D, int S, int MODE>
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
                                                             float* __restrict__ Out,
                                                             float* __restrict__ Sv_out,
                                                             int64_t n_srows) {
-  static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_kernel");
+  static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_*_kernel");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
   __shared__ __align__(16) float Hs[R * LDH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -224,7 +225,96 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
 }
 
 template <int D, int S>
-__global__ __launch_bounds__(2 * D) void taylor_bwd_kernel(const float* __restrict__ Ab,
+__global__ __launch_bounds__(4 * D) void taylor_bwd_split_kernel(const float* __restrict__ Ab,
+                                                           const float* __restrict__ H,
+                                                           const floatx4* __restrict__ wsw,
+                                                           const float* __restrict__ Sv_in,
+                                                           float* __restrict__ Out, int64_t n_srows,
+                                                           float* __restrict__ wpart,
+                                                           float* __restrict__ bpart) {
+  // Two roles of D/32 waves each, running concurrently on the same staged
+  // tile: waves [0, D/32) form the input adjoint (and load the Ab rows),
+  // waves [D/32, 2 D/32) the weight gradient (and load the H rows). Each
+  // role runs its own loop with the same barriers, so each keeps only its
+  // own accumulators in registers.
+  constexpr int R = 64, RB = 2, LDH = D + 4, NW = D / 32, NKB = D / 32;
+  constexpr int RTH = 64 * NW;                 // threads per role
+  constexpr int PER = R * D / 4 / RTH;         // float4 per thread of one tile array
+  __shared__ __align__(16) float HA[R * LDH];
+  __shared__ __align__(16) float HH[R * LDH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, h = lane >> 5;
+  const int64_t n_tiles = (n_srows + R - 1) / R;
+  if (wave < NW) {
+    const int rt = tid;                        // thread within the role
+    const int j = wave * 32 + col;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+      const int64_t row0 = t * R;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int idx = rt + i * RTH;
+        const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+        floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(Ab + (row0 + r) * D)[c4];
+        *reinterpret_cast<floatx4*>(&HA[r * LDH + 4 * c4]) = v;
+      }
+      __syncthreads();
+      floatx16 acc[RB];
+      mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
+      bwd_epilogue<D, S, LDH>(acc, row0, j, h, HH, Sv_in, Out, n_srows);
+      __syncthreads();   // the next tile overwrites the LDS
+    }
+  } else {
+    const int rt = tid - RTH;
+    const int jw = wave - NW;                  // output rows j in [32 jw, 32 jw + 32)
+    const int j = jw * 32 + col;
+    floatx16 accw[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) accw[kb][v] = 0.0f;
+    float bsum = 0.0f;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+      const int64_t row0 = t * R;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int idx = rt + i * RTH;
+        const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+        floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(H + (row0 + r) * D)[c4];
+        *reinterpret_cast<floatx4*>(&HH[r * LDH + 4 * c4]) = v;
+      }
+      __syncthreads();
+      // weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
+      // at MFMA step e to both operands
+#pragma unroll 2
+      for (int g = 0; g < R / 8; ++g) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 8 * g + 4 * h + e;
+          const float a = HA[r * LDH + j];
+#pragma unroll
+          for (int kb = 0; kb < NKB; ++kb) accw[kb] = mfma32x32x2(a, HH[r * LDH + kb * 32 + col], accw[kb]);
+        }
+      }
+      if (rt < D)
+        for (int r = 0; r < R; r += S) bsum += HA[r * LDH + rt];   // value rows (zero beyond the end)
+      __syncthreads();
+    }
+    float* P = wpart + (int64_t)blockIdx.x * D * D;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) P[(int64_t)(jw * 32 + acc_row(lane, v)) * D + kb * 32 + col] = accw[kb][v];
+    if (rt < D) bpart[(int64_t)blockIdx.x * D + rt] = bsum;
+  }
+}
+
+// Width 256: one role per wave (both products in turn); the role-split
+// form above would need more than the 128 VGPRs a 1024-thread workgroup
+// allows.
+template <int D, int S>
+__global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __restrict__ Ab,
                                                            const float* __restrict__ H,
                                                            const floatx4* __restrict__ wsw,
                                                            const float* __restrict__ Sv_in,
@@ -671,12 +761,21 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
   for (int l = 2; l >= 0; --l) {           // hidden layer l+2, input Z[l]
     float* Ab = tb.Ab[cur];
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
-    if (S == 4)
-      hipLaunchKernelGGL((taylor_bwd_kernel<D, 4>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l], wT,
-                         Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
-    else
-      hipLaunchKernelGGL((taylor_bwd_kernel<D, 1>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l], wT,
-                         Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+    if constexpr (D <= 128) {
+      if (S == 4)
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab, Z[l],
+                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+      else
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 1>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab, Z[l],
+                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+    } else {
+      if (S == 4)
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l],
+                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+      else
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 1>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l],
+                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float* gW = grad + off_w2 + l * lstride;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256 / kReduceGroups)), dim3(256), 0, s,
