@@ -43,7 +43,7 @@ INTERIOR_T = 961
 # value the counters were taken with; otherwise "traffic" is null. Summary:
 # profiles/*_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "de645fc376b73af5225b841cb073616fe71ad442fa8e9c6ea5d2d415be7f01ce",
+    "sources_sha256": "acc42db936fde51c4366d1b60602a906538cc61a9465e69d60f6ee37ebe5a066",
     "bytes_per_launch": {"64": (5147.8 * 2.0 + 261.9) * 1024,
                          "64|stream": (5099.4 * 2.0 + 261.9) * 1024,
                          "32": (6006.5 * 2.0 + 268.6) * 1024},

@@ -289,10 +289,6 @@ __device__ __forceinline__ void layer_wreg(typename HType<PREC>::T* Hs,
         }
       }
     }
-    // after the last block's MFMAs (and the barrier that ends them, which
-    // the scheduler does not cross) the next layer's weights are loaded into
-    // the same registers, in flight during the last epilogue
-
     if (rb > 0) {
       const int row = (rb - 1) * 32;
 #pragma unroll
