@@ -14,6 +14,10 @@ c4_one_sweep.npz -- the same 64 x 64-unit problem after ONE sweep from the
     that state at the c4 assembly points (a full-size check of the sweep map
     that does not pass through the early transient, where an untrained
     network amplifies float32 rounding differences by orders of magnitude).
+c5_one_sweep.npz -- the 48-domain batch (sizes 4..48 units, GP data length
+    1.0, seed 7), width 256: for its smallest, median and largest domain (by
+    placement count) one sweep from the initial field, as 4096 sampled
+    skeleton values, and the assembly of that state at 256 sampled points.
 c2_fp32.npz -- 16 x 16 units, width 256, GP ring data (length 2, seed 1),
     Xavier weights seed 0, 200 CROSS sweeps then the assembly. Holds the
     skeleton after 20 and 200 sweeps and u_out at 8192 sampled interior
@@ -151,7 +155,42 @@ def c4_one():
     print(f"c4_one: done in {time.time() - t0:.0f} s", flush=True)
 
 
-JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one}
+def c5_one():
+    """One sweep of three sampled domains of the batched workload (their
+    fields come from the same seeded generator as the whole batch)."""
+    w = mi.WORKLOADS["C5"]
+    t0 = time.time()
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    print(f"c5_one: inputs in {time.time() - t0:.0f} s", flush=True)
+    params = mi.xavier_params(w["width"], seed=0)
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), w["width"])
+    places = [(2 * int(ux) - 1) * (2 * int(uy) - 1) for ux, uy in sizes]
+    order = np.argsort(places, kind="stable")
+    picks = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    out = {"picks": np.array(picks, dtype=np.int32), "sizes": sizes.astype(np.int32),
+           "params_sha": _sha(params)}
+    rng = np.random.default_rng(555)
+    for n, d in enumerate(picks):
+        ux, uy = (int(v) for v in sizes[d])
+        f = fields[d]
+        u1 = sw.sweep(torch.from_numpy(f.astype(np.float64)), ux, uy, solver)
+        mask = sw.skeleton_mask(*f.shape).numpy()
+        sj, si = np.nonzero(mask)
+        pick = rng.choice(sj.size, min(4096, sj.size), replace=False)
+        aj = rng.integers(1, f.shape[0] - 1, 256)
+        ai = rng.integers(1, f.shape[1] - 1, 256)
+        out[f"skel_j{n}"] = sj[pick].astype(np.int32)
+        out[f"skel_i{n}"] = si[pick].astype(np.int32)
+        out[f"skel1_{n}"] = u1.numpy()[sj[pick], si[pick]].copy()
+        out[f"sample_j{n}"] = aj.astype(np.int32)
+        out[f"sample_i{n}"] = ai.astype(np.int32)
+        out[f"u_out{n}"] = sw.assemble_at(u1, ux, uy, solver, list(zip(aj.tolist(), ai.tolist()))).numpy()
+        out[f"field_sha{n}"] = _sha(f)
+        print(f"c5_one: domain {d} ({ux}x{uy}) done at {time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_one_sweep.npz"), **out)
+
+
+JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one, "c5_one": c5_one}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)
