@@ -90,3 +90,34 @@ def test_batch_additive_equals_one_by_one(ctx):
         mf_solve(ctx, params, u, (ux, uy), 5, mode=MF_ADDITIVE)
         torch.cuda.synchronize()
         assert torch.equal(batch.field(i), u), i
+
+
+@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2)])
+def test_full_batch_one_sweep_sampled_domains(ctx, prec, tol):
+    """The 48-domain batch (4..48 units per side, 138,286 placements), width
+    256, in the launch configuration the benchmark uses (one persistent
+    launch per colour for all domains): one sweep and the assembly, checked
+    on its smallest, median and largest domain against float64 oracle values
+    at sampled skeleton and assembly points."""
+    import os
+    print(f"case: 48-domain batch one sweep prec={prec}", flush=True)
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_one_sweep.npz"))
+    w = mi.WORKLOADS["C5"]
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    np.testing.assert_array_equal(sizes, g["sizes"])
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    batch = Batch(fields)
+    out = torch.empty_like(batch.buf)
+    mf_solve(ctx, params, batch, None, 1, prec=prec, u_out=out)
+    torch.cuda.synchronize()
+    for n, d in enumerate(g["picks"]):
+        u = batch.field(int(d)).cpu().numpy().astype(np.float64)
+        uo = batch.field(int(d), out).cpu().numpy().astype(np.float64)
+        s_want = g[f"skel1_{n}"]
+        s_got = u[g[f"skel_j{n}"], g[f"skel_i{n}"]]
+        o_want = g[f"u_out{n}"]
+        o_got = uo[g[f"sample_j{n}"], g[f"sample_i{n}"]]
+        e_s = np.linalg.norm(s_got - s_want) / np.linalg.norm(s_want)
+        e_o = np.linalg.norm(o_got - o_want) / np.linalg.norm(o_want)
+        print(f"domain {int(d)} {tuple(int(v) for v in sizes[d])}: rel L2 skeleton {e_s:.3e} u_out {e_o:.3e}", flush=True)
+        assert e_s <= tol and e_o <= tol, (int(d), e_s, e_o)
