@@ -134,10 +134,11 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
 /* Autotuner: for this network, domain, target set and precision, time
- * `trials` sweeps (after one warm-up sweep) of every available tile height
- * with hipEvents on `stream` and keep the fastest in the context for later
+ * `trials` sweeps of every available tile shape with hipEvents on `stream`
+ * (one warm-up sweep each, then three interleaved rounds, keeping each
+ * shape's fastest round) and keep the fastest shape in the context for later
  * mf_sweep / mf_solve calls on the same configuration. The sweeps run on u
- * itself (it advances by (trials + 1) x candidates sweeps); pass a scratch
+ * itself (it advances by (3 trials + 1) x candidates sweeps); pass a scratch
  * copy to keep the field. rows_out (host, nullable) receives the choice.
  * Synchronises the stream. */
 mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,

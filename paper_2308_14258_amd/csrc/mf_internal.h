@@ -18,6 +18,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct NetLayout {
   int width = 0, prec = 0;
   size_t w1gT = 0;   // float [128][d]: W1 boundary block, k-major
+  size_t w1gb = 0;   // bf16 W1 boundary block in MFMA operand order (MF_BF16 only)
   size_t w1x = 0;    // float [d][2]: W1 coordinate columns
   size_t b1 = 0;     // float [d]
   size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32 or bf16)
@@ -31,6 +32,7 @@ NetLayout net_layout(int width, int prec, size_t base);
 // Device pointers into a prepared network.
 struct NetPtrs {
   const float* w1gT;
+  const void* w1gb;
   const float* w1x;
   const float* b1;
   const void* wh;

@@ -34,7 +34,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // so that one wave's B operand for one k-group is 1 KiB of contiguous memory.
 // ---------------------------------------------------------------------------
 __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int prec,
-                                   float* __restrict__ w1gT, float* __restrict__ w1x,
+                                   float* __restrict__ w1gT, uint16_t* __restrict__ w1gb, float* __restrict__ w1x,
                                    float* __restrict__ b1, void* __restrict__ wh,
                                    float* __restrict__ bh, float* __restrict__ w5,
                                    float* __restrict__ b5) {
@@ -49,6 +49,14 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
   for (int64_t idx = tid; idx < 128 * (int64_t)d; idx += nthr) {
     const int64_t k = idx / d, n = idx - k * d;
     w1gT[idx] = params[n * 130 + k];
+    if (prec == MF_BF16) {
+      // [cb = d/32][kg = 8][lane 64][8]: lane l, element e holds
+      // W1[32 cb + (l & 31)][16 kg + 8 (l >> 5) + e]
+      const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+      const int64_t rest = idx >> 9;
+      const int kg = (int)(rest % 8), cb = (int)(rest / 8);
+      w1gb[idx] = bf16_bits(params[(int64_t)(32 * cb + (lane & 31)) * 130 + 16 * kg + 8 * (lane >> 5) + e]);
+    }
   }
   for (int64_t n = tid; n < d; n += nthr) {
     w1x[2 * n] = params[n * 130 + 128];
@@ -93,7 +101,8 @@ hipError_t launch_prepare_net(const float* params, int width, int prec, const Ne
                               void* ws, hipStream_t s) {
   char* base = static_cast<char*>(ws);
   hipLaunchKernelGGL(prepare_net_kernel, dim3(256), dim3(256), 0, s, params, width, prec,
-                     reinterpret_cast<float*>(base + L.w1gT), reinterpret_cast<float*>(base + L.w1x),
+                     reinterpret_cast<float*>(base + L.w1gT), reinterpret_cast<uint16_t*>(base + L.w1gb),
+                     reinterpret_cast<float*>(base + L.w1x),
                      reinterpret_cast<float*>(base + L.b1), static_cast<void*>(base + L.wh),
                      reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
                      reinterpret_cast<float*>(base + L.b5));
@@ -393,6 +402,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
   asm volatile("" : "+s"(zero));
   NetPtrs net = A.net;
   net.w1gT += zero;
+  net.w1gb = static_cast<const u32x4*>(net.w1gb) + zero;
   net.w1x += zero;
   net.b1 += zero;
   net.bh += zero;
@@ -440,9 +450,11 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
   floatx4 w[KPS];
   const int n4 = tid % NG, ks = tid / NG;
   if constexpr (SRC == SRC_GATHER) {
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int i = 0; i < KPS; ++i)
-      w[i] = *reinterpret_cast<const floatx4*>(net.w1gT + (ks * KPS + i) * D + 4 * n4);
+      for (int i = 0; i < KPS; ++i)
+        w[i] = *reinterpret_cast<const floatx4*>(net.w1gT + (ks * KPS + i) * D + 4 * n4);
+    }
     for (int idx = tid; idx < np * kNB; idx += NTH) {
       const int s = idx >> 7, k = idx & 127;
       int a, b, bi, bj;
@@ -451,6 +463,43 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       gs[idx] = A.u_in[(int64_t)(kHalf * b + bj) * A.pitch + kHalf * a + bi];
     }
     __syncthreads();
+    if constexpr (PREC == 1) {
+      // bf16: W1g G^T on MFMA. A = the tile's boundary vectors (rows p < np,
+      // at most NPMAX <= 8, rounded to bf16), B = the wave's 32-column slice
+      // of W1g in operand order; a lane's accumulator registers 0..3 hold
+      // rows 4 (lane >> 5) .. + 3 of its column. The stored projection
+      // carries b1 and the factor 2 log2(e) of the tanh.
+      static_assert(NPMAX <= 8, "projection rows");
+      const int arow = lane & 31, ahalf = lane >> 5;
+      constexpr int NCBP = CPW / 32;
+#pragma unroll
+      for (int cb = 0; cb < NCBP; ++cb) {
+        const int col = ((wave % (D / CPW)) * NCBP + cb) * 32 + arow;
+        const u32x4* wp = static_cast<const u32x4*>(net.w1gb) + (size_t)((wave % (D / CPW)) * NCBP + cb) * 8 * 64 + lane;
+        floatx16 acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+        for (int kg = 0; kg < 8; ++kg) {
+          bf16x8 a;
+          if (arow < np) {
+            const floatx4 g0 = *reinterpret_cast<const floatx4*>(&gs[arow * kNB + 16 * kg + 8 * ahalf]);
+            const floatx4 g1 = *reinterpret_cast<const floatx4*>(&gs[arow * kNB + 16 * kg + 8 * ahalf + 4]);
+            a = bf16x8{(__bf16)g0[0], (__bf16)g0[1], (__bf16)g0[2], (__bf16)g0[3],
+                       (__bf16)g1[0], (__bf16)g1[1], (__bf16)g1[2], (__bf16)g1[3]};
+          } else {
+            a = bf16x8{};
+          }
+          acc = mfma32x32x16_bf16(a, __builtin_bit_cast(bf16x8, wp[kg * 64]), acc);
+        }
+        const float bb = net.b1[col];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int prow = 4 * ahalf + v;
+          if (prow < np) cs[prow * D + col] = kTwoLog2e * (acc[v] + bb);
+        }
+      }
+    } else {
     // The k-slice partials go to LDS scratch that aliases the activation tile
     // (not in use yet) and are then summed; the stored projection carries b1
     // and the factor 2 log2(e) of the tanh.
@@ -475,6 +524,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
 #pragma unroll
       for (int k = 0; k < KSL; ++k) c += part[(k * NPMAX + s) * D + n];
       cs[idx] = kTwoLog2e * (c + net.b1[n]);
+    }
     }
   }
   __syncthreads();
