@@ -118,8 +118,9 @@ def main():
     ap.add_argument("--only-train", action="store_true", help="only the training-step measurement")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the sweep holds the whole "
-                                   "domain on a single device (see DESIGN.md for sharding)",
+        print(json.dumps({"error": "runs on one GPU only: the sweep holds the whole domain on "
+                                   "a single device; splitting a domain's placement rows over "
+                                   "GPUs with a halo exchange per colour phase is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

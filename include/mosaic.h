@@ -278,6 +278,16 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
                            float* loss_dev, float* grad_out, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* The losses of sdnet_train_step at params and the gradient of
+ * L_data + L_pde, with no parameter update: the same forward (Taylor mode)
+ * and hand-written reverse pass, for callers that run their own optimiser
+ * (a torch.autograd.Function, for one). Arguments as for sdnet_train_step;
+ * grad_out (device, mf_param_count floats) is required and fully written;
+ * loss_dev (device [2]) receives (L_data, L_pde). Same workspace size. */
+mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* G,
+                          int64_t B, const float* Xb, const float* Xc, int64_t nc, float* loss_dev,
+                          float* grad_out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

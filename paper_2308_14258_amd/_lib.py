@@ -79,6 +79,8 @@ _SIG = {
     "sdnet_train_step": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _P, _c.c_int64,
                                       _c.POINTER(Adam), _P, _c.c_int64, _P, _P, _c.c_int64, _P, _P,
                                       _P, _c.c_size_t, _P]),
+    "sdnet_loss_grad": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _P, _c.c_int64, _P,
+                                     _P, _P, _c.c_size_t, _P]),
 }
 
 _lib = None

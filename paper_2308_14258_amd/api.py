@@ -309,7 +309,7 @@ def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: tor
                     grad_out: torch.Tensor | None = None):
     """(L_data, L_pde) of Alg. 1 at `params` and the gradient of
     L_data + L_pde from the library's hand-written reverse pass, with no
-    parameter update (sdnet_train_step with grad_out). Returns (loss [2],
+    parameter update (C entry point sdnet_loss_grad). Returns (loss [2],
     grad), both device tensors."""
     for t, name in ((params, "params"), (G, "G"), (Xb, "Xb"), (Xc, "Xc")):
         _need_cuda_f32(t, name)
@@ -325,11 +325,10 @@ def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: tor
     check(lib.sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nc, ctypes.byref(n)),
           "sdnet_train_ws_size")
     ws = ctx.workspace(n.value)
-    check(lib.sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), None, None, 1,
-                               None, _ptr(G.contiguous()), B, _ptr(Xb.contiguous()),
-                               _ptr(Xc.contiguous()), nc, _ptr(loss), _ptr(grad_out), _ptr(ws),
-                               ws.numel(), _stream()),
-          "sdnet_train_step")
+    check(lib.sdnet_loss_grad(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G.contiguous()), B,
+                              _ptr(Xb.contiguous()), _ptr(Xc.contiguous()), nc, _ptr(loss), _ptr(grad_out),
+                              _ptr(ws), ws.numel(), _stream()),
+          "sdnet_loss_grad")
     return loss, grad_out
 
 

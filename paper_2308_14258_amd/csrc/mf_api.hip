@@ -1101,4 +1101,13 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
   return ok();
 }
 
+mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* G,
+                          int64_t B, const float* Xb, const float* Xc, int64_t nc, float* loss_dev,
+                          float* grad_out, void* ws, size_t ws_bytes, void* stream) {
+  MF_TRY(check_ptr(grad_out, "grad_out"));
+  // the gradient mode of the training step reads params and updates nothing
+  return sdnet_train_step(ctx, desc, const_cast<float*>(params), nullptr, nullptr, 1, nullptr, G, B, Xb, Xc,
+                          nc, loss_dev, grad_out, ws, ws_bytes, stream);
+}
+
 }  // extern "C"

@@ -171,3 +171,29 @@ def test_operator_argument_errors(lib):
     assert op(None, f, 61, MF_CROSS, f, f, ctypes.byref(dom), 4, None) == MF_EINVAL
     assert b"INTERIOR" in lib.mf_last_error()
     assert op(None, None, 61, MF_CROSS, f, None, ctypes.byref(dom), -1, None) == MF_EINVAL
+
+
+def test_train_and_loss_grad_argument_errors(lib):
+    d = SdnetDesc(128, 4, 128, 0)
+    f = ctypes.c_void_p(FAKE)
+    big = 1 << 40
+
+    def train(m=f, v=f, step=1, grad=None, B=4, hp=True):
+        adam = _lib.Adam(1e-3, 0.9, 0.999, 1e-8)
+        return lib.sdnet_train_step(None, ctypes.byref(d), f, m, v, step,
+                                    ctypes.byref(adam) if hp else None, f, B, f, f, 8, f, grad, f,
+                                    big, None)
+
+    assert train() == MF_EINVAL and b"ctx" in lib.mf_last_error()      # all else valid
+    assert train(m=None) == MF_EINVAL and b"m is NULL" in lib.mf_last_error()
+    assert train(step=0) == MF_EINVAL
+    assert train(hp=False) == MF_EINVAL
+    assert train(B=0) == MF_ESHAPE
+    assert train(m=None, v=None, hp=False, grad=f) == MF_EINVAL and b"ctx" in lib.mf_last_error()
+
+    def loss_grad(grad=f, ws_bytes=big):
+        return lib.sdnet_loss_grad(None, ctypes.byref(d), f, f, 4, f, f, 8, f, grad, f, ws_bytes, None)
+
+    assert loss_grad() == MF_EINVAL and b"ctx" in lib.mf_last_error()
+    assert loss_grad(grad=None) == MF_EINVAL and b"grad_out is NULL" in lib.mf_last_error()
+    assert loss_grad(ws_bytes=1024) == MF_ENOMEM

@@ -335,6 +335,30 @@ def test_graph_replay_equals_direct_launches(ctx):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16])
+def test_graph_replay_sees_new_parameter_values(ctx, prec):
+    """A cached graph holds buffer addresses, not values: overwriting the
+    parameters in place between two solves on the same buffers must give
+    the result of the new parameters (the network is prepared outside the
+    graph on every call)."""
+    print(f"case: graph replay after an in-place parameter update prec={prec}", flush=True)
+    pa, pb = mi.random_params(256, seed=41), mi.random_params(256, seed=42)
+    f = mi.gp_field(4, 3, 1.0, seed=8)
+    params = dev(pa)
+    u = dev(f)
+    ctx.graphs(True)
+    mf_solve(ctx, params, u, (4, 3), 32, prec=prec)       # captures and replays with pa
+    params.copy_(dev(pb))
+    u.copy_(dev(f))
+    mf_solve(ctx, params, u, (4, 3), 32, prec=prec)       # same addresses, new values
+    ctx.graphs(False)
+    v = dev(f)
+    mf_solve(ctx, dev(pb), v, (4, 3), 32, prec=prec)
+    ctx.graphs(True)
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+
+
 @pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_FP32, 64 | (1 << 17)), (MF_BF16, 64),
                                        (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
                                        (MF_BF16, 256 | (1 << 16))])
