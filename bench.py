@@ -14,6 +14,13 @@ Prints one JSON line. The "roofline" object reports the colour-phase kernel
 duration, timed with HIP events on the launch stream during the timed
 region. The "cpu_baseline" object times the float64 oracle on the host
 cores on a bounded sample of the same workload.
+
+Beside the headline the line carries: the assembly timed on its own; the
+2 x 2-unit workload in microseconds per sweep; one GPU's share of the
+64 x 64-unit domain split eight ways; the standalone gather and scatter in
+GB/s on a field larger than the last-level cache; the GEMM rates torch.mm
+reaches (achievable peaks); FP32 against BF16 on the 64 x 64-unit domain;
+the training step; optionally the 48-domain batch and its adjoint (--c5).
 """
 from __future__ import annotations
 
@@ -74,6 +81,25 @@ def sweep_points(ux: int, uy: int, T: int) -> int:
     return (2 * ux - 1) * (2 * uy - 1) * T
 
 
+def host_info():
+    """CPU model, logical CPU count and the BLAS torch's CPU operations use."""
+    import torch
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = ""
+    for line in torch.__config__.show().splitlines():
+        if "BLAS_INFO" in line:
+            blas = line.split("BLAS_INFO=")[1].split(",")[0]
+    return {"cpu_model": model, "nproc": os.cpu_count(), "blas": blas}
+
+
 def cpu_baseline(field, params, width, ux, uy, sample_sweeps):
     import torch
     from oracle import sweep as sw
@@ -87,7 +113,7 @@ def cpu_baseline(field, params, width, ux, uy, sample_sweeps):
     dt = time.perf_counter() - t0
     evals = sample_sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
     return {"value": evals / dt, "unit": "point-evals/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_info(),
             "sample": f"{sample_sweeps} CROSS sweeps + 1 assembly of the same 16x16-unit, "
                       f"width-{width} workload, float64, {dt:.1f} s"}
 
@@ -116,6 +142,9 @@ def main():
                          "inputs take about a minute to generate on the host")
     ap.add_argument("--only-c5", action="store_true")
     ap.add_argument("--only-train", action="store_true", help="only the training-step measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip C1, the per-GPU share, gather/scatter bandwidth and the GEMM peaks")
+    ap.add_argument("--only-io", action="store_true", help="only the gather/scatter bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only: the sweep holds the whole domain on "
@@ -138,9 +167,11 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
         return
 
-    if args.only_bf16 or args.only_c5 or args.only_train:
+    if args.only_bf16 or args.only_c5 or args.only_train or args.only_io:
         ctx = Context(0)
-        if args.only_bf16:
+        if args.only_io:
+            out = {"gather_scatter": io_measurement(ctx)}
+        elif args.only_bf16:
             out = {"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)}
         elif args.only_c5:
             out = {"batched": batched_measurement(ctx)}
@@ -236,6 +267,13 @@ def main():
                      "flops_per_point_eval": fpp},
         "parity": parity,
     }
+    out["assembly"] = assembly_measurement(ctx, params, u0, (ux, uy))
+    if not args.no_extras:
+        out["c1"] = c1_measurement(ctx)
+        out["per_gpu_share"] = per_gpu_share_measurement(ctx)
+        out["gather_scatter"] = io_measurement(ctx)
+        out["achievable_peaks"] = achievable_peaks()
+        out["roofline"]["frac_of_achievable"] = achieved / out["achievable_peaks"]["fp32_tflops"]
     if not args.no_bf16:
         out["bf16_vs_fp32"] = bf16_comparison(ctx, args.bf16_sweeps)
     if not args.no_train:
@@ -280,6 +318,126 @@ def train_measurement(ctx, steps):
             "gemm_tflops": flops * steps / dt / 1e12,
             "frac_of_fp32_mfma_peak": flops * steps / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
             "last_loss": [float(x) for x in loss.cpu()]}
+
+
+def _event_ms(fn, reps):
+    """Average milliseconds of fn() over reps calls, timed with events on the
+    current stream (the stream every library call is given)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def achievable_peaks():
+    """Dense GEMM rates the platform library reaches on this GPU (torch.mm,
+    8192^3, fp32 and bf16): the achievable denominators beside the published
+    peaks."""
+    import torch
+    out = {}
+    n = 8192
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.randn(n, n, device="cuda").to(dt)
+        b = torch.randn(n, n, device="cuda").to(dt)
+        ms = _event_ms(lambda: torch.mm(a, b), 10)
+        out[name + "_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        del a, b
+    out["method"] = "torch.mm 8192x8192x8192, mean of 10 after one warm-up"
+    return out
+
+
+def assembly_measurement(ctx, params, field, units):
+    """The overlap-averaged assembly on its own (INTERIOR targets, every
+    placement, four colour launches plus the ring copy): mf_solve with zero
+    sweeps and u_out."""
+    import torch
+    from paper_2308_14258_amd import mf_solve
+    ux, uy = units
+    u = field.clone()
+    u_out = torch.empty_like(u)
+    ms = _event_ms(lambda: mf_solve(ctx, params, u, units, 0, u_out=u_out), 10)
+    evals = sweep_points(ux, uy, INTERIOR_T)
+    return {"ms": ms, "point_evals": evals, "point_evals_per_s": evals / (ms * 1e-3),
+            "tflops": evals * flops_per_point(params_width(params), INTERIOR_T) / (ms * 1e-3) / 1e12}
+
+
+def params_width(params):
+    from paper_2308_14258_amd.api import width_of
+    return width_of(params)
+
+
+def c1_measurement(ctx):
+    """2 x 2 units, width 128, 50 sweeps (graph replay): launch-bound, so
+    microseconds per sweep."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import mf_solve
+    w = mi.WORKLOADS["C1"]
+    units = w["units"]
+    f = torch.from_numpy(mi.workload_field("C1")).cuda()
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    u = f.clone()
+    ms = _event_ms(lambda: mf_solve(ctx, params, u, units, w["sweeps"]), 20)
+    return {"workload": "C1: 2x2 units, width 128, 50 CROSS sweeps", "us_per_sweep": ms * 1e3 / w["sweeps"]}
+
+
+def per_gpu_share_measurement(ctx):
+    """One GPU's block of the 64 x 64-unit domain under a 2 x 4 processor
+    grid: a 32 x 16-unit domain (1,953 placements, against 16,129 / 8 = 2,016
+    for an even split), width 256, 20 sweeps, FP32 and BF16."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_BF16, MF_FP32, mf_autotune, mf_solve
+    ux, uy = 32, 16
+    f = torch.from_numpy(mi.expsin_field(ux, uy)).cuda()
+    params = torch.from_numpy(mi.xavier_params(256, 0)).cuda()
+    K = 20
+    out = {"workload": "32x16 units (one GPU's share of 64x64 on 8 GPUs), width 256, 20 CROSS sweeps"}
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+        mf_autotune(ctx, params, f.clone(), (ux, uy), 0, prec, trials=2)
+        u = f.clone()
+        ms = _event_ms(lambda: mf_solve(ctx, params, u, (ux, uy), K, prec=prec), 3)
+        evals = K * sweep_points(ux, uy, CROSS_T)
+        out[name] = {"ms_per_sweep": ms / K, "point_evals_per_s": evals / (ms * 1e-3)}
+    return out
+
+
+def io_measurement(ctx):
+    """Standalone boundary gather and target scatter of each colour on a
+    256 x 256-unit field (8193^2 floats, 268 MB: larger than the last-level
+    cache). Algorithmic bytes: gather 512 B read + 512 B written per
+    placement; scatter 4 B read + 4 B written per target."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_CROSS, MF_INTERIOR, mf_colour_placements, mf_gather, mf_scatter
+    ux = uy = 256
+    u = torch.from_numpy(mi.random_interior_field(ux, uy, 15).astype(np.float32)).cuda()
+    res = {"field": "256x256 units, 8193x8193 float32 (268 MB)"}
+    tot = {"gather": [0.0, 0.0], "scatter_cross": [0.0, 0.0], "scatter_interior": [0.0, 0.0]}
+    for c in range(4):
+        n = mf_colour_placements((ux, uy), c)
+        G = torch.empty(n, 128, device="cuda")
+        ms = _event_ms(lambda: mf_gather(ctx, u, (ux, uy), c, G), 20)
+        tot["gather"][0] += ms
+        tot["gather"][1] += n * 1024.0
+        for key, targets, T in (("scatter_cross", MF_CROSS, 61), ("scatter_interior", MF_INTERIOR, 961)):
+            pred = torch.randn(n, T, device="cuda")
+            ms = _event_ms(lambda: mf_scatter(ctx, pred, u, (ux, uy), c, targets), 20)
+            tot[key][0] += ms
+            tot[key][1] += n * T * 8.0
+            del pred
+    for key, (ms, nbytes) in tot.items():
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        res[key] = {"us_per_launch": ms * 1e3 / 4, "algorithmic_bytes_per_sweep": nbytes,
+                    "GB_per_s": gbps, "frac_of_hbm_peak": gbps * 1e9 / PEAK_HBM_BYTES_PER_S}
+    return res
 
 
 def batched_measurement(ctx):

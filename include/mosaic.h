@@ -215,6 +215,42 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
                             float* u, float* u_out, const mf_domain_desc* dom, int32_t colour,
                             void* stream);
 
+/* Placements of colour `colour` (0..3) in one domain: (units_x - (c & 1)) x
+ * (units_y - (c >> 1)). Placement q of the colour is (a, b) with
+ * a = (c & 1) + 2 (q mod n_a), b = (c >> 1) + 2 (q div n_a),
+ * n_a = units_x - (c & 1); its 33 x 33 vertices start at grid (16 a, 16 b)
+ * (Sec. 4.2). -1 on an invalid domain or colour. Pure host function. */
+int64_t mf_colour_placements(const mf_domain_desc* dom, int32_t colour);
+
+/* Local coordinates (x, y) = (i / 32, j / 32) of the target set's points in
+ * the library's target order (see mf_sweep_operator), written to X_host
+ * (host memory, [T][2] floats, T = 61 for MF_CROSS, 961 for MF_INTERIOR).
+ * These are the X of sdnet_forward for an unfused colour phase. Pure host
+ * function. */
+mf_status mf_target_coords(int32_t targets, float* X_host);
+
+/* Boundary gather of one colour phase on its own (the first step of a
+ * subdomain solve in Alg. 2): G[q][k] = the field at boundary sample k of
+ * placement q of the colour, k = 0..127 counter-clockwise from the
+ * placement's corner (bottom edge i = 0..31, right edge j = 0..31, top edge
+ * i = 32..1, left edge j = 32..1). u: device field of one domain (layout as
+ * for mf_sweep; field_offset applies); G: device [mf_colour_placements][128]
+ * float32, fully written (G may be NULL when the colour has no placements).
+ * Asynchronous; no workspace. */
+mf_status mf_gather(mf_ctx* ctx, const float* u, const mf_domain_desc* dom, int32_t colour, float* G,
+                    void* stream);
+
+/* Target scatter of one colour phase on its own (the write-back of Alg. 2):
+ * the field at target t of placement q of the colour takes pred[q][t].
+ * pred: device [mf_colour_placements][T] float32 in target order; u: device
+ * field (only those targets are written; the placements of one colour are
+ * disjoint, so every point is written at most once). With mf_gather and
+ * sdnet_forward (X = mf_target_coords, shared) this is the unfused form of
+ * one multiplicative colour phase of mf_sweep. pred may be NULL when the
+ * colour has no placements. Asynchronous; no workspace. */
+mf_status mf_scatter(mf_ctx* ctx, const float* pred, int32_t targets, float* u, const mf_domain_desc* dom,
+                     int32_t colour, void* stream);
+
 /* Workspace bytes for mf_solve_adjoint. */
 mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
                              int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes);

@@ -63,6 +63,10 @@ _SIG = {
     "mf_solve": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
                               _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_float, _c.c_int32,
                               _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),
+    "mf_colour_placements": (_c.c_int64, [_c.POINTER(DomainDesc), _c.c_int32]),
+    "mf_target_coords": (_c.c_int32, [_c.c_int32, _P]),
+    "mf_gather": (_c.c_int32, [_P, _P, _c.POINTER(DomainDesc), _c.c_int32, _P, _P]),
+    "mf_scatter": (_c.c_int32, [_P, _P, _c.c_int32, _P, _c.POINTER(DomainDesc), _c.c_int32, _P]),
     "mf_sweep_operator": (_c.c_int32, [_P, _P, _c.c_int64, _c.c_int32, _P, _P, _c.POINTER(DomainDesc),
                                        _c.c_int32, _P]),
     "mf_adjoint_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,

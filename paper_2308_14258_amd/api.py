@@ -252,6 +252,52 @@ def mf_sweep_operator(ctx: Context, Hop: torch.Tensor, u: torch.Tensor, units, c
                                    ctypes.byref(dom), colour, _stream()), "mf_sweep_operator")
 
 
+def mf_colour_placements(units, colour: int) -> int:
+    """Number of placements of a colour (0..3) in a ux x uy domain."""
+    ux, uy = units
+    n = load().mf_colour_placements(ctypes.byref(DomainDesc(int(ux), int(uy), 32, 16, 32 * int(ux) + 1, 0)),
+                                    colour)
+    if n < 0:
+        check(_lib.MF_EINVAL, "mf_colour_placements")
+    return int(n)
+
+
+def mf_target_coords(targets: int = MF_CROSS) -> torch.Tensor:
+    """[T, 2] local (x, y) of the target set in the library's order (host tensor)."""
+    T = 61 if targets == MF_CROSS else 961
+    X = torch.empty(T, 2, dtype=torch.float32)
+    check(load().mf_target_coords(targets, _ptr(X)), "mf_target_coords")
+    return X
+
+
+def mf_gather(ctx: Context, u: torch.Tensor, units, colour: int, G: torch.Tensor | None = None):
+    """[P_c, 128] boundary vectors of every placement of one colour."""
+    _need_field(u, units)
+    n = mf_colour_placements(units, colour)
+    if G is None:
+        G = torch.empty(n, 128, device=u.device, dtype=torch.float32)
+    elif not (G.is_cuda and G.dtype == torch.float32 and G.is_contiguous() and G.shape == (n, 128)):
+        raise ValueError(f"G must be a contiguous float32 CUDA tensor of shape ({n}, 128)")
+    dom = domain_desc(u, units)
+    check(load().mf_gather(ctx.ptr, _ptr(u), ctypes.byref(dom), colour, _ptr(G) if n else None, _stream()),
+          "mf_gather")
+    return G
+
+
+def mf_scatter(ctx: Context, pred: torch.Tensor, u: torch.Tensor, units, colour: int,
+               targets: int = MF_CROSS) -> None:
+    """Write pred [P_c, T] at the targets of every placement of one colour."""
+    _need_field(u, units)
+    _need_cuda_f32(pred, "pred")
+    T = 61 if targets == MF_CROSS else 961
+    n = mf_colour_placements(units, colour)
+    if not (pred.is_contiguous() and pred.shape == (n, T)):
+        raise ValueError(f"pred must be contiguous of shape ({n}, {T})")
+    dom = domain_desc(u, units)
+    check(load().mf_scatter(ctx.ptr, _ptr(pred) if n else None, targets, _ptr(u), ctypes.byref(dom), colour,
+                            _stream()), "mf_scatter")
+
+
 def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.Tensor,
                   prec: int = MF_FP32, derivatives: bool = False):
     """U [n_bc, n_pts] (and dU [n_bc, n_pts, 2], lapU [n_bc, n_pts])."""
@@ -359,5 +405,5 @@ def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.
 
 
 __all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep", "mf_solve",
-           "mf_sweep_operator", "physics_loss", "sdnet_forward", "sdnet_loss_grad", "sdnet_train_step",
+           "mf_sweep_operator", "mf_colour_placements", "mf_target_coords", "mf_gather", "mf_scatter", "physics_loss", "sdnet_forward", "sdnet_loss_grad", "sdnet_train_step",
            "width_of", "sdnet_desc", "domain_desc", "_lib"]

@@ -805,9 +805,6 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
   MF_HIP(hipSetDevice(ctx->device));
   float* field = u + dom->field_offset;
   if (colour == 4) {
-    if (targets != MF_INTERIOR) return fail(MF_EINVAL, "assembly needs the INTERIOR operator");
-    MF_TRY(check_ptr(u_out, "u_out"));
-    if (u_out == u) return fail(MF_EINVAL, "u_out must not alias u");
     float* out = u_out + dom->field_offset;
     MF_HIP(launch_assembly_init(field, out, dom->pitch, dom->units_x, dom->units_y, s));
     for (int c = 0; c < 4; ++c) {
@@ -820,6 +817,68 @@ mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int
     PhaseArgs p{field, field, dom->pitch, dom->units_x, dom->units_y, c};
     MF_HIP(launch_operator_phase(Hop, targets, false, p, s));
   }
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// One colour's gather and scatter as standalone calls
+// ---------------------------------------------------------------------------
+int64_t mf_colour_placements(const mf_domain_desc* dom, int32_t colour) {
+  if (!dom || colour < 0 || colour > 3 || check_one_domain(dom, 0) != MF_OK) return -1;
+  return (int64_t)(dom->units_x - (colour & 1)) * (dom->units_y - (colour >> 1));
+}
+
+mf_status mf_target_coords(int32_t targets, float* X_host) {
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  if (!X_host) return fail(MF_EINVAL, "X_host is NULL");
+  if (targets == MF_CROSS) {
+    int t = 0;
+    for (int j = 1; j <= 31; ++j, ++t) { X_host[2 * t] = 0.5f; X_host[2 * t + 1] = j / 32.0f; }
+    for (int i = 1; i <= 31; ++i) {
+      if (i == 16) continue;
+      X_host[2 * t] = i / 32.0f;
+      X_host[2 * t + 1] = 0.5f;
+      ++t;
+    }
+  } else {
+    for (int j = 1, t = 0; j <= 31; ++j)
+      for (int i = 1; i <= 31; ++i, ++t) { X_host[2 * t] = i / 32.0f; X_host[2 * t + 1] = j / 32.0f; }
+  }
+  return ok();
+}
+
+static mf_status check_colour_io(const mf_domain_desc* dom, int32_t colour) {
+  MF_TRY(check_domain(dom, 1));
+  if (colour < 0 || colour > 3) return fail(MF_EINVAL, "colour %d not in 0..3", colour);
+  return MF_OK;
+}
+
+mf_status mf_gather(mf_ctx* ctx, const float* u, const mf_domain_desc* dom, int32_t colour, float* G,
+                    void* stream) {
+  MF_TRY(check_ptr(u, "u"));
+  MF_TRY(check_colour_io(dom, colour));
+  const int64_t n_q = mf_colour_placements(dom, colour);
+  if (n_q == 0) return ok();   // a one-unit-wide domain has no placements of some colours
+  MF_TRY(check_ptr(G, "G"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_gather_colour(u + dom->field_offset, dom->pitch, dom->units_x, colour, n_q, G,
+                              static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mf_status mf_scatter(mf_ctx* ctx, const float* pred, int32_t targets, float* u, const mf_domain_desc* dom,
+                     int32_t colour, void* stream) {
+  MF_TRY(check_ptr(u, "u"));
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  MF_TRY(check_colour_io(dom, colour));
+  const int64_t n_q = mf_colour_placements(dom, colour);
+  if (n_q == 0) return ok();
+  MF_TRY(check_ptr(pred, "pred"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_scatter_colour(pred, targets, u + dom->field_offset, dom->pitch, dom->units_x, colour, n_q,
+                               static_cast<hipStream_t>(stream)));
   return ok();
 }
 

@@ -155,6 +155,11 @@ hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, c
 hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Ab[2],
                                  int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
                                  hipStream_t s);
+// io_kernels.hip: one colour's boundary gather and target scatter
+hipError_t launch_gather_colour(const float* u, int64_t pitch, int ux, int colour, int64_t n_q, float* G,
+                                hipStream_t s);
+hipError_t launch_scatter_colour(const float* pred, int targets, float* u, int64_t pitch, int ux, int colour,
+                                 int64_t n_q, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill2d(float* p, int64_t pitch, int ux, int uy, float v, hipStream_t s);
 hipError_t launch_target_coords(float* X_cross, float* X_interior, hipStream_t s);

@@ -129,6 +129,7 @@ struct TileArgs {
   int x_per_bc;
   float* U;
   int64_t total_rows;
+  int64_t block0;   // first tile of this launch (large phases take several launches)
 };
 
 template <int PREC> struct HType { typedef float T; };
@@ -592,7 +593,7 @@ struct Shape {
 
 template <class S, int TMODE, int SRC, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
-  tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (int64_t)blockIdx.x * S::R);
+  tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
 }
 
 // Batched independent domains in one persistent launch per colour: block b
@@ -692,12 +693,20 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
   });
 }
 
+// Tiles per launch: keeps the work-items of one launch below 2^32.
+constexpr int64_t kMaxTilesPerLaunch = 1 << 22;
+
 template <class S, int TMODE, int SRC, int OUT>
-static hipError_t launch_tile(const TileArgs& a, hipStream_t s) {
+static hipError_t launch_tile(TileArgs a, hipStream_t s) {
   const int64_t blocks = (a.total_rows + S::R - 1) / S::R;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL((tile_kernel<S, TMODE, SRC, OUT>), dim3((unsigned)blocks), dim3(S::NTH), 0, s, a);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < blocks; b0 += kMaxTilesPerLaunch) {
+    a.block0 = b0;
+    const int64_t n = std::min<int64_t>(blocks - b0, kMaxTilesPerLaunch);
+    hipLaunchKernelGGL((tile_kernel<S, TMODE, SRC, OUT>), dim3((unsigned)n), dim3(S::NTH), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static int64_t colour_count(int ux, int uy, int colour) {
@@ -986,11 +995,11 @@ hipError_t launch_delta(const float* u, int64_t pitch, int ux, int uy, const flo
 // Check mode: subdomain solver = linear operator Hop [T x 128].
 // ---------------------------------------------------------------------------
 template <int TMODE, int OUT>
-__global__ __launch_bounds__(256) void operator_kernel(const float* __restrict__ Hop, PhaseArgs p) {
+__global__ __launch_bounds__(256) void operator_kernel(const float* __restrict__ Hop, PhaseArgs p, int q0) {
   constexpr int T = n_targets<TMODE>();
   __shared__ float g[kNB];
   int a, b;
-  placement_of(blockIdx.x, p.colour, p.ux, a, b);
+  placement_of(q0 + (int)blockIdx.x, p.colour, p.ux, a, b);
   if (threadIdx.x < kNB) {
     int bi, bj;
     boundary_local(threadIdx.x, bi, bj);
@@ -1013,14 +1022,18 @@ __global__ __launch_bounds__(256) void operator_kernel(const float* __restrict__
 hipError_t launch_operator_phase(const float* Hop, int targets, bool accumulate,
                                  const PhaseArgs& p, hipStream_t s) {
   const int64_t n = colour_count(p.ux, p.uy, p.colour);
-  if (n == 0) return hipSuccess;
-  if (accumulate)
-    hipLaunchKernelGGL((operator_kernel<1, OUT_ACCUM>), dim3((unsigned)n), dim3(256), 0, s, Hop, p);
-  else if (targets == MF_CROSS)
-    hipLaunchKernelGGL((operator_kernel<0, OUT_STORE>), dim3((unsigned)n), dim3(256), 0, s, Hop, p);
-  else
-    hipLaunchKernelGGL((operator_kernel<1, OUT_STORE>), dim3((unsigned)n), dim3(256), 0, s, Hop, p);
-  return hipGetLastError();
+  for (int64_t q0 = 0; q0 < n; q0 += kMaxTilesPerLaunch) {
+    const dim3 grid((unsigned)std::min<int64_t>(n - q0, kMaxTilesPerLaunch));
+    if (accumulate)
+      hipLaunchKernelGGL((operator_kernel<1, OUT_ACCUM>), grid, dim3(256), 0, s, Hop, p, (int)q0);
+    else if (targets == MF_CROSS)
+      hipLaunchKernelGGL((operator_kernel<0, OUT_STORE>), grid, dim3(256), 0, s, Hop, p, (int)q0);
+    else
+      hipLaunchKernelGGL((operator_kernel<1, OUT_STORE>), grid, dim3(256), 0, s, Hop, p, (int)q0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mf

@@ -197,3 +197,44 @@ def test_train_and_loss_grad_argument_errors(lib):
     assert loss_grad() == MF_EINVAL and b"ctx" in lib.mf_last_error()
     assert loss_grad(grad=None) == MF_EINVAL and b"grad_out is NULL" in lib.mf_last_error()
     assert loss_grad(ws_bytes=1024) == MF_ENOMEM
+
+
+def test_colour_placements_and_target_coords(lib):
+    from oracle import geometry as geo
+    for ux, uy in ((16, 16), (1, 1), (3, 5), (64, 64)):
+        dom = _dom(ux, uy)
+        for c in range(4):
+            want = len(geo.placements_of_colour(ux, uy, c))
+            assert lib.mf_colour_placements(ctypes.byref(dom), c) == want, (ux, uy, c)
+    assert [lib.mf_colour_placements(ctypes.byref(_dom(16, 16)), c) for c in range(4)] == [256, 240, 240, 225]
+    assert lib.mf_colour_placements(ctypes.byref(_dom(2, 2)), 4) == -1
+    assert lib.mf_colour_placements(ctypes.byref(_dom(0, 2)), 0) == -1
+    assert lib.mf_colour_placements(None, 0) == -1
+    for targets, kind in ((MF_CROSS, "cross"), (MF_INTERIOR, "interior")):
+        want = [(i / 32.0, j / 32.0) for (i, j) in geo.targets(kind)]
+        X = (ctypes.c_float * (2 * len(want)))()
+        assert lib.mf_target_coords(targets, X) == MF_OK
+        got = [(X[2 * t], X[2 * t + 1]) for t in range(len(want))]
+        assert got == want
+    assert lib.mf_target_coords(2, X) == MF_EINVAL
+    assert lib.mf_target_coords(MF_CROSS, None) == MF_EINVAL
+
+
+def test_gather_scatter_argument_errors(lib):
+    f = ctypes.c_void_p(FAKE)
+    dom = _dom(3, 2)
+    assert lib.mf_gather(None, f, ctypes.byref(dom), 0, f, None) == MF_EINVAL
+    assert b"ctx" in lib.mf_last_error()                              # all else valid
+    assert lib.mf_gather(None, f, ctypes.byref(dom), 4, f, None) == MF_EINVAL
+    assert lib.mf_gather(None, None, ctypes.byref(dom), 0, f, None) == MF_EINVAL
+    assert lib.mf_gather(None, f, ctypes.byref(dom), 0, None, None) == MF_EINVAL
+    assert b"G is NULL" in lib.mf_last_error()
+    assert lib.mf_gather(None, f, ctypes.byref(_dom(3, 2, pitch=64)), 0, f, None) == MF_ESHAPE
+    one = _dom(1, 1)                                                   # colour 3 is empty: nothing to do
+    assert lib.mf_gather(None, f, ctypes.byref(one), 3, None, None) == MF_OK
+    assert lib.mf_scatter(None, f, MF_CROSS, f, ctypes.byref(dom), 1, None) == MF_EINVAL
+    assert b"ctx" in lib.mf_last_error()
+    assert lib.mf_scatter(None, f, 2, f, ctypes.byref(dom), 1, None) == MF_EINVAL
+    assert lib.mf_scatter(None, None, MF_INTERIOR, f, ctypes.byref(dom), 1, None) == MF_EINVAL
+    assert lib.mf_scatter(None, f, MF_CROSS, f, ctypes.byref(dom), -1, None) == MF_EINVAL
+    assert lib.mf_scatter(None, None, MF_CROSS, f, ctypes.byref(one), 1, None) == MF_OK
