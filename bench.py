@@ -483,6 +483,8 @@ def tile_shape_name(code):
         name += "|wide"
     if code & (1 << 17):
         name += "|stream"
+    if code & (1 << 18):
+        name += "|rowsplit"
     return name
 
 

@@ -82,7 +82,7 @@ enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
 enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
 enum { MF_TANH = 0 };                               /* activation          */
 enum { MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1 };        /* mf_solve flags      */
-enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17 }; /* tile-shape flags */
+enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17, MF_TILE_ROWSPLIT = 1 << 18 }; /* tile-shape flags */
 
 typedef struct mf_sdnet_desc {
   int32_t width;       /* d: 128 or 256                                    */

@@ -22,6 +22,7 @@ MF_TANH = 0
 MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1
 MF_TILE_WIDE = 1 << 16
 MF_TILE_STREAM = 1 << 17
+MF_TILE_ROWSPLIT = 1 << 18
 
 
 class SdnetDesc(ctypes.Structure):

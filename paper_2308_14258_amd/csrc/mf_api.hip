@@ -41,6 +41,7 @@ NetLayout net_layout(int width, int prec, size_t base) {
   L.w1x = o;  o = align256(o + 2 * d * 4);
   L.b1 = o;   o = align256(o + d * 4);
   L.wh = o;   o = align256(o + 3 * d * d * (prec == MF_FP32 ? 4 : 2));
+  L.wrs = o;  if (prec == MF_BF16) o = align256(o + 3 * d * d * 2);
   L.bh = o;   o = align256(o + 3 * d * 4);
   L.w5 = o;   o = align256(o + d * 4);
   L.b5 = o;   o = align256(o + 8);
@@ -56,6 +57,7 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws) {
   p.w1x = reinterpret_cast<const float*>(b + L.w1x);
   p.b1 = reinterpret_cast<const float*>(b + L.b1);
   p.wh = static_cast<const void*>(b + L.wh);
+  p.wrs = static_cast<const void*>(b + L.wrs);
   p.bh = reinterpret_cast<const float*>(b + L.bh);
   p.w5 = reinterpret_cast<const float*>(b + L.w5);
   p.b5 = reinterpret_cast<const float*>(b + L.b5);
@@ -155,6 +157,7 @@ static mf_status check_desc(const mf_sdnet_desc* d) {
 static bool valid_tile_rows(int prec, int rows) {
   if (prec == MF_FP32) return rows == 32 || rows == 64 || rows == (64 | MF_TILE_STREAM);
   if (rows & MF_TILE_STREAM) return false;
+  if (rows & MF_TILE_ROWSPLIT) return rows == (256 | MF_TILE_ROWSPLIT);
   const int r = rows & ~MF_TILE_WIDE;
   if (rows & MF_TILE_WIDE) return r == 128 || r == 256;
   return r == 64 || r == 128 || r == 256;
@@ -418,6 +421,8 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
       if (t.width == width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
           t.uy == dom->units_y)
         return t.rows;
+  // one domain with at least one 256-row tile per CU: the row-split bf16 tile
+  if (nd == 1 && prec == MF_BF16 && rows >= (int64_t)256 * ctx->n_cu) return 256 | MF_TILE_ROWSPLIT;
   return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
 }
 
@@ -620,9 +625,9 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   const int cands_fp32[] = {32, 64, 64 | MF_TILE_STREAM};
-  const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE};
+  const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE, 256 | MF_TILE_ROWSPLIT};
   const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
-  const int n_cands = prec == MF_FP32 ? 3 : 5;
+  const int n_cands = prec == MF_FP32 ? 3 : 6;
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;

@@ -24,6 +24,17 @@ namespace mf {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Input unit behind element e of k group kg for half-wave h in the row-split
+// tile. A 32 x 32 MFMA accumulator leaves lane (point n, half h) holding units
+// 8 i + 4 h + e' (i, e' = 0..3) of its 32-unit block; taking k group
+// 2 ob + j to be accumulator registers 8 j .. 8 j + 7 of output block ob lets
+// the next layer read its B operand straight from the converted accumulator.
+// The weights are stored with the same permutation of k, so the contraction
+// is unchanged.
+__host__ __device__ __forceinline__ int rs_unit(int kg, int h, int e) {
+  return 32 * (kg >> 1) + 16 * (kg & 1) + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+
 // ---------------------------------------------------------------------------
 // Network preparation: copy the flat parameters into the kernels' layouts.
 // Hidden matrices, per layer:
@@ -35,7 +46,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int prec,
                                    float* __restrict__ w1gT, uint16_t* __restrict__ w1gb, float* __restrict__ w1x,
-                                   float* __restrict__ b1, void* __restrict__ wh,
+                                   float* __restrict__ b1, void* __restrict__ wh, uint16_t* __restrict__ wrs,
                                    float* __restrict__ bh, float* __restrict__ w5,
                                    float* __restrict__ b5) {
   const int64_t off_b1 = (int64_t)d * 130;
@@ -93,6 +104,11 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
       j = 32 * cb + (lane & 31);
       k = 16 * kg + 8 * (lane >> 5) + e;
       static_cast<uint16_t*>(wh)[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)j * d + k]);
+      // row-split tile: [ob = d/32][kg = d/16][lane 64][8], lane l, element e
+      // holds W[32 ob + (l & 31)][rs_unit(kg, l >> 5, e)]
+      const int kg2 = (int)(rest % (d / 16)), ob = (int)(rest / (d / 16));
+      wrs[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)(32 * ob + (lane & 31)) * d +
+                                  rs_unit(kg2, lane >> 5, e)]);
     }
   }
 }
@@ -104,7 +120,7 @@ hipError_t launch_prepare_net(const float* params, int width, int prec, const Ne
                      reinterpret_cast<float*>(base + L.w1gT), reinterpret_cast<uint16_t*>(base + L.w1gb),
                      reinterpret_cast<float*>(base + L.w1x),
                      reinterpret_cast<float*>(base + L.b1), static_cast<void*>(base + L.wh),
-                     reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
+                     reinterpret_cast<uint16_t*>(base + L.wrs), reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
                      reinterpret_cast<float*>(base + L.b5));
   return hipGetLastError();
 }
@@ -583,7 +599,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
 template <int D_, int R_, int PREC_, int CPW_, bool WREG_>
 struct Shape {
   static constexpr int D = D_, R = R_, PREC = PREC_, CPW = CPW_;
-  static constexpr bool WREG = WREG_;
+  static constexpr bool WREG = WREG_, RS = false;
   static constexpr int NTH = (D / CPW) * 64;
   // waves per SIMD the register budget is sized for (HIP's second launch
   // bound): two 8-wave workgroups per CU, i.e. 128 VGPRs, where the LDS tile
@@ -591,9 +607,218 @@ struct Shape {
   static constexpr int MINW = ((PREC == 1 && CPW == 32 && R <= 128) || (PREC == 0 && !WREG)) ? 2 * NTH / 256 : 1;
 };
 
+// ---------------------------------------------------------------------------
+// Row-split bf16 tile. Each of the 8 waves owns 32 consecutive rows of a
+// 256-row tile and computes all d units of every layer for them, so the
+// activations never leave the registers: the converted accumulator of output
+// block ob is the next layer's B operand for k groups 2 ob and 2 ob + 1 (the
+// weights carry the matching permutation of k, see rs_unit). The hidden
+// weights stream through LDS instead, half a layer at a time (64 KiB at
+// d = 256) in two buffers: while the waves multiply with one half, the next
+// half is copied into the other buffer by direct global-to-LDS loads, so one
+// barrier per half layer is the only synchronisation.
+// ---------------------------------------------------------------------------
+template <int D_>
+struct RsShape {
+  static constexpr int D = D_, R = 256, PREC = 1, CPW = 32;
+  static constexpr bool WREG = true, RS = true;
+  static constexpr int NTH = 512, MINW = 2;
+};
+
+template <int D, int TMODE, int OUT>
+__device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
+  constexpr int R = 256, NTH = 512;
+  constexpr int T = n_targets<TMODE>();
+  constexpr int NPMAX = (R - 1) / T + 2;
+  constexpr int NOB = D / 32, NKG = D / 16, HOB = NOB / 2;
+  constexpr int HALF = HOB * NKG * 64;       // 16-byte pieces per half layer
+  constexpr int PPT = HALF / NTH;            // pieces per thread
+  static_assert(PPT * NTH == HALF && NPMAX <= 8, "row-split tile");
+  __shared__ __align__(16) u32x4 wbuf[2][HALF];
+  __shared__ __align__(16) float gs[NPMAX * kNB];
+  __shared__ __align__(16) float cs[NPMAX * D];
+  __shared__ __align__(16) float nb[4 * D];    // k b2, k b3, k b4, -2 w5
+  __shared__ __align__(16) float wxy[2 * D];   // k W1x[:, 0], k W1x[:, 1]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pn = lane & 31, hh = lane >> 5;
+  const NetPtrs& net = A.net;
+  const u32x4* wrs = static_cast<const u32x4*>(net.wrs);
+
+  // half layer k (layer k / 2, output blocks HOB (k & 1) ..) into LDS buffer
+  // `buf` with direct global-to-LDS loads (each lane's 16 bytes land at the
+  // wave's base + 16 lane), so the copy holds no registers; completion is
+  // awaited (vmcnt) before the barrier that publishes the buffer
+  auto fetch = [&](int k, int buf) {
+    int o = k * HALF;
+    asm volatile("" : "+s"(o));
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(wrs + o + tid + i * NTH),
+          (__attribute__((address_space(3))) void*)(&wbuf[buf][wave * 64 + i * NTH]), 16, 0, 0);
+  };
+  fetch(0, 0);
+
+  for (int i = tid; i < 4 * D; i += NTH) nb[i] = i < 3 * D ? kTwoLog2e * net.bh[i] : -2.0f * net.w5[i - 3 * D];
+  for (int i = tid; i < D; i += NTH) {
+    wxy[i] = kTwoLog2e * net.w1x[2 * i];
+    wxy[D + i] = kTwoLog2e * net.w1x[2 * i + 1];
+  }
+
+  // -- gather and bf16 boundary projection (once per placement) --------------
+  const int64_t q0 = row0 / T;
+  const int np = (int)((min(row0 + R, A.total_rows) - 1) / T - q0 + 1);
+  for (int idx = tid; idx < np * kNB; idx += NTH) {
+    const int sl = idx >> 7, k = idx & 127;
+    int a, b, bi, bj;
+    placement_of((int)(q0 + sl), A.colour, A.ux, a, b);
+    boundary_local(k, bi, bj);
+    gs[idx] = A.u_in[(int64_t)(kHalf * b + bj) * A.pitch + kHalf * a + bi];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (wave < NOB) {
+    // A = the tile's boundary vectors (rows p < np), B = this wave's 32-unit
+    // slice of W1g; registers 0..3 hold rows 4 hh .. 4 hh + 3 of unit col
+    const int col = wave * 32 + pn;
+    const u32x4* wp = static_cast<const u32x4*>(net.w1gb) + (size_t)wave * 8 * 64 + lane;
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+    for (int kg = 0; kg < 8; ++kg) {
+      bf16x8 a = bf16x8{};
+      if (pn < np) {
+        const floatx4 g0 = *reinterpret_cast<const floatx4*>(&gs[pn * kNB + 16 * kg + 8 * hh]);
+        const floatx4 g1 = *reinterpret_cast<const floatx4*>(&gs[pn * kNB + 16 * kg + 8 * hh + 4]);
+        a = bf16x8{(__bf16)g0[0], (__bf16)g0[1], (__bf16)g0[2], (__bf16)g0[3],
+                   (__bf16)g1[0], (__bf16)g1[1], (__bf16)g1[2], (__bf16)g1[3]};
+      }
+      acc = mfma32x32x16_bf16(a, __builtin_bit_cast(bf16x8, wp[kg * 64]), acc);
+    }
+    const float bb = net.b1[col];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * hh + v < np) cs[(4 * hh + v) * D + col] = kTwoLog2e * (acc[v] + bb);
+  }
+
+  // -- this lane's row ---------------------------------------------------------
+  const int64_t row = row0 + wave * 32 + pn;
+  const bool valid = row < A.total_rows;
+  const int64_t rr = valid ? row : A.total_rows - 1;
+  const int64_t q = rr / T;
+  const int t = (int)(rr - q * T);
+  int pa, pb, ti, tj;
+  placement_of((int)q, A.colour, A.ux, pa, pb);
+  target_local<TMODE>(t, ti, tj);
+  const float x = ti * (1.0f / kS), y = tj * (1.0f / kS);
+  const int slot = (int)(q - q0);
+  __syncthreads();   // projections, constants and the first half layer in LDS
+
+  // -- first layer straight into B-operand registers ---------------------------
+  bf16x8 H[2][NKG];
+#pragma unroll
+  for (int kg = 0; kg < NKG; ++kg) {
+    const int u0 = rs_unit(kg, hh, 0);
+    float v[8];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const floatx4 c = *reinterpret_cast<const floatx4*>(&cs[slot * D + u0 + 8 * g]);
+      const floatx4 wx = *reinterpret_cast<const floatx4*>(&wxy[u0 + 8 * g]);
+      const floatx4 wy = *reinterpret_cast<const floatx4*>(&wxy[D + u0 + 8 * g]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * g + e] = ktanh_exp2(fmaf(y, wy[e], fmaf(x, wx[e], c[e])));
+    }
+    H[0][kg] = bf16x8{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
+                      (__bf16)v[4], (__bf16)v[5], (__bf16)v[6], (__bf16)v[7]};
+  }
+
+  // -- hidden layers: six half-layer steps ------------------------------------
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int l = k >> 1, hf = k & 1;
+    bf16x8(&hin)[NKG] = H[l & 1];
+    bf16x8(&hout)[NKG] = H[(l + 1) & 1];
+    // the other buffer's half was finished by every wave before the last barrier
+    if (k < 5) fetch(k + 1, (k + 1) & 1);
+    const u32x4* wb = wbuf[k & 1] + lane;
+    // MFMA i of the half step (output block i / NKG, k group i % NKG) reads
+    // its weight operand from a ring filled four MFMAs ahead; the tanh (or
+    // output dot) of the previous output block's 16 accumulator elements is
+    // spread over the block's MFMAs so both pipes stay busy
+    constexpr int NI = HOB * NKG, RING = 4, EPK = 16 / NKG;   // epilogue elements per MFMA
+    bf16x8 ar[RING];
+#pragma unroll
+    for (int i = 0; i < RING; ++i) ar[i] = __builtin_bit_cast(bf16x8, wb[i * 64]);
+    floatx16 acc[2];
+    float ev[16];
+    float dsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j <= HOB; ++j) {
+      const int obp = hf * HOB + j - 1;   // block whose epilogue runs now
+      if (j < HOB) acc[j & 1] = bias_acc(nb + l * D + 32 * (hf * HOB + j) + 4 * hh);
+      floatx4 w5v[4];
+      if (l == 2 && j > 0) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) w5v[g] = *reinterpret_cast<const floatx4*>(nb + 3 * D + 32 * obp + 4 * hh + 8 * g);
+      }
+#pragma unroll
+      for (int kg = 0; kg < NKG; ++kg) {
+        const int i = j * NKG + kg;
+        if (j < HOB) {
+          acc[j & 1] = mfma32x32x16_bf16(ar[i % RING], hin[kg], acc[j & 1]);
+          if (i + RING < NI) ar[i % RING] = __builtin_bit_cast(bf16x8, wb[(i + RING) * 64]);
+        }
+        if (j > 0) {
+#pragma unroll
+          for (int ee = 0; ee < EPK; ++ee) {
+            const int e = kg * EPK + ee;   // accumulator element 0..15
+            const float c = acc[(j - 1) & 1][e];
+            if (l < 2) {
+              ev[e] = ktanh_exp2(c);
+              if ((e & 7) == 7) {
+                const int h2 = e >> 3;
+                hout[2 * obp + h2] = bf16x8{(__bf16)ev[8 * h2], (__bf16)ev[8 * h2 + 1], (__bf16)ev[8 * h2 + 2],
+                                            (__bf16)ev[8 * h2 + 3], (__bf16)ev[8 * h2 + 4], (__bf16)ev[8 * h2 + 5],
+                                            (__bf16)ev[8 * h2 + 6], (__bf16)ev[8 * h2 + 7]};
+              }
+            } else {
+              dsum = fmaf(w5v[e >> 2][e & 3], rsig_exp2(c), dsum);
+              if (e == 15) {
+                dsum += __shfl_xor(dsum, 32);
+                s += dsum;
+                dsum = 0.0f;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (k < 5) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+
+  // -- output ----------------------------------------------------------------
+  if (valid && hh == 0) {
+    const int gi = kHalf * pa + ti, gj = kHalf * pb + tj;
+    const int64_t addr = (int64_t)gj * A.pitch + gi;
+    const float val = s + net.b5[1];
+    if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
+    else A.u_out[addr] += val * (cover_inv(gi, kS * A.ux) * cover_inv(gj, kS * A.uy));
+  }
+}
+
 template <class S, int TMODE, int SRC, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
-  tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
+  if constexpr (S::RS) {
+    if constexpr (SRC == SRC_GATHER && OUT != OUT_LINEAR) rs_body<S::D, TMODE, OUT>(A, (A.block0 + blockIdx.x) * S::R);
+  } else {
+    tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
+  }
 }
 
 // Batched independent domains in one persistent launch per colour: block b
@@ -628,19 +853,21 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
+    if constexpr (S::RS) rs_body<S::D, TMODE, OUT>(A, (t - M.tile_begin[lo]) * S::R);
+    else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
     __syncthreads();   // the next tile reuses the LDS
   }
 }
 
 // Tile shapes by (width, precision, tile code): fp32 32 (streamed weights),
 // 64 (register weights), 64 | MF_TILE_STREAM (streamed); bf16 64, 128, 256,
-// and 128 or 256 | MF_TILE_WIDE (64 columns per wave). The caller has
-// validated the code.
+// 128 or 256 | MF_TILE_WIDE (64 columns per wave) and 256 | MF_TILE_ROWSPLIT
+// (row-split tile). The caller has validated the code.
 template <int D, class F>
 static hipError_t with_shape_d(int prec, int code, F&& f) {
   const int r = code & 0xffff;
   if (prec == MF_BF16) {
+    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D>{});
     if (code & MF_TILE_WIDE) return r == 256 ? f(Shape<D, 256, 1, 64, true>{}) : f(Shape<D, 128, 1, 64, true>{});
     if (r == 256) return f(Shape<D, 256, 1, 32, true>{});
     if (r == 128) return f(Shape<D, 128, 1, 32, true>{});

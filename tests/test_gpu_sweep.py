@@ -361,7 +361,7 @@ def test_graph_replay_sees_new_parameter_values(ctx, prec):
 
 @pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_FP32, 64 | (1 << 17)), (MF_BF16, 64),
                                        (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
-                                       (MF_BF16, 256 | (1 << 16))])
+                                       (MF_BF16, 256 | (1 << 16)), (MF_BF16, 256 | (1 << 18))])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
 def test_every_tile_height(ctx, prec, rows, targets):
     print(f"case: tile rows {rows} prec {prec} targets {targets}", flush=True)
@@ -391,7 +391,7 @@ def test_autotune_picks_a_candidate_and_is_used(ctx):
     f = mi.gp_field(8, 8, 1.0, seed=2)
     scratch = dev(f)
     best = mf_autotune(ctx, params, scratch, (8, 8), MF_CROSS, MF_BF16, trials=2)
-    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16))
+    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), 256 | (1 << 18))
     a = dev(f)
     mf_solve(ctx, params, a, (8, 8), 5, prec=MF_BF16)
     ctx.tile_rows(MF_BF16, best)
@@ -433,3 +433,33 @@ def test_additive_solve_c1(ctx):
                             mode="additive")
     assert rel_l2(u.cpu().numpy(), uK.numpy(), skel_interior_mask(65, 65)) <= 1e-5
     assert rel_l2(u_out.cpu().numpy(), uo.numpy(), interior_mask(65, 65)) <= 1e-5
+
+
+@pytest.mark.parametrize("width", [128, 256])
+def test_rowsplit_tile_solve_and_assembly(ctx, width):
+    """The row-split bf16 tile (each wave owns 32 rows, weights streamed
+    through LDS) in a full solve: sweeps and the overlap-averaged assembly
+    against the oracle, and against the column-split bf16 tile."""
+    print(f"case: row-split bf16 tile, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
+    ux, uy = 5, 4
+    params = mi.xavier_params(width, 2)
+    f = mi.gp_field(ux, uy, 1.0, seed=6)
+    outs = {}
+    for name, rows in (("rowsplit", 256 | (1 << 18)), ("default", 0)):
+        u = dev(f)
+        u_out = torch.empty_like(u)
+        ctx.tile_rows(MF_BF16, rows)
+        try:
+            mf_solve(ctx, dev(params), u, (ux, uy), 3, prec=MF_BF16, u_out=u_out)
+            torch.cuda.synchronize()
+        finally:
+            ctx.tile_rows(MF_BF16, 0)
+        outs[name] = (u.cpu().numpy(), u_out.cpu().numpy())
+    _, want, _, _ = sw.solve(torch.from_numpy(f.astype(np.float64)), ux, uy, oracle_solver(params, width), 3)
+    ny, nx = f.shape
+    e_or = rel_l2(outs["rowsplit"][1], want.numpy(), interior_mask(ny, nx))
+    e_cs = rel_l2(outs["rowsplit"][1], outs["default"][1], interior_mask(ny, nx))
+    print(f"row-split bf16 width {width}: u_out rel L2 vs oracle {e_or:.3e}, vs column-split bf16 {e_cs:.3e}",
+          flush=True)
+    assert e_or <= 2e-2
+    assert e_cs <= 2e-2
