@@ -128,9 +128,12 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
  * or streams them when or-ed with MF_TILE_STREAM (fewer registers, two
  * workgroups per CU). For MF_BF16 heights 128 and 256 may be or-ed with
  * MF_TILE_WIDE (each wave then owns 64 output columns instead of 32, halving
- * the LDS reads of the activations). 0 restores the automatic choice (a
- * tuned value from mf_autotune, else a rule based on the phase size and the
- * CU count). */
+ * the LDS reads of the activations), and 256 | MF_TILE_ROWSPLIT selects the
+ * row-split tile (each of 8 waves owns 32 rows and every unit; activations
+ * stay in registers and the hidden weights stream through LDS). 0 restores
+ * the automatic choice (a tuned value from mf_autotune, else a rule based on
+ * the phase size and the CU count: the row-split tile for a single domain
+ * with at least 256 rows per CU). */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
 /* Autotuner: for this network, domain, target set and precision, time

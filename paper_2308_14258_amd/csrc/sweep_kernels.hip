@@ -608,26 +608,30 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// Row-split bf16 tile. Each of the 8 waves owns 32 consecutive rows of a
-// 256-row tile and computes all d units of every layer for them, so the
-// activations never leave the registers: the converted accumulator of output
-// block ob is the next layer's B operand for k groups 2 ob and 2 ob + 1 (the
-// weights carry the matching permutation of k, see rs_unit). The hidden
-// weights stream through LDS instead, half a layer at a time (64 KiB at
-// d = 256) in two buffers: while the waves multiply with one half, the next
-// half is copied into the other buffer by direct global-to-LDS loads, so one
-// barrier per half layer is the only synchronisation.
+// Row-split bf16 tile. A 256-row tile is split by rows: each wave owns
+// 32 PB consecutive rows (PB point blocks of 32) and computes all d units of
+// every layer for them, so the activations never leave the registers: the
+// converted accumulator of output block ob is the next layer's B operand for
+// k groups 2 ob and 2 ob + 1 (the weights carry the matching permutation of
+// k, see rs_unit). The hidden weights stream through LDS instead, half a
+// layer at a time (64 KiB at d = 256) in two buffers: while the waves
+// multiply with one half, the next half is copied into the other buffer by
+// direct global-to-LDS loads, so one barrier per half layer is the only
+// synchronisation. Each weight operand read from LDS serves PB MFMAs. The
+// library launches PB = 1 (8 waves, two per SIMD); PB = 2 (4 waves, one per
+// SIMD) needs more than the 256 architectural registers for its activations
+// at d = 256 and ran slower.
 // ---------------------------------------------------------------------------
-template <int D_>
+template <int D_, int PB_>
 struct RsShape {
-  static constexpr int D = D_, R = 256, PREC = 1, CPW = 32;
+  static constexpr int D = D_, R = 256, PREC = 1, CPW = 32, PB = PB_;
   static constexpr bool WREG = true, RS = true;
-  static constexpr int NTH = 512, MINW = 2;
+  static constexpr int NTH = 512 / PB, MINW = PB == 1 ? 2 : 1;
 };
 
-template <int D, int TMODE, int OUT>
+template <int D, int TMODE, int OUT, int PB>
 __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
-  constexpr int R = 256, NTH = 512;
+  constexpr int R = 256, NW = 8 / PB, NTH = 64 * NW;
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = (R - 1) / T + 2;
   constexpr int NOB = D / 32, NKG = D / 16, HOB = NOB / 2;
@@ -678,11 +682,11 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (wave < NOB) {
-    // A = the tile's boundary vectors (rows p < np), B = this wave's 32-unit
-    // slice of W1g; registers 0..3 hold rows 4 hh .. 4 hh + 3 of unit col
-    const int col = wave * 32 + pn;
-    const u32x4* wp = static_cast<const u32x4*>(net.w1gb) + (size_t)wave * 8 * 64 + lane;
+  for (int cbk = wave; cbk < NOB; cbk += NW) {
+    // A = the tile's boundary vectors (rows p < np), B = the 32-unit slice
+    // cbk of W1g; registers 0..3 hold rows 4 hh .. 4 hh + 3 of unit col
+    const int col = cbk * 32 + pn;
+    const u32x4* wp = static_cast<const u32x4*>(net.w1gb) + (size_t)cbk * 8 * 64 + lane;
     floatx16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
@@ -703,62 +707,83 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
       if (4 * hh + v < np) cs[(4 * hh + v) * D + col] = kTwoLog2e * (acc[v] + bb);
   }
 
-  // -- this lane's row ---------------------------------------------------------
-  const int64_t row = row0 + wave * 32 + pn;
-  const bool valid = row < A.total_rows;
-  const int64_t rr = valid ? row : A.total_rows - 1;
-  const int64_t q = rr / T;
-  const int t = (int)(rr - q * T);
-  int pa, pb, ti, tj;
-  placement_of((int)q, A.colour, A.ux, pa, pb);
-  target_local<TMODE>(t, ti, tj);
-  const float x = ti * (1.0f / kS), y = tj * (1.0f / kS);
-  const int slot = (int)(q - q0);
+  // -- this lane's rows (one per point block) -----------------------------------
+  bool valid[PB];
+  int addr_i[PB], addr_j[PB], slot[PB];
+  float x[PB], y[PB];
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    const int64_t row = row0 + (wave * PB + b) * 32 + pn;
+    valid[b] = row < A.total_rows;
+    const int64_t rr = valid[b] ? row : A.total_rows - 1;
+    const int64_t q = rr / T;
+    const int t = (int)(rr - q * T);
+    int pa, pbb, ti, tj;
+    placement_of((int)q, A.colour, A.ux, pa, pbb);
+    target_local<TMODE>(t, ti, tj);
+    x[b] = ti * (1.0f / kS);
+    y[b] = tj * (1.0f / kS);
+    slot[b] = (int)(q - q0);
+    addr_i[b] = kHalf * pa + ti;
+    addr_j[b] = kHalf * pbb + tj;
+  }
   __syncthreads();   // projections, constants and the first half layer in LDS
 
   // -- first layer straight into B-operand registers ---------------------------
-  bf16x8 H[2][NKG];
+  bf16x8 H[2][PB][NKG];
 #pragma unroll
   for (int kg = 0; kg < NKG; ++kg) {
     const int u0 = rs_unit(kg, hh, 0);
-    float v[8];
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      const floatx4 c = *reinterpret_cast<const floatx4*>(&cs[slot * D + u0 + 8 * g]);
       const floatx4 wx = *reinterpret_cast<const floatx4*>(&wxy[u0 + 8 * g]);
       const floatx4 wy = *reinterpret_cast<const floatx4*>(&wxy[D + u0 + 8 * g]);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[4 * g + e] = ktanh_exp2(fmaf(y, wy[e], fmaf(x, wx[e], c[e])));
+      for (int b = 0; b < PB; ++b) {
+        const floatx4 c = *reinterpret_cast<const floatx4*>(&cs[slot[b] * D + u0 + 8 * g]);
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = ktanh_exp2(fmaf(y[b], wy[e], fmaf(x[b], wx[e], c[e])));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) H[0][b][kg][4 * g + e] = (__bf16)v[e];
+      }
     }
-    H[0][kg] = bf16x8{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3],
-                      (__bf16)v[4], (__bf16)v[5], (__bf16)v[6], (__bf16)v[7]};
   }
 
   // -- hidden layers: six half-layer steps ------------------------------------
-  float s = 0.0f;
+  float s[PB];
+#pragma unroll
+  for (int b = 0; b < PB; ++b) s[b] = 0.0f;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const int l = k >> 1, hf = k & 1;
-    bf16x8(&hin)[NKG] = H[l & 1];
-    bf16x8(&hout)[NKG] = H[(l + 1) & 1];
+    bf16x8(&hin)[PB][NKG] = H[l & 1];
+    bf16x8(&hout)[PB][NKG] = H[(l + 1) & 1];
     // the other buffer's half was finished by every wave before the last barrier
     if (k < 5) fetch(k + 1, (k + 1) & 1);
     const u32x4* wb = wbuf[k & 1] + lane;
-    // MFMA i of the half step (output block i / NKG, k group i % NKG) reads
-    // its weight operand from a ring filled four MFMAs ahead; the tanh (or
-    // output dot) of the previous output block's 16 accumulator elements is
-    // spread over the block's MFMAs so both pipes stay busy
-    constexpr int NI = HOB * NKG, RING = 4, EPK = 16 / NKG;   // epilogue elements per MFMA
+    // weight operand i of the half step (output block i / NKG, k group
+    // i % NKG) comes from a ring filled four operands ahead and feeds PB
+    // MFMAs; the tanh (or output dot) of the previous output block's 16 PB
+    // accumulator elements is spread over the block's MFMAs so both pipes
+    // stay busy
+    constexpr int NI = HOB * NKG, RING = 4, EPK = 16 / NKG;   // epilogue elements per k group and block
     bf16x8 ar[RING];
 #pragma unroll
     for (int i = 0; i < RING; ++i) ar[i] = __builtin_bit_cast(bf16x8, wb[i * 64]);
-    floatx16 acc[2];
-    float ev[16];
-    float dsum = 0.0f;
+    floatx16 acc[2][PB];
+    float ev[PB][16];
+    float dsum[PB];
+#pragma unroll
+    for (int b = 0; b < PB; ++b) dsum[b] = 0.0f;
 #pragma unroll
     for (int j = 0; j <= HOB; ++j) {
       const int obp = hf * HOB + j - 1;   // block whose epilogue runs now
-      if (j < HOB) acc[j & 1] = bias_acc(nb + l * D + 32 * (hf * HOB + j) + 4 * hh);
+      if (j < HOB) {
+        const floatx16 bias = bias_acc(nb + l * D + 32 * (hf * HOB + j) + 4 * hh);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) acc[j & 1][b] = bias;
+      }
       floatx4 w5v[4];
       if (l == 2 && j > 0) {
 #pragma unroll
@@ -768,31 +793,33 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
       for (int kg = 0; kg < NKG; ++kg) {
         const int i = j * NKG + kg;
         if (j < HOB) {
-          acc[j & 1] = mfma32x32x16_bf16(ar[i % RING], hin[kg], acc[j & 1]);
+#pragma unroll
+          for (int b = 0; b < PB; ++b) acc[j & 1][b] = mfma32x32x16_bf16(ar[i % RING], hin[b][kg], acc[j & 1][b]);
           if (i + RING < NI) ar[i % RING] = __builtin_bit_cast(bf16x8, wb[(i + RING) * 64]);
         }
         if (j > 0) {
 #pragma unroll
-          for (int ee = 0; ee < EPK; ++ee) {
-            const int e = kg * EPK + ee;   // accumulator element 0..15
-            const float c = acc[(j - 1) & 1][e];
-            if (l < 2) {
-              ev[e] = ktanh_exp2(c);
-              if ((e & 7) == 7) {
-                const int h2 = e >> 3;
-                hout[2 * obp + h2] = bf16x8{(__bf16)ev[8 * h2], (__bf16)ev[8 * h2 + 1], (__bf16)ev[8 * h2 + 2],
-                                            (__bf16)ev[8 * h2 + 3], (__bf16)ev[8 * h2 + 4], (__bf16)ev[8 * h2 + 5],
-                                            (__bf16)ev[8 * h2 + 6], (__bf16)ev[8 * h2 + 7]};
-              }
-            } else {
-              dsum = fmaf(w5v[e >> 2][e & 3], rsig_exp2(c), dsum);
-              if (e == 15) {
-                dsum += __shfl_xor(dsum, 32);
-                s += dsum;
-                dsum = 0.0f;
+          for (int b = 0; b < PB; ++b)
+#pragma unroll
+            for (int ee = 0; ee < EPK; ++ee) {
+              const int e = kg * EPK + ee;   // accumulator element 0..15
+              const float c = acc[(j - 1) & 1][b][e];
+              if (l < 2) {
+                ev[b][e] = ktanh_exp2(c);
+                if ((e & 7) == 7) {
+                  const int h2 = e >> 3;
+#pragma unroll
+                  for (int t = 0; t < 8; ++t) hout[b][2 * obp + h2][t] = (__bf16)ev[b][8 * h2 + t];
+                }
+              } else {
+                dsum[b] = fmaf(w5v[e >> 2][e & 3], rsig_exp2(c), dsum[b]);
+                if (e == 15) {
+                  dsum[b] += __shfl_xor(dsum[b], 32);
+                  s[b] += dsum[b];
+                  dsum[b] = 0.0f;
+                }
               }
             }
-          }
         }
       }
     }
@@ -803,19 +830,22 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   }
 
   // -- output ----------------------------------------------------------------
-  if (valid && hh == 0) {
-    const int gi = kHalf * pa + ti, gj = kHalf * pb + tj;
-    const int64_t addr = (int64_t)gj * A.pitch + gi;
-    const float val = s + net.b5[1];
-    if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
-    else A.u_out[addr] += val * (cover_inv(gi, kS * A.ux) * cover_inv(gj, kS * A.uy));
+#pragma unroll
+  for (int b = 0; b < PB; ++b) {
+    if (valid[b] && hh == 0) {
+      const int64_t addr = (int64_t)addr_j[b] * A.pitch + addr_i[b];
+      const float val = s[b] + net.b5[1];
+      if constexpr (OUT == OUT_STORE) A.u_out[addr] = val;
+      else A.u_out[addr] += val * (cover_inv(addr_i[b], kS * A.ux) * cover_inv(addr_j[b], kS * A.uy));
+    }
   }
 }
 
 template <class S, int TMODE, int SRC, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
   if constexpr (S::RS) {
-    if constexpr (SRC == SRC_GATHER && OUT != OUT_LINEAR) rs_body<S::D, TMODE, OUT>(A, (A.block0 + blockIdx.x) * S::R);
+    if constexpr (SRC == SRC_GATHER && OUT != OUT_LINEAR)
+      rs_body<S::D, TMODE, OUT, S::PB>(A, (A.block0 + blockIdx.x) * S::R);
   } else {
     tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
   }
@@ -853,7 +883,7 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    if constexpr (S::RS) rs_body<S::D, TMODE, OUT>(A, (t - M.tile_begin[lo]) * S::R);
+    if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB>(A, (t - M.tile_begin[lo]) * S::R);
     else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
     __syncthreads();   // the next tile reuses the LDS
   }
@@ -867,7 +897,7 @@ template <int D, class F>
 static hipError_t with_shape_d(int prec, int code, F&& f) {
   const int r = code & 0xffff;
   if (prec == MF_BF16) {
-    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D>{});
+    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D, 1>{});
     if (code & MF_TILE_WIDE) return r == 256 ? f(Shape<D, 256, 1, 64, true>{}) : f(Shape<D, 128, 1, 64, true>{});
     if (r == 256) return f(Shape<D, 256, 1, 32, true>{});
     if (r == 128) return f(Shape<D, 128, 1, 32, true>{});
