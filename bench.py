@@ -50,10 +50,10 @@ INTERIOR_T = 961
 # value the counters were taken with; otherwise "traffic" is null. Summary:
 # profiles/*_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "acc42db936fde51c4366d1b60602a906538cc61a9465e69d60f6ee37ebe5a066",
-    "bytes_per_launch": {"64": (5147.8 * 2.0 + 261.9) * 1024,
-                         "64|stream": (5099.4 * 2.0 + 261.9) * 1024,
-                         "32": (6006.5 * 2.0 + 268.6) * 1024},
+    "sources_sha256": "d3d6b9dcb5786aa804012e78a68ca8062a176f6c518ec3c3273da088efbdf025",
+    "bytes_per_launch": {"64": (5151.3 * 2.0 + 261.9) * 1024,
+                         "64|stream": (5093.8 * 2.0 + 261.9) * 1024,
+                         "32": (6015.4 * 2.0 + 268.6) * 1024},
 }
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
