@@ -534,75 +534,71 @@ __global__ __launch_bounds__(D) void layer1_reduce_kernel(const float* __restric
   out[(2 * B + b) * D + j] = cy;
 }
 
-// grad W1g[j][k] = sum_b (c0[b][j] + c1[b][j]) G[b][k]; b1, W1x from the sums.
-// Workgroup g < D/8 owns rows j in [8 g, 8 g + 8) and all 128 k, with the
-// conditions b staged through LDS in chunks of 64 (each (j, k) is summed
-// over b in ascending order); the last workgroup forms b1 and W1x.
-constexpr int kL1Rows = 8, kL1Chunk = 64;
+// grad W1g[j][k] = sum_b (c0[b][j] + c1[b][j]) G[b][k]; grad b1 = sum_b c[b][j]
+// and grad W1x[j] = (sum_b cx[b][j], sum_b cy[b][j]), c = c0 + c1 from the two
+// passes. Two deterministic stages: workgroup (g, ch) sums the conditions of
+// chunk ch (L consecutive ones, staged through LDS 64 at a time, ascending)
+// for rows j in [8 g, 8 g + 8) into part[ch][j][0..130] (128 W1g columns,
+// then x, y, bias); layer1_sum_kernel adds the chunk partials in chunk order.
+constexpr int kL1Rows = 8, kL1Chunk = 64, kL1MaxChunks = 256, kL1Cols = 131;
 
 template <int D>
-__global__ __launch_bounds__(256) void layer1_grad_kernel(const float* __restrict__ l1a,
+__global__ __launch_bounds__(256) void layer1_part_kernel(const float* __restrict__ l1a,
                                                           const float* __restrict__ l1b,
-                                                          const float* __restrict__ G, int64_t B,
-                                                          float* __restrict__ grad) {
-  const int64_t off_b1 = (int64_t)D * 130;
-  if (blockIdx.x == D / kL1Rows) {
-    // 256 / D threads per j, each summing every (256 / D)-th condition; the
-    // partial sums are added in thread order
-    constexpr int TPJ = 256 / D;
-    __shared__ float red[3][256];
-    const int j = threadIdx.x % D, q = threadIdx.x / D;
-    float c = 0.0f, cx = 0.0f, cy = 0.0f;
-#pragma unroll 8
-    for (int64_t b = q; b < B; b += TPJ) {
-      c += l1a[b * D + j] + l1b[b * D + j];
-      cx += l1a[(B + b) * D + j] + l1b[(B + b) * D + j];
-      cy += l1a[(2 * B + b) * D + j] + l1b[(2 * B + b) * D + j];
-    }
-    red[0][threadIdx.x] = c;
-    red[1][threadIdx.x] = cx;
-    red[2][threadIdx.x] = cy;
-    __syncthreads();
-    if (q == 0) {
-      c = cx = cy = 0.0f;
-#pragma unroll
-      for (int u = 0; u < TPJ; ++u) {
-        c += red[0][u * D + j];
-        cx += red[1][u * D + j];
-        cy += red[2][u * D + j];
-      }
-      grad[(int64_t)j * 130 + 128] = cx;
-      grad[(int64_t)j * 130 + 129] = cy;
-      grad[off_b1 + j] = c;
-    }
-    return;
-  }
+                                                          const float* __restrict__ G, int64_t B, int64_t L,
+                                                          float* __restrict__ part) {
   __shared__ float gs[kL1Chunk][128];
-  __shared__ float ls[kL1Chunk][kL1Rows];
+  __shared__ float ls[3][kL1Chunk][kL1Rows];   // c, cx, cy of the rows
   const int j0 = blockIdx.x * kL1Rows;
+  const int64_t ch = blockIdx.y;
+  const int64_t b_begin = ch * L, b_end = std::min<int64_t>(B, b_begin + L);
   const int k = threadIdx.x & 127, js = threadIdx.x >> 7;   // rows j0 + js + 2 i, i < 4
   float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t b0 = 0; b0 < B; b0 += kL1Chunk) {
+  float sacc = 0.0f;   // threads < 24: sum type t = tid / 8 (x, y, bias) of row j0 + tid % 8
+  for (int64_t b0 = b_begin; b0 < b_end; b0 += kL1Chunk) {
+    const int nb = (int)std::min<int64_t>(kL1Chunk, b_end - b0);
     for (int idx = threadIdx.x; idx < kL1Chunk * 128; idx += 256) {
       const int bb = idx >> 7, kk = idx & 127;
-      gs[bb][kk] = (b0 + bb < B) ? G[(b0 + bb) * 128 + kk] : 0.0f;
+      gs[bb][kk] = bb < nb ? G[(b0 + bb) * 128 + kk] : 0.0f;
     }
-    for (int idx = threadIdx.x; idx < kL1Chunk * kL1Rows; idx += 256) {
-      const int bb = idx / kL1Rows, jj = idx - bb * kL1Rows;
-      const int64_t b = b0 + bb;
-      ls[bb][jj] = (b < B) ? l1a[b * D + j0 + jj] + l1b[b * D + j0 + jj] : 0.0f;
+    for (int idx = threadIdx.x; idx < 3 * kL1Chunk * kL1Rows; idx += 256) {
+      const int t = idx / (kL1Chunk * kL1Rows), r = idx - t * (kL1Chunk * kL1Rows);
+      const int bb = r / kL1Rows, jj = r - bb * kL1Rows;
+      const int64_t o = ((int64_t)t * B + b0 + bb) * D + j0 + jj;
+      ls[t][bb][jj] = bb < nb ? l1a[o] + l1b[o] : 0.0f;
     }
     __syncthreads();
-    const int nb = (int)std::min<int64_t>(kL1Chunk, B - b0);
     for (int bb = 0; bb < nb; ++bb) {
       const float g = gs[bb][k];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = fmaf(ls[bb][js + 2 * i], g, acc[i]);
+      for (int i = 0; i < 4; ++i) acc[i] = fmaf(ls[0][bb][js + 2 * i], g, acc[i]);
+    }
+    if (threadIdx.x < 3 * kL1Rows) {
+      const int t = threadIdx.x / kL1Rows, jj = threadIdx.x - t * kL1Rows;
+      const int src = t == 2 ? 0 : t + 1;   // x <- cx, y <- cy, bias <- c
+      for (int bb = 0; bb < nb; ++bb) sacc += ls[src][bb][jj];
     }
     __syncthreads();
   }
+  float* pp = part + (ch * D + j0) * kL1Cols;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) grad[(int64_t)(j0 + js + 2 * i) * 130 + k] = acc[i];
+  for (int i = 0; i < 4; ++i) pp[(js + 2 * i) * kL1Cols + k] = acc[i];
+  if (threadIdx.x < 3 * kL1Rows) {
+    const int t = threadIdx.x / kL1Rows, jj = threadIdx.x - t * kL1Rows;
+    pp[jj * kL1Cols + 128 + t] = sacc;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void layer1_sum_kernel(const float* __restrict__ part, int n_chunks,
+                                                         float* __restrict__ grad) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= D * kL1Cols) return;
+  const int j = idx / kL1Cols, c = idx - j * kL1Cols;
+  float v = 0.0f;
+  for (int ch = 0; ch < n_chunks; ++ch) v += part[(int64_t)ch * D * kL1Cols + idx];
+  if (c < 130) grad[(int64_t)j * 130 + c] = v;   // W1g columns, then W1x x and y
+  else grad[(int64_t)D * 130 + j] = v;           // b1
 }
 
 // Output-layer gradient and the two losses from the per-wave partials:
@@ -811,7 +807,15 @@ static hipError_t train_step_d(const NetPtrs& net, const float* whT, const Train
   // Alg. 1 step 2: collocation points, four streams; accumulate.
   e = run_pass<D>(net, whT, tb, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((layer1_grad_kernel<D>), dim3(D / kL1Rows + 1), dim3(256), 0, s, tb.l1[0], tb.l1[1], G, B,
+  // first-layer gradient; the weight-gradient partials (already reduced into
+  // grad by both passes) hold its chunk partials
+  const int64_t L = std::max<int64_t>(kL1Chunk, ((B + kL1MaxChunks - 1) / kL1MaxChunks + kL1Chunk - 1) /
+                                                    kL1Chunk * kL1Chunk);
+  const int n_chunks = (int)((B + L - 1) / L);
+  hipLaunchKernelGGL((layer1_part_kernel<D>), dim3(D / kL1Rows, n_chunks), dim3(256), 0, s, tb.l1[0], tb.l1[1], G,
+                     B, L, tb.wpart);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((layer1_sum_kernel<D>), dim3((D * kL1Cols + 255) / 256), dim3(256), 0, s, tb.wpart, n_chunks,
                      grad);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((output_grad_kernel<D>), dim3((D + 2 + 256 / kReduceGroups - 1) / (256 / kReduceGroups)),
