@@ -96,7 +96,8 @@ TrainLayout train_layout(int width, int64_t B, int64_t nc) {
   T.whT = o; o = align256(o + 3 * d * d * 4);
   T.C = o;   o = align256(o + (size_t)B * d * 4);
   for (int l = 0; l < 4; ++l) { T.Z[l] = o; o = align256(o + SR * d * 4); }
-  for (int l = 0; l < 4; ++l) { T.Sv[l] = o; o = align256(o + SR * d * 4); }
+  // Sv[0] (layer 1) is never stored: its a_x, a_y, a_L are W1x and 0 for every row
+  for (int l = 1; l < 4; ++l) { T.Sv[l] = o; o = align256(o + SR * d * 4); }
   for (int l = 0; l < 2; ++l) { T.Ab[l] = o; o = align256(o + SR * d * 4); }
   T.wpart = o; o = align256(o + chunks * d * d * 4);
   T.bpart = o; o = align256(o + chunks * d * 4);
@@ -113,7 +114,7 @@ TrainBuffers train_buffers(const TrainLayout& L, void* ws) {
   t.C = reinterpret_cast<float*>(b + L.C);
   for (int l = 0; l < 4; ++l) {
     t.Z[l] = reinterpret_cast<float*>(b + L.Z[l]);
-    t.Sv[l] = reinterpret_cast<float*>(b + L.Sv[l]);
+    t.Sv[l] = l == 0 ? nullptr : reinterpret_cast<float*>(b + L.Sv[l]);
   }
   for (int l = 0; l < 2; ++l) {
     t.Ab[l] = reinterpret_cast<float*>(b + L.Ab[l]);

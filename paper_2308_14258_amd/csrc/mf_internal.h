@@ -113,7 +113,7 @@ constexpr int kBwdGroups = 512;
 struct TrainBuffers {
   float* C;          // [B][d] boundary projections (b1 included)
   float* Z[4];       // [SR][d] stream rows after layers 1..4 (z, z_x, z_y, z_L)
-  float* Sv[4];      // [SR][d] saved (-, a_x, a_y, a_L) of layers 1..4 (z is Z's value row)
+  float* Sv[4];      // [SR][d] saved (-, a_x, a_y, a_L) of layers 2..4 (z is Z's value row); Sv[0] null
   float* Ab[2];      // [SR][d] ping-pong pre-activation adjoints
   float* wpart;      // [kBwdGroups][d*d] weight-gradient partials
   float* bpart;      // [kBwdGroups][d]

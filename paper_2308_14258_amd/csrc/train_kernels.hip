@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
                                                          const float* __restrict__ X, int x_per_bc,
                                                          int64_t rows_per_bc, int64_t n_rows,
                                                          const float* __restrict__ w1x,
-                                                         float* __restrict__ Z, float* __restrict__ Sv) {
+                                                         float* __restrict__ Z) {
   const int64_t n = n_rows * D;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -84,11 +84,6 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
       Z[o + D] = s * wx;
       Z[o + 2 * D] = s * wy;
       Z[o + 3 * D] = -2.0f * z * s * (wx * wx + wy * wy);
-      if (Sv) {
-        Sv[o + D] = wx;
-        Sv[o + 2 * D] = wy;
-        Sv[o + 3 * D] = 0.0f;
-      }
     }
   }
 }
@@ -188,11 +183,20 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
 
 // Reverse tanh rules of the previous layer applied to Zb = Ab W (acc). z is
 // that layer's output, i.e. the value rows of the layer-input tile `HH`
-// (LDS, row pitch LDH); a_x, a_y, a_L come from the saved streams Sv_in.
-template <int D, int S, int LDH>
+// (LDS, row pitch LDH); a_x, a_y, a_L come from the saved streams Sv_in, or,
+// when Sv_in is null (the previous layer is the first one, whose stream
+// derivatives do not depend on the row), a_x = W1x[j][0], a_y = W1x[j][1],
+// a_L = 0 (L1: the previous layer is the first one).
+template <int D, int S, int LDH, bool L1>
 __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t row0, int j, int h,
                                              const float* HH, const float* __restrict__ Sv_in,
-                                             float* __restrict__ Out, int64_t n_srows) {
+                                             const float* __restrict__ w1x, float* __restrict__ Out,
+                                             int64_t n_srows) {
+  float ax1 = 0.0f, ay1 = 0.0f;
+  if constexpr (S == 4 && L1) {
+    ax1 = w1x[2 * j];
+    ay1 = w1x[2 * j + 1];
+  }
 #pragma unroll
   for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
@@ -202,7 +206,9 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
       if constexpr (S == 4) {
         if (sr >= n_srows) continue;
         const int64_t o = sr * D + j;
-        const float z = HH[lr * LDH + j], ax = Sv_in[o + D], ay = Sv_in[o + 2 * D], aL = Sv_in[o + 3 * D];
+        const float z = HH[lr * LDH + j];
+        const float ax = L1 ? ax1 : Sv_in[o + D], ay = L1 ? ay1 : Sv_in[o + 2 * D];
+        const float aL = L1 ? 0.0f : Sv_in[o + 3 * D];
         const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
         const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
         const float s = 1.0f - z * z, q = ax * ax + ay * ay;
@@ -224,11 +230,13 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
   }
 }
 
-template <int D, int S>
-__global__ __launch_bounds__(4 * D) void taylor_bwd_split_kernel(const float* __restrict__ Ab,
+// Register budget for two 8-wave workgroups per CU (four waves per SIMD).
+template <int D, int S, bool L1>
+__global__ __launch_bounds__(4 * D, 4) void taylor_bwd_split_kernel(const float* __restrict__ Ab,
                                                            const float* __restrict__ H,
                                                            const floatx4* __restrict__ wsw,
                                                            const float* __restrict__ Sv_in,
+                                                           const float* __restrict__ w1x,
                                                            float* __restrict__ Out, int64_t n_srows,
                                                            float* __restrict__ wpart,
                                                            float* __restrict__ bpart) {
@@ -245,23 +253,41 @@ __global__ __launch_bounds__(4 * D) void taylor_bwd_split_kernel(const float* __
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
   const int64_t n_tiles = (n_srows + R - 1) / R;
+  // The adjoint role stages its tile array (Ab) from registers filled one
+  // tile ahead: the loads of tile t + gridDim.x are issued before tile t's
+  // MFMAs. The weight-gradient role, which holds D/32 accumulator blocks,
+  // loads its array (H) at the top of each tile.
+  floatx4 pf[PER];
+  auto fetch = [&](const float* src, int rt, int64_t t) {
+    const int64_t row0 = t * R;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = rt + i * RTH;
+      const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+      pf[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      if (t < n_tiles && row0 + r < n_srows) pf[i] = reinterpret_cast<const floatx4*>(src + (row0 + r) * D)[c4];
+    }
+  };
+  auto stage = [&](float* dst, int rt) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = rt + i * RTH;
+      const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+      *reinterpret_cast<floatx4*>(&dst[r * LDH + 4 * c4]) = pf[i];
+    }
+  };
   if (wave < NW) {
     const int rt = tid;                        // thread within the role
     const int j = wave * 32 + col;
+    fetch(Ab, rt, blockIdx.x);
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
       const int64_t row0 = t * R;
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int idx = rt + i * RTH;
-        const int r = idx / (D / 4), c4 = idx - r * (D / 4);
-        floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(Ab + (row0 + r) * D)[c4];
-        *reinterpret_cast<floatx4*>(&HA[r * LDH + 4 * c4]) = v;
-      }
+      stage(HA, rt);
       __syncthreads();
+      fetch(Ab, rt, t + gridDim.x);
       floatx16 acc[RB];
       mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
-      bwd_epilogue<D, S, LDH>(acc, row0, j, h, HH, Sv_in, Out, n_srows);
+      bwd_epilogue<D, S, LDH, L1>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
       __syncthreads();   // the next tile overwrites the LDS
     }
   } else {
@@ -275,15 +301,8 @@ __global__ __launch_bounds__(4 * D) void taylor_bwd_split_kernel(const float* __
       for (int v = 0; v < 16; ++v) accw[kb][v] = 0.0f;
     float bsum = 0.0f;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-      const int64_t row0 = t * R;
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int idx = rt + i * RTH;
-        const int r = idx / (D / 4), c4 = idx - r * (D / 4);
-        floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(H + (row0 + r) * D)[c4];
-        *reinterpret_cast<floatx4*>(&HH[r * LDH + 4 * c4]) = v;
-      }
+      fetch(H, rt, t);
+      stage(HH, rt);
       __syncthreads();
       // weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
       // at MFMA step e to both operands
@@ -313,11 +332,12 @@ __global__ __launch_bounds__(4 * D) void taylor_bwd_split_kernel(const float* __
 // Width 256: one role per wave (both products in turn); the role-split
 // form above would need more than the 128 VGPRs a 1024-thread workgroup
 // allows.
-template <int D, int S>
+template <int D, int S, bool L1>
 __global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __restrict__ Ab,
                                                            const float* __restrict__ H,
                                                            const floatx4* __restrict__ wsw,
                                                            const float* __restrict__ Sv_in,
+                                                           const float* __restrict__ w1x,
                                                            float* __restrict__ Out, int64_t n_srows,
                                                            float* __restrict__ wpart,
                                                            float* __restrict__ bpart) {
@@ -365,7 +385,7 @@ __global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __re
     // (i) input adjoint and reverse rules
     floatx16 acc[RB];
     mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
-    bwd_epilogue<D, S, LDH>(acc, row0, j, h, HH, Sv_in, Out, n_srows);
+    bwd_epilogue<D, S, LDH, L1>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
     // (ii) weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
     // at MFMA step e to both operands
 #pragma unroll 2
@@ -707,10 +727,10 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
   const int64_t n_srows = S * n_rows;
   if (S == 4)
     hipLaunchKernelGGL((fwd_layer1_kernel<D, 4>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
-                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], Sv[0]);
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
   else
     hipLaunchKernelGGL((fwd_layer1_kernel<D, 1>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
-                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], Sv[0]);
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((n_srows + 63) / 64);
@@ -757,20 +777,30 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
   for (int l = 2; l >= 0; --l) {           // hidden layer l+2, input Z[l]
     float* Ab = tb.Ab[cur];
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
+    // layer 1's stream derivatives are W1x and 0 for every row: not stored
+    const bool l1 = S == 4 && l == 0;
+    const float* svl = l1 ? nullptr : Sv[l];
+    float* out = tb.Ab[cur ^ 1];
     if constexpr (D <= 128) {
-      if (S == 4)
-        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab, Z[l],
-                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+      if (l1)
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, true>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
+      else if (S == 4)
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, false>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else
-        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 1>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab, Z[l],
-                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 1, false>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
     } else {
-      if (S == 4)
-        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l],
-                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+      if (l1)
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, true>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
+      else if (S == 4)
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, false>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else
-        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 1>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab, Z[l],
-                           wT, Sv[l], tb.Ab[cur ^ 1], n_srows, tb.wpart, tb.bpart);
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 1, false>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+                           Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float* gW = grad + off_w2 + l * lstride;
