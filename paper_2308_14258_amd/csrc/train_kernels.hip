@@ -105,7 +105,7 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
                                                             const float* __restrict__ Sv_in,
                                                             float* __restrict__ Out,
                                                             float* __restrict__ Sv_out,
-                                                            int64_t n_srows) {
+                                                            int64_t n_srows, int skip_xy) {
   static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_*_kernel");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
   __shared__ __align__(16) float Hs[R * LDH];
@@ -139,8 +139,10 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
           const float ay = acc[rb][4 * m + 2], aL = acc[rb][4 * m + 3];
           const float z = tanh_f32(a), s = 1.0f - z * z;
           Out[o] = z;
-          Out[o + D] = s * ax;
-          Out[o + 2 * D] = s * ay;
+          if (!skip_xy) {   // the output layer reads only the value and Laplacian streams
+            Out[o + D] = s * ax;
+            Out[o + 2 * D] = s * ay;
+          }
           Out[o + 3 * D] = s * aL - 2.0f * z * s * (ax * ax + ay * ay);
           if (Sv_out) {   // z itself is the value row of Out
             Sv_out[o + D] = ax;
@@ -720,10 +722,12 @@ static int grid_for(int64_t n, int block, int cap = 8192) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, cap));
 }
 
+// skip_last_xy: the last layer's d/dx and d/dy streams are not written (the
+// training loss reads only its value and Laplacian streams).
 template <int D>
 static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const float* X, int x_per_bc,
                                      int64_t rows_per_bc, int64_t n_rows, int S, float* const Z[4],
-                                     float* const Sv[4], hipStream_t s) {
+                                     float* const Sv[4], bool skip_last_xy, hipStream_t s) {
   const int64_t n_srows = S * n_rows;
   if (S == 4)
     hipLaunchKernelGGL((fwd_layer1_kernel<D, 4>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
@@ -738,10 +742,10 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
     const floatx4* w = static_cast<const floatx4*>(net.wh) + (size_t)l * D * D / 4;
     if (S == 4)
       hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
-                         net.bh + l * D, nullptr, Z[l + 1], Sv[l + 1], n_srows);
+                         net.bh + l * D, nullptr, Z[l + 1], Sv[l + 1], n_srows, (skip_last_xy && l == 2) ? 1 : 0);
     else
       hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
-                         net.bh + l * D, nullptr, Z[l + 1], nullptr, n_srows);
+                         net.bh + l * D, nullptr, Z[l + 1], nullptr, n_srows, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -758,7 +762,7 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
   float* const* Z = tb.Z;
   float* const* Sv = (S == 4) ? tb.Sv : tb.Z;   // value-only rows: saved z = Z
   hipError_t e = run_taylor_forward<D>(net, C, X, x_per_bc, rows_per_bc, n_rows, S, Z,
-                                       (S == 4) ? tb.Sv : tb.Z, s);
+                                       (S == 4) ? tb.Sv : tb.Z, true, s);
   if (e != hipSuccess) return e;
   const float inv_n = 1.0f / (float)n_rows;
   if (S == 4)
@@ -875,8 +879,8 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, 
 hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
                                 int64_t n_bc, float* const Z[4], hipStream_t s) {
   float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
-  return width == 256 ? run_taylor_forward<256>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, s)
-                      : run_taylor_forward<128>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, s);
+  return width == 256 ? run_taylor_forward<256>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, false, s)
+                      : run_taylor_forward<128>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, false, s);
 }
 
 // Value-stream reverse pass from ab4 in Ab[0] down to ab1, then per-condition
@@ -889,7 +893,7 @@ static hipError_t value_backward_d(const float* whT, float* const Z[4], float* c
   for (int l = 2; l >= 0; --l) {
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
     hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT, nullptr,
-                       Z[l], Ab[cur ^ 1], nullptr, n_rows);
+                       Z[l], Ab[cur ^ 1], nullptr, n_rows, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
@@ -913,8 +917,8 @@ hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, 
   float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
   const int64_t n_rows = n_bc * n_pts;
   hipError_t e = width == 256
-                     ? run_taylor_forward<256>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, s)
-                     : run_taylor_forward<128>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, s);
+                     ? run_taylor_forward<256>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s)
+                     : run_taylor_forward<128>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s);
   if (e != hipSuccess) return e;
   const int blocks = grid_for(n_rows, 4, 4096);
   if (width == 256)
