@@ -41,7 +41,6 @@ NetLayout net_layout(int width, int prec, size_t base) {
   L.w1x = o;  o = align256(o + 2 * d * 4);
   L.b1 = o;   o = align256(o + d * 4);
   L.wh = o;   o = align256(o + 3 * d * d * (prec == MF_FP32 ? 4 : 2));
-  L.wrs = o;  if (prec == MF_BF16) o = align256(o + 3 * d * d * 2);
   L.bh = o;   o = align256(o + 3 * d * 4);
   L.w5 = o;   o = align256(o + d * 4);
   L.b5 = o;   o = align256(o + 8);
@@ -57,7 +56,6 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws) {
   p.w1x = reinterpret_cast<const float*>(b + L.w1x);
   p.b1 = reinterpret_cast<const float*>(b + L.b1);
   p.wh = static_cast<const void*>(b + L.wh);
-  p.wrs = static_cast<const void*>(b + L.wrs);
   p.bh = reinterpret_cast<const float*>(b + L.bh);
   p.w5 = reinterpret_cast<const float*>(b + L.w5);
   p.b5 = reinterpret_cast<const float*>(b + L.b5);
@@ -422,8 +420,8 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
       if (t.width == width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
           t.uy == dom->units_y)
         return t.rows;
-  // one domain with at least one 256-row tile per CU: the row-split bf16 tile
-  if (nd == 1 && prec == MF_BF16 && rows >= (int64_t)256 * ctx->n_cu) return 256 | MF_TILE_ROWSPLIT;
+  // at least one 256-row tile per CU: the row-split bf16 tile
+  if (prec == MF_BF16 && rows >= (int64_t)256 * ctx->n_cu) return 256 | MF_TILE_ROWSPLIT;
   return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
 }
 

@@ -22,7 +22,6 @@ struct NetLayout {
   size_t w1x = 0;    // float [d][2]: W1 coordinate columns
   size_t b1 = 0;     // float [d]
   size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32 or bf16)
-  size_t wrs = 0;    // bf16 hidden matrices for the row-split tile (MF_BF16 only)
   size_t bh = 0;     // float [3][d]
   size_t w5 = 0;     // float [d]
   size_t b5 = 0;     // float [2]: b5, b5 + sum(w5)
@@ -37,7 +36,6 @@ struct NetPtrs {
   const float* w1x;
   const float* b1;
   const void* wh;
-  const void* wrs;
   const float* bh;
   const float* w5;
   const float* b5;

@@ -24,17 +24,6 @@ namespace mf {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Input unit behind element e of k group kg for half-wave h in the row-split
-// tile. A 32 x 32 MFMA accumulator leaves lane (point n, half h) holding units
-// 8 i + 4 h + e' (i, e' = 0..3) of its 32-unit block; taking k group
-// 2 ob + j to be accumulator registers 8 j .. 8 j + 7 of output block ob lets
-// the next layer read its B operand straight from the converted accumulator.
-// The weights are stored with the same permutation of k, so the contraction
-// is unchanged.
-__host__ __device__ __forceinline__ int rs_unit(int kg, int h, int e) {
-  return 32 * (kg >> 1) + 16 * (kg & 1) + 8 * (e >> 2) + 4 * h + (e & 3);
-}
-
 // ---------------------------------------------------------------------------
 // Network preparation: copy the flat parameters into the kernels' layouts.
 // Hidden matrices, per layer:
@@ -46,7 +35,7 @@ __host__ __device__ __forceinline__ int rs_unit(int kg, int h, int e) {
 // ---------------------------------------------------------------------------
 __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int prec,
                                    float* __restrict__ w1gT, uint16_t* __restrict__ w1gb, float* __restrict__ w1x,
-                                   float* __restrict__ b1, void* __restrict__ wh, uint16_t* __restrict__ wrs,
+                                   float* __restrict__ b1, void* __restrict__ wh,
                                    float* __restrict__ bh, float* __restrict__ w5,
                                    float* __restrict__ b5) {
   const int64_t off_b1 = (int64_t)d * 130;
@@ -104,11 +93,6 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
       j = 32 * cb + (lane & 31);
       k = 16 * kg + 8 * (lane >> 5) + e;
       static_cast<uint16_t*>(wh)[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)j * d + k]);
-      // row-split tile: [ob = d/32][kg = d/16][lane 64][8], lane l, element e
-      // holds W[32 ob + (l & 31)][rs_unit(kg, l >> 5, e)]
-      const int kg2 = (int)(rest % (d / 16)), ob = (int)(rest / (d / 16));
-      wrs[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)(32 * ob + (lane & 31)) * d +
-                                  rs_unit(kg2, lane >> 5, e)]);
     }
   }
 }
@@ -120,7 +104,7 @@ hipError_t launch_prepare_net(const float* params, int width, int prec, const Ne
                      reinterpret_cast<float*>(base + L.w1gT), reinterpret_cast<uint16_t*>(base + L.w1gb),
                      reinterpret_cast<float*>(base + L.w1x),
                      reinterpret_cast<float*>(base + L.b1), static_cast<void*>(base + L.wh),
-                     reinterpret_cast<uint16_t*>(base + L.wrs), reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
+                     reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
                      reinterpret_cast<float*>(base + L.b5));
   return hipGetLastError();
 }
@@ -611,9 +595,10 @@ struct Shape {
 // Row-split bf16 tile. A 256-row tile is split by rows: each wave owns
 // 32 PB consecutive rows (PB point blocks of 32) and computes all d units of
 // every layer for them, so the activations never leave the registers: the
-// converted accumulator of output block ob is the next layer's B operand for
-// k groups 2 ob and 2 ob + 1 (the weights carry the matching permutation of
-// k, see rs_unit). The hidden weights stream through LDS instead, half a
+// converted accumulator of output block ob becomes the next layer's B operand
+// for k groups 2 ob and 2 ob + 1 after one exchange between the half-waves
+// (rs_operand), in the same k order as the column-split tile's, so both tiles
+// give identical results. The hidden weights stream through LDS instead, half a
 // layer at a time (64 KiB at d = 256) in two buffers: while the waves
 // multiply with one half, the next half is copied into the other buffer by
 // direct global-to-LDS loads, so one barrier per half layer is the only
@@ -622,6 +607,22 @@ struct Shape {
 // SIMD) needs more than the 256 architectural registers for its activations
 // at d = 256 and ran slower.
 // ---------------------------------------------------------------------------
+// Next-layer B operand of one k group from eight tanh values of a lane's
+// accumulator block: lane (point n, half h) holds units 4 h + 0..3 (v[0..3])
+// and 8 + 4 h + 0..3 (v[4..7]) of the group's 16, the operand wants units
+// 8 h + 0..7. One v_permlane32_swap per register pair moves the upper
+// half-wave's first quarter and the lower half-wave's second quarter across.
+__device__ __forceinline__ bf16x8 rs_operand(const float* v) {
+  const bf16x2 p0 = {(__bf16)v[0], (__bf16)v[1]}, p1 = {(__bf16)v[2], (__bf16)v[3]};
+  const bf16x2 q0 = {(__bf16)v[4], (__bf16)v[5]}, q1 = {(__bf16)v[6], (__bf16)v[7]};
+  const auto s0 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, q0),
+                                                   false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, p1), __builtin_bit_cast(uint32_t, q1),
+                                                   false, false);
+  // s[0]: lower half-wave keeps its own, upper gets the lower's; s[1] the reverse
+  return __builtin_bit_cast(bf16x8, u32x4{s0[0], s1[0], s0[1], s1[1]});
+}
+
 template <int D_, int PB_>
 struct RsShape {
   static constexpr int D = D_, R = 256, PREC = 1, CPW = 32, PB = PB_;
@@ -647,7 +648,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pn = lane & 31, hh = lane >> 5;
   const NetPtrs& net = A.net;
-  const u32x4* wrs = static_cast<const u32x4*>(net.wrs);
+  const u32x4* whp = static_cast<const u32x4*>(net.wh);   // prepared bf16 weights, [ob][kg][lane][8]
 
   // half layer k (layer k / 2, output blocks HOB (k & 1) ..) into LDS buffer
   // `buf` with direct global-to-LDS loads (each lane's 16 bytes land at the
@@ -659,7 +660,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
 #pragma unroll
     for (int i = 0; i < PPT; ++i)
       __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)(wrs + o + tid + i * NTH),
+          (const __attribute__((address_space(1))) void*)(whp + o + tid + i * NTH),
           (__attribute__((address_space(3))) void*)(&wbuf[buf][wave * 64 + i * NTH]), 16, 0, 0);
   };
   fetch(0, 0);
@@ -733,14 +734,14 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   bf16x8 H[2][PB][NKG];
 #pragma unroll
   for (int kg = 0; kg < NKG; ++kg) {
-    const int u0 = rs_unit(kg, hh, 0);
+    const int u0 = 16 * kg + 8 * hh;   // B operand: lane (point, half h) feeds units 16 kg + 8 h + 0..7
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      const floatx4 wx = *reinterpret_cast<const floatx4*>(&wxy[u0 + 8 * g]);
-      const floatx4 wy = *reinterpret_cast<const floatx4*>(&wxy[D + u0 + 8 * g]);
+      const floatx4 wx = *reinterpret_cast<const floatx4*>(&wxy[u0 + 4 * g]);
+      const floatx4 wy = *reinterpret_cast<const floatx4*>(&wxy[D + u0 + 4 * g]);
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
-        const floatx4 c = *reinterpret_cast<const floatx4*>(&cs[slot[b] * D + u0 + 8 * g]);
+        const floatx4 c = *reinterpret_cast<const floatx4*>(&cs[slot[b] * D + u0 + 4 * g]);
         float v[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = ktanh_exp2(fmaf(y[b], wy[e], fmaf(x[b], wx[e], c[e])));
@@ -808,8 +809,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
                 ev[b][e] = ktanh_exp2(c);
                 if ((e & 7) == 7) {
                   const int h2 = e >> 3;
-#pragma unroll
-                  for (int t = 0; t < 8; ++t) hout[b][2 * obp + h2][t] = (__bf16)ev[b][8 * h2 + t];
+                  hout[b][2 * obp + h2] = rs_operand(ev[b] + 8 * h2);
                 }
               } else {
                 dsum[b] = fmaf(w5v[e >> 2][e & 3], rsig_exp2(c), dsum[b]);
@@ -855,6 +855,9 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
 // takes tiles b, b + gridDim.x, ...; tile t belongs to the domain d with
 // tile_begin[d] <= t < tile_begin[d + 1] and covers rows
 // [(t - tile_begin[d]) R, ... + R) of that domain's phase.
+// Tiles per launch: keeps the work-items of one launch below 2^32.
+constexpr int64_t kMaxTilesPerLaunch = 1 << 22;
+
 struct MultiArgs {
   TileArgs base;             // network; colour
   const float* field_in;     // packed fields (domain offsets are relative to these)
@@ -863,13 +866,17 @@ struct MultiArgs {
   const int32_t* tile_begin; // [n_domains + 1] for this colour and target set
   int n_domains;
   int64_t n_tiles;
+  int64_t tile0;             // row-split tile: first tile of this launch (one tile per workgroup)
 };
 
+// The row-split tile runs one tile per workgroup (its registers are full; a
+// loop-carried tile index made the persistent form spill); the other shapes
+// take tiles round-robin in a persistent grid.
 template <class S, int TMODE, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M) {
   constexpr int T = n_targets<TMODE>();
   const int ca = M.base.colour & 1, cb = M.base.colour >> 1;
-  for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
+  auto run_tile = [&](int64_t t) {
     int lo = 0, hi = M.n_domains - 1;       // last d with tile_begin[d] <= t
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -885,7 +892,14 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
     if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB>(A, (t - M.tile_begin[lo]) * S::R);
     else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
-    __syncthreads();   // the next tile reuses the LDS
+  };
+  if constexpr (S::RS) {
+    run_tile(M.tile0 + blockIdx.x);
+  } else {
+    for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
+      run_tile(t);
+      __syncthreads();   // the next tile reuses the LDS
+    }
   }
 }
 
@@ -913,8 +927,18 @@ static hipError_t with_shape(int width, int prec, int code, F&& f) {
 }
 
 template <class S, int TMODE, int OUT>
-static hipError_t launch_multi(const MultiArgs& m, int n_cu, hipStream_t s) {
+static hipError_t launch_multi(MultiArgs m, int n_cu, hipStream_t s) {
   if (m.n_tiles == 0) return hipSuccess;
+  if constexpr (S::RS) {
+    for (int64_t t0 = 0; t0 < m.n_tiles; t0 += kMaxTilesPerLaunch) {
+      m.tile0 = t0;
+      const int64_t n = std::min<int64_t>(m.n_tiles - t0, kMaxTilesPerLaunch);
+      hipLaunchKernelGGL((tile_kernel_multi<S, TMODE, OUT>), dim3((unsigned)n), dim3(S::NTH), 0, s, m);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
@@ -949,9 +973,6 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
     return targets == MF_CROSS ? launch_multi<S, 0, OUT_STORE>(m, n_cu, s) : launch_multi<S, 1, OUT_STORE>(m, n_cu, s);
   });
 }
-
-// Tiles per launch: keeps the work-items of one launch below 2^32.
-constexpr int64_t kMaxTilesPerLaunch = 1 << 22;
 
 template <class S, int TMODE, int SRC, int OUT>
 static hipError_t launch_tile(TileArgs a, hipStream_t s) {

@@ -63,7 +63,7 @@ def test_workspace_size(lib):
     assert fp32 >= 3 * 256 * 256 * 4 + 32769 * 4
     assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_BF16,
                                  ctypes.byref(n)) == MF_OK
-    assert n.value >= 2 * 3 * 256 * 256 * 2 + 32769 * 4    # two bf16 hidden-weight layouts + skeleton
+    assert n.value < fp32
     assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(0, 2)), 1, MF_FP32,
                                  ctypes.byref(n)) == MF_ESHAPE
     assert b"units" in lib.mf_last_error()

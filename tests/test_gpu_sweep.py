@@ -439,7 +439,7 @@ def test_additive_solve_c1(ctx):
 def test_rowsplit_tile_solve_and_assembly(ctx, width):
     """The row-split bf16 tile (each wave owns 32 rows, weights streamed
     through LDS) in a full solve: sweeps and the overlap-averaged assembly
-    against the oracle, and against the column-split bf16 tile."""
+    against the oracle, and bit for bit against the column-split bf16 tile."""
     print(f"case: row-split bf16 tile, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
     ux, uy = 5, 4
     params = mi.xavier_params(width, 2)
@@ -462,4 +462,6 @@ def test_rowsplit_tile_solve_and_assembly(ctx, width):
     print(f"row-split bf16 width {width}: u_out rel L2 vs oracle {e_or:.3e}, vs column-split bf16 {e_cs:.3e}",
           flush=True)
     assert e_or <= 2e-2
-    assert e_cs <= 2e-2
+    # same k order in every MFMA, same tanh and output sums: identical results
+    np.testing.assert_array_equal(outs["rowsplit"][0], outs["default"][0])
+    np.testing.assert_array_equal(outs["rowsplit"][1], outs["default"][1])
