@@ -50,9 +50,9 @@ INTERIOR_T = 961
 # value the counters were taken with; otherwise "traffic" is null. Summary:
 # profiles/*_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "d3d6b9dcb5786aa804012e78a68ca8062a176f6c518ec3c3273da088efbdf025",
+    "sources_sha256": "ad759b51f02d9576cc90567eeba15707c93340fe723f9edc815b1396aa697403",
     "bytes_per_launch": {"64": (5151.3 * 2.0 + 261.9) * 1024,
-                         "64|stream": (5093.8 * 2.0 + 261.9) * 1024,
+                         "64|stream": (5100.3 * 2.0 + 261.9) * 1024,
                          "32": (6015.4 * 2.0 + 268.6) * 1024},
 }
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
