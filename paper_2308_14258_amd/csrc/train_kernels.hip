@@ -529,16 +529,25 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restri
 // First-layer reductions per boundary condition b:
 //   c[b][j]  = sum_rows ab,  cx[b][j] = sum_rows (ab x + ab_x),
 //   cy[b][j] = sum_rows (ab y + ab_y).
+// One workgroup per condition: kL1Groups row groups of D threads each sum a
+// contiguous quarter of the condition's rows, then the group sums are added
+// in group order.
 // ---------------------------------------------------------------------------
+constexpr int kL1Groups = 4;
+
 template <int D, int S>
-__global__ __launch_bounds__(D) void layer1_reduce_kernel(const float* __restrict__ Ab1,
-                                                          const float* __restrict__ X, int x_per_bc,
-                                                          int64_t rows_per_bc, int64_t B,
-                                                          float* __restrict__ out) {
+__global__ __launch_bounds__(kL1Groups * D) void layer1_reduce_kernel(const float* __restrict__ Ab1,
+                                                                     const float* __restrict__ X, int x_per_bc,
+                                                                     int64_t rows_per_bc, int64_t B,
+                                                                     float* __restrict__ out) {
+  __shared__ float red[3][kL1Groups][D];
   const int64_t b = blockIdx.x;
-  const int j = threadIdx.x;
+  const int j = threadIdx.x % D, grp = threadIdx.x / D;
+  const int64_t per = (rows_per_bc + kL1Groups - 1) / kL1Groups;
+  const int64_t p0 = grp * per, p1 = std::min<int64_t>(rows_per_bc, p0 + per);
   float c = 0.0f, cx = 0.0f, cy = 0.0f;
-  for (int64_t p = 0; p < rows_per_bc; ++p) {
+#pragma unroll 4
+  for (int64_t p = p0; p < p1; ++p) {
     const int64_t r = b * rows_per_bc + p;
     const float* xp = x_per_bc ? X + 2 * r : X + 2 * p;
     const float a = Ab1[S * r * D + j];
@@ -551,9 +560,22 @@ __global__ __launch_bounds__(D) void layer1_reduce_kernel(const float* __restric
     cx += fmaf(a, xp[0], ax);
     cy += fmaf(a, xp[1], ay);
   }
-  out[b * D + j] = c;
-  out[(B + b) * D + j] = cx;
-  out[(2 * B + b) * D + j] = cy;
+  red[0][grp][j] = c;
+  red[1][grp][j] = cx;
+  red[2][grp][j] = cy;
+  __syncthreads();
+  if (grp == 0) {
+    c = cx = cy = 0.0f;
+#pragma unroll
+    for (int g = 0; g < kL1Groups; ++g) {
+      c += red[0][g][j];
+      cx += red[1][g][j];
+      cy += red[2][g][j];
+    }
+    out[b * D + j] = c;
+    out[(B + b) * D + j] = cx;
+    out[(2 * B + b) * D + j] = cy;
+  }
 }
 
 // grad W1g[j][k] = sum_b (c0[b][j] + c1[b][j]) G[b][k]; grad b1 = sum_b c[b][j]
@@ -816,10 +838,10 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
     cur ^= 1;
   }
   if (S == 4)
-    hipLaunchKernelGGL((layer1_reduce_kernel<D, 4>), dim3((unsigned)B), dim3(D), 0, s, tb.Ab[cur], X,
+    hipLaunchKernelGGL((layer1_reduce_kernel<D, 4>), dim3((unsigned)B), dim3(kL1Groups * D), 0, s, tb.Ab[cur], X,
                        x_per_bc, rows_per_bc, B, l1out);
   else
-    hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)B), dim3(D), 0, s, tb.Ab[cur], X,
+    hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)B), dim3(kL1Groups * D), 0, s, tb.Ab[cur], X,
                        x_per_bc, rows_per_bc, B, l1out);
   return hipGetLastError();
 }
@@ -898,7 +920,7 @@ static hipError_t value_backward_d(const float* whT, float* const Z[4], float* c
     if (e != hipSuccess) return e;
     cur ^= 1;
   }
-  hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)n_bc), dim3(D), 0, s, Ab[cur], X, 0, T, n_bc,
+  hipLaunchKernelGGL((layer1_reduce_kernel<D, 1>), dim3((unsigned)n_bc), dim3(kL1Groups * D), 0, s, Ab[cur], X, 0, T, n_bc,
                      csum);
   return hipGetLastError();
 }
