@@ -96,10 +96,12 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
 //   MODE 1 (backward, value stream only): Zb = Ain W -> Aout = (1 - z^2) Zb.
 // The four-stream backward is the fused taylor_bwd_split_kernel /
 // taylor_bwd_seq_kernel below.
-// A tile is 64 stream rows x D columns; the tile is staged in LDS.
+// A tile is 64 stream rows x D columns, staged in LDS; a persistent grid walks
+// the tiles.
 // ---------------------------------------------------------------------------
+// Register budget for four workgroups per CU (the LDS tile allows four).
 template <int D, int S, int MODE>
-__global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restrict__ Ain,
+__global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __restrict__ Ain,
                                                             const floatx4* __restrict__ wsw,
                                                             const float* __restrict__ bias,
                                                             const float* __restrict__ Sv_in,
@@ -108,17 +110,34 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
                                                             int64_t n_srows, int skip_xy) {
   static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_*_kernel");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
+  constexpr int PER = R * D / 4 / NTH;       // float4 of the input tile per thread
   __shared__ __align__(16) float Hs[R * LDH];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
-
-  for (int idx = tid; idx < R * D / 4; idx += NTH) {
+  const int64_t n_tiles = (n_srows + R - 1) / R;
+  // persistent: tiles blockIdx.x, + gridDim.x, ...; the next tile's input rows
+  // are loaded into registers while this tile's MFMAs run
+  floatx4 pf[PER];
+  auto fetch = [&](int64_t t) {
+    const int64_t r0 = t * R;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = tid + i * NTH;
+      const int r = idx / (D / 4), c4 = idx - r * (D / 4);
+      pf[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+      if (t < n_tiles && r0 + r < n_srows) pf[i] = reinterpret_cast<const floatx4*>(Ain + (r0 + r) * D)[c4];
+    }
+  };
+  fetch(blockIdx.x);
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+  const int64_t row0 = t * R;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = tid + i * NTH;
     const int r = idx / (D / 4), c4 = idx - r * (D / 4);
-    floatx4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (row0 + r < n_srows) v = reinterpret_cast<const floatx4*>(Ain + (row0 + r) * D)[c4];
-    *reinterpret_cast<floatx4*>(&Hs[r * LDH + 4 * c4]) = v;
+    *reinterpret_cast<floatx4*>(&Hs[r * LDH + 4 * c4]) = pf[i];
   }
   __syncthreads();
+  fetch(t + gridDim.x);
 
   floatx16 acc[RB];
   mfma_layer_f32<D, RB, LDH>(Hs, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
@@ -165,6 +184,8 @@ __global__ __launch_bounds__(2 * D) void taylor_gemm_kernel(const float* __restr
         }
       }
     }
+  }
+  __syncthreads();   // the next tile overwrites Hs
   }
 }
 
@@ -746,6 +767,20 @@ static int grid_for(int64_t n, int block, int cap = 8192) {
 
 // skip_last_xy: the last layer's d/dx and d/dy streams are not written (the
 // training loss reads only its value and Laplacian streams).
+// Persistent grid of the Taylor GEMM: four workgroups per CU (the LDS tile
+// allows four), at most one per tile.
+static unsigned gemm_grid(int64_t n_tiles) {
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || n < 1)
+      n = 256;
+    n_cu = n;
+  }
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)4 * n_cu));
+}
+
 template <int D>
 static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const float* X, int x_per_bc,
                                      int64_t rows_per_bc, int64_t n_rows, int S, float* const Z[4],
@@ -759,7 +794,7 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
                        X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned blocks = (unsigned)((n_srows + 63) / 64);
+  const unsigned blocks = gemm_grid((n_srows + 63) / 64);
   for (int l = 0; l < 3; ++l) {
     const floatx4* w = static_cast<const floatx4*>(net.wh) + (size_t)l * D * D / 4;
     if (S == 4)
@@ -911,7 +946,7 @@ template <int D>
 static hipError_t value_backward_d(const float* whT, float* const Z[4], float* const Ab[2], int64_t n_rows,
                                    const float* X, int64_t n_bc, int64_t T, float* csum, hipStream_t s) {
   int cur = 0;
-  const unsigned blocks = (unsigned)((n_rows + 63) / 64);
+  const unsigned blocks = gemm_grid((n_rows + 63) / 64);
   for (int l = 2; l >= 0; --l) {
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
     hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT, nullptr,
