@@ -99,7 +99,7 @@ TrainLayout train_layout(int width, int64_t B, int64_t nc) {
   for (int l = 0; l < 2; ++l) { T.Ab[l] = o; o = align256(o + SR * d * 4); }
   T.wpart = o; o = align256(o + chunks * d * d * 4);
   T.bpart = o; o = align256(o + chunks * d * 4);
-  for (int l = 0; l < 2; ++l) { T.opart[l] = o; o = align256(o + 2048 * (d + 2) * 4); }
+  for (int l = 0; l < 2; ++l) { T.opart[l] = o; o = align256(o + (size_t)kOutWaves * (d + 2) * 4); }
   for (int l = 0; l < 2; ++l) { T.l1[l] = o; o = align256(o + 3 * (size_t)B * d * 4); }
   T.grad = o; o = align256(o + P * 4);
   T.total = o;

@@ -107,6 +107,7 @@ hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const fl
 // Upper bound of the fused reverse kernel's persistent grid = number of
 // weight-gradient partials in the training workspace.
 constexpr int kBwdGroups = 512;
+constexpr int kOutWaves = 2048;    // waves of the output-layer kernel: one partial each
 
 struct TrainBuffers {
   float* C;          // [B][d] boundary projections (b1 included)
@@ -115,7 +116,7 @@ struct TrainBuffers {
   float* Ab[2];      // [SR][d] ping-pong pre-activation adjoints
   float* wpart;      // [kBwdGroups][d*d] weight-gradient partials
   float* bpart;      // [kBwdGroups][d]
-  float* opart[2];   // [2048][d+2] output-layer partials (data, collocation)
+  float* opart[2];   // [kOutWaves][d+2] output-layer partials (data, collocation)
   float* l1[2];      // [3][B][d] first-layer sums (data, collocation)
   float* grad;       // [P] gradient (used when the caller gives none)
 };

@@ -33,7 +33,6 @@
 
 namespace mf {
 
-constexpr int kOutWaves = 2048;    // waves of the output-layer kernel
 
 // ---------------------------------------------------------------------------
 // W^T of each hidden layer in MFMA operand order (for h-adjoint = ab W).
