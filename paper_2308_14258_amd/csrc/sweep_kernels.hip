@@ -268,8 +268,10 @@ __device__ __forceinline__ void load_wslice(typename Mma<PREC>::T (&wreg)[CPW / 
 // once it passed the previous barrier) sits in the same basic block as the
 // MFMAs of block rb and the scheduler overlaps them. LAST: the output
 // layer's dot products instead of activations, no writes to the tile and so
-// no barriers.
-template <int D, int R, int PREC, int CPW, bool LAST>
+// no barriers. NEXT: during the last row block each weight register is
+// reloaded with layer l + 1's operand right after its last MFMA, so the next
+// layer's weights arrive while this layer finishes instead of after it.
+template <int D, int R, int PREC, int CPW, bool LAST, bool NEXT = false>
 __device__ __forceinline__ void layer_wreg(typename HType<PREC>::T* Hs,
                                            typename Mma<PREC>::T (&wreg)[CPW / 32][D / Mma<PREC>::K],
                                            const u32x4* wh, int l, const float* nb, float* po, int lane,
@@ -280,6 +282,11 @@ __device__ __forceinline__ void layer_wreg(typename HType<PREC>::T* Hs,
   constexpr int LDH = PREC == 0 ? D + 4 : D + 8;
   const int arow = lane & 31, ahalf = lane >> 5;
   floatx16 acc[2][NCB];
+  // one opaque slice pointer per column block (per-load address arithmetic
+  // would be hoisted ahead of the MFMAs and spill)
+  const u32x4* nsw[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) nsw[cb] = NEXT ? wslice<D, PREC, CPW>(wh, l + 1, wave, lane, cb) : wh;
 #pragma unroll
   for (int rb = 0; rb <= RB; ++rb) {
     floatx16(&cur)[NCB] = acc[rb & 1];
@@ -296,6 +303,14 @@ __device__ __forceinline__ void layer_wreg(typename HType<PREC>::T* Hs,
           floatx16 c1[1] = {cur[cb]};
           M::template run<1>(wreg[cb][kg], h, c1);
           cur[cb] = c1[0];
+          if constexpr (NEXT) {
+            if (rb == RB - 1) {
+              // MFMAs and memory loads may not cross: the reload stays behind
+              // the MFMA that last reads the register
+              __builtin_amdgcn_sched_barrier(0x787);
+              wreg[cb][kg] = __builtin_bit_cast(OT, nsw[cb][kg * 64]);
+            }
+          }
         }
       }
     }
@@ -326,13 +341,16 @@ __device__ __forceinline__ void hidden_and_output(typename HType<PREC>::T* Hs,
                                                   int wave) {
   if constexpr (WREG) {
     // wreg holds layer 0 on entry (loaded by the caller ahead of the first
-    // layer, so those loads overlap its tanh work)
+    // layer, so those loads overlap its tanh work). fp32 reloads the next
+    // layer inside the last row block (-1% per phase); in the bf16 tiles,
+    // built for 128 VGPRs, the reload spills, so they load between layers.
+    constexpr bool RELOAD = PREC == 0;
 #pragma unroll 1
     for (int l = 0; l < 2; ++l) {
-      if (l > 0) load_wslice<D, PREC, CPW>(wreg, wh, l, wave, lane);
-      layer_wreg<D, R, PREC, CPW, false>(Hs, wreg, wh, l, nb, po, lane, wave);
+      if (!RELOAD && l > 0) load_wslice<D, PREC, CPW>(wreg, wh, l, wave, lane);
+      layer_wreg<D, R, PREC, CPW, false, RELOAD>(Hs, wreg, wh, l, nb, po, lane, wave);
     }
-    load_wslice<D, PREC, CPW>(wreg, wh, 2, wave, lane);
+    if (!RELOAD) load_wslice<D, PREC, CPW>(wreg, wh, 2, wave, lane);
     layer_wreg<D, R, PREC, CPW, true>(Hs, wreg, wh, 2, nb, po, lane, wave);
   } else {
     typedef Mma<PREC> M;
