@@ -13,7 +13,7 @@ import torch
 
 import mf_inputs as mi
 from oracle import fd, sweep as sw
-from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, Context
+from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, MF_TILE_STREAM, Context
 from paper_2308_14258_amd import mf_solve, mf_sweep, mf_sweep_operator
 
 pytestmark = pytest.mark.gpu
@@ -465,3 +465,35 @@ def test_rowsplit_tile_solve_and_assembly(ctx, width):
     # same k order in every MFMA, same tanh and output sums: identical results
     np.testing.assert_array_equal(outs["rowsplit"][0], outs["default"][0])
     np.testing.assert_array_equal(outs["rowsplit"][1], outs["default"][1])
+
+
+@pytest.mark.parametrize("width", [128, 256])
+def test_fp32_tile_forms_agree_bit_for_bit(ctx, width):
+    """The fp32 tiles with register-resident weights (64 rows; each weight
+    register is reloaded with the next layer's operand right after its last
+    MFMA) and with weights streamed from L2 (32 and 64 rows) run the same
+    arithmetic per row: same k order in every MFMA, same tanh and output sums.
+    Sweeps and assembly must agree bit for bit, and with the oracle to 1e-5."""
+    print(f"case: fp32 tile forms, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
+    ux, uy = 5, 4
+    params = mi.xavier_params(width, 4)
+    f = mi.gp_field(ux, uy, 1.0, seed=8)
+    outs = {}
+    for name, rows in (("registers", 64), ("stream64", 64 | MF_TILE_STREAM), ("stream32", 32)):
+        u = dev(f)
+        u_out = torch.empty_like(u)
+        ctx.tile_rows(MF_FP32, rows)
+        try:
+            mf_solve(ctx, dev(params), u, (ux, uy), 3, u_out=u_out)
+            torch.cuda.synchronize()
+        finally:
+            ctx.tile_rows(MF_FP32, 0)
+        outs[name] = (u.cpu().numpy(), u_out.cpu().numpy())
+    _, want, _, _ = sw.solve(torch.from_numpy(f.astype(np.float64)), ux, uy, oracle_solver(params, width), 3)
+    ny, nx = f.shape
+    err = rel_l2(outs["registers"][1], want.numpy(), interior_mask(ny, nx))
+    print(f"fp32 register-weight tile width {width}: u_out rel L2 vs oracle {err:.3e}", flush=True)
+    assert err <= 1e-5
+    for name in ("stream64", "stream32"):
+        np.testing.assert_array_equal(outs["registers"][0], outs[name][0], err_msg=name)
+        np.testing.assert_array_equal(outs["registers"][1], outs[name][1], err_msg=name)
