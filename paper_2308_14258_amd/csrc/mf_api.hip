@@ -424,8 +424,12 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
   if (prec == MF_BF16 && rows >= (int64_t)256 * ctx->n_cu) return 256 | MF_TILE_ROWSPLIT;
   // fp32: 64-row tiles with register weights from one 32-row tile per CU up
   // (a 16 x 16-unit phase, ~0.9 such tiles per CU: 54 us against 61 us with
-  // 32-row tiles); below that, 32-row tiles spread the few rows over more CUs
-  if (prec == MF_FP32 && rows >= (int64_t)32 * ctx->n_cu) return 64;
+  // 32-row tiles); below that, 32-row tiles spread the few rows over more CUs.
+  // From two 64-row tiles per CU up a single domain streams the weights
+  // instead (64 x 64 units: 804 against 818 us per sweep phase, 12.07 against
+  // 12.24 ms per assembly phase); the batched kernel's streamed form spills.
+  if (prec == MF_FP32 && rows >= (int64_t)32 * ctx->n_cu)
+    return nd == 1 && rows >= (int64_t)128 * ctx->n_cu ? (64 | MF_TILE_STREAM) : 64;
   return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
 }
 
