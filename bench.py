@@ -50,7 +50,7 @@ INTERIOR_T = 961
 # value the counters were taken with; otherwise "traffic" is null. Summary:
 # profiles/*_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "48a486b498da7c4d5bb30b81721c635a20827cbe97f4568da284ec6eab37fbfa",
+    "sources_sha256": "943990a6e26f9dddd7633f39e00bb5db39c67fc87b01d2af7ff5b4ab8bf6939a",
     "bytes_per_launch": {"64": (5148.3 * 2.0 + 261.9) * 1024,
                          "64|stream": (5100.3 * 2.0 + 261.9) * 1024,
                          "32": (6014.4 * 2.0 + 268.6) * 1024},

@@ -420,17 +420,18 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
       if (t.width == width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
           t.uy == dom->units_y)
         return t.rows;
-  // at least one 256-row tile per CU: the row-split bf16 tile
-  if (prec == MF_BF16 && rows >= (int64_t)256 * ctx->n_cu) return 256 | MF_TILE_ROWSPLIT;
+  const int64_t n_cu = ctx->n_cu;
+  // bf16: the row-split tile from one 256-row tile per CU up; below that the
+  // 64-row column-split tile spreads the rows over more CUs
+  if (prec == MF_BF16) return rows >= 256 * n_cu ? (256 | MF_TILE_ROWSPLIT) : 64;
   // fp32: 64-row tiles with register weights from one 32-row tile per CU up
   // (a 16 x 16-unit phase, ~0.9 such tiles per CU: 54 us against 61 us with
   // 32-row tiles); below that, 32-row tiles spread the few rows over more CUs.
   // From two 64-row tiles per CU up a single domain streams the weights
   // instead (64 x 64 units: 804 against 818 us per sweep phase, 12.07 against
   // 12.24 ms per assembly phase); the batched kernel's streamed form spills.
-  if (prec == MF_FP32 && rows >= (int64_t)32 * ctx->n_cu)
-    return nd == 1 && rows >= (int64_t)128 * ctx->n_cu ? (64 | MF_TILE_STREAM) : 64;
-  return pick_tile_rows(width, prec, targets, rows, ctx->n_cu);
+  if (rows < 32 * n_cu) return 32;
+  return nd == 1 && rows >= 128 * n_cu ? (64 | MF_TILE_STREAM) : 64;
 }
 
 static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int targets, int mode,

@@ -68,8 +68,6 @@ struct PhaseArgs {
 // One colour phase with SDNet. accumulate = assembly mode (u_out += pred / count).
 hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
                         int tile_rows, const PhaseArgs& a, hipStream_t s);
-// Rows per tile picked for this phase size (CU count aware).
-int pick_tile_rows(int width, int prec, int targets, int64_t rows, int n_cu);
 
 hipError_t launch_assembly_init(const float* u, float* u_out, int64_t pitch, int ux, int uy,
                                 hipStream_t s);

@@ -1009,16 +1009,6 @@ static int64_t colour_count(int ux, int uy, int colour) {
   return (int64_t)(ux - (colour & 1)) * (uy - (colour >> 1));
 }
 
-int pick_tile_rows(int width, int prec, int targets, int64_t rows, int n_cu) {
-  (void)width; (void)targets;
-  if (prec == MF_BF16) {
-    if (rows >= (int64_t)256 * 3 * n_cu) return 256;
-    if (rows >= (int64_t)128 * 2 * n_cu) return 128;
-    return 64;
-  }
-  return rows >= (int64_t)64 * 2 * n_cu ? 64 : 32;
-}
-
 hipError_t launch_phase(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
                         int tile_rows, const PhaseArgs& p, hipStream_t s) {
   TileArgs a{};
