@@ -131,9 +131,10 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
  * the LDS reads of the activations), and 256 | MF_TILE_ROWSPLIT selects the
  * row-split tile (each of 8 waves owns 32 rows and every unit; activations
  * stay in registers and the hidden weights stream through LDS). 0 restores
- * the automatic choice (a tuned value from mf_autotune, else a rule based on
- * the phase size and the CU count: the row-split tile for a single domain
- * with at least 256 rows per CU). */
+ * the automatic choice: a tuned value from mf_autotune, else a rule on the
+ * phase's rows per CU. MF_BF16: 256 | MF_TILE_ROWSPLIT from 256 rows per CU
+ * up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
+ * 64 | MF_TILE_STREAM for a single domain from 128 rows per CU up. */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
 /* Autotuner: for this network, domain, target set and precision, time
