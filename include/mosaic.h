@@ -185,6 +185,26 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
                    int32_t colour, int32_t targets, int32_t mode, int32_t prec,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* mf_sweep without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation). Same arguments and result as mf_sweep in
+ * MF_MULTIPLICATIVE mode (the additive mode needs a field-sized buffer and
+ * is not offered here); the results are bit-identical because the same
+ * kernels run. Instead of a caller's workspace it uses a static device
+ * array of 1 MiB, one per GPU, held until the process ends, into which each
+ * call writes the prepared network and the batch table before its kernels
+ * read them. That bounds the request: the network at width 256 (about
+ * 0.9 MiB in MF_FP32, 0.6 MiB in MF_BF16) plus 56 bytes per domain must
+ * fit, else MF_ENOMEM with nothing enqueued (about 2,000 domains at width
+ * 256 in MF_FP32). No hipMalloc, hipFree or other allocating call is made.
+ * All calls on one GPU share its array, so calls that overlap in time on
+ * one GPU (different streams or host threads without ordering between
+ * them) race and give undefined results; calls ordered on one stream are
+ * safe. Asynchronous. */
+mf_status mf_sweep_noalloc(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                           const mf_domain_desc* dom, int32_t n_domains, int32_t colour, int32_t targets,
+                           int32_t prec, void* stream);
+
 /* Alg. 2 on one device: up to max_sweeps sweeps of u (in place), stopping
  * early when eps > 0 and, at a sweep whose index is a multiple of
  * check_every, the relative L2 change of the skeleton values (all grid

@@ -61,6 +61,8 @@ _SIG = {
                                        _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "mf_sweep": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
                               _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P, _c.c_size_t, _P]),
+    "mf_sweep_noalloc": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc),
+                                      _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P]),
     "mf_solve": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
                               _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_float, _c.c_int32,
                               _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),

@@ -169,6 +169,18 @@ def mf_sweep(ctx: Context, params: torch.Tensor, u, units=None, colour: int = -1
                           _stream()), "mf_sweep")
 
 
+def mf_sweep_noalloc(ctx: Context, params: torch.Tensor, u, units=None, colour: int = -1,
+                     targets: int = MF_CROSS, prec: int = MF_FP32):
+    """mf_sweep (multiplicative) with the library's static device scratch in
+    place of a workspace: no device memory is allocated by this call."""
+    _need_cuda_f32(params, "params")
+    buf, dom, nd = _field_and_domains(u, units)
+    width = width_of(params)
+    check(load().mf_sweep_noalloc(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+                                  _dom_arg(dom), nd, colour, targets, prec, _stream()),
+          "mf_sweep_noalloc")
+
+
 def mf_autotune(ctx: Context, params: torch.Tensor, u: torch.Tensor, units,
                 targets: int = MF_CROSS, prec: int = MF_FP32, trials: int = 3) -> int:
     """Time every tile height on u (which advances) and keep the fastest."""
@@ -404,6 +416,7 @@ def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.
     return PhysicsLoss.apply(params, G, Xb, Xc, ctx)
 
 
-__all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep", "mf_solve",
+__all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep",
+           "mf_sweep_noalloc", "mf_solve",
            "mf_sweep_operator", "mf_colour_placements", "mf_target_coords", "mf_gather", "mf_scatter", "physics_loss", "sdnet_forward", "sdnet_loss_grad", "sdnet_train_step",
            "width_of", "sdnet_desc", "domain_desc", "_lib"]

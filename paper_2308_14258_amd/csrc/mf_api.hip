@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -215,6 +216,47 @@ static mf_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
   return MF_OK;
 }
 
+// Static device scratch of mf_sweep_noalloc: the prepared network and the
+// batch table of one call, for callers that cannot allocate a workspace.
+// Each device holds its own copy for the life of the process; host code
+// never uses the array's name as an address, only the per-device pointer
+// taken with hipGetSymbolAddress when a context is created on that device.
+constexpr size_t kScratchBytes = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's scratch array (the device must be current).
+static mf_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(MF_EDEVICE, "device %d: static scratch is kept for devices 0..%d", device, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MF_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return MF_OK;
+}
+
+// Layout of the no-alloc sweep inside the static scratch: the prepared
+// network, then the batch table. Multiplicative sweeps evaluate no delta
+// and keep no next field, so nothing else is needed.
+static SweepLayout noalloc_layout(int width, int prec, int n_domains) {
+  SweepLayout S;
+  S.net = net_layout(width, prec, 0);
+  S.table = S.net.end;
+  const size_t end =
+      align256(S.table + (size_t)n_domains * sizeof(DomEntry) + 2 * 4 * ((size_t)n_domains + 1) * 4);
+  S.skel = S.part = S.dres = S.anext = end;
+  S.total = end;
+  return S;
+}
+
 }  // namespace mf
 
 using namespace mf;
@@ -238,6 +280,7 @@ struct TuneEntry {
 struct mf_ctx {
   int device;
   int n_cu;
+  void* scratch = nullptr;            // this device's static scratch (mf_sweep_noalloc)
   int force_rows[2] = {0, 0};         // per precision; 0 = automatic
   std::vector<TuneEntry> tuned;
   hipStream_t gstream = nullptr;     // graph launches (default priority)
@@ -278,6 +321,13 @@ mf_status mf_ctx_create(int device, mf_ctx** out) {
   if (!c) return fail(MF_ENOMEM, "host allocation failed");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  {
+    const mf_status st = scratch_address(device, &c->scratch);
+    if (st != MF_OK) {
+      delete c;
+      return st;
+    }
+  }
   if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
@@ -612,6 +662,38 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   Plan P;
   MF_TRY(make_plan(ctx, desc, prec, targets, mode, u, dom, n_domains, ws, L, s, &P));
+  if (colour < 0) {
+    MF_TRY(run_sweep(ctx, P, s));
+  } else {
+    MF_TRY(run_colour(ctx, P, colour, PH_SWEEP, nullptr, s));
+  }
+  return ok();
+}
+
+mf_status mf_sweep_noalloc(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                           const mf_domain_desc* dom, int32_t n_domains, int32_t colour, int32_t targets,
+                           int32_t prec, void* stream) {
+  MF_TRY(check_desc(desc));
+  MF_TRY(check_prec(prec));
+  MF_TRY(check_domain(dom, n_domains));
+  MF_TRY(check_ptr(params, "params"));
+  MF_TRY(check_ptr(u, "u"));
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  if (colour < -1 || colour > 3) return fail(MF_EINVAL, "colour %d not in -1..3", colour);
+  const SweepLayout L = noalloc_layout(desc->width, prec, n_domains);
+  if (L.total > kScratchBytes)
+    return fail(MF_ENOMEM,
+                "%d domains at width %d need %zu bytes of static scratch; the limit is %zu bytes "
+                "(use mf_sweep with a workspace)",
+                n_domains, desc->width, L.total, kScratchBytes);
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  if (!ctx->scratch) return fail(MF_EDEVICE, "context has no static scratch address");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  void* ws = ctx->scratch;
+  MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
+  Plan P;
+  MF_TRY(make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, n_domains, ws, L, s, &P));
   if (colour < 0) {
     MF_TRY(run_sweep(ctx, P, s));
   } else {

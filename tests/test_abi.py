@@ -238,3 +238,36 @@ def test_gather_scatter_argument_errors(lib):
     assert lib.mf_scatter(None, None, MF_INTERIOR, f, ctypes.byref(dom), 1, None) == MF_EINVAL
     assert lib.mf_scatter(None, f, MF_CROSS, f, ctypes.byref(dom), -1, None) == MF_EINVAL
     assert lib.mf_scatter(None, None, MF_CROSS, f, ctypes.byref(one), 1, None) == MF_OK
+
+
+def _noalloc(lib, *, ctx=None, desc=None, params=FAKE, u=FAKE, dom=None, nd=1, colour=-1,
+             targets=MF_CROSS, prec=MF_FP32):
+    desc = desc or SdnetDesc(128, 4, 128, 0)
+    dom = dom if dom is not None else _dom()
+    dom_arg = dom if isinstance(dom, ctypes.Array) else ctypes.byref(dom)
+    return lib.mf_sweep_noalloc(ctx, ctypes.byref(desc), ctypes.c_void_p(params) if params else None,
+                                ctypes.c_void_p(u) if u else None, dom_arg, nd, colour, targets, prec,
+                                None)
+
+
+def test_sweep_noalloc_argument_errors(lib):
+    assert _noalloc(lib) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # all else valid
+    assert _noalloc(lib, params=0) == MF_EINVAL and b"params" in lib.mf_last_error()
+    assert _noalloc(lib, u=FAKE + 2) == MF_EINVAL and b"aligned" in lib.mf_last_error()
+    assert _noalloc(lib, desc=SdnetDesc(64, 4, 128, 0)) == MF_ESHAPE
+    assert _noalloc(lib, colour=4) == MF_EINVAL
+    assert _noalloc(lib, targets=3) == MF_EINVAL
+    assert _noalloc(lib, prec=2) == MF_EINVAL
+    # the static scratch holds the width-256 fp32 network (924,928 bytes) plus
+    # 56 bytes per domain of a batch: 2,207 one-unit domains fit, 2,300 do not
+    for n, want in ((2207, MF_EINVAL), (2300, MF_ENOMEM)):
+        many = (DomainDesc * n)()
+        for i in range(n):
+            many[i] = DomainDesc(1, 1, 32, 16, 33, 33 * 33 * i)
+        st = _noalloc(lib, desc=SdnetDesc(256, 4, 128, 0), dom=many, nd=n)
+        assert st == want, (n, st, lib.mf_last_error())
+    assert b"static scratch" in lib.mf_last_error()
+    many = (DomainDesc * 2300)()
+    for i in range(2300):
+        many[i] = DomainDesc(1, 1, 32, 16, 33, 33 * 33 * i)
+    assert _noalloc(lib, desc=SdnetDesc(256, 4, 128, 0), dom=many, nd=2300, prec=MF_BF16) == MF_EINVAL
