@@ -102,3 +102,40 @@ def test_cover_count_closed_form():
         for i in range(1, nx - 1):
             assert cnt[j, i] == c1(i, nx - 1) * c1(j, ny - 1)
     assert cnt[0, :].sum() == 0 and cnt[:, 0].sum() == 0
+
+
+def test_skeleton_counts():
+    """Skeleton = grid points on a line i or j = 0 mod 16 (ring included):
+    625, 32,769 and 512,001 points on the 2 x 2-, 16 x 16- and 64 x 64-unit
+    grids, i.e. L (n + 1) * 2 - L^2 with L = n / 16 + 1 lines per axis."""
+    from oracle import sweep as sw
+    for units, want in ((2, 625), (16, 32769), (64, 512001)):
+        n = 32 * units
+        m = sw.skeleton_mask(n + 1, n + 1)
+        assert int(m.sum()) == want, (units, int(m.sum()))
+        L = n // 16 + 1
+        assert want == 2 * L * (n + 1) - L * L
+
+
+def test_skeleton_is_union_of_placement_boundaries():
+    """Brute force on small domains: the skeleton mask (lines at multiples
+    of the stride, Sec. 4.2) is exactly the set of grid points that are a
+    boundary sample or a centre-cross target of some placement. From two
+    units per side up the boundaries alone cover it; on a one-unit side the
+    sole placement's centre line is a stride line that no boundary holds."""
+    from oracle import sweep as sw
+    for ux, uy in ((1, 1), (1, 3), (2, 2), (3, 2), (2, 5)):
+        ny, nx = geo.grid_shape(ux, uy)
+        bnd = np.zeros((ny, nx), dtype=bool)
+        cross = np.zeros((ny, nx), dtype=bool)
+        for (pa, pb) in geo.placements(ux, uy):
+            for (bi, bj) in geo.boundary_local():
+                bnd[geo.HALF * pb + bj, geo.HALF * pa + bi] = True
+            for (ti, tj) in geo.cross_targets():
+                cross[geo.HALF * pb + tj, geo.HALF * pa + ti] = True
+        mask = sw.skeleton_mask(ny, nx).numpy()
+        assert np.array_equal(bnd | cross, mask), (ux, uy)
+        if ux >= 2 and uy >= 2:
+            assert np.array_equal(bnd, mask), (ux, uy)
+        else:
+            assert not np.array_equal(bnd, mask), (ux, uy)

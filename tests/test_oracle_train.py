@@ -98,3 +98,68 @@ def test_training_decreases_loss():
         th, m, v, ld, lp = train.train_step(th, m, v, step, D, G, Xb, Xc, lr=3e-3)
         first = first if first is not None else ld + lp
     assert ld + lp < 0.7 * first
+
+
+def _zero_params(d):
+    return torch.zeros(mi.param_count(d), dtype=torch.float64)
+
+
+def test_losses_hand_computed_constant_network():
+    """Only b5 non-zero: every hidden activation is tanh(0) = 0, so u = b5
+    everywhere and the Laplacian vanishes. With boundary data constant per
+    condition (1 and 3) and b5 = 0.5 the data loss is, by hand,
+    ((0.5 - 1)^2 + (0.5 - 3)^2) / 2 = (0.25 + 6.25) / 2 = 3.25: the mean
+    over conditions and nodes (a sum over the 256 entries would give 832, a
+    half-squared error 1.625)."""
+    d = 32
+    th = _zero_params(d)
+    th[-1] = 0.5
+    G = torch.cat([torch.full((1, 128), 1.0), torch.full((1, 128), 3.0)]).double()
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes())
+    Xc = torch.from_numpy(mi.collocation_points(2, 5, seed=4).astype(np.float64))
+    l_data, l_pde = train.losses(th, d, G, Xb, Xc)
+    assert l_data.item() == pytest.approx(3.25, rel=1e-15)
+    assert l_pde.item() == 0.0
+
+
+def test_losses_hand_computed_laplacian():
+    """A single-unit chain: W1x row 0 = (a, b), W2..W4 entry (0, 0) = beta,
+    w5 entry 0 = gamma, everything else zero. Then u = gamma T4(s) with
+    s = a x + b y, T1 = tanh s, T_{l+1} = tanh(beta T_l), and
+    Laplacian u = (a^2 + b^2) gamma T4''(s). The derivatives follow from
+    tanh' = 1 - tanh^2 by the chain rule:
+        T1' = 1 - T1^2,  T1'' = -2 T1 (1 - T1^2),
+        T' = beta (1 - T^2) T_prev',
+        T'' = beta (1 - T^2) T_prev'' - 2 beta^2 T (1 - T^2) T_prev'^2.
+    All collocation points sit at one (x0, y0), so the mean of the squared
+    residual is that one value squared: any sum/mean or factor slip in the
+    PDE term changes it by a factor of 12 (the point count) or 2."""
+    d = 32
+    a, b, beta, gamma = 1.3, -0.7, 1.1, 0.9
+    th = _zero_params(d)
+    off_w1, off_b1 = 0, d * 130
+    th[off_w1 + 128] = a
+    th[off_w1 + 129] = b
+    lstride = d * d + d
+    off_w2 = off_b1 + d
+    for layer in range(3):
+        th[off_w2 + layer * lstride] = beta
+    off_w5 = off_w2 + 3 * lstride
+    th[off_w5] = gamma
+    x0, y0 = 0.37, 0.81
+    s = a * x0 + b * y0
+    T = np.tanh(s)
+    dT = 1.0 - T * T
+    ddT = -2.0 * T * (1.0 - T * T)
+    for _ in range(3):
+        Tn = np.tanh(beta * T)
+        dTn = beta * (1.0 - Tn * Tn) * dT
+        ddTn = beta * (1.0 - Tn * Tn) * ddT - 2.0 * beta * beta * Tn * (1.0 - Tn * Tn) * dT * dT
+        T, dT, ddT = Tn, dTn, ddTn
+    lap = (a * a + b * b) * gamma * ddT
+    G = torch.from_numpy(mi.gp_perimeter_batch(3, 0.5, seed=5).astype(np.float64))
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes())
+    Xc = torch.tensor([x0, y0], dtype=torch.float64).expand(3, 4, 2).contiguous()
+    _, l_pde = train.losses(th, d, G, Xb, Xc)
+    assert l_pde.item() == pytest.approx(lap * lap, rel=1e-12)
+    assert abs(lap) > 0.05                       # the case is not degenerate
