@@ -1,8 +1,10 @@
 """SDNet N(x, g; theta) in float64 (oracle).
 
-Sec. 3.2 describes the network as an MLP fed with a discretised boundary
-function g (4N samples) and a point x. The network used here has four tanh
-hidden layers and a scalar output: the first layer acts on [g, x, y]
+Sec. 3.1 describes SDNet as a stack of linear layers with smooth
+activations fed with a discretised boundary function g (4N samples) and a
+point x, through the input-split first layer of Sec. 3.2. The network here
+is the plain form of it (no boundary embedding): four tanh hidden layers and
+a scalar output, the first layer acting on [g, x, y]
 
     h1 = tanh(W1 [g; x; y] + b1),   h_{l+1} = tanh(W_{l+1} h_l + b_{l+1}),
     u  = w5 . h4 + b5.
@@ -13,7 +15,8 @@ coordinate part once per point. ``forward_concat`` is Eq. 6 (the replicated
 input matrix I = [G X]) and exists only so that tests can show the two agree.
 
 Derivatives with respect to x (needed for the PDE loss, Eq. 3) are taken by
-automatic differentiation, which is how the paper computes them (Sec. 3.4).
+automatic differentiation, which is how the paper computes them (Sec. 5.2,
+"Training Methodology").
 
 Parameter layout (one flat vector):
 W1 (d x 130, cols 0..127 boundary, 128 -> x, 129 -> y) | b1 | W2 | b2 | W3 |

@@ -5,14 +5,18 @@ collocation points, gradients summed, then one optimiser step (the allreduce
 of step 3 is the identity on one device).
 
 Loss:
-* data term: the network evaluated at the 128 boundary nodes of the unit
-  square must reproduce the boundary vector it was given,
-  L_data = mean_{b,k} (N(x_k, g_b) - g_{b,k})^2;
+* data term: a mean squared error against known values at data points,
+  L_data = mean_{b,k} (N(x_{b,k}, g_b) - y_{b,k})^2. The paper's data are
+  solutions of each boundary value problem (Sec. 5.2, "Training
+  Methodology"); without them the default is the boundary match: the data
+  points are the 128 boundary nodes of the unit square and y_b = g_b, the
+  boundary vector the network was given;
 * PDE term (Eq. 3): L_pde = mean_{b,j} (Laplacian N(x_{b,j}, g_b))^2 over the
   collocation points.
 
 Gradients come from automatic differentiation (the paper obtains the
-second derivatives and the parameter gradient the same way, Sec. 3.4).
+second derivatives and the parameter gradient the same way, Sec. 5.2,
+"Training Methodology").
 Adam is the textbook update of Kingma and Ba with bias correction.
 """
 from __future__ import annotations
@@ -22,24 +26,27 @@ import torch
 from . import sdnet
 
 
-def losses(theta: torch.Tensor, width: int, G: torch.Tensor, Xb: torch.Tensor,
-           Xc: torch.Tensor):
+def losses(theta: torch.Tensor, width: int, G: torch.Tensor, Xd: torch.Tensor,
+           Xc: torch.Tensor, Yd: torch.Tensor | None = None):
     """(L_data, L_pde) as differentiable scalars.
 
-    G: [B, 128]; Xb: [128, 2] boundary node coordinates; Xc: [B, nc, 2].
+    G: [B, 128]; Xd: data points, shared [nd, 2] or per condition
+    [B, nd, 2]; Yd: data targets [B, nd], or None for the boundary match
+    (then Xd are the 128 boundary nodes and the targets are G); Xc:
+    [B, nc, 2] collocation points.
     """
     layers = sdnet.unpack(theta, width)
-    u_b = sdnet.forward(layers, G, Xb)
-    l_data = torch.mean((u_b - G) ** 2)
+    u_d = sdnet.forward(layers, G, Xd)
+    l_data = torch.mean((u_d - (G if Yd is None else Yd)) ** 2)
     _, _, _, lap = sdnet.derivatives(layers, G, Xc, create_graph=True)
     l_pde = torch.mean(lap ** 2)
     return l_data, l_pde
 
 
-def gradient(theta: torch.Tensor, width: int, G, Xb, Xc):
+def gradient(theta: torch.Tensor, width: int, G, Xd, Xc, Yd=None):
     """Returns (L_data, L_pde, grad_data, grad_pde) in float64."""
     th = theta.detach().clone().requires_grad_(True)
-    l_data, l_pde = losses(th, width, G, Xb, Xc)
+    l_data, l_pde = losses(th, width, G, Xd, Xc, Yd)
     (g_data,) = torch.autograd.grad(l_data, th)
     (g_pde,) = torch.autograd.grad(l_pde, th)
     return l_data.item(), l_pde.item(), g_data, g_pde
@@ -55,9 +62,9 @@ def adam_update(theta, m, v, grad, step: int, lr=1e-3, beta1=0.9, beta2=0.999, e
     return theta, m, v
 
 
-def train_step(theta, m, v, step: int, width: int, G, Xb, Xc, **adam):
+def train_step(theta, m, v, step: int, width: int, G, Xd, Xc, Yd=None, **adam):
     """Alg. 1 then Adam: returns (theta, m, v, L_data, L_pde)."""
-    l_data, l_pde, g_data, g_pde = gradient(theta, width, G, Xb, Xc)
+    l_data, l_pde, g_data, g_pde = gradient(theta, width, G, Xd, Xc, Yd)
     grad = g_data + g_pde
     theta, m, v = adam_update(theta, m, v, grad, step, **adam)
     return theta, m, v, l_data, l_pde

@@ -1,4 +1,4 @@
-"""Pins for the oracle's SDNet (Sec. 3.2-3.3, Eqs. 5-8) and its derivatives."""
+"""Pins for the oracle's SDNet (Sec. 3.1-3.2, Eqs. 5-8) and its derivatives."""
 import numpy as np
 import torch
 

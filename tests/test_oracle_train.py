@@ -163,3 +163,31 @@ def test_losses_hand_computed_laplacian():
     _, l_pde = train.losses(th, d, G, Xb, Xc)
     assert l_pde.item() == pytest.approx(lap * lap, rel=1e-12)
     assert abs(lap) > 0.05                       # the case is not degenerate
+
+
+def test_losses_hand_computed_per_condition_data_targets():
+    """The data term against per-condition targets at per-condition points
+    (the supervised form with solution values): with only b5 = 2 non-zero,
+    u = 2 everywhere, so for targets y = [[1, 2, 4], [0, 2, 3]] the loss is,
+    by hand, ((1 + 0 + 4) + (4 + 0 + 1)) / 6 = 10 / 6."""
+    d = 32
+    th = _zero_params(d)
+    th[-1] = 2.0
+    G = torch.from_numpy(mi.gp_perimeter_batch(2, 0.5, seed=6).astype(np.float64))
+    Xd = torch.from_numpy(mi.collocation_points(2, 3, seed=7).astype(np.float64))
+    Yd = torch.tensor([[1.0, 2.0, 4.0], [0.0, 2.0, 3.0]], dtype=torch.float64)
+    Xc = torch.from_numpy(mi.collocation_points(2, 5, seed=8).astype(np.float64))
+    l_data, l_pde = train.losses(th, d, G, Xd, Xc, Yd)
+    assert l_data.item() == pytest.approx(10.0 / 6.0, rel=1e-15)
+    assert l_pde.item() == 0.0
+
+
+def test_boundary_match_is_the_data_term_with_targets_g():
+    """Yd = None is the data term with the boundary vector as targets."""
+    G = torch.from_numpy(mi.gp_perimeter_batch(3, 0.5, seed=9).astype(np.float64))
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes())
+    Xc = torch.from_numpy(mi.collocation_points(3, 4, seed=10).astype(np.float64))
+    th = torch.from_numpy(mi.random_params(D, 23).astype(np.float64))
+    a = train.losses(th, D, G, Xb, Xc)
+    b = train.losses(th, D, G, Xb.expand(3, 128, 2), Xc, G)
+    assert a[0].item() == b[0].item() and a[1].item() == b[1].item()
