@@ -7,7 +7,7 @@
  *
  * Problem (Sec. 2.1, Eqs. 1-2): the 2-D Laplace equation with Dirichlet data
  * on a rectangle of units_x x units_y unit squares. A pretrained subdomain
- * network (SDNet, Sec. 2.4 and 3.2) maps the boundary values of a unit
+ * network (SDNet, Sec. 2.4 and 3.1) maps the boundary values of a unit
  * square, sampled at 128 points, plus a point (x, y) of that square to the
  * solution there. The predictor (Sec. 4.1-4.2, Alg. 2) covers the domain
  * with overlapping unit squares placed every half unit, and sweeps: each
@@ -37,10 +37,14 @@
  *   vector, 128 on x and 129 on y. The first layer is evaluated in the
  *   input-split form of Eq. 8: W1g g + b1 once per placement (or boundary
  *   condition), plus W1x (x, y) per point.
- * Precision: MF_FP32 computes every GEMM with float32 MFMA; MF_BF16 runs the
- *   three hidden d x d GEMMs on bf16 MFMA with float32 accumulation. The
- *   field, the boundary projection, tanh, the output layer and the overlap
- *   averaging stay float32 in both.
+ * Precision: MF_FP32 computes every GEMM with float32 MFMA (the boundary
+ *   projection on the float32 VALU). MF_BF16 rounds the GEMM operands to
+ *   bf16 and accumulates in float32 on MFMA: the boundary projection
+ *   W1g g (g and W1g rounded to bf16) and the three hidden d x d GEMMs
+ *   (weights and the incoming activations rounded to bf16). In both, the
+ *   field, the gather and scatter, the coordinate term W1x (x, y) + b1 of
+ *   the first layer, every bias, tanh, the output layer w5 . h4 + b5 and
+ *   the overlap averaging are float32.
  *
  * Memory and streams: every pointer argument marked "device" is device
  * memory owned by the caller; "host" pointers are host memory. The library
@@ -163,10 +167,16 @@ mf_status mf_ctx_timing_read(mf_ctx* ctx, int64_t* launches, double* total_ms, i
  * an invalid descriptor. Pure host function. */
 int64_t mf_param_count(const mf_sdnet_desc* desc);
 
-/* Workspace bytes needed by mf_sweep / mf_solve / mf_sweep_operator for this
- * network, domain and precision. Pure host function. */
+/* Workspace bytes needed by mf_sweep / mf_solve / mf_autotune for this
+ * network, domain list (n_domains descriptors), precision, target set
+ * (MF_CROSS or MF_INTERIOR) and sweep mode (MF_MULTIPLICATIVE, or
+ * MF_ADDITIVE, which adds one buffer as large as the packed field for the
+ * next field). A workspace sized for one set of these arguments serves any
+ * call whose requirement is no larger. MF_EINVAL for unknown enum values or
+ * a NULL bytes, MF_ESHAPE for an invalid domain. Pure host function. */
 mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom,
-                            int32_t n_domains, int32_t prec, size_t* bytes);
+                            int32_t n_domains, int32_t prec, int32_t targets, int32_t mode,
+                            size_t* bytes);
 
 /* One colour phase (colour = 0..3) or one full sweep (colour = -1) of the
  * predictor (Sec. 4.1; the loop body of Alg. 2), updating the device field u
@@ -217,13 +227,23 @@ mf_status mf_sweep_noalloc(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
  * last_delta (host, nullable) the last delta (NaN if never evaluated).
  * Synchronises the stream when eps > 0 (one float pair read per check) and
  * when sweeps_done or last_delta is requested; otherwise asynchronous.
- * MF_ENONFINITE if a delta evaluates to NaN/inf with a nonzero reference. */
+ * MF_ENONFINITE if a delta evaluates to NaN/inf with a nonzero reference.
+ * Failure injection for tests of callers' recovery: when the environment
+ * variable MF_FAULT_INJECT holds "k:c" at mf_ctx_create (k >= 1, c in 0..3),
+ * a multiplicative solve on that context runs without graphs and returns
+ * MF_EDEVICE just before colour phase c of sweep k, leaving u as the earlier
+ * phases made it (no assembly). */
 mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
                    float* u, const mf_domain_desc* dom, int32_t n_domains,
                    int32_t targets, int32_t mode, int32_t prec,
                    int32_t max_sweeps, float eps, int32_t check_every, int32_t flags,
                    float* u_out, int32_t* sweeps_done, float* last_delta,
                    void* ws, size_t ws_bytes, void* stream);
+
+/* Parses a MF_FAULT_INJECT value ("k:c", see mf_solve) into sweep k and
+ * colour c (host, nullable); returns 1 when it enables injection, else 0
+ * (and k = c = 0). Pure host function. */
+int32_t mf_fault_inject_parse(const char* spec, int32_t* sweep, int32_t* colour);
 
 /* Check mode: the same sweep with the subdomain solver replaced by a linear
  * operator, pred = Hop g, Hop a device float32 [T x 128] row-major matrix
@@ -279,24 +299,38 @@ mf_status mf_scatter(mf_ctx* ctx, const float* pred, int32_t targets, float* u, 
 mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
                              int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes);
 
-/* Sensitivity of the assembled solution to the initial field, float32.
- * Forward: K multiplicative sweeps of u0 (device, read only; not modified)
- * then the overlap-averaged assembly into u_out (device, same layout as u0;
- * nullable) and J = sum over interior grid points of u_out^2 (device [1],
- * nullable; summed over the domains of a batch). Reverse: writes
- * u0_bar = dJ/du0 (device, same layout as u0, grid points only) through the
- * assembly and every colour phase in reverse order, recomputing field
- * states from checkpoints taken every ckpt_every sweeps. Its values on the
- * outer ring are dJ/dg, the sensitivity to the Dirichlet data. Each phase
- * is reversed by reading and zeroing the target adjoints, re-running the
- * network forward from the stored field, the hand-written value-stream
- * reverse pass, gb = W1g^T sum_t ab1 (Eq. 8), and a deterministic scatter-
- * add of gb onto the placement boundaries in four sub-colours. Batches
- * (n_domains > 1) are processed domain by domain. Asynchronous. */
+/* Adjoint of Alg. 2's output with respect to its input field, float32:
+ * u0_bar = (d u_out / d u0)^T uout_bar, where u_out is the overlap-averaged
+ * assembly after K multiplicative sweeps of u0 (the loop and final phase of
+ * Alg. 2) and uout_bar is a seed given per grid point.
+ *   u0       device, read only (not modified); layout as for mf_sweep.
+ *   uout_bar device seed, same layout as u0, nullable. NULL selects the
+ *            objective J = sum over interior grid points of u_out^2, i.e.
+ *            the seed 2 u_out on the interior and 0 on the ring. The ring of
+ *            u_out is the ring of u0, so a seed's ring values are added to
+ *            u0_bar's ring unchanged.
+ *   u_out    device, nullable: receives the forward assembly (same layout).
+ *   J        device [1], nullable: sum of squared interior values of u_out,
+ *            or <uout_bar, u_out> over every grid point when a seed is
+ *            given; summed over the domains of a batch.
+ *   u0_bar   device, same layout as u0: fully written at the grid points
+ *            (row padding untouched). Its values on the outer ring are the
+ *            sensitivity to the Dirichlet data g.
+ * The forward keeps field checkpoints every ckpt_every sweeps (1..1000);
+ * the reverse pass runs through the assembly and every colour phase in
+ * reverse order, recomputing a segment's field states from its checkpoint.
+ * Each phase is reversed by reading and zeroing the target adjoints,
+ * re-running the network forward from the stored field, the hand-written
+ * value-stream reverse pass, gb = W1g^T sum_t ab1 (the input-split first
+ * layer of Eq. 8), and a deterministic scatter-add of gb onto the placement
+ * boundaries in four sub-colours. The network is evaluated in float32
+ * throughout (this differentiates the MF_FP32 forward). Batches
+ * (n_domains > 1) are processed domain by domain. u0, u_out, u0_bar and
+ * uout_bar must be distinct buffers (MF_EINVAL). Asynchronous. */
 mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
                            const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
-                           int32_t ckpt_every, float* u_out, float* J, float* u0_bar, void* ws,
-                           size_t ws_bytes, void* stream);
+                           int32_t ckpt_every, const float* uout_bar, float* u_out, float* J,
+                           float* u0_bar, void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for sdnet_forward with n_bc boundary conditions and n_pts
  * points per condition; derivatives != 0 when dU or lapU will be requested
@@ -317,36 +351,49 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
                         int32_t x_per_bc, float* U, float* dU, float* lapU, int32_t prec,
                         void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes for sdnet_train_step with B conditions and nc
- * collocation points per condition. */
-mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nc, size_t* bytes);
+/* Workspace bytes for sdnet_train_step / sdnet_loss_grad with B conditions,
+ * nd data points and nc collocation points per condition. */
+mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nd, int64_t nc, size_t* bytes);
 
 /* One physics-informed training iteration (Alg. 1 on one device, then Adam):
- *   L_data = mean_{b,k} (N(Xb_k, G_b) - G_{b,k})^2   (boundary match)
- *   L_pde  = mean_{b,j} (Laplacian N(Xc_{b,j}, G_b))^2  (Eq. 3)
+ *   L_data = mean_{b,k} (N(Xd_{b,k}, G_b) - Yd_{b,k})^2   (data term)
+ *   L_pde  = mean_{b,j} (Laplacian N(Xc_{b,j}, G_b))^2     (Eq. 3)
+ * The data term is the paper's mean squared error against known solution
+ * values (Sec. 5.2, "Training Methodology"); with Yd = NULL it is the
+ * boundary match: the targets are G itself, so nd must be 128 and Xd holds
+ * the boundary node coordinates in boundary-vector order.
  * The gradient of L_data + L_pde is accumulated from the data pass and the
  * collocation pass into one buffer; then one Adam step with bias correction
  * (step counts from 1) updates params, m and v in place (all device,
- * mf_param_count floats). G: device [B x 128]; Xb: device [128 x 2] boundary
- * node coordinates; Xc: device [B x nc x 2]. loss_dev: device [2] receives
- * (L_data, L_pde) at the incoming parameters. When grad_out (device,
- * nullable) is given the gradient is written there and no update is made.
- * prec must be MF_FP32. */
+ * mf_param_count floats).
+ *   G        device [B x 128] boundary vectors.
+ *   Xd       device data points in the unit square: shared [nd x 2]
+ *            (xd_per_bc = 0) or per condition [B x nd x 2] (xd_per_bc = 1).
+ *   Yd       device [B x nd] data targets, nullable (see above).
+ *   Xc       device [B x nc x 2] collocation points.
+ *   loss_dev device [3]: (L_data, L_pde, L_data + L_pde) at the incoming
+ *            parameters.
+ *   grad_out device, nullable: when given, the gradient is written there and
+ *            no update is made (m, v and hp may then be NULL).
+ * Sizes: B, nd, nc >= 1 and B nd, B nc <= 2^29 (MF_ESHAPE otherwise).
+ * Float32 throughout. Asynchronous. */
 mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params, float* m,
-                           float* v, int64_t step, const mf_adam* hp, const float* G,
-                           int64_t B, const float* Xb, const float* Xc, int64_t nc,
-                           float* loss_dev, float* grad_out, void* ws, size_t ws_bytes,
-                           void* stream);
+                           float* v, int64_t step, const mf_adam* hp, const float* G, int64_t B,
+                           const float* Xd, int64_t nd, int32_t xd_per_bc, const float* Yd,
+                           const float* Xc, int64_t nc, float* loss_dev, float* grad_out,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* The losses of sdnet_train_step at params and the gradient of
  * L_data + L_pde, with no parameter update: the same forward (Taylor mode)
  * and hand-written reverse pass, for callers that run their own optimiser
  * (a torch.autograd.Function, for one). Arguments as for sdnet_train_step;
  * grad_out (device, mf_param_count floats) is required and fully written;
- * loss_dev (device [2]) receives (L_data, L_pde). Same workspace size. */
+ * loss_dev (device [3]) receives (L_data, L_pde, L_data + L_pde). Same
+ * workspace size. */
 mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* G,
-                          int64_t B, const float* Xb, const float* Xc, int64_t nc, float* loss_dev,
-                          float* grad_out, void* ws, size_t ws_bytes, void* stream);
+                          int64_t B, const float* Xd, int64_t nd, int32_t xd_per_bc, const float* Yd,
+                          const float* Xc, int64_t nc, float* loss_dev, float* grad_out, void* ws,
+                          size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

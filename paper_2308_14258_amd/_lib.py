@@ -58,7 +58,7 @@ _SIG = {
     "mf_ctx_timing_read": (_c.c_int32, [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double),
                                         _c.POINTER(_c.c_int64)]),
     "mf_workspace_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
-                                       _c.c_int32, _c.POINTER(_c.c_size_t)]),
+                                       _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "mf_sweep": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
                               _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P, _c.c_size_t, _P]),
     "mf_sweep_noalloc": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc),
@@ -67,6 +67,7 @@ _SIG = {
                               _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_float, _c.c_int32,
                               _c.c_int32, _P, _c.POINTER(_c.c_int32), _F, _P, _c.c_size_t, _P]),
     "mf_colour_placements": (_c.c_int64, [_c.POINTER(DomainDesc), _c.c_int32]),
+    "mf_fault_inject_parse": (_c.c_int32, [_c.c_char_p, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "mf_target_coords": (_c.c_int32, [_c.c_int32, _P]),
     "mf_gather": (_c.c_int32, [_P, _P, _c.POINTER(DomainDesc), _c.c_int32, _P, _P]),
     "mf_scatter": (_c.c_int32, [_P, _P, _c.c_int32, _P, _c.POINTER(DomainDesc), _c.c_int32, _P]),
@@ -76,18 +77,18 @@ _SIG = {
                                         _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "mf_solve_adjoint": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc),
                                       _c.c_int32, _c.c_int32,
-                                      _c.c_int32, _c.c_int32, _P, _P, _P, _P, _c.c_size_t, _P]),
+                                      _c.c_int32, _c.c_int32, _P, _P, _P, _P, _P, _c.c_size_t, _P]),
     "sdnet_forward_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,
                                            _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "sdnet_forward": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,
                                    _c.c_int32, _P, _P, _P, _c.c_int32, _P, _c.c_size_t, _P]),
-    "sdnet_train_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64,
+    "sdnet_train_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.c_int64, _c.c_int64, _c.c_int64,
                                          _c.POINTER(_c.c_size_t)]),
     "sdnet_train_step": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _P, _c.c_int64,
-                                      _c.POINTER(Adam), _P, _c.c_int64, _P, _P, _c.c_int64, _P, _P,
-                                      _P, _c.c_size_t, _P]),
-    "sdnet_loss_grad": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _P, _c.c_int64, _P,
-                                     _P, _P, _c.c_size_t, _P]),
+                                      _c.POINTER(Adam), _P, _c.c_int64, _P, _c.c_int64, _c.c_int32, _P,
+                                      _P, _c.c_int64, _P, _P, _P, _c.c_size_t, _P]),
+    "sdnet_loss_grad": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,
+                                     _c.c_int32, _P, _P, _c.c_int64, _P, _P, _P, _c.c_size_t, _P]),
 }
 
 _lib = None

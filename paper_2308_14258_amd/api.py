@@ -100,10 +100,11 @@ class Context:
             pass
 
 
-def _sweep_ws(ctx: Context, width: int, dom, prec: int, n_domains: int = 1) -> torch.Tensor:
+def _sweep_ws(ctx: Context, width: int, dom, prec: int, n_domains: int = 1, targets: int = MF_CROSS,
+              mode: int = MF_MULTIPLICATIVE) -> torch.Tensor:
     n = ctypes.c_size_t()
     check(load().mf_workspace_size(ctypes.byref(sdnet_desc(width)), _dom_arg(dom), n_domains, prec,
-                                   ctypes.byref(n)), "mf_workspace_size")
+                                   targets, mode, ctypes.byref(n)), "mf_workspace_size")
     return ctx.workspace(n.value)
 
 
@@ -163,7 +164,7 @@ def mf_sweep(ctx: Context, params: torch.Tensor, u, units=None, colour: int = -1
     _need_cuda_f32(params, "params")
     buf, dom, nd = _field_and_domains(u, units)
     width = width_of(params)
-    ws = _sweep_ws(ctx, width, dom, prec, nd)
+    ws = _sweep_ws(ctx, width, dom, prec, nd, targets, mode)
     check(load().mf_sweep(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
                           _dom_arg(dom), nd, colour, targets, mode, prec, _ptr(ws), ws.numel(),
                           _stream()), "mf_sweep")
@@ -214,7 +215,7 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
         elif u_out.numel() != buf.numel():
             raise ValueError("u_out must match the batch buffer")
     width = width_of(params)
-    ws = _sweep_ws(ctx, width, dom, prec, nd)
+    ws = _sweep_ws(ctx, width, dom, prec, nd, targets, mode)
     done = ctypes.c_int32(-1)
     last = ctypes.c_float(float("nan"))
     check(load().mf_solve(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
@@ -227,12 +228,18 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
 
 def mf_solve_adjoint(ctx: Context, params: torch.Tensor, u0, units, K: int, ckpt_every: int = 5,
                      targets: int = MF_CROSS, u_out=None, J: torch.Tensor | None = None,
-                     u0_bar=None):
-    """d J / d u0 for J = sum of squared interior values of the assembly
-    after K sweeps. u0 is a 2-D field (units (ux, uy)) or a Batch (then
-    u_out / u0_bar are flat buffers like u0.buf). Returns (u0_bar, J)."""
+                     u0_bar=None, uout_bar=None):
+    """u0_bar = (d u_out / d u0)^T uout_bar through K sweeps and the assembly.
+    Without uout_bar the seed is that of J = sum of squared interior values
+    of u_out; with it, J = <uout_bar, u_out> over every grid point. u0 is a
+    2-D field (units (ux, uy)) or a Batch (then u_out / u0_bar / uout_bar
+    are flat buffers like u0.buf). Returns (u0_bar, J)."""
     _need_cuda_f32(params, "params")
     buf, dom, nd = _field_and_domains(u0, units)
+    if uout_bar is not None:
+        _need_cuda_f32(uout_bar, "uout_bar")
+        if uout_bar.numel() != buf.numel() or (nd == 1 and uout_bar.stride(0) != buf.stride(0)):
+            raise ValueError("uout_bar must be laid out like u0")
     width = width_of(params)
     if u0_bar is None:
         u0_bar = torch.zeros_like(buf)
@@ -244,8 +251,9 @@ def mf_solve_adjoint(ctx: Context, params: torch.Tensor, u0, units, K: int, ckpt
                                  ckpt_every, ctypes.byref(n)), "mf_adjoint_ws_size")
     ws = ctx.workspace(n.value)
     check(lib.mf_solve_adjoint(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
-                               _dom_arg(dom), nd, targets, K, ckpt_every, _ptr(u_out), _ptr(J),
-                               _ptr(u0_bar), _ptr(ws), ws.numel(), _stream()), "mf_solve_adjoint")
+                               _dom_arg(dom), nd, targets, K, ckpt_every, _ptr(uout_bar), _ptr(u_out),
+                               _ptr(J), _ptr(u0_bar), _ptr(ws), ws.numel(), _stream()),
+          "mf_solve_adjoint")
     return u0_bar, J
 
 
@@ -337,83 +345,106 @@ def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.
     return (U, dU, lapU) if derivatives else U
 
 
+def _data_args(G: torch.Tensor, Xd: torch.Tensor, Yd):
+    """(Xd, nd, xd_per_bc, Yd) for the training entry points: Xd is shared
+    [nd, 2] or per condition [B, nd, 2]; Yd is [B, nd] or None (boundary
+    match, targets G)."""
+    _need_cuda_f32(Xd, "Xd")
+    per_bc = 1 if Xd.dim() == 3 else 0
+    nd = Xd.shape[1] if per_bc else Xd.shape[0]
+    if Xd.shape[-1] != 2 or (per_bc and Xd.shape[0] != G.shape[0]):
+        raise ValueError("Xd must be [nd, 2] or [B, nd, 2]")
+    if Yd is not None:
+        _need_cuda_f32(Yd, "Yd")
+        if tuple(Yd.shape) != (G.shape[0], nd):
+            raise ValueError(f"Yd must be [{G.shape[0]}, {nd}]")
+        Yd = Yd.contiguous()
+    return Xd.contiguous(), nd, per_bc, Yd
+
+
+def _train_ws(ctx: Context, width: int, B: int, nd: int, nc: int) -> torch.Tensor:
+    n = ctypes.c_size_t()
+    check(load().sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nd, nc, ctypes.byref(n)),
+          "sdnet_train_ws_size")
+    return ctx.workspace(n.value)
+
+
 def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
-                     step: int, G: torch.Tensor, Xb: torch.Tensor, Xc: torch.Tensor,
+                     step: int, G: torch.Tensor, Xd: torch.Tensor, Xc: torch.Tensor,
                      lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-                     loss: torch.Tensor | None = None, grad_out: torch.Tensor | None = None):
-    """One Alg. 1 iteration + Adam. Returns the device loss tensor [2]."""
-    for t, name in ((params, "params"), (m, "m"), (v, "v"), (G, "G"), (Xb, "Xb"), (Xc, "Xc")):
+                     loss: torch.Tensor | None = None, grad_out: torch.Tensor | None = None,
+                     Yd: torch.Tensor | None = None):
+    """One Alg. 1 iteration + Adam. Xd: data points ([nd, 2] shared or
+    [B, nd, 2]); Yd: their targets [B, nd], or None for the boundary match
+    (Xd = the 128 perimeter nodes, targets G). Returns the device loss
+    tensor [3] = (L_data, L_pde, L_data + L_pde)."""
+    for t, name in ((params, "params"), (m, "m"), (v, "v"), (G, "G"), (Xc, "Xc")):
         _need_cuda_f32(t, name)
     width = width_of(params)
     B, nc = Xc.shape[0], Xc.shape[1]
+    Xd, nd, per_bc, Yd = _data_args(G, Xd, Yd)
     if loss is None:
-        loss = torch.empty(2, device=G.device, dtype=torch.float32)
-    n = ctypes.c_size_t()
-    lib = load()
-    check(lib.sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nc, ctypes.byref(n)),
-          "sdnet_train_ws_size")
-    ws = ctx.workspace(n.value)
+        loss = torch.empty(3, device=G.device, dtype=torch.float32)
+    ws = _train_ws(ctx, width, B, nd, nc)
     hp = Adam(lr, beta1, beta2, eps)
-    check(lib.sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(m),
-                               _ptr(v), step, ctypes.byref(hp), _ptr(G.contiguous()), B,
-                               _ptr(Xb.contiguous()), _ptr(Xc.contiguous()), nc, _ptr(loss),
-                               _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
+    check(load().sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(m),
+                                  _ptr(v), step, ctypes.byref(hp), _ptr(G.contiguous()), B, _ptr(Xd), nd,
+                                  per_bc, _ptr(Yd), _ptr(Xc.contiguous()), nc, _ptr(loss),
+                                  _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
           "sdnet_train_step")
     return loss
 
 
-def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.Tensor,
+def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xd: torch.Tensor,
                     Xc: torch.Tensor, loss: torch.Tensor | None = None,
-                    grad_out: torch.Tensor | None = None):
-    """(L_data, L_pde) of Alg. 1 at `params` and the gradient of
-    L_data + L_pde from the library's hand-written reverse pass, with no
-    parameter update (C entry point sdnet_loss_grad). Returns (loss [2],
-    grad), both device tensors."""
-    for t, name in ((params, "params"), (G, "G"), (Xb, "Xb"), (Xc, "Xc")):
+                    grad_out: torch.Tensor | None = None, Yd: torch.Tensor | None = None):
+    """(L_data, L_pde, L_data + L_pde) of Alg. 1 at `params` and the
+    gradient of L_data + L_pde from the library's hand-written reverse pass,
+    with no parameter update (C entry point sdnet_loss_grad). Returns
+    (loss [3], grad), both device tensors."""
+    for t, name in ((params, "params"), (G, "G"), (Xc, "Xc")):
         _need_cuda_f32(t, name)
     width = width_of(params)
     B, nc = Xc.shape[0], Xc.shape[1]
+    Xd, nd, per_bc, Yd = _data_args(G, Xd, Yd)
     if loss is None:
-        loss = torch.empty(2, device=G.device, dtype=torch.float32)
+        loss = torch.empty(3, device=G.device, dtype=torch.float32)
     if grad_out is None:
         grad_out = torch.empty_like(params)
     _need_cuda_f32(grad_out, "grad_out")
-    n = ctypes.c_size_t()
-    lib = load()
-    check(lib.sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nc, ctypes.byref(n)),
-          "sdnet_train_ws_size")
-    ws = ctx.workspace(n.value)
-    check(lib.sdnet_loss_grad(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G.contiguous()), B,
-                              _ptr(Xb.contiguous()), _ptr(Xc.contiguous()), nc, _ptr(loss), _ptr(grad_out),
-                              _ptr(ws), ws.numel(), _stream()),
+    ws = _train_ws(ctx, width, B, nd, nc)
+    check(load().sdnet_loss_grad(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G.contiguous()), B,
+                                 _ptr(Xd), nd, per_bc, _ptr(Yd), _ptr(Xc.contiguous()), nc, _ptr(loss),
+                                 _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
           "sdnet_loss_grad")
     return loss, grad_out
 
 
 class PhysicsLoss(torch.autograd.Function):
-    """L = L_data + L_pde (Alg. 1: boundary match plus the squared Laplacian
+    """L = L_data + L_pde (Alg. 1: data term plus the squared Laplacian
     residual of Eq. 3) as a differentiable function of the flat parameter
     vector. The forward and the backward are one call of the library's
-    training kernels (Taylor-mode forward, hand-written reverse pass); the
-    backward returns the saved gradient scaled by the incoming one, so the
-    loss composes with torch optimisers and other loss terms."""
+    training kernels (Taylor-mode forward, hand-written reverse pass), which
+    also forms the sum; the backward returns the saved gradient scaled by
+    the incoming one, so the loss composes with torch optimisers and other
+    loss terms."""
 
     @staticmethod
-    def forward(fctx, params, G, Xb, Xc, mf_ctx):
-        loss, grad = sdnet_loss_grad(mf_ctx, params.detach(), G, Xb, Xc)
+    def forward(fctx, params, G, Xd, Xc, mf_ctx, Yd=None):
+        loss, grad = sdnet_loss_grad(mf_ctx, params.detach(), G, Xd, Xc, Yd=Yd)
         fctx.save_for_backward(grad)
-        return loss.sum()
+        return loss[2]
 
     @staticmethod
     def backward(fctx, g):
         (grad,) = fctx.saved_tensors
-        return g * grad, None, None, None, None
+        return g * grad, None, None, None, None, None
 
 
-def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xb: torch.Tensor,
-                 Xc: torch.Tensor) -> torch.Tensor:
+def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xd: torch.Tensor,
+                 Xc: torch.Tensor, Yd: torch.Tensor | None = None) -> torch.Tensor:
     """Scalar L_data + L_pde whose .backward() runs the hand-written reverse pass."""
-    return PhysicsLoss.apply(params, G, Xb, Xc, ctx)
+    return PhysicsLoss.apply(params, G, Xd, Xc, ctx, Yd)
 
 
 __all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep",

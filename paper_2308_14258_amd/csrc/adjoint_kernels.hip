@@ -1,6 +1,8 @@
-// Reverse mode of the predictor: d J / d u0 for J = sum over interior grid
-// points of u_out^2, where u_out is the overlap-averaged assembly (Alg. 2,
-// final phase) after K multiplicative sweeps started from u0.
+// Reverse mode of the predictor: u0_bar = (d u_out / d u0)^T u_out_bar, where
+// u_out is the overlap-averaged assembly (Alg. 2, final phase) after K
+// multiplicative sweeps started from u0 and u_out_bar is a seed given per grid
+// point. Without a seed the objective is J = sum over interior grid points of
+// u_out^2, i.e. the seed 2 u_out on the interior and 0 on the ring.
 //
 // A colour phase writes u'[x] = N(g_p(u), t) at the targets x of every
 // placement p of the colour and leaves every other point unchanged. Its
@@ -16,8 +18,9 @@
 //      one colour share boundary edges, so the scatter runs in four
 //      sub-colours (a mod 4, b mod 4) whose boundaries are disjoint: the sum
 //      is deterministic with no atomics.
-// The assembly's adjoint is the same with ubp[p, t] = 2 u_out[x] / count(x)
-// and no zeroing. Field states are recomputed from checkpoints taken every
+// The assembly's adjoint is the same with ubp[p, t] = seed[x] / count(x) and
+// no zeroing; the ring of u_out is the ring of u0, so the seed's ring values
+// pass straight into u0_bar. Field states are recomputed from checkpoints taken every
 // ckpt_every sweeps.
 #include <algorithm>
 
@@ -53,8 +56,9 @@ __global__ void gather_boundaries_kernel(const float* __restrict__ u, int64_t pi
 }
 
 // Target adjoints of placements q0 .. q0 + n_q - 1.
-//   MODE 0 (sweep phase): ubp = ub[x], then ub[x] = 0.
-//   MODE 1 (assembly):    ubp = 2 u_out[x] / count(x).
+//   MODE 0 (sweep phase):          ubp = ub[x], then ub[x] = 0.
+//   MODE 1 (assembly, sum of u^2): ubp = 2 u_out[x] / count(x).
+//   MODE 2 (assembly, seed):       ubp = seed[x] / count(x), seed in u_out's place.
 template <int TMODE, int MODE>
 __global__ void target_adjoint_kernel(float* __restrict__ ub, const float* __restrict__ u_out,
                                       int64_t pitch, int ux, int uy, int colour, int q0, int n_q,
@@ -72,8 +76,10 @@ __global__ void target_adjoint_kernel(float* __restrict__ ub, const float* __res
     if constexpr (MODE == 0) {
       ubp[idx] = ub[o];
       ub[o] = 0.0f;
-    } else {
+    } else if constexpr (MODE == 1) {
       ubp[idx] = 2.0f * u_out[o] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
+    } else {
+      ubp[idx] = u_out[o] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
     }
   }
 }
@@ -145,6 +151,25 @@ __global__ __launch_bounds__(256) void interior_sumsq_kernel(const float* __rest
   if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// Partial sums of seed * u over every grid point (ring included).
+__global__ __launch_bounds__(256) void grid_dot_kernel(const float* __restrict__ w, const float* __restrict__ u,
+                                                       int64_t pitch, int nx, int ny, float* __restrict__ part) {
+  __shared__ float sh[4];
+  const int64_t n = (int64_t)nx * ny;
+  float acc = 0.0f;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nx), i = (int)(idx % nx);
+    const int64_t o = (int64_t)j * pitch + i;
+    acc = fmaf(w[o], u[o], acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 __global__ void sum_parts_kernel(const float* __restrict__ part, int n, float* __restrict__ out,
                                  int accumulate) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -200,14 +225,24 @@ hipError_t launch_interior_sumsq(const float* u, int64_t pitch, int ux, int uy, 
   return hipGetLastError();
 }
 
-// Reverse one colour phase (assembly = false) or one assembly colour
-// (assembly = true) for placements processed in chunks that fit the
-// buffers in ab.
+hipError_t launch_grid_dot(const float* w, const float* u, int64_t pitch, int ux, int uy, float* part, float* out,
+                           int accumulate, hipStream_t s) {
+  const int nx = kS * ux + 1, ny = kS * uy + 1;
+  const int blocks = grid_of((int64_t)nx * ny, 256, 1024);
+  hipLaunchKernelGGL(grid_dot_kernel, dim3(blocks), dim3(256), 0, s, w, u, pitch, nx, ny, part);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, s, part, blocks, out, accumulate);
+  return hipGetLastError();
+}
+
+// Reverse one colour phase (kind ADJ_SWEEP) or one assembly colour (ADJ_SUMSQ:
+// J = sum of squared interior values, u_out is the assembly; ADJ_SEED: u_out
+// is the seed) for placements processed in chunks that fit the buffers in ab.
 template <int D>
 static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const AdjointBuffers& ab,
                                    const float* u_before, const float* u_out, float* ub, int64_t pitch,
-                                   int ux, int uy, int colour, int targets, bool assembly,
+                                   int ux, int uy, int colour, int targets, int kind,
                                    hipStream_t s) {
+  const bool assembly = kind != ADJ_SWEEP;
   const int tm = assembly ? MF_INTERIOR : targets;
   const int T = tm == MF_INTERIOR ? kInterior : kCross;
   const int n_place = (ux - (colour & 1)) * (uy - (colour >> 1));
@@ -218,8 +253,11 @@ static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const A
     const int nq = std::min(chunk, n_place - q0);
     const int64_t n_rows = (int64_t)nq * T;
     // 1. target adjoints
-    if (assembly)
+    if (kind == ADJ_SUMSQ)
       hipLaunchKernelGGL((target_adjoint_kernel<1, 1>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
+                         u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
+    else if (kind == ADJ_SEED)
+      hipLaunchKernelGGL((target_adjoint_kernel<1, 2>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
                          u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
     else if (tm == MF_CROSS)
       hipLaunchKernelGGL((target_adjoint_kernel<0, 0>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
@@ -254,11 +292,11 @@ static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const A
 
 hipError_t launch_adjoint_colour(const NetPtrs& net, int width, const float* whT, const AdjointBuffers& ab,
                                  const float* u_before, const float* u_out, float* ub, int64_t pitch, int ux,
-                                 int uy, int colour, int targets, bool assembly, hipStream_t s) {
+                                 int uy, int colour, int targets, int kind, hipStream_t s) {
   return width == 256 ? adjoint_colour_d<256>(net, whT, ab, u_before, u_out, ub, pitch, ux, uy, colour,
-                                             targets, assembly, s)
+                                             targets, kind, s)
                       : adjoint_colour_d<128>(net, whT, ab, u_before, u_out, ub, pitch, ux, uy, colour,
-                                             targets, assembly, s);
+                                             targets, kind, s);
 }
 
 }  // namespace mf

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -63,7 +64,7 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws) {
   return p;
 }
 
-SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains) {
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode) {
   SweepLayout S;
   S.net = net_layout(width, prec, 0);
   size_t o = S.net.end;
@@ -78,17 +79,17 @@ SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_d
   for (int d = 0; d < n_domains; ++d)
     span = std::max<int64_t>(span, dom[d].field_offset + (32LL * dom[d].units_y) * dom[d].pitch +
                                        32LL * dom[d].units_x + 1);
-  S.anext = o;
-  o = align256(o + (size_t)span * 4);
+  S.anext = o;   // the additive mode's next field; the multiplicative mode needs none
+  if (mode == MF_ADDITIVE) o = align256(o + (size_t)span * 4);
   S.total = o;
   return S;
 }
 
-TrainLayout train_layout(int width, int64_t B, int64_t nc) {
+TrainLayout train_layout(int width, int64_t B, int64_t nd, int64_t nc) {
   TrainLayout T;
   T.net = net_layout(width, MF_FP32, 0);
   const size_t d = (size_t)width;
-  const size_t SR = (size_t)std::max<int64_t>(4 * B * nc, B * 128);   // stream rows
+  const size_t SR = (size_t)std::max<int64_t>(4 * B * nc, B * nd);   // stream rows
   const size_t chunks = kBwdGroups;   // weight-gradient partials: one per reverse-kernel workgroup
   const size_t P = (size_t)(d * 130 + d + 3 * (d * d + d) + d + 1);
   size_t o = T.net.end;
@@ -292,11 +293,35 @@ struct mf_ctx {
   std::vector<int64_t> rows;        // point evaluations of each timed record
   std::vector<int64_t> nlaunch;     // colour-phase launches in each timed record
   size_t used = 0;                  // pairs recorded since the last read
+  int fault_sweep = 0, fault_colour = 0;   // MF_FAULT_INJECT: fail before this phase (0 = off)
 };
+
+// MF_FAULT_INJECT=k:c makes mf_solve fail with MF_EDEVICE just before colour
+// phase c (0..3) of sweep k (>= 1) of a multiplicative solve, leaving the
+// field as the earlier phases made it. Parsed once per context; anything
+// else leaves injection off.
+static void parse_fault_inject(const char* v, int* sweep, int* colour) {
+  *sweep = 0;
+  *colour = 0;
+  int k = 0, c = 0;
+  char tail = 0;
+  if (v && sscanf(v, "%d:%d%c", &k, &c, &tail) == 2 && k >= 1 && c >= 0 && c <= 3) {
+    *sweep = k;
+    *colour = c;
+  }
+}
 
 extern "C" {
 
 const char* mf_last_error(void) { return g_err; }
+
+int32_t mf_fault_inject_parse(const char* spec, int32_t* sweep, int32_t* colour) {
+  int k, c;
+  parse_fault_inject(spec, &k, &c);
+  if (sweep) *sweep = k;
+  if (colour) *colour = c;
+  return k > 0 ? 1 : 0;
+}
 
 int64_t mf_param_count(const mf_sdnet_desc* desc) {
   if (check_desc(desc) != MF_OK) return -1;
@@ -321,6 +346,7 @@ mf_status mf_ctx_create(int device, mf_ctx** out) {
   if (!c) return fail(MF_ENOMEM, "host allocation failed");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  parse_fault_inject(getenv("MF_FAULT_INJECT"), &c->fault_sweep, &c->fault_colour);
   {
     const mf_status st = scratch_address(device, &c->scratch);
     if (st != MF_OK) {
@@ -391,13 +417,15 @@ mf_status mf_ctx_timing_read(mf_ctx* ctx, int64_t* launches, double* total_ms, i
 }
 
 mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
-                            int32_t prec, size_t* bytes) {
+                            int32_t prec, int32_t targets, int32_t mode, size_t* bytes) {
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
   MF_TRY(check_prec(prec));
   MF_TRY(check_domain(dom, n_domains));
-  *bytes = sweep_layout(desc->width, prec, dom, n_domains).total;
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
+  *bytes = sweep_layout(desc->width, prec, dom, n_domains, mode).total;
   return ok();
 }
 
@@ -412,7 +440,7 @@ static mf_status sweep_common_checks(const mf_sdnet_desc* desc, const float* par
   MF_TRY(check_ptr(u, "u"));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
-  *L = sweep_layout(desc->width, prec, dom, n_domains);
+  *L = sweep_layout(desc->width, prec, dom, n_domains, mode);
   MF_TRY(check_ws(ws, ws_bytes, L->total));
   return MF_OK;
 }
@@ -841,13 +869,19 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   int done = 0;
   float last = NAN;
   bool converged = false;
-  if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0) {
+  const bool inject = ctx->fault_sweep > 0 && mode == MF_MULTIPLICATIVE;
+  if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0 && !inject) {
     MF_TRY(run_sweeps_graph(ctx, P, max_sweeps, s));
     done = max_sweeps;
   }
   for (int k = done + 1; k <= max_sweeps; ++k) {
     const bool check = eps > 0.0f && (k % check_every) == 0;
     if (check) MF_TRY(delta_snapshot(P, L, ws, s));
+    if (inject && k == ctx->fault_sweep) {
+      for (int c = 0; c < ctx->fault_colour; ++c) MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s));
+      return fail(MF_EDEVICE, "injected fault (MF_FAULT_INJECT) before colour %d of sweep %d", ctx->fault_colour,
+                  k);
+    }
     MF_TRY(run_sweep(ctx, P, s));
     done = k;
     if (check) {
@@ -1060,16 +1094,19 @@ static Plan single_plan(const mf_sdnet_desc* desc, int targets, float* field, co
 
 mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
                            const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
-                           int32_t ckpt_every, float* u_out, float* J, float* u0_bar, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           int32_t ckpt_every, const float* uout_bar, float* u_out, float* J, float* u0_bar,
+                           void* ws, size_t ws_bytes, void* stream) {
   MF_TRY(adjoint_checks(desc, dom, n_domains, targets, K, ckpt_every));
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(u0, "u0"));
   MF_TRY(check_ptr(u0_bar, "u0_bar"));
   if (u_out) MF_TRY(check_ptr(u_out, "u_out"));
   if (J) MF_TRY(check_ptr(J, "J"));
+  if (uout_bar) MF_TRY(check_ptr(uout_bar, "uout_bar"));
   if (u0_bar == u0 || (u_out && (u_out == u0 || u_out == u0_bar)))
     return fail(MF_EINVAL, "u0, u_out and u0_bar must be distinct buffers");
+  if (uout_bar && (uout_bar == u0_bar || uout_bar == u_out))
+    return fail(MF_EINVAL, "uout_bar must not alias u0_bar or u_out");
   const AdjLayout A = adjoint_layout(desc->width, dom, n_domains, K, ckpt_every);
   MF_TRY(check_ws(ws, ws_bytes, A.total));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
@@ -1114,12 +1151,20 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
     }
     MF_HIP(launch_assembly_init(F, uo, D.pitch, D.units_x, D.units_y, s));
     for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ASSEMBLY, uo, s, false));
-    if (J) MF_HIP(launch_interior_sumsq(uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
-    // reverse: assembly, then the sweeps segment by segment
-    MF_HIP(launch_fill2d(ub, D.pitch, D.units_x, D.units_y, 0.0f, s));
+    const float* seed = uout_bar ? uout_bar + D.field_offset : nullptr;
+    if (J && seed)
+      MF_HIP(launch_grid_dot(seed, uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
+    else if (J)
+      MF_HIP(launch_interior_sumsq(uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
+    // reverse: assembly (the ring of u_out is u0's, so a seed's ring passes
+    // straight to u0_bar), then the sweeps segment by segment
+    if (seed)
+      MF_HIP(launch_assembly_init(seed, ub, D.pitch, D.units_x, D.units_y, s));
+    else
+      MF_HIP(launch_fill2d(ub, D.pitch, D.units_x, D.units_y, 0.0f, s));
     for (int c = 3; c >= 0; --c)
-      MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, F, uo, ub, D.pitch, D.units_x, D.units_y, c,
-                                   targets, true, s));
+      MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, F, seed ? seed : uo, ub, D.pitch, D.units_x,
+                                   D.units_y, c, targets, seed ? ADJ_SEED : ADJ_SUMSQ, s));
     for (int i = A.n_ckpt - 1; i >= 0; --i) {
       const int n_s = std::min(ckpt_every, K - i * ckpt_every);
       MF_HIP(hipMemcpyAsync(F, ckpt + (size_t)i * A.fsize, ext * 4, hipMemcpyDeviceToDevice, s));
@@ -1131,7 +1176,7 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
       for (int k = n_s - 1; k >= 0; --k)
         for (int c = 3; c >= 0; --c)
           MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, states + (size_t)(4 * k + c) * A.fsize,
-                                       nullptr, ub, D.pitch, D.units_x, D.units_y, c, targets, false, s));
+                                       nullptr, ub, D.pitch, D.units_x, D.units_y, c, targets, ADJ_SWEEP, s));
     }
   }
   return ok();
@@ -1204,28 +1249,39 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
   return ok();
 }
 
-mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nc, size_t* bytes) {
+static mf_status train_sizes(int64_t B, int64_t nd, int64_t nc) {
+  if (B < 1 || nd < 1 || nc < 1) return fail(MF_ESHAPE, "B, nd and nc must be >= 1");
+  if (B * nc > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nc too large");
+  if (B * nd > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nd too large");
+  return MF_OK;
+}
+
+mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nd, int64_t nc, size_t* bytes) {
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
-  if (B < 1 || nc < 1) return fail(MF_ESHAPE, "B and nc must be >= 1");
-  if (B * nc > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nc too large");
-  *bytes = train_layout(desc->width, B, nc).total;
+  MF_TRY(train_sizes(B, nd, nc));
+  *bytes = train_layout(desc->width, B, nd, nc).total;
   return ok();
 }
 
 mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params, float* m, float* v,
-                           int64_t step, const mf_adam* hp, const float* G, int64_t B, const float* Xb,
-                           const float* Xc, int64_t nc, float* loss_dev, float* grad_out, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           int64_t step, const mf_adam* hp, const float* G, int64_t B, const float* Xd,
+                           int64_t nd, int32_t xd_per_bc, const float* Yd, const float* Xc, int64_t nc,
+                           float* loss_dev, float* grad_out, void* ws, size_t ws_bytes, void* stream) {
   MF_TRY(check_desc(desc));
-  if (B < 1 || nc < 1) return fail(MF_ESHAPE, "B and nc must be >= 1");
-  if (B * nc > (1LL << 31) / 4) return fail(MF_ESHAPE, "B * nc too large");
+  MF_TRY(train_sizes(B, nd, nc));
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(G, "G"));
-  MF_TRY(check_ptr(Xb, "Xb"));
+  MF_TRY(check_ptr(Xd, "Xd"));
   MF_TRY(check_ptr(Xc, "Xc"));
   MF_TRY(check_ptr(loss_dev, "loss_dev"));
+  if (xd_per_bc != 0 && xd_per_bc != 1) return fail(MF_EINVAL, "xd_per_bc %d is not 0 or 1", xd_per_bc);
+  if (Yd) {
+    MF_TRY(check_ptr(Yd, "Yd"));
+  } else if (nd != 128) {
+    return fail(MF_ESHAPE, "without Yd the targets are G, so nd must be 128 (got %lld)", (long long)nd);
+  }
   if (grad_out) {
     MF_TRY(check_ptr(grad_out, "grad_out"));
   } else {
@@ -1237,7 +1293,7 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
         !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) || !(hp->eps > 0.0))
       return fail(MF_EINVAL, "adam hyperparameters out of range");
   }
-  const TrainLayout L = train_layout(desc->width, B, nc);
+  const TrainLayout L = train_layout(desc->width, B, nd, nc);
   MF_TRY(check_ws(ws, ws_bytes, L.total));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1248,7 +1304,7 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
   MF_HIP(launch_prepare_wT(params, desc->width, whT, s));
   const TrainBuffers tb = train_buffers(L, ws);
   float* grad = grad_out ? grad_out : tb.grad;
-  MF_HIP(launch_train_grad(net, desc->width, whT, tb, G, B, Xb, Xc, nc, grad, loss_dev, s));
+  MF_HIP(launch_train_grad(net, desc->width, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss_dev, s));
   if (!grad_out)
     MF_HIP(launch_adam(params, m, v, grad, mf_param_count(desc), hp->lr, hp->beta1, hp->beta2, hp->eps,
                        step, s));
@@ -1256,12 +1312,13 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
 }
 
 mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* G,
-                          int64_t B, const float* Xb, const float* Xc, int64_t nc, float* loss_dev,
-                          float* grad_out, void* ws, size_t ws_bytes, void* stream) {
+                          int64_t B, const float* Xd, int64_t nd, int32_t xd_per_bc, const float* Yd,
+                          const float* Xc, int64_t nc, float* loss_dev, float* grad_out, void* ws,
+                          size_t ws_bytes, void* stream) {
   MF_TRY(check_ptr(grad_out, "grad_out"));
   // the gradient mode of the training step reads params and updates nothing
-  return sdnet_train_step(ctx, desc, const_cast<float*>(params), nullptr, nullptr, 1, nullptr, G, B, Xb, Xc,
-                          nc, loss_dev, grad_out, ws, ws_bytes, stream);
+  return sdnet_train_step(ctx, desc, const_cast<float*>(params), nullptr, nullptr, 1, nullptr, G, B, Xd, nd,
+                          xd_per_bc, Yd, Xc, nc, loss_dev, grad_out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -88,7 +88,7 @@ struct DomEntry {
   int64_t pitch;    // row pitch in floats
   int32_t ux, uy;   // units
 };
-SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains);
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode);
 hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
                               int tile_rows, const float* field_in, float* field_out,
                               const DomEntry* doms, const int32_t* tile_begin, int n_domains,
@@ -123,13 +123,14 @@ struct TrainLayout {
   size_t whT = 0, C = 0, Z[4] = {0, 0, 0, 0}, Sv[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
   size_t wpart = 0, bpart = 0, opart[2] = {0, 0}, l1[2] = {0, 0}, grad = 0, total = 0;
 };
-TrainLayout train_layout(int width, int64_t B, int64_t nc);
+TrainLayout train_layout(int width, int64_t B, int64_t nd, int64_t nc);
 TrainBuffers train_buffers(const TrainLayout& L, void* ws);
 
 hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStream_t s);
 hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
-                             const float* G, int64_t B, const float* Xb, const float* Xc, int64_t nc,
-                             float* grad, float* loss, hipStream_t s);
+                             const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
+                             const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
+                             hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
                        double b2, double eps, int64_t step, hipStream_t s);
 hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
@@ -164,8 +165,13 @@ hipError_t launch_fill2d(float* p, int64_t pitch, int ux, int uy, float v, hipSt
 hipError_t launch_target_coords(float* X_cross, float* X_interior, hipStream_t s);
 hipError_t launch_interior_sumsq(const float* u, int64_t pitch, int ux, int uy, float* part, float* out,
                                  int accumulate, hipStream_t s);
+hipError_t launch_grid_dot(const float* w, const float* u, int64_t pitch, int ux, int uy, float* part, float* out,
+                           int accumulate, hipStream_t s);
+// What an adjoint colour reverses: a sweep phase, or an assembly colour whose
+// output seed is 2 u_out on the interior (ADJ_SUMSQ) or a caller's seed (ADJ_SEED).
+enum { ADJ_SWEEP = 0, ADJ_SUMSQ = 1, ADJ_SEED = 2 };
 hipError_t launch_adjoint_colour(const NetPtrs& net, int width, const float* whT, const AdjointBuffers& ab,
                                  const float* u_before, const float* u_out, float* ub, int64_t pitch, int ux,
-                                 int uy, int colour, int targets, bool assembly, hipStream_t s);
+                                 int uy, int colour, int targets, int kind, hipStream_t s);
 
 }  // namespace mf

@@ -699,8 +699,10 @@ __global__ __launch_bounds__(256) void output_grad_kernel(const float* __restric
     }
     if (j <= D) grad[off_w5 + j] = t0 + t1;
     else {
-      loss[0] = t0 * inv_data;
-      loss[1] = t1 * inv_col;
+      const float ld = t0 * inv_data, lp = t1 * inv_col;
+      loss[0] = ld;
+      loss[1] = lp;
+      loss[2] = ld + lp;
     }
   }
 }
@@ -887,12 +889,15 @@ hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStre
 
 template <int D>
 static hipError_t train_step_d(const NetPtrs& net, const float* whT, const TrainBuffers& tb,
-                               const float* G, int64_t B, const float* Xb, const float* Xc,
-                               int64_t nc, float* grad, float* loss, hipStream_t s) {
+                               const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
+                               const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
+                               hipStream_t s) {
   hipError_t e = launch_projection(net, D, G, B, tb.C, s);
   if (e != hipSuccess) return e;
-  // Alg. 1 step 1: data points (the 128 boundary nodes), value stream only.
-  e = run_pass<D>(net, whT, tb, tb.C, Xb, 0, 128, B, 1, G, grad, tb.opart[0], tb.l1[0], false, s);
+  // Alg. 1 step 1: data points, value stream only; the targets are Yd, or
+  // the boundary vector itself (boundary match at the 128 perimeter nodes).
+  e = run_pass<D>(net, whT, tb, tb.C, Xd, xd_per_bc, nd, B, 1, Yd ? Yd : G, grad, tb.opart[0], tb.l1[0],
+                  false, s);
   if (e != hipSuccess) return e;
   // Alg. 1 step 2: collocation points, four streams; accumulate.
   e = run_pass<D>(net, whT, tb, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true, s);
@@ -910,15 +915,16 @@ static hipError_t train_step_d(const NetPtrs& net, const float* whT, const Train
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((output_grad_kernel<D>), dim3((D + 2 + 256 / kReduceGroups - 1) / (256 / kReduceGroups)),
                      dim3(256), 0, s, tb.opart[0], tb.opart[1],
-                     1.0f / (float)(B * 128), 1.0f / (float)(B * nc), grad, loss);
+                     1.0f / (float)(B * nd), 1.0f / (float)(B * nc), grad, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
-                             const float* G, int64_t B, const float* Xb, const float* Xc, int64_t nc,
-                             float* grad, float* loss, hipStream_t s) {
-  return width == 256 ? train_step_d<256>(net, whT, tb, G, B, Xb, Xc, nc, grad, loss, s)
-                      : train_step_d<128>(net, whT, tb, G, B, Xb, Xc, nc, grad, loss, s);
+                             const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
+                             const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
+                             hipStream_t s) {
+  return width == 256 ? train_step_d<256>(net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss, s)
+                      : train_step_d<128>(net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss, s);
 }
 
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,

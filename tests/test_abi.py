@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "mosaic.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return set(re.findall(r"^\s*(?:mf_status|void|int64_t|const char\*)\s+(\w+)\s*\(", txt, re.M))
+    return set(re.findall(r"^\s*(?:mf_status|void|int64_t|int32_t|const char\*)\s+(\w+)\s*\(", txt, re.M))
 
 
 @pytest.fixture(scope="module")
@@ -57,21 +57,30 @@ def _dom(ux=2, uy=2, pitch=None, cpu=32, stride=16):
 def test_workspace_size(lib):
     n = ctypes.c_size_t()
     d = SdnetDesc(256, 4, 128, 0)
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_FP32,
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_FP32, 0, 0,
                                  ctypes.byref(n)) == MF_OK
     fp32 = n.value
     assert fp32 >= 3 * 256 * 256 * 4 + 32769 * 4
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_BF16,
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_BF16, 0, 0,
                                  ctypes.byref(n)) == MF_OK
     assert n.value < fp32
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(0, 2)), 1, MF_FP32,
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(0, 2)), 1, MF_FP32, 0, 0,
                                  ctypes.byref(n)) == MF_ESHAPE
     assert b"units" in lib.mf_last_error()
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(2, 2, cpu=16)), 1, MF_FP32,
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(2, 2, cpu=16)), 1, MF_FP32, 0, 0,
                                  ctypes.byref(n)) == MF_ESHAPE
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, 7,
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, 7, 0, 0,
                                  ctypes.byref(n)) == MF_EINVAL
-    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, MF_FP32, None) == MF_EINVAL
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, MF_FP32, 0, 0, None) == MF_EINVAL
+    # target set and sweep mode: unknown values are rejected; the additive
+    # mode adds one field-sized buffer (the next field) to the workspace
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, MF_FP32, 2, 0,
+                                 ctypes.byref(n)) == MF_EINVAL
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom()), 1, MF_FP32, 0, 2,
+                                 ctypes.byref(n)) == MF_EINVAL
+    assert lib.mf_workspace_size(ctypes.byref(d), ctypes.byref(_dom(16, 16)), 1, MF_FP32, 1, 1,
+                                 ctypes.byref(n)) == MF_OK
+    assert n.value >= fp32 + 513 * 513 * 4
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-GPU path")
@@ -178,21 +187,27 @@ def test_train_and_loss_grad_argument_errors(lib):
     f = ctypes.c_void_p(FAKE)
     big = 1 << 40
 
-    def train(m=f, v=f, step=1, grad=None, B=4, hp=True):
+    def train(m=f, v=f, step=1, grad=None, B=4, hp=True, nd=128, per_bc=0, Yd=None):
         adam = _lib.Adam(1e-3, 0.9, 0.999, 1e-8)
         return lib.sdnet_train_step(None, ctypes.byref(d), f, m, v, step,
-                                    ctypes.byref(adam) if hp else None, f, B, f, f, 8, f, grad, f,
-                                    big, None)
+                                    ctypes.byref(adam) if hp else None, f, B, f, nd, per_bc, Yd, f, 8, f,
+                                    grad, f, big, None)
 
     assert train() == MF_EINVAL and b"ctx" in lib.mf_last_error()      # all else valid
     assert train(m=None) == MF_EINVAL and b"m is NULL" in lib.mf_last_error()
     assert train(step=0) == MF_EINVAL
     assert train(hp=False) == MF_EINVAL
     assert train(B=0) == MF_ESHAPE
+    assert train(nd=0, Yd=f) == MF_ESHAPE
     assert train(m=None, v=None, hp=False, grad=f) == MF_EINVAL and b"ctx" in lib.mf_last_error()
+    # without targets the data term is the boundary match: nd must be 128
+    assert train(nd=64) == MF_ESHAPE and b"nd must be 128" in lib.mf_last_error()
+    assert train(nd=64, per_bc=1, Yd=f) == MF_EINVAL and b"ctx" in lib.mf_last_error()
+    assert train(per_bc=2) == MF_EINVAL and b"xd_per_bc" in lib.mf_last_error()
 
     def loss_grad(grad=f, ws_bytes=big):
-        return lib.sdnet_loss_grad(None, ctypes.byref(d), f, f, 4, f, f, 8, f, grad, f, ws_bytes, None)
+        return lib.sdnet_loss_grad(None, ctypes.byref(d), f, f, 4, f, 128, 0, None, f, 8, f, grad, f, ws_bytes,
+                                   None)
 
     assert loss_grad() == MF_EINVAL and b"ctx" in lib.mf_last_error()
     assert loss_grad(grad=None) == MF_EINVAL and b"grad_out is NULL" in lib.mf_last_error()
@@ -271,3 +286,12 @@ def test_sweep_noalloc_argument_errors(lib):
     for i in range(2300):
         many[i] = DomainDesc(1, 1, 32, 16, 33, 33 * 33 * i)
     assert _noalloc(lib, desc=SdnetDesc(256, 4, 128, 0), dom=many, nd=2300, prec=MF_BF16) == MF_EINVAL
+
+
+def test_fault_inject_spec_parsing(lib):
+    k, c = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    assert lib.mf_fault_inject_parse(b"3:2", ctypes.byref(k), ctypes.byref(c)) == 1
+    assert (k.value, c.value) == (3, 2)
+    for bad in (b"", b"0:1", b"3:4", b"3", b"3:1x", b"a:b", None):
+        assert lib.mf_fault_inject_parse(bad, ctypes.byref(k), ctypes.byref(c)) == 0, bad
+        assert (k.value, c.value) == (0, 0)

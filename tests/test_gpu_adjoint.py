@@ -88,3 +88,53 @@ def test_adjoint_batch_equals_single(ctx):
         assert torch.equal(batch.field(i, ub), ubi), i
         total += Ji.item()
     assert abs(J.item() - total) <= 1e-6 * abs(total)
+
+
+@pytest.mark.parametrize("units,K,ce", [((2, 2), 3, 2), ((3, 1), 4, 3)])
+def test_seeded_adjoint_matches_oracle(ctx, units, K, ce):
+    """u0_bar = (d u_out / d u0)^T seed for a random seed over every grid
+    point (ring included) against the oracle's autograd, and
+    J = <seed, u_out>."""
+    print(f"case: seeded adjoint units={units} K={K} ckpt={ce}", flush=True)
+    ux, uy = units
+    width = 128
+    params = mi.random_params(width, seed=45)
+    f = mi.gp_field(ux, uy, 0.6, seed=ux * 7 + uy)
+    seed = np.random.default_rng(ux + 10 * uy).standard_normal(f.shape).astype(np.float32)
+    u0 = torch.from_numpy(f).cuda()
+    ub, J = mf_solve_adjoint(ctx, torch.from_numpy(params).cuda(), u0, units, K, ce,
+                             uout_bar=torch.from_numpy(seed).cuda())
+    torch.cuda.synchronize()
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), width)
+    Jo, go = adjoint.solve_adjoint(torch.from_numpy(f.astype(np.float64)), ux, uy, solver, K,
+                                   uout_bar=torch.from_numpy(seed.astype(np.float64)))
+    err = _rel(ub.cpu().numpy().astype(np.float64), go.numpy())
+    print(f"seeded adjoint rel L2 {err:.3e}, J {J.item():.6e} vs {Jo:.6e}", flush=True)
+    assert err <= 1e-4
+    assert abs(J.item() - Jo) <= 1e-5 * max(abs(Jo), 1e-3 * np.abs(seed).sum())
+
+
+def test_adjoint_batch_domain_k20_against_stored_oracle(ctx):
+    """The smallest domain of the 48-domain batch (9 x 5 units, width 256)
+    at the batch's stated 20 sweeps with a checkpoint every 5: the default
+    objective and a random seed against stored float64 oracle gradients."""
+    import os
+    print("case: adjoint 9x5 units K=20 ckpt=5", flush=True)
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_adjoint.npz"))
+    w = mi.WORKLOADS["C5"]
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    d = int(g["domain"])
+    ux, uy = (int(v) for v in g["units"])
+    assert (ux, uy) == tuple(int(v) for v in sizes[d])
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    u0 = torch.from_numpy(fields[d]).cuda()
+    ub, J = mf_solve_adjoint(ctx, params, u0, (ux, uy), w["sweeps"], w["ckpt"])
+    ubs, Js = mf_solve_adjoint(ctx, params, u0, (ux, uy), w["sweeps"], w["ckpt"],
+                               uout_bar=torch.from_numpy(g["seed"]).cuda())
+    torch.cuda.synchronize()
+    e = _rel(ub.cpu().numpy().astype(np.float64), g["u0_bar"])
+    es = _rel(ubs.cpu().numpy().astype(np.float64), g["u0_bar_seed"])
+    print(f"adjoint K=20 rel L2: sum of squares {e:.3e} (J {J.item():.6e} vs {float(g['J']):.6e}); "
+          f"seeded {es:.3e} (J {Js.item():.6e} vs {float(g['J_seed']):.6e})", flush=True)
+    assert e <= 1e-4 and es <= 1e-4
+    assert abs(J.item() - float(g["J"])) <= 1e-5 * abs(float(g["J"]))

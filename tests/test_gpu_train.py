@@ -80,6 +80,34 @@ def test_gradient_matches_oracle(ctx, width):
     assert abs(loss[0] - ld) <= 1e-5 * ld and abs(loss[1] - lp) <= 1e-5 * lp
 
 
+@pytest.mark.parametrize("width,per_bc", [(128, True), (256, False)])
+def test_gradient_with_data_targets_matches_oracle(ctx, width, per_bc):
+    """The supervised data term (targets at data points, Sec. 5.2), with the
+    data points per condition or shared and a count that is not the 128 of
+    the boundary match: losses and gradient against the oracle."""
+    print(f"case: train gradient with data targets width={width} per_bc={per_bc} B=6 nd=37 nc=16",
+          flush=True)
+    B, nd, nc = 6, 37, 16
+    params = mi.random_params(width, seed=31)
+    G, _, Xc = _batch(B, nc, seed=7)
+    rng = np.random.default_rng(8)
+    Xd = mi.collocation_points(B, nd, 9) if per_bc else mi.collocation_points(1, nd, 9)[0]
+    Yd = rng.standard_normal((B, nd)).astype(np.float32)
+    p = _d(params)
+    grad = torch.empty_like(p)
+    loss, _ = sdnet_loss_grad(ctx, p, _d(G), _d(Xd), _d(Xc), grad_out=grad, Yd=_d(Yd))
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    loss = loss.cpu().numpy().astype(np.float64)
+    ld, lp, gd, gp = train.gradient(_t64(params), width, _t64(G), _t64(Xd), _t64(Xc), _t64(Yd))
+    want = (gd + gp).numpy()
+    err = np.linalg.norm(g - want) / np.linalg.norm(want)
+    print(f"gradient rel L2 {err:.3e}; loss {loss} vs {(ld, lp)}", flush=True)
+    assert err <= 1e-4
+    assert abs(loss[0] - ld) <= 1e-5 * ld and abs(loss[1] - lp) <= 1e-5 * lp
+    assert abs(loss[2] - (ld + lp)) <= 1e-5 * (ld + lp)
+
+
 def test_gradient_matches_finite_differences(ctx):
     """4 conditions x 8 collocation points: directional derivatives of the
     float64 oracle loss by central differences."""
@@ -149,7 +177,7 @@ def test_c3_full_batch_gradient_and_curve(ctx):
     for step in range(1, w["steps"] + 1):
         loss = sdnet_train_step(ctx, p, m, v, step, Gd, Xbd, Xcd)
         losses.append(loss.clone())
-    curve = torch.stack(losses).cpu().numpy().astype(np.float64)
+    curve = torch.stack(losses).cpu().numpy().astype(np.float64)[:, :2]
     rel = np.abs(curve - gold["curve"]) / np.abs(gold["curve"])
     print(f"C3 loss curve: max rel diff {rel.max():.3e}; final {curve[-1]} vs {gold['curve'][-1]}",
           flush=True)
@@ -194,7 +222,8 @@ def test_autograd_function_gives_the_library_gradient(ctx):
     loss, grad = sdnet_loss_grad(ctx, _d(params), Gd, Xbd, Xcd)
     torch.cuda.synchronize()
     assert torch.equal(p.grad, 3.0 * grad)
-    assert abs(L.item() - loss.sum().item()) <= 1e-6 * abs(loss.sum().item())
+    assert L.item() == loss[2].item()           # the library forms L_data + L_pde
+    assert abs(L.item() - loss[:2].sum().item()) <= 1e-6 * abs(loss[:2].sum().item())
     ld, lp, gd, gp = train.gradient(_t64(params), width, _t64(G), _t64(Xb), _t64(Xc))
     want = (gd + gp).numpy()
     got = grad.cpu().numpy().astype(np.float64)
