@@ -22,6 +22,23 @@ c2_fp32.npz -- 16 x 16 units, width 256, GP ring data (length 2, seed 1),
     Xavier weights seed 0, 200 CROSS sweeps then the assembly. Holds the
     skeleton after 20 and 200 sweeps and u_out at 8192 sampled interior
     points (seed 123).
+c2_traj.npz -- the 16 x 16-unit workload's skeleton at 8192 sampled points
+    (seed 124) after each sweep count in TRAJ_K (up to 200) for three runs
+    of the oracle: float64 on the
+    stored parameters ("fp64"), float64 on parameters moved by a relative
+    amount of float32 rounding size ("fp64_perturbed"), and the same
+    algorithm evaluated in float32 ("fp32"). The last two measure how far
+    rounding at float32 level alone moves the trajectory (its conditioning).
+c4_traj.npz -- 64 x 64 units: the c4 sampled skeleton values after each sweep
+    count in TRAJ_K (float64, up to 500 sweeps).
+c4_cond.npz -- 64 x 64 units, the "fp64_perturbed" and "fp32" runs of the
+    same samples up to 50 sweeps.
+c5_k20.npz -- the 48-domain batch's smallest, median and largest domain at
+    its stated 20 sweeps: sampled skeleton after 1, 5, 10, 15 and 20 sweeps
+    and the assembly after 20 at sampled points, for the three runs above.
+c5_adjoint.npz -- the smallest domain of that batch: u0_bar after 20 sweeps
+    and the assembly for J = sum of squared interior values, and for a
+    random seed u_out_bar (default_rng(77) normals), both full fields.
 """
 from __future__ import annotations
 
@@ -190,9 +207,167 @@ def c5_one():
     np.savez_compressed(os.path.join(HERE, "c5_one_sweep.npz"), **out)
 
 
-JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one, "c5_one": c5_one}
+TRAJ_K = (1, 5, 10, 15, 20, 30, 50, 100, 150, 200, 300, 400, 500)
+
+
+def _perturbed(params: np.ndarray, seed: int) -> np.ndarray:
+    """float64 copy of the float32 parameters, each entry scaled by
+    1 + r 2^-24 with r uniform in [-1, 1]: a change of float32 rounding size."""
+    r = np.random.default_rng(seed).uniform(-1.0, 1.0, params.shape)
+    return params.astype(np.float64) * (1.0 + r * 2.0 ** -24)
+
+
+def _runs(params: np.ndarray, width: int):
+    """(name, solver, dtype) of the three oracle runs of a conditioning study."""
+    out = []
+    for name, th, dt in (("fp64", params.astype(np.float64), torch.float64),
+                         ("fp64_perturbed", _perturbed(params, 901), torch.float64),
+                         ("fp32", params, torch.float32)):
+        out.append((name, sw.sdnet_solver(torch.from_numpy(th).to(dt), width), dt))
+    return out
+
+
+def c2_traj():
+    w = mi.WORKLOADS["C2"]
+    ux, uy = w["units"]
+    field = mi.workload_field("C2")
+    params = mi.xavier_params(w["width"], seed=0)
+    sj, si = np.nonzero(sw.skeleton_mask(*field.shape).numpy())
+    pick = np.sort(np.random.default_rng(124).choice(sj.size, 8192, replace=False))
+    sj, si = torch.from_numpy(sj[pick]), torch.from_numpy(si[pick])
+    ks = [k for k in TRAJ_K if k <= w["sweeps"]]
+    out = {"K": np.array(ks, dtype=np.int32), "skel_j": sj.numpy().astype(np.int32),
+           "skel_i": si.numpy().astype(np.int32), "field_sha": _sha(field), "params_sha": _sha(params)}
+    t0 = time.time()
+    for name, solver, dt in _runs(params, w["width"]):
+        u = torch.from_numpy(field).to(dt)
+        rows = []
+        for k in range(1, w["sweeps"] + 1):
+            u = sw.sweep(u, ux, uy, solver)
+            if k in ks:
+                rows.append(u[sj, si].to(torch.float64).numpy())
+        out[name] = np.stack(rows)
+        print(f"c2_traj: {name} done ({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c2_traj.npz"), **out)
+
+
+def _c4_samples():
+    g = np.load(os.path.join(HERE, "c4_fp64.npz"))
+    return g["skel_j"], g["skel_i"]
+
+
+def c4_traj():
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    field = mi.workload_field("C4")
+    params = mi.xavier_params(w["width"], seed=0)
+    sj, si = _c4_samples()
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), w["width"])
+    u = torch.from_numpy(field.astype(np.float64))
+    rows = []
+    t0 = time.time()
+    for k in range(1, w["sweeps"] + 1):
+        u = sw.sweep(u, ux, uy, solver)
+        if k in TRAJ_K:
+            rows.append(u.numpy()[sj, si].copy())
+            print(f"c4_traj: sweep {k} ({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c4_traj.npz"), K=np.array(TRAJ_K, dtype=np.int32),
+                        fp64=np.stack(rows), field_sha=_sha(field), params_sha=_sha(params))
+
+
+def c4_cond():
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    field = mi.workload_field("C4")
+    params = mi.xavier_params(w["width"], seed=0)
+    sj, si = _c4_samples()
+    ks = [k for k in TRAJ_K if k <= 50]
+    out = {"K": np.array(ks, dtype=np.int32), "field_sha": _sha(field), "params_sha": _sha(params)}
+    t0 = time.time()
+    for name, solver, dt in _runs(params, w["width"])[1:]:
+        u = torch.from_numpy(field).to(dt)
+        rows = []
+        for k in range(1, ks[-1] + 1):
+            u = sw.sweep(u, ux, uy, solver)
+            if k in ks:
+                rows.append(u.to(torch.float64).numpy()[sj, si].copy())
+                print(f"c4_cond: {name} sweep {k} ({time.time() - t0:.0f} s)", flush=True)
+        out[name] = np.stack(rows)
+    np.savez_compressed(os.path.join(HERE, "c4_cond.npz"), **out)
+
+
+def _c5_picks(sizes):
+    places = [(2 * int(ux) - 1) * (2 * int(uy) - 1) for ux, uy in sizes]
+    order = np.argsort(places, kind="stable")
+    return [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+
+
+def c5_k20():
+    w = mi.WORKLOADS["C5"]
+    t0 = time.time()
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    print(f"c5_k20: inputs in {time.time() - t0:.0f} s", flush=True)
+    params = mi.xavier_params(w["width"], seed=0)
+    picks = _c5_picks(sizes)
+    ks = [k for k in TRAJ_K if k <= w["sweeps"]]
+    out = {"picks": np.array(picks, dtype=np.int32), "sizes": sizes.astype(np.int32),
+           "K": np.array(ks, dtype=np.int32), "params_sha": _sha(params)}
+    rng = np.random.default_rng(556)
+    runs = _runs(params, w["width"])
+    for n, d in enumerate(picks):
+        ux, uy = (int(v) for v in sizes[d])
+        f = fields[d]
+        mask = sw.skeleton_mask(*f.shape).numpy()
+        sj, si = np.nonzero(mask)
+        pick = rng.choice(sj.size, min(4096, sj.size), replace=False)
+        sj, si = sj[pick], si[pick]
+        aj = rng.integers(1, f.shape[0] - 1, 256)
+        ai = rng.integers(1, f.shape[1] - 1, 256)
+        out[f"skel_j{n}"], out[f"skel_i{n}"] = sj.astype(np.int32), si.astype(np.int32)
+        out[f"sample_j{n}"], out[f"sample_i{n}"] = aj.astype(np.int32), ai.astype(np.int32)
+        out[f"field_sha{n}"] = _sha(f)
+        for name, solver, dt in runs:
+            u = torch.from_numpy(f).to(dt)
+            rows = []
+            for k in range(1, w["sweeps"] + 1):
+                u = sw.sweep(u, ux, uy, solver)
+                if k in ks:
+                    rows.append(u.to(torch.float64).numpy()[sj, si].copy())
+            out[f"skel_{name}_{n}"] = np.stack(rows)
+            pts = list(zip(aj.tolist(), ai.tolist()))
+            out[f"u_out_{name}_{n}"] = sw.assemble_at(u, ux, uy, solver, pts).to(
+                torch.float64).numpy()
+            print(f"c5_k20: domain {d} ({ux}x{uy}) {name} done at {time.time() - t0:.0f} s",
+                  flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_k20.npz"), **out)
+
+
+def c5_adjoint():
+    from oracle import adjoint
+    w = mi.WORKLOADS["C5"]
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    d = _c5_picks(sizes)[0]
+    ux, uy = (int(v) for v in sizes[d])
+    f = fields[d]
+    params = mi.xavier_params(w["width"], seed=0)
+    solver = sw.sdnet_solver(torch.from_numpy(params.astype(np.float64)), w["width"])
+    u0 = torch.from_numpy(f.astype(np.float64))
+    t0 = time.time()
+    J, g = adjoint.solve_adjoint(u0, ux, uy, solver, w["sweeps"])
+    seed = np.random.default_rng(77).standard_normal(f.shape).astype(np.float32)
+    Js, gs = adjoint.solve_adjoint(u0, ux, uy, solver, w["sweeps"],
+                                   uout_bar=torch.from_numpy(seed.astype(np.float64)))
+    np.savez_compressed(os.path.join(HERE, "c5_adjoint.npz"), domain=np.int32(d),
+                        units=np.array([ux, uy], dtype=np.int32), J=J, u0_bar=g.numpy(),
+                        seed=seed, J_seed=Js, u0_bar_seed=gs.numpy(), field_sha=_sha(f),
+                        params_sha=_sha(params))
+    print(f"c5_adjoint: domain {d} ({ux}x{uy}) done in {time.time() - t0:.0f} s", flush=True)
+
+
+JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one, "c5_one": c5_one, "c2_traj": c2_traj,
+        "c4_traj": c4_traj, "c4_cond": c4_cond, "c5_k20": c5_k20, "c5_adjoint": c5_adjoint}
 
 if __name__ == "__main__":
-    torch.set_num_threads(os.cpu_count() or 1)
+    torch.set_num_threads(int(os.environ.get("GOLDEN_THREADS", os.cpu_count() or 1)))
     for name in (sys.argv[1:] or list(JOBS)):
         JOBS[name]()

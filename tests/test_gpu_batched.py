@@ -121,3 +121,67 @@ def test_full_batch_one_sweep_sampled_domains(ctx, prec, tol):
         e_o = np.linalg.norm(o_got - o_want) / np.linalg.norm(o_want)
         print(f"domain {int(d)} {tuple(int(v) for v in sizes[d])}: rel L2 skeleton {e_s:.3e} u_out {e_o:.3e}", flush=True)
         assert e_s <= tol and e_o <= tol, (int(d), e_s, e_o)
+
+
+# Float32 results after many sweeps are held to the spread that float32
+# rounding alone causes along the same trajectory: the oracle's algorithm
+# evaluated in float32 on the CPU (the "fp32" run stored with the float64
+# values) differs from float64 by e32(K); the GPU float32 error must stay
+# within max(1e-5, COND_FACTOR * e32(K)). BF16 is held to 2e-2 where the
+# trajectory is well conditioned (e32 <= 1e-6) and its error is reported
+# elsewhere.
+COND_FACTOR = 10.0
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16])
+def test_full_batch_k20_sampled_domains(ctx, prec):
+    """The 48-domain batch at its stated 20 sweeps, in the benchmark's
+    launch configuration: sampled skeleton of the smallest, median and
+    largest domain after 1, 5, 10, 15 and 20 sweeps and the assembly after
+    20, against the float64 oracle, with the trajectory maximum reported."""
+    import os
+    print(f"case: 48-domain batch K=20 prec={prec}", flush=True)
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_k20.npz"))
+    w = mi.WORKLOADS["C5"]
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    np.testing.assert_array_equal(sizes, g["sizes"])
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    batch = Batch(fields)
+    out = torch.empty_like(batch.buf)
+    ks = [int(k) for k in g["K"]]
+    assert ks[-1] == w["sweeps"]
+    done = 0
+    worst = {}
+    for i, k in enumerate(ks):
+        mf_solve(ctx, params, batch, None, k - done, prec=prec, u_out=out if k == ks[-1] else None)
+        done = k
+        torch.cuda.synchronize()
+        for n, d in enumerate(g["picks"]):
+            u = batch.field(int(d)).cpu().numpy().astype(np.float64)
+            got = u[g[f"skel_j{n}"], g[f"skel_i{n}"]]
+            want = g[f"skel_fp64_{n}"][i]
+            e = _rel(got, want)
+            e32 = _rel(g[f"skel_fp32_{n}"][i], want)
+            worst[n] = max(worst.get(n, 0.0), e)
+            print(f"K={k} domain {int(d)} {tuple(int(v) for v in sizes[d])}: rel L2 skeleton {e:.3e} "
+                  f"(float32 oracle spread {e32:.3e})", flush=True)
+            if prec == MF_FP32:
+                assert e <= max(1e-5, COND_FACTOR * e32), (k, int(d), e, e32)
+            elif e32 <= 1e-6:
+                assert e <= 2e-2, (k, int(d), e, e32)
+    for n, d in enumerate(g["picks"]):
+        uo = batch.field(int(d), out).cpu().numpy().astype(np.float64)
+        got = uo[g[f"sample_j{n}"], g[f"sample_i{n}"]]
+        want = g[f"u_out_fp64_{n}"]
+        e = _rel(got, want)
+        e32 = _rel(g[f"u_out_fp32_{n}"], want)
+        print(f"K=20 domain {int(d)}: rel L2 u_out {e:.3e} (float32 oracle spread {e32:.3e}); "
+              f"trajectory max skeleton {worst[n]:.3e}", flush=True)
+        if prec == MF_FP32:
+            assert e <= max(1e-5, COND_FACTOR * e32), (int(d), e, e32)
+        elif e32 <= 1e-6:
+            assert e <= 2e-2, (int(d), e, e32)
