@@ -1,11 +1,13 @@
 """Throughput of the Mosaic Flow predictor on one MI355X.
 
 One step = one full pass of the hot path over one synthetic domain: the
-predictor loop of Alg. 2 (200 four-colour sweeps, CROSS targets) followed by
-the overlap-averaged assembly, on a 16 x 16 unit domain (513 x 513 grid,
-961 placements) with a width-256 SDNet (Xavier weights, seed 0) and GP
-boundary data (length scale 2, seed 1). The value is SDNet point
-evaluations per second over the whole step (sweeps + assembly), float32.
+predictor loop of Alg. 2 (500 four-colour sweeps, CROSS targets) followed by
+the overlap-averaged assembly, on a 64 x 64-unit domain (2049 x 2049 grid,
+16,129 placements) with a width-256 SDNet (Xavier weights, seed 0) and
+e^x sin y ring data scaled to [0, 1]. The headline value is SDNet point
+evaluations per second over the whole step (sweeps + assembly) in float32;
+the same steps with BF16 hidden GEMMs are reported beside it ("bf16"), each
+with its error against the float64 oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -15,12 +17,13 @@ duration, timed with HIP events on the launch stream during the timed
 region. The "cpu_baseline" object times the float64 oracle on the host
 cores on a bounded sample of the same workload.
 
-Beside the headline the line carries: the assembly timed on its own; the
-2 x 2-unit workload in microseconds per sweep; one GPU's share of the
-64 x 64-unit domain split eight ways; the standalone gather and scatter in
-GB/s on a field larger than the last-level cache; the GEMM rates torch.mm
-reaches (achievable peaks); FP32 against BF16 on the 64 x 64-unit domain;
-the training step; optionally the 48-domain batch and its adjoint (--c5).
+Beside the headline the line carries: errors along the trajectory against
+stored oracle values; the 16 x 16-unit workload; the 48-domain batch (BF16
+sweeps, parity at its 20 sweeps) and its adjoint; the training step; the
+assembly timed on its own; the 2 x 2-unit workload in microseconds per
+sweep; one GPU's share of the 64 x 64-unit domain split eight ways; the
+standalone gather and scatter in GB/s on a field larger than the last-level
+cache; the GEMM rates torch.mm reaches (achievable peaks).
 """
 from __future__ import annotations
 
@@ -41,19 +44,18 @@ PEAK_BF16_MFMA_TFLOPS = 2516.6
 PEAK_HBM_BYTES_PER_S = 8.0e12
 CROSS_T = 61
 INTERIOR_T = 961
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-# HBM traffic of the colour-phase kernel per launch on this workload, by tile
-# shape, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per
-# dispatch) scaled by what the same counters read for a plain 512 MiB device
-# copy (FETCH_SIZE reads half the copied bytes on this part: factor 2.0;
-# WRITE_SIZE: 1.0). It is reported only while the kernel sources hash to the
-# value the counters were taken with; otherwise "traffic" is null. Summary:
-# profiles/*_traffic.md.
+# HBM traffic of the colour-phase kernel per launch on the 64 x 64-unit
+# workload, by precision and tile shape, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same counters
+# read for a plain 512 MiB device copy (FETCH_SIZE reads half the copied bytes
+# on this part: factor 2.0; WRITE_SIZE: 1.0). It is reported only while the
+# kernel sources hash to the value the counters were taken with; otherwise
+# "traffic" is null. Summary: profiles/tile_kernel_c4_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "943990a6e26f9dddd7633f39e00bb5db39c67fc87b01d2af7ff5b4ab8bf6939a",
-    "bytes_per_launch": {"64": (5148.3 * 2.0 + 261.9) * 1024,
-                         "64|stream": (5100.3 * 2.0 + 261.9) * 1024,
-                         "32": (6014.4 * 2.0 + 268.6) * 1024},
+    "sources_sha256": None,
+    "bytes_per_launch": {},
 }
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
@@ -101,6 +103,11 @@ def host_info():
 
 
 def cpu_baseline(field, params, width, ux, uy, sample_sweeps):
+    """The float64 oracle's sweep rate on the host cores: `sample_sweeps`
+    CROSS sweeps of the headline domain from its initial field, in
+    point-evals/s. The step's assembly (one INTERIOR pass, 16x the points of
+    a sweep) is not in the sample; its rate per point is the sweep's within
+    the projection's share (T = 961 instead of 61)."""
     import torch
     from oracle import sweep as sw
     torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
@@ -109,41 +116,203 @@ def cpu_baseline(field, params, width, ux, uy, sample_sweeps):
     t0 = time.perf_counter()
     for _ in range(sample_sweeps):
         u = sw.sweep(u, ux, uy, solver)
-    sw.assemble(u, ux, uy, solver)
     dt = time.perf_counter() - t0
-    evals = sample_sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    evals = sample_sweeps * sweep_points(ux, uy, CROSS_T)
     return {"value": evals / dt, "unit": "point-evals/s", "cores": torch.get_num_threads(),
             "kind": "oracle", "host": host_info(),
-            "sample": f"{sample_sweeps} CROSS sweeps + 1 assembly of the same 16x16-unit, "
-                      f"width-{width} workload, float64, {dt:.1f} s"}
+            "sample": f"{sample_sweeps} CROSS sweeps of the same 64x64-unit, width-{width} workload "
+                      f"from its initial field, float64, {dt:.1f} s; the rate stands for the "
+                      f"500-sweep step by extrapolation (the assembly is not in the sample)"}
+
+
+def _rel(a, b) -> float:
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _timed_steps(ctx, step, steps, warmup):
+    """Warm-up, then `steps` timed calls of step() bracketed by device
+    synchronisation; returns (total seconds, per-step seconds, colour-phase
+    launches, their summed ms, their rows) with library timing on."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_read()                      # drop anything recorded so far
+    ctx.timing(True)
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t1)
+    dt = time.perf_counter() - t0
+    ctx.timing(False)
+    launches, phase_ms, phase_rows = ctx.timing_read()
+    return dt, per, launches, phase_ms, phase_rows
+
+
+def _roofline(prec, width, launches, phase_ms, phase_rows, shape):
+    fpp = flops_per_point(width, CROSS_T)
+    achieved = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
+    avg_us = phase_ms * 1e3 / max(launches, 1)
+    peak = PEAK_FP32_MFMA_TFLOPS if prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    key = f"{prec}:{shape}"
+    traffic = (MEASURED_TRAFFIC["bytes_per_launch"].get(key)
+               if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha() else None)
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+            "hbm_gbps": traffic / (avg_us * 1e3) if traffic else None,
+            "hbm_frac": traffic / (avg_us * 1e-6) / PEAK_HBM_BYTES_PER_S if traffic else None,
+            "kernel": f"tile_kernel (colour phase, {prec}, tile {shape})",
+            "avg_launch_us": avg_us, "launches": launches,
+            "flops_per_point_eval": fpp,
+            "units_per_launch": phase_rows / max(launches, 1)}
+
+
+def trajectory_parity(ctx, params, field, units, prec, gold_skel, ks, skel_j, skel_i, spread=None):
+    """Error of the skeleton samples against oracle values after each sweep
+    count in ks (mf_solve in segments; resuming is exact), and its maximum."""
+    import torch
+    from paper_2308_14258_amd import mf_solve
+    u = field.clone()
+    done = 0
+    errs = {}
+    for i, k in enumerate(ks):
+        mf_solve(ctx, params, u, units, int(k) - done, prec=prec)
+        done = int(k)
+        torch.cuda.synchronize()
+        got = u.cpu().numpy().astype(np.float64)[skel_j, skel_i]
+        errs[int(k)] = _rel(got, gold_skel[i])
+    out = {"rel_l2_skeleton_by_sweep": errs, "max": max(errs.values()),
+           "argmax_sweep": max(errs, key=errs.get)}
+    if spread is not None:
+        out["float32_oracle_spread_by_sweep"] = spread
+    return out
+
+
+def c4_section(ctx, args, prec_name):
+    """The 64 x 64-unit step in one precision: autotuned tile shape, warm-up,
+    `steps` timed steps, the phase roofline, errors at 500 sweeps and along
+    the trajectory."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, mf_autotune, mf_solve
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    width = w["width"]
+    K = args.sweeps
+    prec = MF_FP32 if prec_name == "fp32" else MF_BF16
+    field = torch.from_numpy(mi.workload_field("C4")).cuda()
+    params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
+    # tile shape chosen by the autotuner on a scratch copy (outside the timed region)
+    shape = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, prec, trials=2)
+    u = field.clone()
+    u_out = torch.empty_like(u)
+
+    def step():
+        u.copy_(field)
+        mf_solve(ctx, params, u, (ux, uy), K, targets=MF_CROSS, prec=prec, u_out=u_out)
+
+    steps = args.steps if prec_name == "fp32" else max(args.steps, 5)
+    dt, per, launches, phase_ms, phase_rows = _timed_steps(ctx, step, steps, args.warmup)
+    evals = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    res = {"value": evals * steps / dt, "steps": steps, "ms_per_step": dt * 1e3 / steps,
+           "step_ms": {"median": float(np.median(per)) * 1e3, "min": min(per) * 1e3,
+                       "max": max(per) * 1e3},
+           "evals_per_step": evals, "tile_shape": tile_shape_name(shape),
+           "roofline": _roofline(prec_name, width, launches, phase_ms, phase_rows, tile_shape_name(shape))}
+    gpath = os.path.join(GOLDEN, "c4_fp64.npz")
+    if K == w["sweeps"] and os.path.exists(gpath):
+        g = np.load(gpath)
+        sk = u.cpu().numpy().astype(np.float64)[g["skel_j"], g["skel_i"]]
+        uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
+        res["parity"] = {"rel_l2_skeleton_vs_oracle": _rel(sk, g["skel500"]),
+                         "rel_l2_u_out_vs_oracle": _rel(uo, g["u_out_sample"])}
+        tpath = os.path.join(GOLDEN, "c4_traj.npz")
+        if os.path.exists(tpath):
+            t = np.load(tpath)
+            spread = None
+            cpath = os.path.join(GOLDEN, "c4_cond.npz")
+            if os.path.exists(cpath):
+                c = np.load(cpath)
+                ref = {int(k): t["fp64"][list(t["K"]).index(k)] for k in c["K"] if k in t["K"]}
+                spread = {int(k): _rel(c["fp32"][i], ref[int(k)]) for i, k in enumerate(c["K"])
+                          if int(k) in ref}
+            res["parity"]["trajectory"] = trajectory_parity(ctx, params, field, (ux, uy), prec, t["fp64"],
+                                                            t["K"], g["skel_j"], g["skel_i"], spread)
+    return res, u_out
+
+
+def c2_section(ctx, args):
+    """16 x 16 units (961 placements), width 256, GP ring data, 200 sweeps +
+    assembly, FP32: throughput and error against the oracle, with the
+    trajectory."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_CROSS, MF_FP32, mf_autotune, mf_solve
+    w = mi.WORKLOADS["C2"]
+    ux, uy = w["units"]
+    K = w["sweeps"]
+    f = mi.workload_field("C2")
+    field = torch.from_numpy(f).cuda()
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    shape = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, MF_FP32, trials=2)
+    u = field.clone()
+    u_out = torch.empty_like(u)
+
+    def step():
+        u.copy_(field)
+        mf_solve(ctx, params, u, (ux, uy), K, u_out=u_out)
+
+    dt, per, launches, phase_ms, phase_rows = _timed_steps(ctx, step, 5, 1)
+    evals = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    res = {"workload": "C2: 16x16 units (513x513 grid, 961 placements), width 256, GP ring data "
+                       "(l=2, seed 1), 200 CROSS sweeps + assembly, FP32",
+           "point_evals_per_s": evals * 5 / dt, "ms_per_step": dt * 1e3 / 5,
+           "tile_shape": tile_shape_name(shape),
+           "roofline": _roofline("fp32", w["width"], launches, phase_ms, phase_rows, tile_shape_name(shape))}
+    gpath = os.path.join(GOLDEN, "c2_fp32.npz")
+    if os.path.exists(gpath):
+        from oracle.sweep import skeleton_mask
+        g = np.load(gpath)
+        uh = u.cpu().numpy().astype(np.float64)
+        m = skeleton_mask(*f.shape).numpy()
+        uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
+        res["parity"] = {"rel_l2_skeleton_vs_oracle": _rel(uh[m], g["skel200"]),
+                         "rel_l2_u_out_vs_oracle": _rel(uo, g["u_out_sample"])}
+    tpath = os.path.join(GOLDEN, "c2_traj.npz")
+    if os.path.exists(tpath):
+        t = np.load(tpath)
+        spread = {int(k): _rel(t["fp32"][i], t["fp64"][i]) for i, k in enumerate(t["K"])}
+        res.setdefault("parity", {})["trajectory"] = trajectory_parity(
+            ctx, params, field, (ux, uy), MF_FP32, t["fp64"], t["K"], t["skel_j"], t["skel_i"], spread)
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sweeps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-sweeps", type=int, default=20)
+    ap.add_argument("--cpu-sample-sweeps", type=int, default=3)
     ap.add_argument("--mode", choices=["solve", "copy"], default="solve",
                     help="copy: one plain device copy of --copy-mb MiB, the reference "
                          "kernel for scaling HBM counters")
     ap.add_argument("--copy-mb", type=int, default=512)
-    ap.add_argument("--no-bf16", action="store_true",
-                    help="skip the 64x64-unit BF16-vs-FP32 comparison")
-    ap.add_argument("--bf16-sweeps", type=int, default=500)
-    ap.add_argument("--only-bf16", action="store_true",
-                    help="run only the 64x64-unit comparison (for counter collection)")
-    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
-    ap.add_argument("--train-steps", type=int, default=20)
-    ap.add_argument("--c5", action="store_true",
-                    help="also time the 48-domain batch (BF16 sweeps + FP32 adjoint); its GP "
-                         "inputs take about a minute to generate on the host")
-    ap.add_argument("--only-c5", action="store_true")
-    ap.add_argument("--only-train", action="store_true", help="only the training-step measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 64x64-unit FP32 and BF16 steps (for profiling and counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip C1, the per-GPU share, gather/scatter bandwidth and the GEMM peaks")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 48-domain batch and its adjoint")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step measurement")
+    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--only-c5", action="store_true")
+    ap.add_argument("--only-train", action="store_true", help="only the training-step measurement")
     ap.add_argument("--only-io", action="store_true", help="only the gather/scatter bandwidth")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -155,7 +324,7 @@ def main():
 
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import Context, MF_CROSS, MF_FP32, mf_autotune, mf_solve
+    from paper_2308_14258_amd import Context
 
     if args.mode == "copy":
         n = args.copy_mb * (1 << 20) // 4
@@ -167,121 +336,76 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}), flush=True)
         return
 
-    if args.only_bf16 or args.only_c5 or args.only_train or args.only_io:
+    if args.only_c5 or args.only_train or args.only_io:
         ctx = Context(0)
         if args.only_io:
             out = {"gather_scatter": io_measurement(ctx)}
-        elif args.only_bf16:
-            out = {"bf16_vs_fp32": bf16_comparison(ctx, args.bf16_sweeps)}
         elif args.only_c5:
-            out = {"batched": batched_measurement(ctx)}
+            out = {"c5": batched_measurement(ctx)}
         else:
             out = {"train": train_measurement(ctx, args.train_steps)}
         print(json.dumps(out), flush=True)
         ctx.close()
         return
 
-    w = mi.WORKLOADS["C2"]
+    w = mi.WORKLOADS["C4"]
     ux, uy = w["units"]
     width = w["width"]
-    K = args.sweeps
-    field = mi.workload_field("C2")
-    params_np = mi.xavier_params(width, 0)
-
-    dev = torch.device("cuda:0")
     ctx = Context(0)
-    params = torch.from_numpy(params_np).to(dev)
-    u0 = torch.from_numpy(field).to(dev)
-    u = u0.clone()
-    u_out = torch.empty_like(u)
-
-    # tile height chosen by the autotuner on a scratch copy (outside the timed region)
-    tile_rows = mf_autotune(ctx, params, u0.clone(), (ux, uy), MF_CROSS, MF_FP32, trials=3)
-
-    def step():
-        u.copy_(u0)
-        mf_solve(ctx, params, u, (ux, uy), K, targets=MF_CROSS, prec=MF_FP32, u_out=u_out)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing_read()                      # drop anything recorded so far
-    ctx.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.timing(False)
-    launches, phase_ms, phase_rows = ctx.timing_read()
-
-    evals_per_step = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
-    value = evals_per_step * args.steps / dt
-    fpp = flops_per_point(width, CROSS_T)
-    achieved = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
-    avg_us = phase_ms * 1e3 / max(launches, 1)
-
-    # parity of the last step against stored oracle values (16x16, 200 sweeps)
-    parity = None
-    gpath = os.path.join(ROOT, "tests", "golden", "c2_fp32.npz")
-    if K == 200 and os.path.exists(gpath):
-        from oracle.sweep import skeleton_mask
-        g = np.load(gpath)
-        uh = u.cpu().numpy().astype(np.float64)
-        m = skeleton_mask(*field.shape).numpy()
-        e_s = np.linalg.norm(uh[m] - g["skel200"]) / np.linalg.norm(g["skel200"])
-        uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
-        e_o = np.linalg.norm(uo - g["u_out_sample"]) / np.linalg.norm(g["u_out_sample"])
-        parity = {"rel_l2_skeleton_vs_oracle": float(e_s), "rel_l2_u_out_vs_oracle": float(e_o)}
-
-    traffic = (MEASURED_TRAFFIC["bytes_per_launch"].get(tile_shape_name(tile_rows))
-               if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha() else None)
+    fp32, uo32 = c4_section(ctx, args, "fp32")
+    print(f"# fp32 64x64: {fp32['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
+    bf16, uo16 = c4_section(ctx, args, "bf16")
+    print(f"# bf16 64x64: {bf16['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
+    d = uo16.double()[1:-1, 1:-1] - uo32.double()[1:-1, 1:-1]
+    bf16["rel_l2_vs_fp32_u_out"] = float(d.norm() / uo32.double()[1:-1, 1:-1].norm())
+    bf16["speedup_over_fp32"] = bf16["value"] / fp32["value"]
+    del uo16, uo32
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": fp32["value"],
         "unit": "point-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "ms_per_step": fp32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "C2: plain Mosaic Flow, 16x16 units (513x513 grid, 961 "
-                               "placements), SDNet width 256, GP ring data (l=2, seed 1), "
-                               f"{K} CROSS sweeps + assembly",
-                   "units": [ux, uy], "width": width, "sweeps": K, "targets": "cross",
-                   "evals_per_step": evals_per_step, "tile_shape": tile_shape_name(tile_rows)},
-        "sweep_phase": {"launches": launches, "avg_launch_us": avg_us,
-                        "point_evals_per_s": phase_rows / (phase_ms * 1e-3)},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic,
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
-                     "hbm_gbps": traffic / (avg_us * 1e3) if traffic else None,
-                     "hbm_frac": traffic / (avg_us * 1e-6) / PEAK_HBM_BYTES_PER_S if traffic else None,
-                     "kernel": "tile_kernel<256,R,CROSS,FP32> (colour phase)",
-                     "flops_per_point_eval": fpp},
-        "parity": parity,
+        "config": {"workload": "C4: plain Mosaic Flow, 64x64 units (2049x2049 grid, 16,129 placements), "
+                               "SDNet width 256 (Xavier-normal, seed 0), e^x sin y ring data scaled to "
+                               f"[0, 1], {args.sweeps} CROSS sweeps + overlap-averaged assembly",
+                   "units": [ux, uy], "width": width, "sweeps": args.sweeps, "targets": "cross",
+                   "evals_per_step": fp32["evals_per_step"], "tile_shape": fp32["tile_shape"]},
+        "step_ms": fp32["step_ms"],
+        "roofline": fp32["roofline"],
+        "parity": fp32.get("parity"),
+        "bf16": bf16,
     }
-    out["assembly"] = assembly_measurement(ctx, params, u0, (ux, uy))
-    if not args.no_extras:
-        out["c1"] = c1_measurement(ctx)
-        out["per_gpu_share"] = per_gpu_share_measurement(ctx)
-        out["gather_scatter"] = io_measurement(ctx)
-        out["achievable_peaks"] = achievable_peaks()
-        out["roofline"]["frac_of_achievable"] = achieved / out["achievable_peaks"]["fp32_tflops"]
-    if not args.no_bf16:
-        out["bf16_vs_fp32"] = bf16_comparison(ctx, args.bf16_sweeps)
-    if not args.no_train:
-        out["train"] = train_measurement(ctx, args.train_steps)
-    if args.c5:
-        out["batched"] = batched_measurement(ctx)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(field, params_np, width, ux, uy, args.cpu_sample_sweeps)
+    if not args.headline_only:
+        out["c2"] = c2_section(ctx, args)
+        print("# c2 done", file=sys.stderr, flush=True)
+        if not args.no_c5:
+            out["c5"] = batched_measurement(ctx)
+            print("# c5 done", file=sys.stderr, flush=True)
+        if not args.no_train:
+            out["train"] = train_measurement(ctx, args.train_steps)
+        params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
+        out["assembly"] = assembly_measurement(ctx, params, torch.from_numpy(mi.workload_field("C4")).cuda(),
+                                               (ux, uy))
+        if not args.no_extras:
+            out["c1"] = c1_measurement(ctx)
+            out["per_gpu_share"] = per_gpu_share_measurement(ctx)
+            out["gather_scatter"] = io_measurement(ctx)
+            out["achievable_peaks"] = achievable_peaks()
+            out["roofline"]["frac_of_achievable"] = (out["roofline"]["achieved"] /
+                                                     out["achievable_peaks"]["fp32_tflops"])
+            out["bf16"]["roofline"]["frac_of_achievable"] = (out["bf16"]["roofline"]["achieved"] /
+                                                             out["achievable_peaks"]["bf16_tflops"])
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(mi.workload_field("C4"), mi.xavier_params(width, 0), width,
+                                               ux, uy, args.cpu_sample_sweeps)
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -441,12 +565,16 @@ def io_measurement(ctx):
 
 
 def batched_measurement(ctx):
-    """48 independent domains (4..48 units per side, seed 7), width 256: 20
-    BF16 sweeps + assembly in one persistent launch per colour, and the FP32
-    adjoint of J = sum u_out^2 through 20 sweeps with checkpoints every 5."""
+    """48 independent domains (4..48 units per side, seed 7), width 256, GP
+    ring data: 20 sweeps + assembly in one launch per colour for the whole
+    batch, BF16 (the workload's precision) and FP32, each timed over three
+    steps and checked at its smallest, median and largest domain against
+    oracle values along the 20 sweeps; then the FP32 adjoint of
+    J = sum u_out^2 through the 20 sweeps with checkpoints every 5, checked
+    on the smallest domain against the oracle's gradient."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_CROSS, Batch, mf_solve, mf_solve_adjoint
+    from paper_2308_14258_amd import MF_BF16, MF_FP32, Batch, mf_solve, mf_solve_adjoint
     w = mi.WORKLOADS["C5"]
     t0 = time.perf_counter()
     sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
@@ -456,24 +584,61 @@ def batched_measurement(ctx):
     base = batch.buf.clone()
     out = torch.empty_like(batch.buf)
     K = w["sweeps"]
-    mf_solve(ctx, params, batch, None, 2, prec=MF_BF16)
+    placements = int(sum((2 * ux - 1) * (2 * uy - 1) for ux, uy in sizes))
+    evals = K * placements * CROSS_T + placements * INTERIOR_T
+    res = {"workload": f"C5: 48 domains (4..48 units per side, seed 7), {placements} placements, width 256, "
+                       f"GP ring data (l=1), {K} CROSS sweeps + assembly",
+           "input_generation_s": gen_s}
+    gpath = os.path.join(GOLDEN, "c5_k20.npz")
+    g = np.load(gpath) if os.path.exists(gpath) else None
+    for name, prec in (("bf16", MF_BF16), ("fp32", MF_FP32)):
+        def step():
+            batch.buf.copy_(base)
+            mf_solve(ctx, params, batch, None, K, prec=prec, u_out=out)
+
+        dt, per, launches, phase_ms, phase_rows = _timed_steps(ctx, step, 3, 1)
+        r = {"point_evals_per_s": evals * 3 / dt, "ms_per_step": dt * 1e3 / 3,
+             "roofline": _roofline(name, w["width"], launches, phase_ms, phase_rows, "auto")}
+        if g is not None:
+            # errors at the stored sweep counts (solve in segments; resuming is exact)
+            batch.buf.copy_(base)
+            done = 0
+            traj = {}
+            for i, k in enumerate(g["K"]):
+                k = int(k)
+                mf_solve(ctx, params, batch, None, k - done, prec=prec, u_out=out if k == K else None)
+                done = k
+                torch.cuda.synchronize()
+                for n, d in enumerate(g["picks"]):
+                    u = batch.field(int(d)).cpu().numpy().astype(np.float64)
+                    e = _rel(u[g[f"skel_j{n}"], g[f"skel_i{n}"]], g[f"skel_fp64_{n}"][i])
+                    traj.setdefault(int(d), {})[k] = e
+            par = {}
+            for n, d in enumerate(g["picks"]):
+                d = int(d)
+                uo = batch.field(d, out).cpu().numpy().astype(np.float64)
+                par[d] = {"units": [int(v) for v in sizes[d]],
+                          "rel_l2_skeleton_vs_oracle_by_sweep": traj[d],
+                          "trajectory_max": max(traj[d].values()),
+                          "rel_l2_u_out_vs_oracle": _rel(uo[g[f"sample_j{n}"], g[f"sample_i{n}"]],
+                                                         g[f"u_out_fp64_{n}"]),
+                          "float32_oracle_spread_at_K": _rel(g[f"skel_fp32_{n}"][-1], g[f"skel_fp64_{n}"][-1])}
+            r["parity"] = par
+        res[name] = r
     batch.buf.copy_(base)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mf_solve(ctx, params, batch, None, K, prec=MF_BF16, u_out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    placements = int(sum((2 * ux - 1) * (2 * uy - 1) for ux, uy in sizes))
-    evals = K * placements * CROSS_T + placements * INTERIOR_T
-    t0 = time.perf_counter()
-    ub, J = mf_solve_adjoint(ctx, params, Batch(fields), None, K, w["ckpt"])
+    ub, J = mf_solve_adjoint(ctx, params, batch, None, K, w["ckpt"])
     torch.cuda.synchronize()
     dta = time.perf_counter() - t0
-    return {"workload": f"C5: 48 domains, {placements} placements, width 256, {K} sweeps",
-            "input_generation_s": gen_s,
-            "bf16_solve": {"s": dt, "point_evals_per_s": evals / dt},
-            "fp32_adjoint": {"s": dta, "J": float(J.item()),
-                             "grad_norm": float(ub.double().norm().item())}}
+    adj = {"s": dta, "J": float(J.item()), "grad_norm": float(ub.double().norm().item())}
+    apath = os.path.join(GOLDEN, "c5_adjoint.npz")
+    if os.path.exists(apath):
+        a = np.load(apath)
+        got = batch.field(int(a["domain"]), ub).cpu().numpy().astype(np.float64)
+        adj["rel_l2_u0_bar_vs_oracle_smallest_domain"] = _rel(got, a["u0_bar"])
+    res["fp32_adjoint"] = adj
+    return res
 
 
 def tile_shape_name(code):
@@ -486,60 +651,6 @@ def tile_shape_name(code):
     if code & (1 << 18):
         name += "|rowsplit"
     return name
-
-
-def bf16_comparison(ctx, sweeps):
-    """64 x 64 units (2049^2 grid, 16,129 placements), width 256, e^x sin y
-    ring data: the same solve in FP32 and with BF16 hidden GEMMs, one timed
-    run each after a short warm-up; error of BF16 against the FP32 run."""
-    import torch
-    import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, mf_solve
-    w = mi.WORKLOADS["C4"]
-    ux, uy = w["units"]
-    width = w["width"]
-    field = torch.from_numpy(mi.workload_field("C4")).cuda()
-    params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
-    res = {"workload": f"C4: 64x64 units, width {width}, e^x sin y scaled, {sweeps} CROSS sweeps "
-                       "+ assembly"}
-    outs = {}
-    gpath = os.path.join(ROOT, "tests", "golden", "c4_fp64.npz")   # oracle values, 500 sweeps
-    evals = sweeps * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
-    from paper_2308_14258_amd import mf_autotune
-    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
-        shape = mf_autotune(ctx, params, field.clone(), (ux, uy), MF_CROSS, prec, trials=2)
-        u = field.clone()
-        u_out = torch.empty_like(u)
-        mf_solve(ctx, params, u, (ux, uy), 2, targets=MF_CROSS, prec=prec)   # warm-up + capture
-        u.copy_(field)
-        ctx.timing_read()
-        ctx.timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mf_solve(ctx, params, u, (ux, uy), sweeps, targets=MF_CROSS, prec=prec, u_out=u_out)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ctx.timing(False)
-        launches, ms, rows = ctx.timing_read()
-        fpp = flops_per_point(width, CROSS_T)
-        peak = PEAK_FP32_MFMA_TFLOPS if prec == MF_FP32 else PEAK_BF16_MFMA_TFLOPS
-        ach = rows * fpp / (ms * 1e-3) / 1e12
-        res[name] = {"point_evals_per_s": evals / dt, "s_per_solve": dt, "tile_shape": tile_shape_name(shape),
-                     "phase_avg_us": ms * 1e3 / max(launches, 1),
-                     "phase_tflops": ach, "phase_frac_of_mfma_peak": ach / peak}
-        if sweeps == w["sweeps"] and os.path.exists(gpath):
-            g = np.load(gpath)
-            sk = u.cpu().numpy().astype(np.float64)[g["skel_j"], g["skel_i"]]
-            uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
-            res[name]["rel_l2_skeleton_vs_oracle"] = float(np.linalg.norm(sk - g["skel500"]) /
-                                                           np.linalg.norm(g["skel500"]))
-            res[name]["rel_l2_u_out_vs_oracle"] = float(np.linalg.norm(uo - g["u_out_sample"]) /
-                                                        np.linalg.norm(g["u_out_sample"]))
-        outs[name] = u_out.double()
-    d = outs["bf16"][1:-1, 1:-1] - outs["fp32"][1:-1, 1:-1]
-    res["rel_l2_bf16_vs_fp32_u_out"] = float(d.norm() / outs["fp32"][1:-1, 1:-1].norm())
-    res["speedup_bf16_over_fp32"] = res["bf16"]["point_evals_per_s"] / res["fp32"]["point_evals_per_s"]
-    return res
 
 
 if __name__ == "__main__":

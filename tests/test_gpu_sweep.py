@@ -287,8 +287,10 @@ def test_solve_c4_full_size_golden(ctx, prec, tol):
     oracle values at 32768 sampled skeleton points and 2048 assembly points:
     after one sweep (the sweep map itself) and after 500 sweeps (the end
     state). After 20 sweeps the untrained network's iteration is in a
-    transient that amplifies float32 rounding by about 1e5 on this domain, so
-    that comparison is reported, not bounded."""
+    transient that amplifies rounding at every phase: the same algorithm
+    evaluated in float32 on the CPU is 6.8e-3 away from float64 there (0.6
+    at 30 sweeps, c4_cond.npz). Float32 is held to 10x that spread; BF16 is
+    reported."""
     print(f"case: mf_solve C4 (64x64, d=256) prec {prec} vs golden", flush=True)
     from paper_2308_14258_amd import mf_autotune
     g = np.load(os.path.join(HERE, "golden", "c4_fp64.npz"))
@@ -318,6 +320,35 @@ def test_solve_c4_full_size_golden(ctx, prec, tol):
           flush=True)
     assert err1 <= tol and err1_out <= tol
     assert err500 <= tol and err_out <= tol
+    if prec == MF_FP32:
+        c = np.load(os.path.join(HERE, "golden", "c4_cond.npz"))
+        e32 = rel_l2(c["fp32"][list(c["K"]).index(20)], g["skel20"])
+        print(f"C4 sweep 20: float32 oracle spread {e32:.3e}, bound {max(1e-5, 10 * e32):.3e}", flush=True)
+        assert err20 <= max(1e-5, 10.0 * e32)
+
+
+def test_solve_c2_trajectory(ctx):
+    """16 x 16 units, width 256, 200 sweeps: the skeleton at 8192 sampled
+    points after each stored sweep count against the float64 oracle, held to
+    max(1e-5, 10 x the float32 oracle's spread at that count); reports the
+    trajectory maximum."""
+    print("case: C2 trajectory vs golden", flush=True)
+    t = np.load(os.path.join(HERE, "golden", "c2_traj.npz"))
+    w = mi.WORKLOADS["C2"]
+    p = dev(mi.xavier_params(w["width"], 0))
+    u = dev(mi.workload_field("C2"))
+    done = 0
+    worst = 0.0
+    for i, k in enumerate(t["K"]):
+        mf_solve(ctx, p, u, (16, 16), int(k) - done)
+        done = int(k)
+        torch.cuda.synchronize()
+        e = rel_l2(u.cpu().numpy()[t["skel_j"], t["skel_i"]], t["fp64"][i])
+        e32 = rel_l2(t["fp32"][i], t["fp64"][i])
+        worst = max(worst, e)
+        print(f"C2 K={int(k)}: rel L2 skeleton {e:.3e} (float32 oracle spread {e32:.3e})", flush=True)
+        assert e <= max(1e-5, 10.0 * e32), (int(k), e, e32)
+    print(f"C2 trajectory max {worst:.3e}", flush=True)
 
 
 def test_graph_replay_equals_direct_launches(ctx):
