@@ -245,3 +245,100 @@ def workload_field(name: str) -> np.ndarray:
     if w["data"] == "expsin":
         return expsin_field(ux, uy)
     raise ValueError(name)
+
+
+# ----------------------------------------------------------------------------
+# SDNet training data (Sec. 5.1 "Data Generation"): boundary conditions from
+# Gaussian processes whose hyperparameters come from a Sobol sequence, and the
+# solution of each subdomain problem, which the paper obtains with pyAMG.
+# ----------------------------------------------------------------------------
+
+def sobol_gp_perimeter_batch(n_bc: int, seed: int, length_range=(0.25, 2.0),
+                             amplitude_range=(0.5, 1.5)) -> tuple[np.ndarray, np.ndarray]:
+    """[n_bc x 128] GP samples on the unit-square perimeter nodes, each with
+    its own squared-exponential hyperparameters, and those [n_bc x 2]
+    (length scale, amplitude).
+
+    A scrambled 2-D Sobol sequence (scipy.stats.qmc, seed) gives (s1, s2)
+    per condition; the length scale is log-uniform over ``length_range``
+    (l = l_lo (l_hi / l_lo)^s1) and the amplitude (standard deviation)
+    uniform over ``amplitude_range``. The kernel uses the Euclidean distance
+    between perimeter nodes, as ``gp_perimeter_batch`` does, and the sample
+    is cholesky(K + 1e-6 I) z with z from default_rng(seed + 1).
+    """
+    import warnings
+
+    from scipy.stats import qmc
+    pts = unit_perimeter_nodes()
+    diff = pts[:, None, :] - pts[None, :, :]
+    r2 = np.sum(diff * diff, -1)
+    with warnings.catch_warnings():   # balance is exact only for powers of two; any n is valid
+        warnings.simplefilter("ignore", UserWarning)
+        s = qmc.Sobol(d=2, scramble=True, seed=seed).random(n_bc)
+    lo, hi = length_range
+    ell = lo * (hi / lo) ** s[:, 0]
+    amp = amplitude_range[0] + (amplitude_range[1] - amplitude_range[0]) * s[:, 1]
+    z = np.random.default_rng(seed + 1).standard_normal((n_bc, pts.shape[0]))
+    out = np.empty((n_bc, pts.shape[0]))
+    eye = 1e-6 * np.eye(pts.shape[0])
+    for b in range(n_bc):
+        chol = np.linalg.cholesky(amp[b] ** 2 * np.exp(-r2 / (2.0 * ell[b] ** 2)) + eye)
+        out[b] = chol @ z[b]
+    return out.astype(np.float32), np.stack([ell, amp], 1)
+
+
+def perimeter_grid_indices(cells: int = CELLS_PER_UNIT) -> tuple[np.ndarray, np.ndarray]:
+    """(j, i) grid indices of the 128 perimeter nodes on a (cells+1)^2 grid,
+    in the boundary-vector order of ``unit_perimeter_nodes``."""
+    p = np.rint(unit_perimeter_nodes(cells) * cells).astype(np.int64)
+    return p[:, 1], p[:, 0]
+
+
+def subdomain_solutions(G: np.ndarray, cells: int = CELLS_PER_UNIT) -> np.ndarray:
+    """[B x (cells+1) x (cells+1)] float64 grids: ring = the boundary vectors
+    G [B x 4 cells] (corners included), interior = the solution of the
+    5-point discrete Laplace equation with that Dirichlet ring.
+
+    Training targets for the data loss (the paper solves each boundary value
+    problem with pyAMG; here the 5-point system on the square is solved
+    exactly by diagonalisation: the discrete sine transform (type I) turns
+    the operator 4 u - (the four neighbours) into multiplication by
+    4 sin^2(p pi / 2n) + 4 sin^2(q pi / 2n), n = cells)."""
+    from scipy.fft import dstn, idstn
+    G = np.asarray(G, dtype=np.float64)
+    B = G.shape[0]
+    n = cells
+    U = np.zeros((B, n + 1, n + 1))
+    jj, ii = perimeter_grid_indices(cells)
+    U[:, jj, ii] = G
+    rhs = np.zeros((B, n - 1, n - 1))
+    rhs[:, 0, :] += U[:, 0, 1:-1]
+    rhs[:, -1, :] += U[:, -1, 1:-1]
+    rhs[:, :, 0] += U[:, 1:-1, 0]
+    rhs[:, :, -1] += U[:, 1:-1, -1]
+    k = np.arange(1, n)
+    s2 = 4.0 * np.sin(k * np.pi / (2.0 * n)) ** 2
+    lam = s2[:, None] + s2[None, :]
+    U[:, 1:-1, 1:-1] = idstn(dstn(rhs, type=1, axes=(1, 2)) / lam, type=1, axes=(1, 2))
+    return U
+
+
+def training_set(n_bc: int, n_data: int, n_colloc: int, seed: int, cells: int = CELLS_PER_UNIT):
+    """A seeded SDNet training set of n_bc boundary conditions
+    (``sobol_gp_perimeter_batch``), each with n_data data points drawn
+    without replacement from its (cells+1)^2 grid nodes (coordinates in
+    [0, 1]^2) and their exact values (``subdomain_solutions``), and n_colloc
+    collocation points uniform in (0, 1)^2. Returns float32 arrays
+    G [n_bc, 128], Xd [n_bc, n_data, 2], Yd [n_bc, n_data],
+    Xc [n_bc, n_colloc, 2] and the hyperparameters [n_bc, 2]."""
+    G, hyper = sobol_gp_perimeter_batch(n_bc, seed)
+    U = subdomain_solutions(G, cells)
+    rng = np.random.default_rng(seed + 2)
+    nodes = (cells + 1) ** 2
+    idx = np.stack([rng.choice(nodes, n_data, replace=False) for _ in range(n_bc)])
+    jj, ii = idx // (cells + 1), idx % (cells + 1)
+    Xd = np.stack([ii / cells, jj / cells], -1)
+    Yd = np.take_along_axis(U.reshape(n_bc, -1), idx, 1)
+    Xc = rng.uniform(0.0, 1.0, size=(n_bc, n_colloc, 2))
+    f32 = np.float32
+    return G, Xd.astype(f32), Yd.astype(f32), Xc.astype(f32), hyper
