@@ -54,8 +54,9 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # kernel sources hash to the value the counters were taken with; otherwise
 # "traffic" is null. Summary: profiles/tile_kernel_c4_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": None,
-    "bytes_per_launch": {},
+    "sources_sha256": "943990a6e26f9dddd7633f39e00bb5db39c67fc87b01d2af7ff5b4ab8bf6939a",
+    "bytes_per_launch": {"C4:fp32:64|stream": (27768.4 * 2.0 + 4396.5) * 1024,
+                         "C4:bf16:256|rowsplit": (14262.5 * 2.0 + 4312.4) * 1024},
 }
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
@@ -153,12 +154,12 @@ def _timed_steps(ctx, step, steps, warmup):
     return dt, per, launches, phase_ms, phase_rows
 
 
-def _roofline(prec, width, launches, phase_ms, phase_rows, shape):
+def _roofline(prec, width, launches, phase_ms, phase_rows, shape, workload=""):
     fpp = flops_per_point(width, CROSS_T)
     achieved = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
     avg_us = phase_ms * 1e3 / max(launches, 1)
     peak = PEAK_FP32_MFMA_TFLOPS if prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
-    key = f"{prec}:{shape}"
+    key = f"{workload}:{prec}:{shape}"
     traffic = (MEASURED_TRAFFIC["bytes_per_launch"].get(key)
                if MEASURED_TRAFFIC["sources_sha256"] == kernel_sources_sha() else None)
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -223,7 +224,7 @@ def c4_section(ctx, args, prec_name):
            "step_ms": {"median": float(np.median(per)) * 1e3, "min": min(per) * 1e3,
                        "max": max(per) * 1e3},
            "evals_per_step": evals, "tile_shape": tile_shape_name(shape),
-           "roofline": _roofline(prec_name, width, launches, phase_ms, phase_rows, tile_shape_name(shape))}
+           "roofline": _roofline(prec_name, width, launches, phase_ms, phase_rows, tile_shape_name(shape), "C4")}
     gpath = os.path.join(GOLDEN, "c4_fp64.npz")
     if K == w["sweeps"] and os.path.exists(gpath):
         g = np.load(gpath)
@@ -273,7 +274,7 @@ def c2_section(ctx, args):
                        "(l=2, seed 1), 200 CROSS sweeps + assembly, FP32",
            "point_evals_per_s": evals * 5 / dt, "ms_per_step": dt * 1e3 / 5,
            "tile_shape": tile_shape_name(shape),
-           "roofline": _roofline("fp32", w["width"], launches, phase_ms, phase_rows, tile_shape_name(shape))}
+           "roofline": _roofline("fp32", w["width"], launches, phase_ms, phase_rows, tile_shape_name(shape), "C2")}
     gpath = os.path.join(GOLDEN, "c2_fp32.npz")
     if os.path.exists(gpath):
         from oracle.sweep import skeleton_mask
