@@ -74,6 +74,40 @@ def random_params(width: int, seed: int, scale: float = 1.0,
     return (flat * scale).astype(np.float32)
 
 
+def conv_param_count(width: int, channels: int, n_boundary: int = N_BOUNDARY, kernel: int = 5) -> int:
+    """Flat parameter count of the network with a convolutional boundary
+    embedding: Wc1 (C x 1 x k) | bc1 | Wc2 (C x C x k) | bc2 | W1 (d x (C n_b + 2))
+    | b1 | W2 | b2 | W3 | b3 | W4 | b4 | w5 | b5."""
+    d, C = width, channels
+    return C * kernel + C + C * C * kernel + C + d * (C * n_boundary + 2) + d + 3 * (d * d + d) + d + 1
+
+
+def xavier_conv_params(width: int, channels: int, seed: int = 0, bias_scale: float = 0.0,
+                       n_boundary: int = N_BOUNDARY, kernel: int = 5) -> np.ndarray:
+    """Xavier-normal weights for the network with a convolutional boundary
+    embedding, drawn from ``default_rng(seed).standard_normal`` in the order
+    Wc1, Wc2, W1, W2, W3, W4, w5 (each in its row-major layout), scaled by
+    sqrt(2 / (fan_in + fan_out)) (a convolution's fans are its channel counts
+    times the kernel size). Biases are 0, or, with bias_scale > 0, normal
+    with that standard deviation from ``default_rng(seed + 1000)`` in the
+    same order (tests use that to exercise every bias)."""
+    d, C = width, channels
+    E = C * n_boundary
+    rng = np.random.default_rng(seed)
+    brng = np.random.default_rng(seed + 1000)
+    parts = []
+    for (shape, fan_in, fan_out) in [((C, 1, kernel), kernel, C * kernel),
+                                     ((C, C, kernel), C * kernel, C * kernel),
+                                     ((d, E + 2), E + 2, d), ((d, d), d, d), ((d, d), d, d), ((d, d), d, d),
+                                     ((1, d), d, 1)]:
+        parts.append((rng.standard_normal(shape) * np.sqrt(2.0 / (fan_in + fan_out))).reshape(-1))
+        nb = shape[0]
+        parts.append(bias_scale * brng.standard_normal(nb) if bias_scale > 0 else np.zeros(nb))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == conv_param_count(width, channels, n_boundary, kernel)
+    return flat
+
+
 # ----------------------------------------------------------------------------
 # Outer-ring enumeration (input side only: which grid points carry data).
 # ----------------------------------------------------------------------------

@@ -13,6 +13,9 @@ no blocking, fusion or reordering beyond what the definitions state:
   order, target sets (Sec. 4.2 "Domain Parallelization", Fig. 2).
 * ``sdnet``     -- the subdomain network N(x, g; theta) with the input-split
   first layer (Sec. 3.2, Eqs. 5-8) and its derivatives by autograd.
+* ``sdnet_conv`` -- the paper's architecture: a circular 1-D convolutional
+  embedding of the boundary curve, the input-split first layer and GELU
+  layers (Sec. 3.1, Fig. 3; Sec. 3.2, Eq. 8).
 * ``sweep``     -- batched colour phases, sweeps, the delta test and the
   overlap-averaged final assembly (Sec. 4.1, Alg. 2).
 * ``fd``        -- exact 5-point subdomain solver and global 5-point solve,
@@ -25,4 +28,4 @@ no blocking, fusion or reordering beyond what the definitions state:
 Every function states which passage it follows. Pins that tie the oracle to
 facts outside itself live in ``tests/test_oracle_*.py``.
 """
-from . import adjoint, fd, geometry, sdnet, sweep, train  # noqa: F401
+from . import adjoint, fd, geometry, sdnet, sdnet_conv, sweep, train  # noqa: F401
