@@ -30,13 +30,29 @@
  * Targets: MF_CROSS = the 61 interior points of the two centre lines (the
  *   per-iteration set of Alg. 2), MF_INTERIOR = all 31 x 31 interior points.
  *   SDNet sees local coordinates (i / 32, j / 32) in [0, 1].
- * SDNet (mf_sdnet_desc): width d in {128, 256}, depth 4 tanh hidden layers,
- *   scalar output. Parameters are one flat float32 vector
+ * SDNet (mf_sdnet_desc): width d in {128, 256}, depth 4 hidden layers,
+ *   scalar output, in one of two architectures.
+ *   MF_TANH (embed_channels = 0): tanh layers on [g, x, y]. Parameters are
+ *   one flat float32 vector
  *     W1 (d x 130) | b1 (d) | W2 (d x d) | b2 | W3 | b3 | W4 | b4 | w5 (d) | b5
  *   every matrix row-major (out, in); W1 columns 0..127 act on the boundary
- *   vector, 128 on x and 129 on y. The first layer is evaluated in the
- *   input-split form of Eq. 8: W1g g + b1 once per placement (or boundary
- *   condition), plus W1x (x, y) per point.
+ *   vector, 128 on x and 129 on y.
+ *   MF_GELU (embed_channels = C in 1..8): the paper's architecture (Sec. 3.1,
+ *   Fig. 3): the boundary curve passes through two circular 1-D
+ *   convolutions (1 -> C -> C channels, kernel 5, padding 2 wrapping around
+ *   the closed curve), each followed by GELU, giving an embedding e of
+ *   E = 128 C values (channel-major, e[c * 128 + k]); the layers are GELU,
+ *   GELU(a) = a Phi(a) with Phi the standard normal distribution function.
+ *   Parameters: Wc1 (C x 1 x 5) | bc1 (C) | Wc2 (C x C x 5) | bc2 (C) |
+ *   W1 (d x (E + 2)) | b1 | W2 | b2 | W3 | b3 | W4 | b4 | w5 | b5, W1 columns
+ *   0..E-1 on the embedding, E on x, E+1 on y.
+ *   Either way the first layer is evaluated in the input-split form of
+ *   Eq. 8: W1g g (or W1e e) + b1 once per placement (or boundary
+ *   condition), plus W1x (x, y) per point. The MF_GELU network runs in
+ *   MF_FP32 through mf_sweep / mf_solve (multiplicative; a placement's
+ *   embedding and projection once per phase, then the value stream through
+ *   MFMA GEMMs with a GELU epilogue) and sdnet_forward (with its gradient
+ *   and Laplacian); the other entry points return MF_EUNSUPPORTED for it.
  * Precision: MF_FP32 computes every GEMM with float32 MFMA (the boundary
  *   projection on the float32 VALU). MF_BF16 rounds the GEMM operands to
  *   bf16 and accumulates in float32 on MFMA: the boundary projection
@@ -84,15 +100,17 @@ enum {
 enum { MF_FP32 = 0, MF_BF16 = 1 };                 /* precision           */
 enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
 enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
-enum { MF_TANH = 0 };                               /* activation          */
+enum { MF_TANH = 0, MF_GELU = 1 };                  /* activation          */
 enum { MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1 };        /* mf_solve flags      */
 enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17, MF_TILE_ROWSPLIT = 1 << 18 }; /* tile-shape flags */
 
 typedef struct mf_sdnet_desc {
-  int32_t width;       /* d: 128 or 256                                    */
-  int32_t depth;       /* number of tanh hidden layers: 4                  */
-  int32_t n_boundary;  /* boundary samples: 128                            */
-  int32_t activation;  /* MF_TANH                                          */
+  int32_t width;           /* d: 128 or 256                                */
+  int32_t depth;           /* number of hidden layers: 4                   */
+  int32_t n_boundary;      /* boundary samples: 128                        */
+  int32_t activation;      /* MF_TANH or MF_GELU                           */
+  int32_t embed_channels;  /* MF_TANH: 0; MF_GELU: convolution channels,
+                              1..8                                         */
 } mf_sdnet_desc;
 
 typedef struct mf_domain_desc {

@@ -19,6 +19,7 @@ MF_FP32, MF_BF16 = 0, 1
 MF_CROSS, MF_INTERIOR = 0, 1
 MF_MULTIPLICATIVE, MF_ADDITIVE = 0, 1
 MF_TANH = 0
+MF_GELU = 1
 MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1
 MF_TILE_WIDE = 1 << 16
 MF_TILE_STREAM = 1 << 17
@@ -27,7 +28,8 @@ MF_TILE_ROWSPLIT = 1 << 18
 
 class SdnetDesc(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("n_boundary", ctypes.c_int32), ("activation", ctypes.c_int32)]
+                ("n_boundary", ctypes.c_int32), ("activation", ctypes.c_int32),
+                ("embed_channels", ctypes.c_int32)]
 
 
 class DomainDesc(ctypes.Structure):

@@ -12,20 +12,38 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
+from ._lib import (MF_GELU, MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
                    check, load)
 
 
-def width_of(params: torch.Tensor) -> int:
+def _gelu_count(d: int, C: int) -> int:
+    return 5 * C + C + 5 * C * C + C + d * (128 * C + 2) + d + 3 * (d * d + d) + d + 1
+
+
+def net_of(params: torch.Tensor):
+    """(width, activation, embedding channels) of a flat parameter vector:
+    the tanh network (no embedding) or the convolutional-embedding GELU
+    network with 1..8 channels, at width 128 or 256."""
     n = params.numel()
     for d in (128, 256):
         if 3 * d * d + 135 * d + 1 == n:
-            return d
-    raise ValueError(f"parameter vector of {n} floats matches no supported width")
+            return d, MF_TANH, 0
+        for C in range(1, 9):
+            if _gelu_count(d, C) == n:
+                return d, MF_GELU, C
+    raise ValueError(f"parameter vector of {n} floats matches no supported network")
 
 
-def sdnet_desc(width: int) -> SdnetDesc:
-    return SdnetDesc(width, 4, 128, MF_TANH)
+def width_of(params: torch.Tensor) -> int:
+    return net_of(params)[0]
+
+
+def sdnet_desc(width: int, activation: int = MF_TANH, embed_channels: int = 0) -> SdnetDesc:
+    return SdnetDesc(width, 4, 128, activation, embed_channels)
+
+
+def desc_of(params: torch.Tensor) -> SdnetDesc:
+    return sdnet_desc(*net_of(params))
 
 
 def domain_desc(u: torch.Tensor, units) -> DomainDesc:
@@ -100,10 +118,10 @@ class Context:
             pass
 
 
-def _sweep_ws(ctx: Context, width: int, dom, prec: int, n_domains: int = 1, targets: int = MF_CROSS,
+def _sweep_ws(ctx: Context, params: torch.Tensor, dom, prec: int, n_domains: int = 1, targets: int = MF_CROSS,
               mode: int = MF_MULTIPLICATIVE) -> torch.Tensor:
     n = ctypes.c_size_t()
-    check(load().mf_workspace_size(ctypes.byref(sdnet_desc(width)), _dom_arg(dom), n_domains, prec,
+    check(load().mf_workspace_size(ctypes.byref(desc_of(params)), _dom_arg(dom), n_domains, prec,
                                    targets, mode, ctypes.byref(n)), "mf_workspace_size")
     return ctx.workspace(n.value)
 
@@ -164,8 +182,8 @@ def mf_sweep(ctx: Context, params: torch.Tensor, u, units=None, colour: int = -1
     _need_cuda_f32(params, "params")
     buf, dom, nd = _field_and_domains(u, units)
     width = width_of(params)
-    ws = _sweep_ws(ctx, width, dom, prec, nd, targets, mode)
-    check(load().mf_sweep(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+    ws = _sweep_ws(ctx, params, dom, prec, nd, targets, mode)
+    check(load().mf_sweep(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf),
                           _dom_arg(dom), nd, colour, targets, mode, prec, _ptr(ws), ws.numel(),
                           _stream()), "mf_sweep")
 
@@ -177,7 +195,7 @@ def mf_sweep_noalloc(ctx: Context, params: torch.Tensor, u, units=None, colour: 
     _need_cuda_f32(params, "params")
     buf, dom, nd = _field_and_domains(u, units)
     width = width_of(params)
-    check(load().mf_sweep_noalloc(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+    check(load().mf_sweep_noalloc(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf),
                                   _dom_arg(dom), nd, colour, targets, prec, _stream()),
           "mf_sweep_noalloc")
 
@@ -189,9 +207,9 @@ def mf_autotune(ctx: Context, params: torch.Tensor, u: torch.Tensor, units,
     _need_cuda_f32(params, "params")
     width = width_of(params)
     dom = domain_desc(u, units)
-    ws = _sweep_ws(ctx, width, dom, prec)
+    ws = _sweep_ws(ctx, params, dom, prec)
     rows = ctypes.c_int32(0)
-    check(load().mf_autotune(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(u),
+    check(load().mf_autotune(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(u),
                              ctypes.byref(dom), 1, targets, prec, trials, _ptr(ws), ws.numel(),
                              _stream(), ctypes.byref(rows)), "mf_autotune")
     return rows.value
@@ -215,10 +233,10 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
         elif u_out.numel() != buf.numel():
             raise ValueError("u_out must match the batch buffer")
     width = width_of(params)
-    ws = _sweep_ws(ctx, width, dom, prec, nd, targets, mode)
+    ws = _sweep_ws(ctx, params, dom, prec, nd, targets, mode)
     done = ctypes.c_int32(-1)
     last = ctypes.c_float(float("nan"))
-    check(load().mf_solve(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+    check(load().mf_solve(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf),
                           _dom_arg(dom), nd, targets, mode, prec, max_sweeps, eps, check_every,
                           flags, _ptr(u_out), ctypes.byref(done) if report else None,
                           ctypes.byref(last) if report else None, _ptr(ws), ws.numel(),
@@ -247,10 +265,10 @@ def mf_solve_adjoint(ctx: Context, params: torch.Tensor, u0, units, K: int, ckpt
         J = torch.zeros(1, dtype=torch.float32, device=buf.device)
     n = ctypes.c_size_t()
     lib = load()
-    check(lib.mf_adjoint_ws_size(ctypes.byref(sdnet_desc(width)), _dom_arg(dom), nd, targets, K,
+    check(lib.mf_adjoint_ws_size(ctypes.byref(desc_of(params)), _dom_arg(dom), nd, targets, K,
                                  ckpt_every, ctypes.byref(n)), "mf_adjoint_ws_size")
     ws = ctx.workspace(n.value)
-    check(lib.mf_solve_adjoint(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(buf),
+    check(lib.mf_solve_adjoint(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf),
                                _dom_arg(dom), nd, targets, K, ckpt_every, _ptr(uout_bar), _ptr(u_out),
                                _ptr(J), _ptr(u0_bar), _ptr(ws), ws.numel(), _stream()),
           "mf_solve_adjoint")
@@ -335,11 +353,11 @@ def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.
     lapU = torch.empty(n_bc, n_pts, device=G.device, dtype=torch.float32) if derivatives else None
     n = ctypes.c_size_t()
     lib = load()
-    check(lib.sdnet_forward_ws_size(ctypes.byref(sdnet_desc(width)), n_bc, n_pts,
+    check(lib.sdnet_forward_ws_size(ctypes.byref(desc_of(params)), n_bc, n_pts,
                                     1 if derivatives else 0, prec, ctypes.byref(n)),
           "sdnet_forward_ws_size")
     ws = ctx.workspace(n.value)
-    check(lib.sdnet_forward(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G), n_bc,
+    check(lib.sdnet_forward(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(G), n_bc,
                             _ptr(X), n_pts, x_per_bc, _ptr(U), _ptr(dU), _ptr(lapU), prec, _ptr(ws),
                             ws.numel(), _stream()), "sdnet_forward")
     return (U, dU, lapU) if derivatives else U
@@ -362,9 +380,9 @@ def _data_args(G: torch.Tensor, Xd: torch.Tensor, Yd):
     return Xd.contiguous(), nd, per_bc, Yd
 
 
-def _train_ws(ctx: Context, width: int, B: int, nd: int, nc: int) -> torch.Tensor:
+def _train_ws(ctx: Context, params: torch.Tensor, B: int, nd: int, nc: int) -> torch.Tensor:
     n = ctypes.c_size_t()
-    check(load().sdnet_train_ws_size(ctypes.byref(sdnet_desc(width)), B, nd, nc, ctypes.byref(n)),
+    check(load().sdnet_train_ws_size(ctypes.byref(desc_of(params)), B, nd, nc, ctypes.byref(n)),
           "sdnet_train_ws_size")
     return ctx.workspace(n.value)
 
@@ -385,9 +403,9 @@ def sdnet_train_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: tor
     Xd, nd, per_bc, Yd = _data_args(G, Xd, Yd)
     if loss is None:
         loss = torch.empty(3, device=G.device, dtype=torch.float32)
-    ws = _train_ws(ctx, width, B, nd, nc)
+    ws = _train_ws(ctx, params, B, nd, nc)
     hp = Adam(lr, beta1, beta2, eps)
-    check(load().sdnet_train_step(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(m),
+    check(load().sdnet_train_step(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(m),
                                   _ptr(v), step, ctypes.byref(hp), _ptr(G.contiguous()), B, _ptr(Xd), nd,
                                   per_bc, _ptr(Yd), _ptr(Xc.contiguous()), nc, _ptr(loss),
                                   _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
@@ -412,8 +430,8 @@ def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xd: tor
     if grad_out is None:
         grad_out = torch.empty_like(params)
     _need_cuda_f32(grad_out, "grad_out")
-    ws = _train_ws(ctx, width, B, nd, nc)
-    check(load().sdnet_loss_grad(ctx.ptr, ctypes.byref(sdnet_desc(width)), _ptr(params), _ptr(G.contiguous()), B,
+    ws = _train_ws(ctx, params, B, nd, nc)
+    check(load().sdnet_loss_grad(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(G.contiguous()), B,
                                  _ptr(Xd), nd, per_bc, _ptr(Yd), _ptr(Xc.contiguous()), nc, _ptr(loss),
                                  _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
           "sdnet_loss_grad")

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmosaic.so")
-SOURCES = ["mf_api.hip", "sweep_kernels.hip", "train_kernels.hip", "adjoint_kernels.hip", "io_kernels.hip"]
+SOURCES = ["mf_api.hip", "sweep_kernels.hip", "train_kernels.hip", "adjoint_kernels.hip", "io_kernels.hip",
+           "embed_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -32,14 +32,14 @@ static mf_status ok() {
   return MF_OK;
 }
 
-NetLayout net_layout(int width, int prec, size_t base) {
+NetLayout net_layout(int width, int prec, size_t base, int n_in) {
   NetLayout L;
   L.width = width;
   L.prec = prec;
   const size_t d = (size_t)width;
   size_t o = align256(base);
-  L.w1gT = o; o = align256(o + 128 * d * 4);
-  L.w1gb = o; if (prec == MF_BF16) o = align256(o + 128 * d * 2);
+  L.w1gT = o; o = align256(o + (size_t)n_in * d * 4);
+  L.w1gb = o; if (prec == MF_BF16 && n_in == 128) o = align256(o + 128 * d * 2);
   L.w1x = o;  o = align256(o + 2 * d * 4);
   L.b1 = o;   o = align256(o + d * 4);
   L.wh = o;   o = align256(o + 3 * d * d * (prec == MF_FP32 ? 4 : 2));
@@ -64,9 +64,9 @@ NetPtrs net_ptrs(const NetLayout& L, const void* ws) {
   return p;
 }
 
-SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode) {
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode, int embed_c) {
   SweepLayout S;
-  S.net = net_layout(width, prec, 0);
+  S.net = net_layout(width, prec, 0, embed_c ? embed_c * 128 : 128);
   size_t o = S.net.end;
   int64_t n_skel = 0;
   for (int d = 0; d < n_domains; ++d) n_skel += skeleton_count(dom[d].units_x, dom[d].units_y);
@@ -81,6 +81,11 @@ SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_d
                                        32LL * dom[d].units_x + 1);
   S.anext = o;   // the additive mode's next field; the multiplicative mode needs none
   if (mode == MF_ADDITIVE) o = align256(o + (size_t)span * 4);
+  if (embed_c) {   // the GELU network's phase chunks: projections, target coordinates, two row buffers
+    S.gC = o; o = align256(o + (size_t)(kGeluRows / 61) * width * 4);
+    S.gX = o; o = align256(o + (61 + 961) * 2 * 4);
+    for (int l = 0; l < 2; ++l) { S.gZ[l] = o; o = align256(o + (size_t)kGeluRows * width * 4); }
+  }
   S.total = o;
   return S;
 }
@@ -151,7 +156,32 @@ static mf_status check_desc(const mf_sdnet_desc* d) {
   if (d->depth != 4) return fail(MF_ESHAPE, "sdnet depth %d unsupported (4)", d->depth);
   if (d->n_boundary != 128)
     return fail(MF_ESHAPE, "n_boundary %d unsupported (128)", d->n_boundary);
-  if (d->activation != MF_TANH) return fail(MF_EINVAL, "activation %d unknown", d->activation);
+  if (d->activation == MF_TANH) {
+    if (d->embed_channels != 0)
+      return fail(MF_ESHAPE, "the tanh network has no boundary embedding (embed_channels %d, must be 0)",
+                  d->embed_channels);
+  } else if (d->activation == MF_GELU) {
+    if (d->embed_channels < 1 || d->embed_channels > 8)
+      return fail(MF_ESHAPE, "embed_channels %d not in 1..8 for the GELU network", d->embed_channels);
+  } else {
+    return fail(MF_EINVAL, "activation %d unknown", d->activation);
+  }
+  return MF_OK;
+}
+
+static bool is_gelu(const mf_sdnet_desc* d) { return d->activation == MF_GELU; }
+
+// The entry points built for the tanh network only.
+static mf_status need_tanh(const mf_sdnet_desc* d, const char* what) {
+  if (is_gelu(d)) return fail(MF_EUNSUPPORTED, "%s is built for the tanh network only", what);
+  return MF_OK;
+}
+
+// The GELU network runs in float32, multiplicative sweeps.
+static mf_status gelu_limits(const mf_sdnet_desc* d, int prec, int mode) {
+  if (!is_gelu(d)) return MF_OK;
+  if (prec != MF_FP32) return fail(MF_EUNSUPPORTED, "the GELU network runs in MF_FP32 only");
+  if (mode != MF_MULTIPLICATIVE) return fail(MF_EUNSUPPORTED, "the GELU network runs multiplicative sweeps only");
   return MF_OK;
 }
 
@@ -326,6 +356,10 @@ int32_t mf_fault_inject_parse(const char* spec, int32_t* sweep, int32_t* colour)
 int64_t mf_param_count(const mf_sdnet_desc* desc) {
   if (check_desc(desc) != MF_OK) return -1;
   const int64_t d = desc->width;
+  if (is_gelu(desc)) {
+    const int64_t C = desc->embed_channels;
+    return embed_param_offset((int)C) + d * (C * desc->n_boundary + 2) + d + 3 * (d * d + d) + d + 1;
+  }
   return d * (desc->n_boundary + 2) + d + 3 * (d * d + d) + d + 1;
 }
 
@@ -425,7 +459,8 @@ mf_status mf_workspace_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom
   MF_TRY(check_domain(dom, n_domains));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
-  *bytes = sweep_layout(desc->width, prec, dom, n_domains, mode).total;
+  MF_TRY(gelu_limits(desc, prec, mode));
+  *bytes = sweep_layout(desc->width, prec, dom, n_domains, mode, desc->embed_channels).total;
   return ok();
 }
 
@@ -440,7 +475,8 @@ static mf_status sweep_common_checks(const mf_sdnet_desc* desc, const float* par
   MF_TRY(check_ptr(u, "u"));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (mode != MF_MULTIPLICATIVE && mode != MF_ADDITIVE) return fail(MF_EINVAL, "mode %d unknown", mode);
-  *L = sweep_layout(desc->width, prec, dom, n_domains, mode);
+  MF_TRY(gelu_limits(desc, prec, mode));
+  *L = sweep_layout(desc->width, prec, dom, n_domains, mode, desc->embed_channels);
   MF_TRY(check_ws(ws, ws_bytes, L->total));
   return MF_OK;
 }
@@ -488,6 +524,12 @@ struct Plan {
   int64_t n_tiles[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   int64_t rows[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   uint64_t key = 0;                               // identifies the domain list
+  // the GELU network (activation MF_GELU): unfused phases in row chunks
+  int embed_c = 0;                                // embedding channels; 0 = the tanh tile kernels
+  const float* params = nullptr;                  // caller's flat parameters (convolutions)
+  float* gC = nullptr;                            // [chunk placements][d] projections
+  float* gX[2] = {nullptr, nullptr};              // target coordinates: CROSS, INTERIOR
+  float* gZ[2] = {nullptr, nullptr};              // [kGeluRows][d] value rows
 };
 
 static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, const mf_domain_desc* dom,
@@ -525,6 +567,16 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
   P->targets = targets;
   P->net = net_ptrs(L.net, ws);
   P->ws = ws;
+  P->embed_c = desc->embed_channels;
+  if (P->embed_c) {
+    char* b = static_cast<char*>(ws);
+    P->gC = reinterpret_cast<float*>(b + L.gC);
+    P->gX[0] = reinterpret_cast<float*>(b + L.gX);
+    P->gX[1] = P->gX[0] + 61 * 2;
+    P->gZ[0] = reinterpret_cast<float*>(b + L.gZ[0]);
+    P->gZ[1] = reinterpret_cast<float*>(b + L.gZ[1]);
+    MF_HIP(launch_target_coords(P->gX[0], P->gX[1], s));
+  }
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 4; ++c)
       for (int d = 0; d < nd; ++d) P->rows[a][c] += phase_rows(&dom[d], c, a ? MF_INTERIOR : targets);
@@ -568,6 +620,34 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
 //   PH_ADDITIVE  predictions at the plan's targets / cover count accumulated into out.
 // Sweep and additive phases are timed when the context's timing is on.
 enum { PH_SWEEP = 0, PH_ASSEMBLY = 1, PH_ADDITIVE = 2 };
+// A colour phase of the GELU network, domain by domain, in chunks of at most
+// kGeluRows rows: embedding + projection per placement (gathered from the
+// field), the value stream through the four GELU layers, and the output
+// layer storing at the targets (sweep) or averaging into out (assembly).
+// Chunks of one colour may run in any order: same-colour placements never
+// read each other's targets.
+static mf_status run_colour_gelu(const Plan& P, int colour, int kind, float* out, hipStream_t s) {
+  const int tg = kind == PH_ASSEMBLY ? MF_INTERIOR : P.targets;
+  const int T = tg == MF_INTERIOR ? 961 : 61;
+  const int chunk = (int)(kGeluRows / T);
+  float* Z[4] = {P.gZ[0], P.gZ[1], P.gZ[0], P.gZ[1]};
+  for (int d = 0; d < P.nd; ++d) {
+    const mf_domain_desc& D = P.dom[d];
+    const int n_q = (D.units_x - (colour & 1)) * (D.units_y - (colour >> 1));
+    const float* u = P.u + D.field_offset;
+    float* dst = (kind == PH_SWEEP ? P.u : out) + D.field_offset;
+    for (int q0 = 0; q0 < n_q; q0 += chunk) {
+      const int nq = std::min(chunk, n_q - q0);
+      MF_HIP(launch_embed_project(P.params, P.width, P.embed_c, P.net, nullptr, nq, u, D.pitch, D.units_x, colour,
+                                  q0, P.gC, s));
+      MF_HIP(launch_value_forward_act(P.net, P.width, ACT_GELU, P.gC, P.gX[tg], 0, T, (int64_t)nq * T, Z, s));
+      MF_HIP(launch_rows_output(P.net, P.width, tg, Z[3], (int64_t)nq * T, kind == PH_SWEEP ? 1 : 2, dst, D.pitch,
+                                D.units_x, D.units_y, colour, q0, s));
+    }
+  }
+  return MF_OK;
+}
+
 static mf_status run_colour(mf_ctx* ctx, const Plan& P, int colour, int kind, float* out, hipStream_t s,
                             bool allow_timing = true) {
   const int a = kind == PH_ASSEMBLY ? 1 : 0;
@@ -578,7 +658,9 @@ static mf_status run_colour(mf_ctx* ctx, const Plan& P, int colour, int kind, fl
   const bool timed = allow_timing && ctx->timing && kind != PH_ASSEMBLY;
   if (timed) MF_TRY(timing_begin(ctx, s));
   float* dst = acc ? out : P.u;
-  if (P.nd == 1) {
+  if (P.embed_c) {
+    MF_TRY(run_colour_gelu(P, colour, kind, out, s));
+  } else if (P.nd == 1) {
     const mf_domain_desc* dom = P.dom;
     PhaseArgs p{P.u + dom->field_offset, dst + dom->field_offset, dom->pitch, dom->units_x,
                 dom->units_y, colour};
@@ -676,6 +758,13 @@ static mf_status run_sweeps_graph(mf_ctx* ctx, const Plan& P, int max_sweeps, hi
   return MF_OK;
 }
 
+// Prepared network of either architecture into the layout L.
+static hipError_t prepare_net(const mf_sdnet_desc* desc, const float* params, int prec, const NetLayout& L, void* ws,
+                              hipStream_t s) {
+  if (is_gelu(desc)) return launch_prepare_net_embed(params, desc->width, desc->embed_channels, L, ws, s);
+  return launch_prepare_net(params, desc->width, prec, L, ws, s);
+}
+
 mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
                    const mf_domain_desc* dom, int32_t n_domains, int32_t colour, int32_t targets,
                    int32_t mode, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
@@ -687,9 +776,10 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
+  MF_HIP(prepare_net(desc, params, prec, L.net, ws, s));
   Plan P;
   MF_TRY(make_plan(ctx, desc, prec, targets, mode, u, dom, n_domains, ws, L, s, &P));
+  P.params = params;
   if (colour < 0) {
     MF_TRY(run_sweep(ctx, P, s));
   } else {
@@ -702,6 +792,7 @@ mf_status mf_sweep_noalloc(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
                            const mf_domain_desc* dom, int32_t n_domains, int32_t colour, int32_t targets,
                            int32_t prec, void* stream) {
   MF_TRY(check_desc(desc));
+  MF_TRY(need_tanh(desc, "mf_sweep_noalloc"));
   MF_TRY(check_prec(prec));
   MF_TRY(check_domain(dom, n_domains));
   MF_TRY(check_ptr(params, "params"));
@@ -736,6 +827,7 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   SweepLayout L;
   MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, MF_MULTIPLICATIVE, prec, ws,
                              ws_bytes, &L));
+  MF_TRY(need_tanh(desc, "mf_autotune (tile shapes of the tanh kernels)"));
   if (n_domains != 1) return fail(MF_EUNSUPPORTED, "autotune takes one domain");
   if (trials < 1 || trials > 1000) return fail(MF_EINVAL, "trials %d not in 1..1000", trials);
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
@@ -862,15 +954,16 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
+  MF_HIP(prepare_net(desc, params, prec, L.net, ws, s));
   Plan P;
   MF_TRY(make_plan(ctx, desc, prec, targets, mode, u, dom, n_domains, ws, L, s, &P));
+  P.params = params;
 
   int done = 0;
   float last = NAN;
   bool converged = false;
   const bool inject = ctx->fault_sweep > 0 && mode == MF_MULTIPLICATIVE;
-  if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0 && !inject) {
+  if (eps == 0.0f && ctx->use_graphs && max_sweeps > 0 && !inject && !P.embed_c) {
     MF_TRY(run_sweeps_graph(ctx, P, max_sweeps, s));
     done = max_sweeps;
   }
@@ -1060,6 +1153,7 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
 static mf_status adjoint_checks(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int targets,
                                 int K, int ckpt_every) {
   MF_TRY(check_desc(desc));
+  MF_TRY(need_tanh(desc, "mf_solve_adjoint"));
   MF_TRY(check_domain(dom, nd));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (K < 0) return fail(MF_EINVAL, "K %d < 0", K);
@@ -1187,14 +1281,17 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
 // ---------------------------------------------------------------------------
 // Workspace of sdnet_forward: prepared network, projections C [n_bc][d] and,
 // for derivative outputs, two stream-row buffers [4 n_bc n_pts][d].
-static size_t forward_ws(int width, int prec, int64_t n_bc, int64_t n_pts, bool derivs,
+// The GELU network always runs the row kernels: two value-row buffers
+// [n_bc n_pts][d] without derivatives.
+static size_t forward_ws(int width, int prec, int64_t n_bc, int64_t n_pts, bool derivs, int embed_c,
                          NetLayout* Lout, size_t* c_off, size_t* z_off) {
-  NetLayout L = net_layout(width, prec, 0);
+  NetLayout L = net_layout(width, prec, 0, embed_c ? embed_c * 128 : 128);
   size_t o = L.end;
   *c_off = o;
   o = align256(o + (size_t)n_bc * width * 4);
   *z_off = o;
   if (derivs) o = align256(o + 2 * (size_t)4 * n_bc * n_pts * width * 4);
+  else if (embed_c) o = align256(o + 2 * (size_t)n_bc * n_pts * width * 4);
   if (Lout) *Lout = L;
   return o;
 }
@@ -1206,8 +1303,10 @@ mf_status sdnet_forward_ws_size(const mf_sdnet_desc* desc, int64_t n_bc, int64_t
   MF_TRY(check_desc(desc));
   MF_TRY(check_prec(prec));
   if (n_bc < 0 || n_pts < 0) return fail(MF_ESHAPE, "n_bc and n_pts must be >= 0");
+  MF_TRY(gelu_limits(desc, prec, MF_MULTIPLICATIVE));
   size_t c_off, z_off;
-  *bytes = forward_ws(desc->width, prec, n_bc, n_pts, derivatives != 0, nullptr, &c_off, &z_off);
+  *bytes = forward_ws(desc->width, prec, n_bc, n_pts, derivatives != 0, desc->embed_channels, nullptr, &c_off,
+                      &z_off);
   return ok();
 }
 
@@ -1221,6 +1320,7 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
   if (n_bc * n_pts > (1LL << 40)) return fail(MF_ESHAPE, "too many rows");
   const bool derivs = dU || lapU;
   if (derivs && prec != MF_FP32) return fail(MF_EUNSUPPORTED, "derivative outputs need MF_FP32");
+  MF_TRY(gelu_limits(desc, prec, MF_MULTIPLICATIVE));
   if (n_bc == 0 || n_pts == 0) return ctx ? ok() : fail(MF_EINVAL, "ctx is NULL");
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(G, "G"));
@@ -1230,21 +1330,31 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
   if (lapU) MF_TRY(check_ptr(lapU, "lapU"));
   NetLayout L;
   size_t c_off, z_off;
-  const size_t need = forward_ws(desc->width, prec, n_bc, n_pts, derivs, &L, &c_off, &z_off);
+  const size_t need = forward_ws(desc->width, prec, n_bc, n_pts, derivs, desc->embed_channels, &L, &c_off, &z_off);
   MF_TRY(check_ws(ws, ws_bytes, need));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  MF_HIP(launch_prepare_net(params, desc->width, prec, L, ws, s));
+  MF_HIP(prepare_net(desc, params, prec, L, ws, s));
   const NetPtrs net = net_ptrs(L, ws);
   float* C = reinterpret_cast<float*>(static_cast<char*>(ws) + c_off);
-  MF_HIP(launch_projection(net, desc->width, G, n_bc, C, s));
-  if (!derivs) {
-    MF_HIP(launch_forward_rows(net, desc->width, prec, C, X, n_bc, n_pts, x_per_bc, U, s));
-  } else {
-    float* Z0 = reinterpret_cast<float*>(static_cast<char*>(ws) + z_off);
+  const bool gelu = is_gelu(desc);
+  if (gelu)
+    MF_HIP(launch_embed_project(params, desc->width, desc->embed_channels, net, G, n_bc, nullptr, 0, 0, 0, 0, C, s));
+  else
+    MF_HIP(launch_projection(net, desc->width, G, n_bc, C, s));
+  float* Z0 = reinterpret_cast<float*>(static_cast<char*>(ws) + z_off);
+  if (derivs) {
     float* Z1 = Z0 + (size_t)4 * n_bc * n_pts * desc->width;
-    MF_HIP(launch_forward_derivs(net, desc->width, C, X, x_per_bc, n_bc, n_pts, Z0, Z1, U, dU, lapU, s));
+    MF_HIP(launch_forward_derivs(net, desc->width, gelu ? ACT_GELU : ACT_TANH, C, X, x_per_bc, n_bc, n_pts, Z0, Z1,
+                                 U, dU, lapU, s));
+  } else if (gelu) {
+    float* Z1 = Z0 + (size_t)n_bc * n_pts * desc->width;
+    float* Z[4] = {Z0, Z1, Z0, Z1};
+    MF_HIP(launch_value_forward_act(net, desc->width, ACT_GELU, C, X, x_per_bc, n_pts, n_bc * n_pts, Z, s));
+    MF_HIP(launch_rows_output(net, desc->width, MF_CROSS, Z1, n_bc * n_pts, 0, U, 0, 0, 0, 0, 0, s));
+  } else {
+    MF_HIP(launch_forward_rows(net, desc->width, prec, C, X, n_bc, n_pts, x_per_bc, U, s));
   }
   return ok();
 }
@@ -1260,6 +1370,7 @@ mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nd, 
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
+  MF_TRY(need_tanh(desc, "sdnet training"));
   MF_TRY(train_sizes(B, nd, nc));
   *bytes = train_layout(desc->width, B, nd, nc).total;
   return ok();
@@ -1270,6 +1381,7 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
                            int64_t nd, int32_t xd_per_bc, const float* Yd, const float* Xc, int64_t nc,
                            float* loss_dev, float* grad_out, void* ws, size_t ws_bytes, void* stream) {
   MF_TRY(check_desc(desc));
+  MF_TRY(need_tanh(desc, "sdnet_train_step"));
   MF_TRY(train_sizes(B, nd, nc));
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(G, "G"));

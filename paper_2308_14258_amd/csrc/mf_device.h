@@ -83,6 +83,23 @@ __device__ __forceinline__ float tanh_f32(float x) {
   return ax < 0.125f ? p : copysignf(r, x);
 }
 
+// GELU(a) = a Phi(a), Phi the standard normal distribution function
+// (Phi(a) = (1 + erf(a / sqrt 2)) / 2), with the first two derivatives
+// GELU'(a) = Phi(a) + a phi(a) and GELU''(a) = phi(a) (2 - a^2), phi the
+// standard normal density. erff is the device library's; the density uses
+// the hardware exp2.
+__device__ __forceinline__ float gelu_f32(float a) {
+  return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f));
+}
+__device__ __forceinline__ void gelu_rules(float a, float& z, float& d1, float& d2) {
+  const float Phi = 0.5f * (1.0f + erff(a * 0.70710678118654752f));
+  // phi(a) = e^(-a^2/2) / sqrt(2 pi) = 2^(-a^2 log2(e) / 2) / sqrt(2 pi)
+  const float phi = 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * a * a);
+  z = a * Phi;
+  d1 = fmaf(a, phi, Phi);
+  d2 = phi * (2.0f - a * a);
+}
+
 // Cheaper tanh for activations that are rounded to bf16 next:
 // tanh x = 1 - 2 / (1 + exp(2x)); absolute error a few float32 ulps of 1.
 __device__ __forceinline__ float tanh_fast(float x) {

@@ -14,6 +14,10 @@ mf_status fail(mf_status s, const char* fmt, ...);
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Hidden-layer activation of the row kernels: tanh, or GELU (the
+// convolutional-embedding network).
+enum { ACT_TANH = 0, ACT_GELU = 1 };
+
 // Prepared network parameters inside a workspace (offsets in bytes).
 struct NetLayout {
   int width = 0, prec = 0;
@@ -27,7 +31,7 @@ struct NetLayout {
   size_t b5 = 0;     // float [2]: b5, b5 + sum(w5)
   size_t end = 0;
 };
-NetLayout net_layout(int width, int prec, size_t base);
+NetLayout net_layout(int width, int prec, size_t base, int n_in = 128);
 
 // Device pointers into a prepared network.
 struct NetPtrs {
@@ -50,14 +54,22 @@ struct SweepLayout {
   size_t dres = 0;     // float [n_domains][2]
   size_t table = 0;    // batched domains: DomEntry [n] + int32 tile prefixes [2][4][n + 1]
   size_t anext = 0;    // additive sweeps: the next field, laid out like the caller's buffer
+  size_t gC = 0, gX = 0, gZ[2] = {0, 0};   // the GELU network's phase chunks (see kGeluRows)
   size_t total = 0;
 };
+// Rows (placement, target) per chunk of a GELU-network colour phase.
+constexpr int64_t kGeluRows = 65536;
 constexpr int kDeltaBlocks = 512;
 int64_t skeleton_count(int ux, int uy);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_prepare_net(const float* params, int width, int prec, const NetLayout& L,
                               void* ws, hipStream_t s);
+// The hidden layers, W1x, b1, w5 and b5 of the convolutional-embedding GELU
+// network (its W1 has 128 C + 2 columns and follows the convolutions), plus
+// its transposed embedding block into w1gT.
+hipError_t launch_prepare_net_embed(const float* params, int width, int C, const NetLayout& L, void* ws,
+                                    hipStream_t s);
 
 struct PhaseArgs {
   const float* u_in;
@@ -88,7 +100,7 @@ struct DomEntry {
   int64_t pitch;    // row pitch in floats
   int32_t ux, uy;   // units
 };
-SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode);
+SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode, int embed_c = 0);
 hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
                               int tile_rows, const float* field_in, float* field_out,
                               const DomEntry* doms, const int32_t* tile_begin, int n_domains,
@@ -133,9 +145,22 @@ hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, co
                              hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
                        double b2, double eps, int64_t step, hipStream_t s);
-hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
+hipError_t launch_forward_derivs(const NetPtrs& net, int width, int act, const float* C, const float* X,
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s);
+hipError_t launch_value_forward_act(const NetPtrs& net, int width, int act, const float* C, const float* X,
+                                    int x_per_bc, int64_t rows_per_bc, int64_t n_rows, float* const Z[4],
+                                    hipStream_t s);
+// embed_kernels.hip: the convolutional-embedding GELU network (activation
+// MF_GELU). Its prepared network uses NetLayout with n_in = 128 C: w1gT holds
+// the transposed embedding block of W1 ([128 C][d]).
+int64_t embed_param_offset(int C);
+hipError_t launch_prepare_w1eT(const float* params, int width, int C, float* w1eT, hipStream_t s);
+hipError_t launch_embed_project(const float* params, int width, int C, const NetPtrs& net, const float* G,
+                                int64_t n_bc, const float* u, int64_t pitch, int ux, int colour, int q0,
+                                float* Cout, hipStream_t s);
+hipError_t launch_rows_output(const NetPtrs& net, int width, int targets, const float* Z, int64_t n_rows, int mode,
+                              float* out, int64_t pitch, int ux, int uy, int colour, int q0, hipStream_t s);
 
 // Adjoint of the sweep: device buffers carved from the workspace.
 struct AdjointBuffers {

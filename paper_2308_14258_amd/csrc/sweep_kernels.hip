@@ -33,12 +33,16 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 //         W[32 cb + (l & 31)][16 kg + 8 (l >> 5) + e]
 // so that one wave's B operand for one k-group is 1 KiB of contiguous memory.
 // ---------------------------------------------------------------------------
-__global__ void prepare_net_kernel(const float* __restrict__ params, int d, int prec,
+// n_in: columns of W1 before the (x, y) columns: 128 boundary values, or the
+// 128 C values of a convolutional embedding (then params points at W1, past
+// the convolutions, and w1gT is filled by prepare_w1eT_kernel instead).
+__global__ void prepare_net_kernel(const float* __restrict__ params, int d, int prec, int n_in,
                                    float* __restrict__ w1gT, uint16_t* __restrict__ w1gb, float* __restrict__ w1x,
                                    float* __restrict__ b1, void* __restrict__ wh,
                                    float* __restrict__ bh, float* __restrict__ w5,
                                    float* __restrict__ b5) {
-  const int64_t off_b1 = (int64_t)d * 130;
+  const int64_t ld1 = n_in + 2;   // row length of W1
+  const int64_t off_b1 = (int64_t)d * ld1;
   const int64_t off_w2 = off_b1 + d;
   const int64_t lstride = (int64_t)d * d + d;
   const int64_t off_w5 = off_w2 + 3 * lstride;
@@ -46,7 +50,7 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
 
-  for (int64_t idx = tid; idx < 128 * (int64_t)d; idx += nthr) {
+  for (int64_t idx = tid; n_in == 128 && idx < 128 * (int64_t)d; idx += nthr) {
     const int64_t k = idx / d, n = idx - k * d;
     w1gT[idx] = params[n * 130 + k];
     if (prec == MF_BF16) {
@@ -59,8 +63,8 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
     }
   }
   for (int64_t n = tid; n < d; n += nthr) {
-    w1x[2 * n] = params[n * 130 + 128];
-    w1x[2 * n + 1] = params[n * 130 + 129];
+    w1x[2 * n] = params[n * ld1 + n_in];
+    w1x[2 * n + 1] = params[n * ld1 + n_in + 1];
     b1[n] = params[off_b1 + n];
     w5[n] = params[off_w5 + n];
     for (int l = 0; l < 3; ++l) bh[l * d + n] = params[off_w2 + l * lstride + (int64_t)d * d + n];
@@ -100,13 +104,26 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
 hipError_t launch_prepare_net(const float* params, int width, int prec, const NetLayout& L,
                               void* ws, hipStream_t s) {
   char* base = static_cast<char*>(ws);
-  hipLaunchKernelGGL(prepare_net_kernel, dim3(256), dim3(256), 0, s, params, width, prec,
+  hipLaunchKernelGGL(prepare_net_kernel, dim3(256), dim3(256), 0, s, params, width, prec, 128,
                      reinterpret_cast<float*>(base + L.w1gT), reinterpret_cast<uint16_t*>(base + L.w1gb),
                      reinterpret_cast<float*>(base + L.w1x),
                      reinterpret_cast<float*>(base + L.b1), static_cast<void*>(base + L.wh),
                      reinterpret_cast<float*>(base + L.bh), reinterpret_cast<float*>(base + L.w5),
                      reinterpret_cast<float*>(base + L.b5));
   return hipGetLastError();
+}
+
+hipError_t launch_prepare_net_embed(const float* params, int width, int C, const NetLayout& L, void* ws,
+                                    hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  hipLaunchKernelGGL(prepare_net_kernel, dim3(256), dim3(256), 0, s, params + embed_param_offset(C), width,
+                     (int)MF_FP32, C * kNB, reinterpret_cast<float*>(base + L.w1gT), nullptr,
+                     reinterpret_cast<float*>(base + L.w1x), reinterpret_cast<float*>(base + L.b1),
+                     static_cast<void*>(base + L.wh), reinterpret_cast<float*>(base + L.bh),
+                     reinterpret_cast<float*>(base + L.w5), reinterpret_cast<float*>(base + L.b5));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_prepare_w1eT(params, width, C, reinterpret_cast<float*>(base + L.w1gT), s);
 }
 
 // ---------------------------------------------------------------------------

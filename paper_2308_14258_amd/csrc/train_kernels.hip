@@ -56,9 +56,10 @@ __global__ void prepare_wT_kernel(const float* __restrict__ params, int d, float
 
 // ---------------------------------------------------------------------------
 // First layer: a = C[b] + x W1x[:,0] + y W1x[:,1]; streams for S = 4 use
-// a_x = W1x[:,0], a_y = W1x[:,1], a_L = 0.
+// a_x = W1x[:,0], a_y = W1x[:,1], a_L = 0. ACT selects tanh or GELU (for
+// GELU: z_x = GELU'(a) a_x, z_L = GELU''(a) (a_x^2 + a_y^2)).
 // ---------------------------------------------------------------------------
-template <int D, int S>
+template <int D, int S, int ACT = ACT_TANH>
 __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict__ C,
                                                          const float* __restrict__ X, int x_per_bc,
                                                          int64_t rows_per_bc, int64_t n_rows,
@@ -73,6 +74,20 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
     const float* xp = x_per_bc ? X + 2 * r : X + 2 * (r - b * rows_per_bc);
     const float wx = w1x[2 * j], wy = w1x[2 * j + 1];
     const float a = fmaf(xp[1], wy, fmaf(xp[0], wx, C[b * D + j]));
+    if constexpr (ACT == ACT_GELU) {
+      float z, d1, d2;
+      gelu_rules(a, z, d1, d2);
+      if constexpr (S == 1) {
+        Z[r * D + j] = z;
+      } else {
+        const int64_t o = 4 * r * D + j;
+        Z[o] = z;
+        Z[o + D] = d1 * wx;
+        Z[o + 2 * D] = d1 * wy;
+        Z[o + 3 * D] = d2 * (wx * wx + wy * wy);
+      }
+      continue;
+    }
     const float z = tanh_f32(a);
     if constexpr (S == 1) {
       Z[r * D + j] = z;
@@ -99,7 +114,7 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
 // the tiles.
 // ---------------------------------------------------------------------------
 // Register budget for four workgroups per CU (the LDS tile allows four).
-template <int D, int S, int MODE>
+template <int D, int S, int MODE, int ACT = ACT_TANH>
 __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __restrict__ Ain,
                                                             const floatx4* __restrict__ wsw,
                                                             const float* __restrict__ bias,
@@ -108,6 +123,7 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
                                                             float* __restrict__ Sv_out,
                                                             int64_t n_srows, int skip_xy) {
   static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_*_kernel");
+  static_assert(MODE == 0 || ACT == ACT_TANH, "value backward: tanh only");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
   constexpr int PER = R * D / 4 / NTH;       // float4 of the input tile per thread
   __shared__ __align__(16) float Hs[R * LDH];
@@ -152,7 +168,23 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
       if constexpr (S == 4) {
         if (sr >= n_srows) continue;
         const int64_t o = sr * D + j;
-        if constexpr (MODE == 0) {
+        if constexpr (MODE == 0 && ACT == ACT_GELU) {
+          const float a = acc[rb][4 * m] + bj, ax = acc[rb][4 * m + 1];
+          const float ay = acc[rb][4 * m + 2], aL = acc[rb][4 * m + 3];
+          float z, d1, d2;
+          gelu_rules(a, z, d1, d2);
+          Out[o] = z;
+          if (!skip_xy) {
+            Out[o + D] = d1 * ax;
+            Out[o + 2 * D] = d1 * ay;
+          }
+          Out[o + 3 * D] = fmaf(d2, ax * ax + ay * ay, d1 * aL);
+          if (Sv_out) {
+            Sv_out[o + D] = ax;
+            Sv_out[o + 2 * D] = ay;
+            Sv_out[o + 3 * D] = aL;
+          }
+        } else if constexpr (MODE == 0) {
           const float a = acc[rb][4 * m] + bj, ax = acc[rb][4 * m + 1];
           const float ay = acc[rb][4 * m + 2], aL = acc[rb][4 * m + 3];
           const float z = tanh_f32(a), s = 1.0f - z * z;
@@ -175,7 +207,7 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
           if (row >= n_srows) continue;
           const int64_t o = row * D + j;
           if constexpr (MODE == 0) {
-            Out[o] = tanh_f32(acc[rb][4 * m + e] + bj);
+            Out[o] = ACT == ACT_GELU ? gelu_f32(acc[rb][4 * m + e] + bj) : tanh_f32(acc[rb][4 * m + e] + bj);
           } else {
             const float z = Sv_in[o];
             Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
@@ -782,16 +814,16 @@ static unsigned gemm_grid(int64_t n_tiles) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)4 * n_cu));
 }
 
-template <int D>
+template <int D, int ACT = ACT_TANH>
 static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const float* X, int x_per_bc,
                                      int64_t rows_per_bc, int64_t n_rows, int S, float* const Z[4],
                                      float* const Sv[4], bool skip_last_xy, hipStream_t s) {
   const int64_t n_srows = S * n_rows;
   if (S == 4)
-    hipLaunchKernelGGL((fwd_layer1_kernel<D, 4>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
+    hipLaunchKernelGGL((fwd_layer1_kernel<D, 4, ACT>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
                        X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
   else
-    hipLaunchKernelGGL((fwd_layer1_kernel<D, 1>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
+    hipLaunchKernelGGL((fwd_layer1_kernel<D, 1, ACT>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
                        X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -799,10 +831,10 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
   for (int l = 0; l < 3; ++l) {
     const floatx4* w = static_cast<const floatx4*>(net.wh) + (size_t)l * D * D / 4;
     if (S == 4)
-      hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 4, 0, ACT>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
                          net.bh + l * D, nullptr, Z[l + 1], Sv[l + 1], n_srows, (skip_last_xy && l == 2) ? 1 : 0);
     else
-      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 0>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 0, ACT>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
                          net.bh + l * D, nullptr, Z[l + 1], nullptr, n_srows, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -972,14 +1004,32 @@ hipError_t launch_value_backward(const float* whT, int width, float* const Z[4],
                       : value_backward_d<128>(whT, Z, Ab, n_rows, X, n_bc, T, csum, s);
 }
 
-hipError_t launch_forward_derivs(const NetPtrs& net, int width, const float* C, const float* X,
+// Value stream of either activation, rows_per_bc points per condition (X
+// shared [rows_per_bc][2] or per row [n_rows][2]); Z[l] receives layer
+// l+1's activations (buffers may alternate: layer l reads only Z[l - 1]).
+hipError_t launch_value_forward_act(const NetPtrs& net, int width, int act, const float* C, const float* X,
+                                    int x_per_bc, int64_t rows_per_bc, int64_t n_rows, float* const Z[4],
+                                    hipStream_t s) {
+  float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (act == ACT_GELU)
+    return width == 256 ? run_taylor_forward<256, ACT_GELU>(net, C, X, x_per_bc, rows_per_bc, n_rows, 1, Z, Sv, false, s)
+                        : run_taylor_forward<128, ACT_GELU>(net, C, X, x_per_bc, rows_per_bc, n_rows, 1, Z, Sv, false, s);
+  return width == 256 ? run_taylor_forward<256>(net, C, X, x_per_bc, rows_per_bc, n_rows, 1, Z, Sv, false, s)
+                      : run_taylor_forward<128>(net, C, X, x_per_bc, rows_per_bc, n_rows, 1, Z, Sv, false, s);
+}
+
+hipError_t launch_forward_derivs(const NetPtrs& net, int width, int act, const float* C, const float* X,
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s) {
   float* Z[4] = {Z0, Z1, Z0, Z1};
   float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
   const int64_t n_rows = n_bc * n_pts;
-  hipError_t e = width == 256
-                     ? run_taylor_forward<256>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s)
+  hipError_t e;
+  if (act == ACT_GELU)
+    e = width == 256 ? run_taylor_forward<256, ACT_GELU>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s)
+                     : run_taylor_forward<128, ACT_GELU>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s);
+  else
+    e = width == 256 ? run_taylor_forward<256>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s)
                      : run_taylor_forward<128>(net, C, X, x_per_bc, n_pts, n_rows, 4, Z, Sv, false, s);
   if (e != hipSuccess) return e;
   const int blocks = grid_for(n_rows, 4, 4096);
