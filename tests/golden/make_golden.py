@@ -36,6 +36,11 @@ c4_cond.npz -- 64 x 64 units, the "fp64_perturbed" and "fp32" runs of the
 c5_k20.npz -- the 48-domain batch's smallest, median and largest domain at
     its stated 20 sweeps: sampled skeleton after 1, 5, 10, 15 and 20 sweeps
     and the assembly after 20 at sampled points, for the three runs above.
+mfp_global.npz -- ground truth for the trained network's accuracy: the global
+    5-point Dirichlet solution (the oracle's sparse direct solve) of a
+    4 x 4-unit domain with GP ring data (length 1, seed 31), whole, and of a
+    64 x 64-unit domain with GP ring data (length 2, seed 41) at 65536
+    sampled interior points (seed 557).
 c5_adjoint.npz -- the smallest domain of that batch: u0_bar after 20 sweeps
     and the assembly for J = sum of squared interior values, and for a
     random seed u_out_bar (default_rng(77) normals), both full fields.
@@ -364,7 +369,23 @@ def c5_adjoint():
     print(f"c5_adjoint: domain {d} ({ux}x{uy}) done in {time.time() - t0:.0f} s", flush=True)
 
 
-JOBS = {"c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one, "c5_one": c5_one, "c2_traj": c2_traj,
+def mfp_global():
+    from oracle import fd
+    t0 = time.time()
+    f4 = mi.gp_field(4, 4, 1.0, seed=31)
+    u4 = fd.global_solve(f4)
+    f64 = mi.gp_field(64, 64, 2.0, seed=41)
+    u64 = fd.global_solve(f64)
+    rng = np.random.default_rng(557)
+    jj = rng.integers(1, f64.shape[0] - 1, 65536)
+    ii = rng.integers(1, f64.shape[1] - 1, 65536)
+    np.savez_compressed(os.path.join(HERE, "mfp_global.npz"), u4=u4, field4_sha=_sha(f4),
+                        sample_j=jj.astype(np.int32), sample_i=ii.astype(np.int32), u64_sample=u64[jj, ii],
+                        field64_sha=_sha(f64))
+    print(f"mfp_global: done in {time.time() - t0:.0f} s", flush=True)
+
+
+JOBS = {"mfp_global": mfp_global, "c2": c2, "c3": c3, "c4": c4, "c4_one": c4_one, "c5_one": c5_one, "c2_traj": c2_traj,
         "c4_traj": c4_traj, "c4_cond": c4_cond, "c5_k20": c5_k20, "c5_adjoint": c5_adjoint}
 
 if __name__ == "__main__":
