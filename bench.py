@@ -20,6 +20,8 @@ cores on a bounded sample of the same workload.
 Beside the headline the line carries: errors along the trajectory against
 stored oracle values; the 16 x 16-unit workload; the 48-domain batch (BF16
 sweeps, parity at its 20 sweeps) and its adjoint; the training step; the
+paper's convolutional-embedding GELU network on the 64 x 64-unit domain; a
+trained network's accuracy against the global 5-point solve; the
 assembly timed on its own; the 2 x 2-unit workload in microseconds per
 sweep; one GPU's share of the 64 x 64-unit domain split eight ways; the
 standalone gather and scatter in GB/s on a field larger than the last-level
@@ -293,6 +295,100 @@ def c2_section(ctx, args):
     return res
 
 
+def gelu_section(ctx):
+    """The paper's SDNet architecture (Sec. 3.1): circular convolutional
+    boundary embedding (4 channels) + GELU layers, width 256, Xavier weights
+    (seed 0), on the 64 x 64-unit workload: 20 CROSS sweeps + assembly,
+    float32, three timed steps. Each colour phase is the per-placement
+    embedding and projection, then the row kernels (first layer, three
+    MFMA GEMMs with the GELU epilogue, output layer and scatter)."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import mf_solve
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    d, C, K = 256, 4, 20
+    field = torch.from_numpy(mi.workload_field("C4")).cuda()
+    params = torch.from_numpy(mi.xavier_conv_params(d, C, 0)).cuda()
+    u = field.clone()
+    u_out = torch.empty_like(u)
+
+    def step():
+        u.copy_(field)
+        mf_solve(ctx, params, u, (ux, uy), K, u_out=u_out)
+
+    dt, per, launches, phase_ms, phase_rows = _timed_steps(ctx, step, 3, 1)
+    evals = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    E = 128 * C
+    fpp = 6.0 * d * d + 6.0 * d + (2.0 * E * d + 10.0 * 128 * C * (1 + C)) / CROSS_T
+    ach = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
+    return {"workload": f"64x64 units, conv-embedding GELU SDNet (C={C}, width {d}), {K} CROSS sweeps + assembly, "
+                        "float32",
+            "point_evals_per_s": evals * 3 / dt, "ms_per_step": dt * 1e3 / 3,
+            "colour_phase": {"avg_us": phase_ms * 1e3 / max(launches, 1), "tflops": ach,
+                             "frac_of_fp32_mfma_peak": ach / PEAK_FP32_MFMA_TFLOPS,
+                             "flops_per_point_eval": fpp,
+                             "kernels": "embed_project + fwd_layer1<GELU> + 3 x taylor_gemm<GELU> + rows_output"}}
+
+
+def trained_section(ctx):
+    """A trained SDNet (weights/sdnet_laplace_d256.npz) and the predictor's
+    accuracy against the global 5-point solve (oracle values stored in
+    tests/golden/mfp_global.npz): the 4 x 4-unit problem after 100 sweeps,
+    and on the 64 x 64-unit problem the float32 sweep count and time to MAE
+    0.05 (checked every 100 sweeps) and the MAE after 2000 sweeps."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_BF16, MF_FP32, mf_solve
+    from paper_2308_14258_amd.sdnet_training import WEIGHTS_DIR, load_trained
+    params, width, cfg, hist = load_trained(os.path.join(WEIGHTS_DIR, "sdnet_laplace_d256.npz"))
+    p = torch.from_numpy(params).cuda()
+    gpath = os.path.join(GOLDEN, "mfp_global.npz")
+    if not os.path.exists(gpath):
+        return None
+    g = np.load(gpath)
+    res = {"network": f"width {width}, tanh, {cfg['epochs']} epochs on {cfg['n_bc']} GP conditions, "
+                      f"validation MSE {hist['val_mse'][-1]:.2e}"}
+    f4 = mi.gp_field(4, 4, 1.0, seed=31)
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+        u = torch.from_numpy(f4).cuda()
+        uo = torch.empty_like(u)
+        mf_solve(ctx, p, u, (4, 4), 100, prec=prec, u_out=uo)
+        torch.cuda.synchronize()
+        res.setdefault("fig1_4x4_units_100_sweeps_mae", {})[name] = float(
+            np.abs(uo.cpu().numpy().astype(np.float64) - g["u4"])[1:-1, 1:-1].mean())
+    f64 = mi.gp_field(64, 64, 2.0, seed=41)
+
+    def mae(uo):
+        return float(np.mean(np.abs(uo.cpu().numpy()[g["sample_j"], g["sample_i"]] - g["u64_sample"])))
+
+    t4 = {}
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+        u = torch.from_numpy(f64).cuda()
+        uo = torch.empty_like(u)
+        hit = None
+        curve = {}
+        for k in range(100, 2001, 100):
+            mf_solve(ctx, p, u, (64, 64), 100, prec=prec, u_out=uo)
+            torch.cuda.synchronize()
+            curve[k] = mae(uo)
+            if hit is None and curve[k] < 0.05:
+                hit = k
+        r = {"mae_by_sweeps": curve, "sweeps_to_mae_0.05": hit}
+        if hit is not None:
+            u = torch.from_numpy(f64).cuda()
+            mf_solve(ctx, p, u, (64, 64), 10, prec=prec)
+            u.copy_(torch.from_numpy(f64).cuda())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mf_solve(ctx, p, u, (64, 64), hit, prec=prec, u_out=uo)
+            torch.cuda.synchronize()
+            r["seconds_to_mae_0.05"] = time.perf_counter() - t0
+        t4[name] = r
+    res["table4_64x64_units"] = t4
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +488,10 @@ def main():
             print("# c5 done", file=sys.stderr, flush=True)
         if not args.no_train:
             out["train"] = train_measurement(ctx, args.train_steps)
+        out["gelu_conv_sdnet"] = gelu_section(ctx)
+        print("# gelu done", file=sys.stderr, flush=True)
+        out["trained"] = trained_section(ctx)
+        print("# trained done", file=sys.stderr, flush=True)
         params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
         out["assembly"] = assembly_measurement(ctx, params, torch.from_numpy(mi.workload_field("C4")).cuda(),
                                                (ux, uy))
