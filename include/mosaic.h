@@ -102,7 +102,8 @@ enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
 enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
 enum { MF_TANH = 0, MF_GELU = 1 };                  /* activation          */
 enum { MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1 };        /* mf_solve flags      */
-enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17, MF_TILE_ROWSPLIT = 1 << 18 }; /* tile-shape flags */
+enum { MF_TILE_WIDE = 1 << 16, MF_TILE_STREAM = 1 << 17, MF_TILE_ROWSPLIT = 1 << 18,
+       MF_TILE_PERSIST = 1 << 19 };                 /* tile-shape flags */
 
 typedef struct mf_sdnet_desc {
   int32_t width;           /* d: 128 or 256                                */
@@ -152,21 +153,29 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
  * MF_TILE_WIDE (each wave then owns 64 output columns instead of 32, halving
  * the LDS reads of the activations), and 256 | MF_TILE_ROWSPLIT selects the
  * row-split tile (each of 8 waves owns 32 rows and every unit; activations
- * stay in registers and the hidden weights stream through LDS). 0 restores
+ * stay in registers and the hidden weights stream through LDS); or-ed also
+ * with MF_TILE_PERSIST, a batch's row-split phase runs as a persistent grid
+ * (one workgroup per CU walking the tiles) instead of one tile per
+ * workgroup (single domains ignore the flag). 0 restores
  * the automatic choice: a tuned value from mf_autotune, else a rule on the
  * phase's rows per CU. MF_BF16: 256 | MF_TILE_ROWSPLIT from 256 rows per CU
  * up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
  * 64 | MF_TILE_STREAM for a single domain from 128 rows per CU up. */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
-/* Autotuner: for this network, domain, target set and precision, time
- * `trials` sweeps of every available tile shape with hipEvents on `stream`
- * (one warm-up sweep each, then three interleaved rounds, keeping each
- * shape's fastest round) and keep the fastest shape in the context for later
- * mf_sweep / mf_solve calls on the same configuration. The sweeps run on u
- * itself (it advances by (3 trials + 1) x candidates sweeps); pass a scratch
- * copy to keep the field. rows_out (host, nullable) receives the choice.
- * Synchronises the stream. */
+/* Autotuner: for this network, domain (or batch of n_domains domains), target
+ * set and precision, time `trials` sweeps of every available tile shape with
+ * hipEvents on `stream` (one warm-up sweep each, then three interleaved
+ * rounds, keeping each shape's fastest round) and keep the fastest shape in
+ * the context for later mf_sweep / mf_solve calls on the same configuration:
+ * a single domain is matched by its units, a batch by its list of domain
+ * descriptors. Candidates: MF_FP32 32, 64, 64 | MF_TILE_STREAM (batches: 32,
+ * 64); MF_BF16 64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE,
+ * 256 | MF_TILE_ROWSPLIT (batches also 256 | MF_TILE_ROWSPLIT |
+ * MF_TILE_PERSIST). The sweeps run on u itself (it advances by
+ * (3 trials + 1) x candidates sweeps); pass a scratch copy to keep the field.
+ * rows_out (host, nullable) receives the choice. The tanh network only
+ * (MF_EUNSUPPORTED for MF_GELU). Synchronises the stream. */
 mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
                       const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
                       int32_t trials, void* ws, size_t ws_bytes, void* stream, int32_t* rows_out);

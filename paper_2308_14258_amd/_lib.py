@@ -23,6 +23,7 @@ MF_GELU = 1
 MF_SOLVE_FAIL_IF_NOT_CONVERGED = 1
 MF_TILE_WIDE = 1 << 16
 MF_TILE_STREAM = 1 << 17
+MF_TILE_PERSIST = 1 << 19
 MF_TILE_ROWSPLIT = 1 << 18
 
 

@@ -200,17 +200,17 @@ def mf_sweep_noalloc(ctx: Context, params: torch.Tensor, u, units=None, colour: 
           "mf_sweep_noalloc")
 
 
-def mf_autotune(ctx: Context, params: torch.Tensor, u: torch.Tensor, units,
+def mf_autotune(ctx: Context, params: torch.Tensor, u, units=None,
                 targets: int = MF_CROSS, prec: int = MF_FP32, trials: int = 3) -> int:
-    """Time every tile height on u (which advances) and keep the fastest."""
-    _need_field(u, units)
+    """Time every tile shape on u (which advances; a 2-D field with units
+    (ux, uy), or a Batch) and keep the fastest for later calls on the same
+    domain (or domain list). Returns the chosen shape code."""
     _need_cuda_f32(params, "params")
-    width = width_of(params)
-    dom = domain_desc(u, units)
-    ws = _sweep_ws(ctx, params, dom, prec)
+    buf, dom, nd = _field_and_domains(u, units)
+    ws = _sweep_ws(ctx, params, dom, prec, nd, targets)
     rows = ctypes.c_int32(0)
-    check(load().mf_autotune(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(u),
-                             ctypes.byref(dom), 1, targets, prec, trials, _ptr(ws), ws.numel(),
+    check(load().mf_autotune(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf),
+                             _dom_arg(dom), nd, targets, prec, trials, _ptr(ws), ws.numel(),
                              _stream(), ctypes.byref(rows)), "mf_autotune")
     return rows.value
 

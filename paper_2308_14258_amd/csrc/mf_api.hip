@@ -188,7 +188,8 @@ static mf_status gelu_limits(const mf_sdnet_desc* d, int prec, int mode) {
 static bool valid_tile_rows(int prec, int rows) {
   if (prec == MF_FP32) return rows == 32 || rows == 64 || rows == (64 | MF_TILE_STREAM);
   if (rows & MF_TILE_STREAM) return false;
-  if (rows & MF_TILE_ROWSPLIT) return rows == (256 | MF_TILE_ROWSPLIT);
+  if (rows & MF_TILE_ROWSPLIT)
+    return rows == (256 | MF_TILE_ROWSPLIT) || rows == (256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST);
   const int r = rows & ~MF_TILE_WIDE;
   if (rows & MF_TILE_WIDE) return r == 128 || r == 256;
   return r == 64 || r == 128 || r == 256;
@@ -303,9 +304,11 @@ struct SweepGraph {
   hipGraphExec_t exec;
 };
 
-// Tile height chosen by mf_autotune for one phase configuration.
+// Tile height chosen by mf_autotune for one phase configuration: a single
+// domain (by its units) or a batch (by the hash of its descriptors).
 struct TuneEntry {
   int width, prec, targets, ux, uy, rows;
+  uint64_t key;   // batches: domain-list hash; single domains: 0
 };
 
 struct mf_ctx {
@@ -533,13 +536,12 @@ struct Plan {
 };
 
 static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, const mf_domain_desc* dom,
-                         int nd, int64_t rows) {
+                         int nd, int64_t rows, uint64_t key = 0) {
   if (ctx->force_rows[prec]) return ctx->force_rows[prec];
-  if (nd == 1)
-    for (const TuneEntry& t : ctx->tuned)
-      if (t.width == width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
-          t.uy == dom->units_y)
-        return t.rows;
+  for (const TuneEntry& t : ctx->tuned)
+    if (t.width == width && t.prec == prec && t.targets == targets &&
+        (nd == 1 ? (t.key == 0 && t.ux == dom->units_x && t.uy == dom->units_y) : t.key == key))
+      return t.rows;
   const int64_t n_cu = ctx->n_cu;
   // bf16: the row-split tile from one 256-row tile per CU up; below that the
   // 64-row column-split tile spreads the rows over more CUs
@@ -592,7 +594,7 @@ static mf_status make_plan(mf_ctx* ctx, const mf_sdnet_desc* desc, int prec, int
     he[d] = DomEntry{dom[d].field_offset, dom[d].pitch, dom[d].units_x, dom[d].units_y};
   for (int a = 0; a < 2; ++a) {
     const int tg = a ? MF_INTERIOR : targets;
-    P->R[a] = tile_rows_for(ctx, desc->width, prec, tg, dom, nd, P->rows[a][0]);
+    P->R[a] = tile_rows_for(ctx, desc->width, prec, tg, dom, nd, P->rows[a][0], h);
     for (int c = 0; c < 4; ++c) {
       int32_t* tb = htb + (a * 4 + c) * (nd + 1);
       int64_t acc = 0;
@@ -828,16 +830,20 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   MF_TRY(sweep_common_checks(desc, params, u, dom, n_domains, targets, MF_MULTIPLICATIVE, prec, ws,
                              ws_bytes, &L));
   MF_TRY(need_tanh(desc, "mf_autotune (tile shapes of the tanh kernels)"));
-  if (n_domains != 1) return fail(MF_EUNSUPPORTED, "autotune takes one domain");
   if (trials < 1 || trials > 1000) return fail(MF_EINVAL, "trials %d not in 1..1000", trials);
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
+  // Candidates. A batch runs the batched kernel, whose streamed-weight fp32
+  // form spills (not offered); its row-split tile comes in both launch forms
+  // (one tile per workgroup, or a persistent grid).
+  const bool batch = n_domains > 1;
   const int cands_fp32[] = {32, 64, 64 | MF_TILE_STREAM};
-  const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE, 256 | MF_TILE_ROWSPLIT};
+  const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE, 256 | MF_TILE_ROWSPLIT,
+                            256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
   const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
-  const int n_cands = prec == MF_FP32 ? 3 : 6;
+  const int n_cands = prec == MF_FP32 ? (batch ? 2 : 3) : (batch ? 7 : 6);
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;
@@ -847,22 +853,27 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   // every candidate: one warm-up sweep; then kTuneRounds rounds that time
   // `trials` sweeps of each candidate in turn, keeping each one's fastest
   // round (interleaving keeps clock ramps and neighbours' noise from
-  // favouring whichever shape happens to run first)
+  // favouring whichever shape happens to run first). A batch's plan uploads
+  // the tile table of its shape, so it is made again before each timing.
   constexpr int kTuneRounds = 3;
-  Plan plans[8];
+  Plan plan;
   float ms_best[8];
+  uint64_t key = 0;
   mf_status st = MF_OK;
   for (int ci = 0; ci < n_cands && st == MF_OK; ++ci) {
     ctx->force_rows[prec] = cands[ci];
-    st = make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, 1, ws, L, s, &plans[ci]);
-    if (st == MF_OK) st = run_sweep(ctx, plans[ci], s);   // warm-up
+    st = make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, n_domains, ws, L, s, &plan);
+    if (st == MF_OK) st = run_sweep(ctx, plan, s);   // warm-up
+    key = plan.key;
     ms_best[ci] = 0.0f;
   }
   for (int round = 0; round < kTuneRounds && st == MF_OK; ++round) {
     for (int ci = 0; ci < n_cands && st == MF_OK; ++ci) {
       ctx->force_rows[prec] = cands[ci];   // the single-domain launch reads the shape from the context
+      st = make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, n_domains, ws, L, s, &plan);
+      if (st != MF_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MF_EDEVICE, "event record failed"); break; }
-      for (int k = 0; k < trials && st == MF_OK; ++k) st = run_sweep(ctx, plans[ci], s);
+      for (int k = 0; k < trials && st == MF_OK; ++k) st = run_sweep(ctx, plan, s);
       if (st != MF_OK) break;
       float ms = 0.0f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -885,14 +896,15 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   ctx->force_rows[prec] = saved_force;
   ctx->timing = saved_timing;
   if (st != MF_OK) return st;
+  const int ux = batch ? 0 : dom->units_x, uy = batch ? 0 : dom->units_y;
+  const uint64_t k = batch ? key : 0;
   bool found = false;
   for (TuneEntry& t : ctx->tuned)
-    if (t.width == desc->width && t.prec == prec && t.targets == targets && t.ux == dom->units_x &&
-        t.uy == dom->units_y) {
+    if (t.width == desc->width && t.prec == prec && t.targets == targets && t.ux == ux && t.uy == uy && t.key == k) {
       t.rows = best;
       found = true;
     }
-  if (!found) ctx->tuned.push_back(TuneEntry{desc->width, prec, targets, dom->units_x, dom->units_y, best});
+  if (!found) ctx->tuned.push_back(TuneEntry{desc->width, prec, targets, ux, uy, best, k});
   for (SweepGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
   ctx->graphs.clear();
   if (rows_out) *rows_out = best;

@@ -901,13 +901,16 @@ struct MultiArgs {
   const int32_t* tile_begin; // [n_domains + 1] for this colour and target set
   int n_domains;
   int64_t n_tiles;
-  int64_t tile0;             // row-split tile: first tile of this launch (one tile per workgroup)
+  int64_t tile0;             // row-split tile: first tile of this launch
+  int64_t n_launch;          // row-split tile: tiles of this launch
 };
 
-// The row-split tile runs one tile per workgroup (its registers are full; a
-// loop-carried tile index made the persistent form spill); the other shapes
-// take tiles round-robin in a persistent grid.
-template <class S, int TMODE, int OUT>
+// The row-split tile runs one tile per workgroup by default (its registers
+// are full); with PERSIST a grid of one workgroup per CU walks the launch's
+// tiles, the network pointers made opaque per tile so that no tile-invariant
+// load is hoisted across tiles (which spilled). The other shapes always take
+// tiles round-robin in a persistent grid.
+template <class S, int TMODE, int OUT, bool PERSIST = false>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M) {
   constexpr int T = n_targets<TMODE>();
   const int ca = M.base.colour & 1, cb = M.base.colour >> 1;
@@ -919,6 +922,18 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     }
     const DomEntry e = M.doms[lo];
     TileArgs A = M.base;
+    if constexpr (PERSIST) {
+      int z = 0;
+      asm volatile("" : "+s"(z));
+      A.net.w1gT += z;
+      A.net.w1gb = static_cast<const u32x4*>(A.net.w1gb) + z;
+      A.net.w1x += z;
+      A.net.b1 += z;
+      A.net.bh += z;
+      A.net.w5 += z;
+      A.net.b5 += z;
+      A.net.wh = static_cast<const u32x4*>(A.net.wh) + z;
+    }
     A.u_in = M.field_in + e.offset;
     A.u_out = M.field_out + e.offset;
     A.pitch = e.pitch;
@@ -928,8 +943,14 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB>(A, (t - M.tile_begin[lo]) * S::R);
     else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
   };
-  if constexpr (S::RS) {
+  if constexpr (S::RS && !PERSIST) {
     run_tile(M.tile0 + blockIdx.x);
+  } else if constexpr (S::RS) {
+    const int64_t end = M.tile0 + M.n_launch;
+    for (int64_t t = M.tile0 + blockIdx.x; t < end; t += gridDim.x) {
+      run_tile(t);
+      __syncthreads();   // the next tile reuses the LDS
+    }
   } else {
     for (int64_t t = blockIdx.x; t < M.n_tiles; t += gridDim.x) {
       run_tile(t);
@@ -962,13 +983,28 @@ static hipError_t with_shape(int width, int prec, int code, F&& f) {
 }
 
 template <class S, int TMODE, int OUT>
-static hipError_t launch_multi(MultiArgs m, int n_cu, hipStream_t s) {
+static hipError_t launch_multi(MultiArgs m, int n_cu, bool persist, hipStream_t s) {
   if (m.n_tiles == 0) return hipSuccess;
   if constexpr (S::RS) {
     for (int64_t t0 = 0; t0 < m.n_tiles; t0 += kMaxTilesPerLaunch) {
       m.tile0 = t0;
       const int64_t n = std::min<int64_t>(m.n_tiles - t0, kMaxTilesPerLaunch);
-      hipLaunchKernelGGL((tile_kernel_multi<S, TMODE, OUT>), dim3((unsigned)n), dim3(S::NTH), 0, s, m);
+      m.n_launch = n;
+      if (persist) {
+        static int per_cu_p = 0;
+        if (per_cu_p == 0) {
+          int nb = 0;
+          if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tile_kernel_multi<S, TMODE, OUT, true>, S::NTH, 0) !=
+                  hipSuccess ||
+              nb < 1)
+            nb = 1;
+          per_cu_p = nb;
+        }
+        const int64_t grid = std::min<int64_t>(n, (int64_t)per_cu_p * n_cu);
+        hipLaunchKernelGGL((tile_kernel_multi<S, TMODE, OUT, true>), dim3((unsigned)grid), dim3(S::NTH), 0, s, m);
+      } else {
+        hipLaunchKernelGGL((tile_kernel_multi<S, TMODE, OUT>), dim3((unsigned)n), dim3(S::NTH), 0, s, m);
+      }
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -1001,11 +1037,14 @@ hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targe
   m.tile_begin = tile_begin;
   m.n_domains = n_domains;
   m.n_tiles = n_tiles;
+  const bool persist = (tile_rows & MF_TILE_PERSIST) != 0;
   return with_shape(width, prec, tile_rows, [&](auto sh) {
     typedef decltype(sh) S;
     if (accumulate)
-      return targets == MF_CROSS ? launch_multi<S, 0, OUT_ACCUM>(m, n_cu, s) : launch_multi<S, 1, OUT_ACCUM>(m, n_cu, s);
-    return targets == MF_CROSS ? launch_multi<S, 0, OUT_STORE>(m, n_cu, s) : launch_multi<S, 1, OUT_STORE>(m, n_cu, s);
+      return targets == MF_CROSS ? launch_multi<S, 0, OUT_ACCUM>(m, n_cu, persist, s)
+                                 : launch_multi<S, 1, OUT_ACCUM>(m, n_cu, persist, s);
+    return targets == MF_CROSS ? launch_multi<S, 0, OUT_STORE>(m, n_cu, persist, s)
+                               : launch_multi<S, 1, OUT_STORE>(m, n_cu, persist, s);
   });
 }
 

@@ -185,3 +185,32 @@ def test_full_batch_k20_sampled_domains(ctx, prec):
             assert e <= max(1e-5, COND_FACTOR * e32), (int(d), e, e32)
         elif e32 <= 1e-6:
             assert e <= 2e-2, (int(d), e, e32)
+
+
+def test_autotune_on_a_batch_and_the_persistent_row_split_form(ctx):
+    """mf_autotune takes a batch (candidates include the persistent
+    row-split launch); its choice is used by later solves of the same
+    domain list, and every bf16 batched form gives the same fields as the
+    one-tile-per-workgroup row-split form, bit for bit."""
+    print("case: batch autotune + persistent row-split", flush=True)
+    from paper_2308_14258_amd import MF_TILE_PERSIST, MF_TILE_ROWSPLIT, mf_autotune
+    sizes, fields = _fields(seed=13, n=6, lo=2, hi=9)
+    params = torch.from_numpy(mi.xavier_params(256, 0)).cuda()
+    rs = 256 | MF_TILE_ROWSPLIT
+    scratch = Batch(fields)
+    best = mf_autotune(ctx, params, scratch, None, MF_CROSS, MF_BF16, trials=2)
+    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), rs, rs | MF_TILE_PERSIST), best
+    print(f"batch autotune chose {best:#x}", flush=True)
+    outs = {}
+    for code in (rs, rs | MF_TILE_PERSIST, 0):   # 0: the tuned choice
+        ctx.tile_rows(MF_BF16, code)
+        b = Batch(fields)
+        o = torch.empty_like(b.buf)
+        mf_solve(ctx, params, b, None, 4, prec=MF_BF16, u_out=o)
+        torch.cuda.synchronize()
+        outs[code] = (b.buf.clone(), o)
+    ctx.tile_rows(MF_BF16, 0)
+    assert torch.equal(outs[rs][0], outs[rs | MF_TILE_PERSIST][0])
+    assert torch.equal(outs[rs][1], outs[rs | MF_TILE_PERSIST][1])
+    if best in (rs, rs | MF_TILE_PERSIST):
+        assert torch.equal(outs[0][0], outs[rs][0])
