@@ -658,10 +658,38 @@ def io_measurement(ctx):
             tot[key][0] += ms
             tot[key][1] += n * T * 8.0
             del pred
+    # the skeleton side layout: vertical edges and centre lines from the
+    # transposed skeleton columns, the field's rows padded to a multiple of
+    # 32 floats (128 bytes) so that even-offset edges start on a cache line
+    from paper_2308_14258_amd import SkeletonCols, mf_gather_skel, mf_scatter_skel, mf_skeleton_pack, mf_skeleton_unpack
+    ny, nx = u.shape
+    padded = torch.empty(ny, (nx + 31) // 32 * 32, device="cuda")[:, :nx]
+    padded.copy_(u)
+    del u
+    u = padded
+    res["side_layout_row_pitch_floats"] = int(u.stride(0))
+    cols = SkeletonCols(u, (ux, uy))
+    pack_ms = _event_ms(lambda: mf_skeleton_pack(ctx, u, cols), 5)
+    unpack_ms = _event_ms(lambda: mf_skeleton_unpack(ctx, cols, u), 5)
+    tot["gather_side_layout"] = [0.0, 0.0]
+    tot["scatter_cross_side_layout"] = [0.0, 0.0]
+    for c in range(4):
+        n = mf_colour_placements((ux, uy), c)
+        G = torch.empty(n, 128, device="cuda")
+        ms = _event_ms(lambda: mf_gather_skel(ctx, u, cols, c, G), 20)
+        tot["gather_side_layout"][0] += ms
+        tot["gather_side_layout"][1] += n * 1024.0
+        pred = torch.randn(n, 61, device="cuda")
+        ms = _event_ms(lambda: mf_scatter_skel(ctx, pred, u, cols, c), 20)
+        tot["scatter_cross_side_layout"][0] += ms
+        tot["scatter_cross_side_layout"][1] += n * 61 * 8.0
+        del pred, G
     for key, (ms, nbytes) in tot.items():
         gbps = nbytes / (ms * 1e-3) / 1e9
         res[key] = {"us_per_launch": ms * 1e3 / 4, "algorithmic_bytes_per_sweep": nbytes,
                     "GB_per_s": gbps, "frac_of_hbm_peak": gbps * 1e9 / PEAK_HBM_BYTES_PER_S}
+    res["side_layout_pack_us"] = pack_ms * 1e3
+    res["side_layout_unpack_us"] = unpack_ms * 1e3
     return res
 
 

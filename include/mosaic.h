@@ -322,6 +322,34 @@ mf_status mf_gather(mf_ctx* ctx, const float* u, const mf_domain_desc* dom, int3
 mf_status mf_scatter(mf_ctx* ctx, const float* pred, int32_t targets, float* u, const mf_domain_desc* dom,
                      int32_t colour, void* stream);
 
+/* Skeleton side layout for the unfused colour phase. Every boundary that a
+ * gather reads and every CROSS target that a scatter writes lies on the
+ * skeleton: grid rows j = 16 r and grid columns i = 16 c (Sec. 4.2). The
+ * rows are contiguous in the row-major field; the columns are kept
+ * transposed in a caller-owned side buffer cols (device, float32,
+ * mf_skeleton_cols_size floats): cols[c * cpitch + j] = u[j][16 c],
+ * c = 0 .. 2 units_x, cpitch = 32 units_y + 1 rounded up to a multiple of
+ * 32. Then each boundary edge and each centre line is one contiguous run.
+ *   mf_skeleton_pack     fills cols from the field.
+ *   mf_gather_skel       as mf_gather, reading vertical edges from cols.
+ *   mf_scatter_skel      as mf_scatter with MF_CROSS targets, writing the
+ *                        vertical centre line into cols, the horizontal one
+ *                        into the field's row and the centre into both.
+ *   mf_skeleton_unpack   writes cols back into the field's skeleton columns.
+ * Between pack and unpack the skeleton state is the field's skeleton rows
+ * plus cols (the field's own column entries go stale); gather -> network ->
+ * scatter on this state, then unpack, gives the same field as mf_gather /
+ * mf_scatter on the field, bit for bit. One domain (field_offset applies
+ * to u). Asynchronous; no workspace. mf_skeleton_cols_size returns -1 on an
+ * invalid domain (pure host function). */
+int64_t mf_skeleton_cols_size(const mf_domain_desc* dom);
+mf_status mf_skeleton_pack(mf_ctx* ctx, const float* u, const mf_domain_desc* dom, float* cols, void* stream);
+mf_status mf_skeleton_unpack(mf_ctx* ctx, const float* cols, float* u, const mf_domain_desc* dom, void* stream);
+mf_status mf_gather_skel(mf_ctx* ctx, const float* u, const float* cols, const mf_domain_desc* dom, int32_t colour,
+                         float* G, void* stream);
+mf_status mf_scatter_skel(mf_ctx* ctx, const float* pred, float* u, float* cols, const mf_domain_desc* dom,
+                          int32_t colour, void* stream);
+
 /* Workspace bytes for mf_solve_adjoint. */
 mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
                              int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes);

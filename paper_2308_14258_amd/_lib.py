@@ -74,6 +74,11 @@ _SIG = {
     "mf_target_coords": (_c.c_int32, [_c.c_int32, _P]),
     "mf_gather": (_c.c_int32, [_P, _P, _c.POINTER(DomainDesc), _c.c_int32, _P, _P]),
     "mf_scatter": (_c.c_int32, [_P, _P, _c.c_int32, _P, _c.POINTER(DomainDesc), _c.c_int32, _P]),
+    "mf_skeleton_cols_size": (_c.c_int64, [_c.POINTER(DomainDesc)]),
+    "mf_skeleton_pack": (_c.c_int32, [_P, _P, _c.POINTER(DomainDesc), _P, _P]),
+    "mf_skeleton_unpack": (_c.c_int32, [_P, _P, _P, _c.POINTER(DomainDesc), _P]),
+    "mf_gather_skel": (_c.c_int32, [_P, _P, _P, _c.POINTER(DomainDesc), _c.c_int32, _P, _P]),
+    "mf_scatter_skel": (_c.c_int32, [_P, _P, _P, _P, _c.POINTER(DomainDesc), _c.c_int32, _P]),
     "mf_sweep_operator": (_c.c_int32, [_P, _P, _c.c_int64, _c.c_int32, _P, _P, _c.POINTER(DomainDesc),
                                        _c.c_int32, _P]),
     "mf_adjoint_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,

@@ -336,6 +336,50 @@ def mf_scatter(ctx: Context, pred: torch.Tensor, u: torch.Tensor, units, colour:
                             _stream()), "mf_scatter")
 
 
+class SkeletonCols:
+    """The transposed skeleton columns of one field (the side layout of
+    mf_gather_skel / mf_scatter_skel): cols[c, j] = u[j, 16 c]."""
+
+    def __init__(self, u: torch.Tensor, units):
+        _need_field(u, units)
+        self.units = (int(units[0]), int(units[1]))
+        self.dom = domain_desc(u, units)
+        n = load().mf_skeleton_cols_size(ctypes.byref(self.dom))
+        if n < 0:
+            check(_lib.MF_EINVAL, "mf_skeleton_cols_size")
+        self.buf = torch.empty(int(n), dtype=torch.float32, device=u.device)
+
+
+def mf_skeleton_pack(ctx: Context, u: torch.Tensor, cols: SkeletonCols) -> None:
+    check(load().mf_skeleton_pack(ctx.ptr, _ptr(u), ctypes.byref(cols.dom), _ptr(cols.buf), _stream()),
+          "mf_skeleton_pack")
+
+
+def mf_skeleton_unpack(ctx: Context, cols: SkeletonCols, u: torch.Tensor) -> None:
+    check(load().mf_skeleton_unpack(ctx.ptr, _ptr(cols.buf), _ptr(u), ctypes.byref(cols.dom), _stream()),
+          "mf_skeleton_unpack")
+
+
+def mf_gather_skel(ctx: Context, u: torch.Tensor, cols: SkeletonCols, colour: int, G: torch.Tensor | None = None):
+    """[P_c, 128] boundary vectors of one colour from the side layout."""
+    n = mf_colour_placements(cols.units, colour)
+    if G is None:
+        G = torch.empty(n, 128, device=u.device, dtype=torch.float32)
+    check(load().mf_gather_skel(ctx.ptr, _ptr(u), _ptr(cols.buf), ctypes.byref(cols.dom), colour,
+                                _ptr(G) if n else None, _stream()), "mf_gather_skel")
+    return G
+
+
+def mf_scatter_skel(ctx: Context, pred: torch.Tensor, u: torch.Tensor, cols: SkeletonCols, colour: int) -> None:
+    """CROSS predictions [P_c, 61] of one colour into the side layout."""
+    _need_cuda_f32(pred, "pred")
+    n = mf_colour_placements(cols.units, colour)
+    if not (pred.is_contiguous() and pred.shape == (n, 61)):
+        raise ValueError(f"pred must be contiguous of shape ({n}, 61)")
+    check(load().mf_scatter_skel(ctx.ptr, _ptr(pred) if n else None, _ptr(u), _ptr(cols.buf),
+                                 ctypes.byref(cols.dom), colour, _stream()), "mf_scatter_skel")
+
+
 def sdnet_forward(ctx: Context, params: torch.Tensor, G: torch.Tensor, X: torch.Tensor,
                   prec: int = MF_FP32, derivatives: bool = False):
     """U [n_bc, n_pts] (and dU [n_bc, n_pts, 2], lapU [n_bc, n_pts])."""
@@ -465,7 +509,8 @@ def physics_loss(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xd: torch.
     return PhysicsLoss.apply(params, G, Xd, Xc, ctx, Yd)
 
 
-__all__ = ["Batch", "Context", "PhysicsLoss", "mf_autotune", "mf_solve_adjoint", "mf_sweep",
+__all__ = ["Batch", "Context", "PhysicsLoss", "SkeletonCols", "mf_skeleton_pack", "mf_skeleton_unpack",
+           "mf_gather_skel", "mf_scatter_skel", "mf_autotune", "mf_solve_adjoint", "mf_sweep",
            "mf_sweep_noalloc", "mf_solve",
            "mf_sweep_operator", "mf_colour_placements", "mf_target_coords", "mf_gather", "mf_scatter", "physics_loss", "sdnet_forward", "sdnet_loss_grad", "sdnet_train_step",
            "width_of", "sdnet_desc", "domain_desc", "_lib"]

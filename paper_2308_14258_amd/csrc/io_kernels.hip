@@ -13,6 +13,8 @@
 // horizontal target lines are contiguous runs, vertical ones touch one
 // element per row (one memory transaction per element: on a row-major field
 // the vertical edges dominate the traffic).
+#include <algorithm>
+
 #include "mf_device.h"
 #include "mf_internal.h"
 
@@ -82,7 +84,139 @@ __global__ __launch_bounds__(NT) void scatter_colour_kernel(const float* __restr
 
 int64_t per_xcd_of(int64_t n_q) { return (n_q + kXcds - 1) / kXcds; }
 
+// ---------------------------------------------------------------------------
+// Skeleton side layout. The boundaries every gather reads and the CROSS
+// targets every scatter writes are skeleton points: grid rows j = 16 r and
+// grid columns i = 16 c. The rows are contiguous in the row-major field;
+// the columns are kept transposed in a side buffer, cols[c * cpitch + j] =
+// u[j][16 c], so that vertical edges and vertical centre lines are
+// contiguous too. Between pack and unpack the state of a CROSS sweep is the
+// field's skeleton rows plus cols (the intersections live in both and are
+// written to both); the field's own column entries are refreshed by unpack.
+// ---------------------------------------------------------------------------
+
+// cols[c][j] = u[j][16 c]; one thread per (c, j), j fastest.
+__global__ void skel_pack_kernel(const float* __restrict__ u, int64_t pitch, int nc, int ny, int64_t cpitch,
+                                 float* __restrict__ cols) {
+  const int64_t n = (int64_t)nc * ny;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / ny, j = idx - c * ny;
+    cols[c * cpitch + j] = u[j * pitch + kHalf * c];
+  }
+}
+
+__global__ void skel_unpack_kernel(const float* __restrict__ cols, int64_t cpitch, int nc, int ny,
+                                   float* __restrict__ u, int64_t pitch) {
+  const int64_t n = (int64_t)nc * ny;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / ny, j = idx - c * ny;
+    u[j * pitch + kHalf * c] = cols[c * cpitch + j];
+  }
+}
+
+// Gather from the side layout: each of the four edges is one contiguous run
+// (bottom and top in the field's rows, right and left in cols). A workgroup
+// of 128 kSkelPPW threads takes kSkelPPW consecutive placements of its die's
+// range.
+constexpr int kSkelPPW = 4;
+// Placement of slot `sub` of workgroup `blk` (die blk mod 8): each die's
+// workgroups walk its contiguous range kSkelPPW placements at a time.
+__device__ __forceinline__ int64_t xcd_placement_ppw(int64_t blk, int sub, int64_t per_xcd, int64_t q0,
+                                                     int64_t n_q) {
+  const int64_t q = (blk % kXcds) * per_xcd + (blk / kXcds) * kSkelPPW + sub;
+  return q < n_q ? q0 + q : -1;
+}
+__global__ __launch_bounds__(kNB * kSkelPPW) void gather_skel_kernel(const float* __restrict__ u, int64_t pitch,
+                                                          const float* __restrict__ cols, int64_t cpitch, int ux,
+                                                          int colour, int64_t q0, int64_t n_q, int64_t per_xcd,
+                                                          float* __restrict__ G) {
+  const int64_t q = xcd_placement_ppw(blockIdx.x, threadIdx.x >> 7, per_xcd, q0, n_q);
+  if (q < 0) return;
+  int a, b;
+  placement_of((int)q, colour, ux, a, b);
+  const int k = threadIdx.x & 127, side = k >> 5, m = k & 31;
+  const int64_t r0 = (int64_t)kHalf * b;   // bottom row / first row of the vertical edges
+  float v;
+  if (side == 0) v = u[r0 * pitch + kHalf * a + m];                          // (m, 0)
+  else if (side == 1) v = cols[(int64_t)(a + 2) * cpitch + r0 + m];          // (32, m)
+  else if (side == 2) v = u[(r0 + kS) * pitch + kHalf * a + kS - m];         // (32 - m, 32)
+  else v = cols[(int64_t)a * cpitch + r0 + kS - m];                          // (0, 32 - m)
+  G[q * kNB + k] = v;
+}
+
+// CROSS scatter into the side layout: the vertical centre line (targets
+// 0..30, j = 1..31) into cols, the horizontal one (targets 31..60) into the
+// field's row, and the centre (target 15) into that row as well.
+__global__ __launch_bounds__(64 * kSkelPPW) void scatter_skel_kernel(const float* __restrict__ pred,
+                                                          float* __restrict__ u,
+                                                          int64_t pitch, float* __restrict__ cols, int64_t cpitch,
+                                                          int ux, int colour, int64_t q0, int64_t n_q,
+                                                          int64_t per_xcd) {
+  const int64_t q = xcd_placement_ppw(blockIdx.x, threadIdx.x >> 6, per_xcd, q0, n_q);
+  if (q < 0) return;
+  int a, b;
+  placement_of((int)q, colour, ux, a, b);
+  const int t = threadIdx.x & 63;
+  const float* src = pred + q * kCross;
+  float* row = u + (int64_t)(kHalf * b + kHalf) * pitch + kHalf * a;   // row j = 16 b + 16 from i = 16 a
+  if (t < 31) {
+    cols[(int64_t)(a + 1) * cpitch + kHalf * b + 1 + t] = src[t];
+  } else if (t < kCross) {
+    int ti, tj;
+    target_local<0>(t, ti, tj);
+    row[ti] = src[t];
+  } else if (t == kCross) {
+    row[kHalf] = src[kHalf - 1];
+  }
+}
+
 }  // namespace
+
+int64_t skel_cols_pitch(int uy) { return ((int64_t)kS * uy + 1 + 31) / 32 * 32; }
+
+hipError_t launch_skel_pack(const float* u, int64_t pitch, int ux, int uy, float* cols, hipStream_t s) {
+  const int nc = 2 * ux + 1, ny = kS * uy + 1;
+  const int64_t n = (int64_t)nc * ny;
+  hipLaunchKernelGGL(skel_pack_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0, s,
+                     u, pitch, nc, ny, skel_cols_pitch(uy), cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_skel_unpack(const float* cols, float* u, int64_t pitch, int ux, int uy, hipStream_t s) {
+  const int nc = 2 * ux + 1, ny = kS * uy + 1;
+  const int64_t n = (int64_t)nc * ny;
+  hipLaunchKernelGGL(skel_unpack_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                     s, cols, skel_cols_pitch(uy), nc, ny, u, pitch);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_skel(const float* u, int64_t pitch, const float* cols, int ux, int uy, int colour,
+                              int64_t n_q, float* G, hipStream_t s) {
+  for (int64_t q0 = 0; q0 < n_q; q0 += kIoChunk) {
+    const int64_t n = n_q - q0 < kIoChunk ? n_q - q0 : kIoChunk;
+    const int64_t per = (per_xcd_of(n) + kSkelPPW - 1) / kSkelPPW * kSkelPPW;
+    hipLaunchKernelGGL(gather_skel_kernel, dim3((unsigned)(per * kXcds / kSkelPPW)), dim3(kNB * kSkelPPW), 0, s, u,
+                       pitch, cols, skel_cols_pitch(uy), ux, colour, q0, n, per, G);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_scatter_skel(const float* pred, float* u, int64_t pitch, float* cols, int ux, int uy, int colour,
+                               int64_t n_q, hipStream_t s) {
+  for (int64_t q0 = 0; q0 < n_q; q0 += kIoChunk) {
+    const int64_t n = n_q - q0 < kIoChunk ? n_q - q0 : kIoChunk;
+    const int64_t per = (per_xcd_of(n) + kSkelPPW - 1) / kSkelPPW * kSkelPPW;
+    hipLaunchKernelGGL(scatter_skel_kernel, dim3((unsigned)(per * kXcds / kSkelPPW)), dim3(64 * kSkelPPW), 0, s,
+                       pred, u, pitch, cols, skel_cols_pitch(uy), ux, colour, q0, n, per);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_gather_colour(const float* u, int64_t pitch, int ux, int colour, int64_t n_q, float* G,
                                 hipStream_t s) {

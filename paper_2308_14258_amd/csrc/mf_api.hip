@@ -1116,6 +1116,63 @@ mf_status mf_scatter(mf_ctx* ctx, const float* pred, int32_t targets, float* u, 
   return ok();
 }
 
+int64_t mf_skeleton_cols_size(const mf_domain_desc* dom) {
+  if (check_domain(dom, 1) != MF_OK) return -1;
+  return (int64_t)(2 * dom->units_x + 1) * skel_cols_pitch(dom->units_y);
+}
+
+mf_status mf_skeleton_pack(mf_ctx* ctx, const float* u, const mf_domain_desc* dom, float* cols, void* stream) {
+  MF_TRY(check_domain(dom, 1));
+  MF_TRY(check_ptr(u, "u"));
+  MF_TRY(check_ptr(cols, "cols"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_skel_pack(u + dom->field_offset, dom->pitch, dom->units_x, dom->units_y, cols,
+                          static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mf_status mf_skeleton_unpack(mf_ctx* ctx, const float* cols, float* u, const mf_domain_desc* dom, void* stream) {
+  MF_TRY(check_domain(dom, 1));
+  MF_TRY(check_ptr(u, "u"));
+  MF_TRY(check_ptr(cols, "cols"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_skel_unpack(cols, u + dom->field_offset, dom->pitch, dom->units_x, dom->units_y,
+                            static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mf_status mf_gather_skel(mf_ctx* ctx, const float* u, const float* cols, const mf_domain_desc* dom, int32_t colour,
+                         float* G, void* stream) {
+  MF_TRY(check_ptr(u, "u"));
+  MF_TRY(check_colour_io(dom, colour));
+  MF_TRY(check_ptr(cols, "cols"));
+  const int64_t n_q = mf_colour_placements(dom, colour);
+  if (n_q == 0) return ok();
+  MF_TRY(check_ptr(G, "G"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_gather_skel(u + dom->field_offset, dom->pitch, cols, dom->units_x, dom->units_y, colour, n_q, G,
+                            static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+mf_status mf_scatter_skel(mf_ctx* ctx, const float* pred, float* u, float* cols, const mf_domain_desc* dom,
+                          int32_t colour, void* stream) {
+  MF_TRY(check_ptr(u, "u"));
+  MF_TRY(check_colour_io(dom, colour));
+  MF_TRY(check_ptr(cols, "cols"));
+  const int64_t n_q = mf_colour_placements(dom, colour);
+  if (n_q == 0) return ok();
+  MF_TRY(check_ptr(pred, "pred"));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_scatter_skel(pred, u + dom->field_offset, dom->pitch, cols, dom->units_x, dom->units_y, colour, n_q,
+                             static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 // ---------------------------------------------------------------------------
 // mf_solve_adjoint
 // ---------------------------------------------------------------------------

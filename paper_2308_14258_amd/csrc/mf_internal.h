@@ -185,6 +185,14 @@ hipError_t launch_gather_colour(const float* u, int64_t pitch, int ux, int colou
                                 hipStream_t s);
 hipError_t launch_scatter_colour(const float* pred, int targets, float* u, int64_t pitch, int ux, int colour,
                                  int64_t n_q, hipStream_t s);
+// the skeleton side layout: transposed skeleton columns (io_kernels.hip)
+int64_t skel_cols_pitch(int uy);
+hipError_t launch_skel_pack(const float* u, int64_t pitch, int ux, int uy, float* cols, hipStream_t s);
+hipError_t launch_skel_unpack(const float* cols, float* u, int64_t pitch, int ux, int uy, hipStream_t s);
+hipError_t launch_gather_skel(const float* u, int64_t pitch, const float* cols, int ux, int uy, int colour,
+                              int64_t n_q, float* G, hipStream_t s);
+hipError_t launch_scatter_skel(const float* pred, float* u, int64_t pitch, float* cols, int ux, int uy, int colour,
+                               int64_t n_q, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill2d(float* p, int64_t pitch, int ux, int uy, float v, hipStream_t s);
 hipError_t launch_target_coords(float* X_cross, float* X_interior, hipStream_t s);

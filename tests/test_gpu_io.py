@@ -126,3 +126,59 @@ def test_gather_scatter_at_256x256_units(ctx):
     mf_scatter(ctx, pred.cuda(), u, (ux, uy), c, MF_CROSS)
     want = sw._scatter(u_cpu, plist, geo.targets("cross"), pred)
     assert torch.equal(u.cpu(), want)
+
+
+@pytest.mark.parametrize("ux,uy", [(1, 1), (3, 5), (7, 2), (9, 8)])
+def test_skeleton_side_layout_gather_and_scatter(ctx, ux, uy):
+    """Pack, gather from the side layout, scatter into it, unpack: the same
+    boundary vectors as the oracle's gather and the same field as the
+    oracle's CROSS scatter, bit for bit, colour by colour."""
+    print(f"case: skeleton side layout {ux}x{uy}", flush=True)
+    from paper_2308_14258_amd import SkeletonCols, mf_gather_skel, mf_scatter_skel, mf_skeleton_pack, mf_skeleton_unpack
+    f = _field(ux, uy, 13)
+    u = torch.from_numpy(f).cuda()
+    cols = SkeletonCols(u, (ux, uy))
+    mf_skeleton_pack(ctx, u, cols)
+    ref = torch.from_numpy(f.astype(np.float64))
+    rng = np.random.default_rng(ux * 31 + uy)
+    for c in range(4):
+        plist = geo.placements_of_colour(ux, uy, c)
+        G = mf_gather_skel(ctx, u, cols, c)
+        if plist:
+            np.testing.assert_array_equal(G.cpu().numpy(), sw.gather(ref, plist).numpy().astype(np.float32))
+        pred = rng.standard_normal((len(plist), 61)).astype(np.float32)
+        mf_scatter_skel(ctx, torch.from_numpy(pred).cuda(), u, cols, c)
+        if plist:
+            ref = sw._scatter(ref, plist, geo.cross_targets(), torch.from_numpy(pred.astype(np.float64)))
+    mf_skeleton_unpack(ctx, cols, u)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u.cpu().numpy(), ref.numpy().astype(np.float32))
+
+
+def test_skeleton_side_layout_unfused_sweep_equals_mf_sweep(ctx):
+    """gather (side layout) -> sdnet_forward -> scatter (side layout) for the
+    four colours, then unpack: the fused sweep to the float32 bar, and the
+    field-layout unfused sweep bit for bit."""
+    print("case: skeleton side layout unfused sweep", flush=True)
+    from paper_2308_14258_amd import SkeletonCols, mf_gather_skel, mf_scatter_skel, mf_skeleton_pack, mf_skeleton_unpack
+    ux, uy = 6, 5
+    params = torch.from_numpy(mi.random_params(256, seed=19)).cuda()
+    f = mi.gp_field(ux, uy, 1.0, seed=20)
+    X = mf_target_coords(MF_CROSS).cuda()
+    a = torch.from_numpy(f).cuda()
+    cols = SkeletonCols(a, (ux, uy))
+    mf_skeleton_pack(ctx, a, cols)
+    b = torch.from_numpy(f).cuda()
+    for c in range(4):
+        pa = sdnet_forward(ctx, params, mf_gather_skel(ctx, a, cols, c), X)
+        mf_scatter_skel(ctx, pa.contiguous(), a, cols, c)
+        pb = sdnet_forward(ctx, params, mf_gather(ctx, b, (ux, uy), c), X)
+        mf_scatter(ctx, pb.contiguous(), b, (ux, uy), c, MF_CROSS)
+    mf_skeleton_unpack(ctx, cols, a)
+    fused = torch.from_numpy(f).cuda()
+    mf_sweep(ctx, params, fused, (ux, uy))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    m = sw.skeleton_mask(*f.shape).numpy()
+    got, want = a.cpu().numpy()[m].astype(np.float64), fused.cpu().numpy()[m].astype(np.float64)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5
