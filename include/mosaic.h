@@ -379,9 +379,13 @@ mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* do
  * value-stream reverse pass, gb = W1g^T sum_t ab1 (the input-split first
  * layer of Eq. 8), and a deterministic scatter-add of gb onto the placement
  * boundaries in four sub-colours. The network is evaluated in float32
- * throughout (this differentiates the MF_FP32 forward). Batches
- * (n_domains > 1) are processed domain by domain. u0, u_out, u0_bar and
- * uout_bar must be distinct buffers (MF_EINVAL). Asynchronous. */
+ * throughout (this differentiates the MF_FP32 forward). A batch
+ * (n_domains > 1) runs every domain's placements of a colour in the same
+ * launches, forward and reverse. The workspace holds 2 + ceil(K / ckpt_every)
+ * + 4 ckpt_every copies of the span the domains occupy in the caller's
+ * buffer (from the lowest field_offset to the end of the last domain) plus
+ * fixed chunk buffers (about 1.6 GB at width 256). u0, u_out, u0_bar and uout_bar
+ * must be distinct buffers (MF_EINVAL). Asynchronous. */
 mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
                            const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
                            int32_t ckpt_every, const float* uout_bar, float* u_out, float* J,

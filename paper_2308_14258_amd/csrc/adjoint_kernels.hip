@@ -41,17 +41,42 @@ __global__ void target_coords_kernel(float* __restrict__ X) {
   }
 }
 
-// Boundary vectors G [n_q][128] of placements q0 .. q0 + n_q - 1 of a colour.
-__global__ void gather_boundaries_kernel(const float* __restrict__ u, int64_t pitch, int ux, int colour,
+// The placements of one colour over all domains of a batch are numbered
+// consecutively, domain by domain: domain d holds the indices
+// qbegin[d] .. qbegin[d + 1] - 1 (qbegin: the colour's prefix table, nd + 1
+// entries). `locate` finds the domain of a global index g and its local index.
+// Domain offsets are those of the caller's buffers; a field copy held in the
+// workspace starts `shift` floats later in that frame (its index is the
+// caller's minus shift).
+struct AdjDomains {
+  const DomEntry* doms;     // [nd]
+  const int32_t* qbegin;    // [4][nd + 1] per-colour placement prefixes
+  int nd;
+};
+
+__device__ __forceinline__ DomEntry locate(const AdjDomains& D, int colour, int g, int& lq) {
+  const int32_t* qb = D.qbegin + colour * (D.nd + 1);
+  int lo = 0, hi = D.nd - 1;   // last d with qb[d] <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (qb[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  lq = g - qb[lo];
+  return D.doms[lo];
+}
+
+// Boundary vectors G [n_q][128] of global placements q0 .. q0 + n_q - 1 of a colour.
+__global__ void gather_boundaries_kernel(const float* __restrict__ u, int64_t shift, AdjDomains D, int colour,
                                          int q0, int n_q, float* __restrict__ G) {
   const int64_t n = (int64_t)n_q * kNB;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int q = (int)(idx >> 7), k = (int)(idx & 127);
-    int a, b, bi, bj;
-    placement_of(q0 + q, colour, ux, a, b);
+    int lq, a, b, bi, bj;
+    const DomEntry e = locate(D, colour, q0 + q, lq);
+    placement_of(lq, colour, e.ux, a, b);
     boundary_local(k, bi, bj);
-    G[idx] = u[(int64_t)(kHalf * b + bj) * pitch + kHalf * a + bi];
+    G[idx] = u[e.offset - shift + (int64_t)(kHalf * b + bj) * e.pitch + kHalf * a + bi];
   }
 }
 
@@ -60,26 +85,27 @@ __global__ void gather_boundaries_kernel(const float* __restrict__ u, int64_t pi
 //   MODE 1 (assembly, sum of u^2): ubp = 2 u_out[x] / count(x).
 //   MODE 2 (assembly, seed):       ubp = seed[x] / count(x), seed in u_out's place.
 template <int TMODE, int MODE>
-__global__ void target_adjoint_kernel(float* __restrict__ ub, const float* __restrict__ u_out,
-                                      int64_t pitch, int ux, int uy, int colour, int q0, int n_q,
-                                      float* __restrict__ ubp) {
+__global__ void target_adjoint_kernel(float* __restrict__ ub, const float* __restrict__ u_out, int64_t out_shift,
+                                      AdjDomains D, int colour, int q0, int n_q, float* __restrict__ ubp) {
   constexpr int T = n_targets<TMODE>();
   const int64_t n = (int64_t)n_q * T;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int q = (int)(idx / T), t = (int)(idx - (int64_t)q * T);
-    int a, b, ti, tj;
-    placement_of(q0 + q, colour, ux, a, b);
+    int lq, a, b, ti, tj;
+    const DomEntry e = locate(D, colour, q0 + q, lq);
+    const int ux = e.ux, uy = e.uy;
+    placement_of(lq, colour, ux, a, b);
     target_local<TMODE>(t, ti, tj);
     const int gi = kHalf * a + ti, gj = kHalf * b + tj;
-    const int64_t o = (int64_t)gj * pitch + gi;
+    const int64_t o = e.offset + (int64_t)gj * e.pitch + gi;
     if constexpr (MODE == 0) {
       ubp[idx] = ub[o];
       ub[o] = 0.0f;
     } else if constexpr (MODE == 1) {
-      ubp[idx] = 2.0f * u_out[o] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
+      ubp[idx] = 2.0f * u_out[o - out_shift] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
     } else {
-      ubp[idx] = u_out[o] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
+      ubp[idx] = u_out[o - out_shift] * cover_inv(gi, kS * ux) * cover_inv(gj, kS * uy);
     }
   }
 }
@@ -117,18 +143,20 @@ __global__ __launch_bounds__(128) void boundary_adjoint_kernel(const float* __re
 }
 
 // ub[B_p(k)] += gb[p][k] for the placements of one sub-colour (a mod 4,
-// b mod 4 fixed) among q0 .. q0 + n_q - 1 of the colour.
-__global__ __launch_bounds__(128) void boundary_scatter_add_kernel(float* __restrict__ ub, int64_t pitch,
-                                                                   int ux, int colour, int q0, int n_q,
-                                                                   int sub, const float* __restrict__ gb) {
+// b mod 4 fixed) among global placements q0 .. q0 + n_q - 1 of the colour
+// (domains do not share memory, so only same-domain placements meet).
+__global__ __launch_bounds__(128) void boundary_scatter_add_kernel(float* __restrict__ ub, AdjDomains D, int colour,
+                                                                   int q0, int n_q, int sub,
+                                                                   const float* __restrict__ gb) {
   const int q = blockIdx.x;
   if (q >= n_q) return;
-  int a, b;
-  placement_of(q0 + q, colour, ux, a, b);
+  int lq, a, b;
+  const DomEntry e = locate(D, colour, q0 + q, lq);
+  placement_of(lq, colour, e.ux, a, b);
   if (((a >> 1) & 1) != (sub & 1) || ((b >> 1) & 1) != (sub >> 1)) return;
   int bi, bj;
   boundary_local(threadIdx.x, bi, bj);
-  const int64_t o = (int64_t)(kHalf * b + bj) * pitch + kHalf * a + bi;
+  const int64_t o = e.offset + (int64_t)(kHalf * b + bj) * e.pitch + kHalf * a + bi;
   ub[o] += gb[(int64_t)q * kNB + threadIdx.x];
 }
 
@@ -239,13 +267,12 @@ hipError_t launch_grid_dot(const float* w, const float* u, int64_t pitch, int ux
 // is the seed) for placements processed in chunks that fit the buffers in ab.
 template <int D>
 static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const AdjointBuffers& ab,
-                                   const float* u_before, const float* u_out, float* ub, int64_t pitch,
-                                   int ux, int uy, int colour, int targets, int kind,
-                                   hipStream_t s) {
+                                   const float* u_before, int64_t before_shift, const float* u_out,
+                                   int64_t out_shift, float* ub, const AdjDomains& dd, int n_place, int colour,
+                                   int targets, int kind, hipStream_t s) {
   const bool assembly = kind != ADJ_SWEEP;
   const int tm = assembly ? MF_INTERIOR : targets;
   const int T = tm == MF_INTERIOR ? kInterior : kCross;
-  const int n_place = (ux - (colour & 1)) * (uy - (colour >> 1));
   const int chunk = (int)std::max<int64_t>(1, ab.max_rows / T);
   const float* X = tm == MF_INTERIOR ? ab.X_interior : ab.X_cross;
   hipError_t e;
@@ -255,20 +282,20 @@ static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const A
     // 1. target adjoints
     if (kind == ADJ_SUMSQ)
       hipLaunchKernelGGL((target_adjoint_kernel<1, 1>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
-                         u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
+                         u_out, out_shift, dd, colour, q0, nq, ab.ubp);
     else if (kind == ADJ_SEED)
       hipLaunchKernelGGL((target_adjoint_kernel<1, 2>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
-                         u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
+                         u_out, out_shift, dd, colour, q0, nq, ab.ubp);
     else if (tm == MF_CROSS)
       hipLaunchKernelGGL((target_adjoint_kernel<0, 0>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
-                         u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
+                         u_out, out_shift, dd, colour, q0, nq, ab.ubp);
     else
       hipLaunchKernelGGL((target_adjoint_kernel<1, 0>), dim3(grid_of(n_rows, 256)), dim3(256), 0, s, ub,
-                         u_out, pitch, ux, uy, colour, q0, nq, ab.ubp);
+                         u_out, out_shift, dd, colour, q0, nq, ab.ubp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 2. forward of the phase from the field before it
     hipLaunchKernelGGL(gather_boundaries_kernel, dim3(grid_of((int64_t)nq * kNB, 256)), dim3(256), 0, s,
-                       u_before, pitch, ux, colour, q0, nq, ab.G);
+                       u_before, before_shift, dd, colour, q0, nq, ab.G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_projection(net, D, ab.G, nq, ab.C, s)) != hipSuccess) return e;
     if ((e = launch_value_forward(net, D, ab.C, X, T, nq, ab.Z, s)) != hipSuccess) return e;
@@ -282,21 +309,27 @@ static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const A
     hipLaunchKernelGGL((boundary_adjoint_kernel<D>), dim3(nq), dim3(128), 0, s, net.w1gT, ab.csum, nq, ab.gb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int sub = 0; sub < 4; ++sub) {
-      hipLaunchKernelGGL(boundary_scatter_add_kernel, dim3(nq), dim3(128), 0, s, ub, pitch, ux, colour, q0, nq,
-                         sub, ab.gb);
+      hipLaunchKernelGGL(boundary_scatter_add_kernel, dim3(nq), dim3(128), 0, s, ub, dd, colour, q0, nq, sub,
+                         ab.gb);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
   return hipSuccess;
 }
 
+// One colour phase (or assembly colour) reversed for every domain of the
+// batch at once: doms [nd] (the caller's offsets) and qbegin [4][nd + 1] are
+// device tables; u_before and u_out are read shifted by their shifts, ub is
+// in the caller's frame.
 hipError_t launch_adjoint_colour(const NetPtrs& net, int width, const float* whT, const AdjointBuffers& ab,
-                                 const float* u_before, const float* u_out, float* ub, int64_t pitch, int ux,
-                                 int uy, int colour, int targets, int kind, hipStream_t s) {
-  return width == 256 ? adjoint_colour_d<256>(net, whT, ab, u_before, u_out, ub, pitch, ux, uy, colour,
-                                             targets, kind, s)
-                      : adjoint_colour_d<128>(net, whT, ab, u_before, u_out, ub, pitch, ux, uy, colour,
-                                             targets, kind, s);
+                                 const float* u_before, int64_t before_shift, const float* u_out,
+                                 int64_t out_shift, float* ub, const DomEntry* doms, const int32_t* qbegin, int nd,
+                                 int n_place, int colour, int targets, int kind, hipStream_t s) {
+  const AdjDomains dd{doms, qbegin, nd};
+  return width == 256 ? adjoint_colour_d<256>(net, whT, ab, u_before, before_shift, u_out, out_shift, ub, dd,
+                                             n_place, colour, targets, kind, s)
+                      : adjoint_colour_d<128>(net, whT, ab, u_before, before_shift, u_out, out_shift, ub, dd,
+                                             n_place, colour, targets, kind, s);
 }
 
 }  // namespace mf

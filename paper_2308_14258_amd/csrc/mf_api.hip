@@ -1178,11 +1178,16 @@ mf_status mf_scatter_skel(mf_ctx* ctx, const float* pred, float* u, float* cols,
 // ---------------------------------------------------------------------------
 static constexpr int64_t kAdjRows = 262144;   // (placement, target) rows per chunk
 
+// Workspace of mf_solve_adjoint. The field copies (the running field, the
+// checkpoints, the per-phase states of one segment and the assembly) cover the
+// span [lo, hi) that the domains occupy in the caller's buffer, each domain at
+// its own offset minus lo, so that one copy moves every domain of the batch.
 struct AdjLayout {
   NetLayout net;
   size_t whT = 0, X_cross = 0, X_interior = 0, G = 0, C = 0, ubp = 0, Z[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
-  size_t csum = 0, gb = 0, part = 0, field = 0, ckpt = 0, states = 0, uout = 0, total = 0;
-  size_t fsize = 0;   // floats per field copy (largest domain)
+  size_t csum = 0, gb = 0, part = 0, ftable = 0, atable = 0, field = 0, ckpt = 0, states = 0, uout = 0, total = 0;
+  int64_t lo = 0;       // first float of the span
+  size_t fsize = 0;     // floats per field copy (hi - lo)
   int n_ckpt = 0;
 };
 
@@ -1195,9 +1200,13 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
   A.net = net_layout(width, MF_FP32, 0);
   const size_t d = (size_t)width;
   const size_t max_q = (size_t)(kAdjRows / 61);
-  int64_t fs = 0;
-  for (int i = 0; i < nd; ++i) fs = std::max<int64_t>(fs, field_extent(dom[i]));
-  A.fsize = (size_t)fs;
+  int64_t lo = INT64_MAX, hi = 0;
+  for (int i = 0; i < nd; ++i) {
+    lo = std::min<int64_t>(lo, dom[i].field_offset);
+    hi = std::max<int64_t>(hi, dom[i].field_offset + field_extent(dom[i]));
+  }
+  A.lo = lo;
+  A.fsize = (size_t)(hi - lo);
   A.n_ckpt = K > 0 ? (K + ckpt_every - 1) / ckpt_every : 0;
   size_t o = A.net.end;
   A.whT = o; o = align256(o + 3 * d * d * 4);
@@ -1211,6 +1220,10 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
   A.csum = o; o = align256(o + 3 * max_q * d * 4);
   A.gb = o; o = align256(o + max_q * 128 * 4);
   A.part = o; o = align256(o + 1024 * 4);
+  // the forward plan's batch table (as in the sweep workspace) and the
+  // adjoint's: DomEntry [nd] + placement prefixes [4][nd + 1]
+  A.ftable = o; o = align256(o + (size_t)nd * sizeof(DomEntry) + 2 * 4 * ((size_t)nd + 1) * 4);
+  A.atable = o; o = align256(o + (size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
   A.field = o; o = align256(o + A.fsize * 4);
   A.ckpt = o; o = align256(o + (size_t)A.n_ckpt * A.fsize * 4);
   A.states = o; o = align256(o + 4 * (size_t)ckpt_every * A.fsize * 4);
@@ -1227,6 +1240,9 @@ static mf_status adjoint_checks(const mf_sdnet_desc* desc, const mf_domain_desc*
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (K < 0) return fail(MF_EINVAL, "K %d < 0", K);
   if (ckpt_every < 1 || ckpt_every > 1000) return fail(MF_EINVAL, "ckpt_every %d not in 1..1000", ckpt_every);
+  int64_t n_place = 0;
+  for (int d = 0; d < nd; ++d) n_place += (int64_t)dom[d].units_x * dom[d].units_y;
+  if (n_place > INT32_MAX) return fail(MF_ESHAPE, "batch has too many placements");
   return MF_OK;
 }
 
@@ -1239,22 +1255,9 @@ mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* do
   return ok();
 }
 
-static Plan single_plan(const mf_sdnet_desc* desc, int targets, float* field, const mf_domain_desc* dom1,
-                        const NetPtrs& net, const void* ws) {
-  Plan P;
-  P.nd = 1;
-  P.dom = dom1;
-  P.u = field;
-  P.width = desc->width;
-  P.prec = MF_FP32;
-  P.targets = targets;
-  P.net = net;
-  P.ws = ws;
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 4; ++c) P.rows[a][c] = phase_rows(dom1, c, a ? MF_INTERIOR : targets);
-  return P;
-}
-
+// The K sweeps and the assembly run forward with checkpoints on a copy of the
+// domains' span, batched as mf_solve batches them; the reverse then takes
+// every domain's placements of a colour in the same launches.
 mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, const float* u0,
                            const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t K,
                            int32_t ckpt_every, const float* uout_bar, float* u_out, float* J, float* u0_bar,
@@ -1276,6 +1279,7 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
   char* b = static_cast<char*>(ws);
+  const int nd = n_domains;
   MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, A.net, ws, s));
   const NetPtrs net = net_ptrs(A.net, ws);
   float* whT = reinterpret_cast<float*>(b + A.whT);
@@ -1296,51 +1300,86 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
   float* F = reinterpret_cast<float*>(b + A.field);
   float* ckpt = reinterpret_cast<float*>(b + A.ckpt);
   float* states = reinterpret_cast<float*>(b + A.states);
+  float* uo = reinterpret_cast<float*>(b + A.uout);
+  const size_t fbytes = A.fsize * 4;
+  const int64_t lo = A.lo;
 
-  for (int d = 0; d < n_domains; ++d) {
-    const mf_domain_desc& D = dom[d];
-    const size_t ext = (size_t)field_extent(D);
-    const mf_domain_desc D1{D.units_x, D.units_y, 32, 16, D.pitch, 0};
-    const Plan P = single_plan(desc, targets, F, &D1, net, ws);
-    float* uo = u_out ? u_out + D.field_offset : reinterpret_cast<float*>(b + A.uout);
-    float* ub = u0_bar + D.field_offset;
-    // forward with checkpoints
-    MF_HIP(hipMemcpyAsync(F, u0 + D.field_offset, ext * 4, hipMemcpyDeviceToDevice, s));
-    for (int i = 0; i < A.n_ckpt; ++i) {
-      MF_HIP(hipMemcpyAsync(ckpt + (size_t)i * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
-      const int n_s = std::min(ckpt_every, K - i * ckpt_every);
-      for (int k = 0; k < n_s; ++k)
-        for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
+  // forward plan on the span copy (domain offsets relative to lo)
+  std::vector<mf_domain_desc> dint(dom, dom + nd);
+  for (mf_domain_desc& e : dint) e.field_offset -= lo;
+  SweepLayout SL;
+  SL.net = A.net;
+  SL.table = A.ftable;
+  Plan P;
+  MF_TRY(make_plan(ctx, desc, MF_FP32, targets, MF_MULTIPLICATIVE, F, dint.data(), nd, ws, SL, s, &P));
+  // the adjoint's table: caller offsets and per-colour placement prefixes
+  std::vector<char> host((size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
+  DomEntry* he = reinterpret_cast<DomEntry*>(host.data());
+  int32_t* hq = reinterpret_cast<int32_t*>(host.data() + (size_t)nd * sizeof(DomEntry));
+  int n_place[4] = {0, 0, 0, 0};
+  for (int d = 0; d < nd; ++d) he[d] = DomEntry{dom[d].field_offset, dom[d].pitch, dom[d].units_x, dom[d].units_y};
+  for (int c = 0; c < 4; ++c) {
+    int32_t acc = 0;
+    for (int d = 0; d < nd; ++d) {
+      hq[c * (nd + 1) + d] = acc;
+      acc += (dom[d].units_x - (c & 1)) * (dom[d].units_y - (c >> 1));
     }
-    MF_HIP(launch_assembly_init(F, uo, D.pitch, D.units_x, D.units_y, s));
-    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ASSEMBLY, uo, s, false));
+    hq[c * (nd + 1) + nd] = acc;
+    n_place[c] = acc;
+  }
+  char* at = b + A.atable;
+  MF_HIP(hipMemcpyAsync(at, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  const DomEntry* d_doms = reinterpret_cast<const DomEntry*>(at);
+  const int32_t* d_q = reinterpret_cast<const int32_t*>(at + (size_t)nd * sizeof(DomEntry));
+
+  // forward with checkpoints
+  MF_HIP(hipMemcpyAsync(F, u0 + lo, fbytes, hipMemcpyDeviceToDevice, s));
+  for (int i = 0; i < A.n_ckpt; ++i) {
+    MF_HIP(hipMemcpyAsync(ckpt + (size_t)i * A.fsize, F, fbytes, hipMemcpyDeviceToDevice, s));
+    const int n_s = std::min(ckpt_every, K - i * ckpt_every);
+    for (int k = 0; k < n_s; ++k)
+      for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
+  }
+  for (int d = 0; d < nd; ++d) {
+    const mf_domain_desc& D = dint[d];
+    MF_HIP(launch_assembly_init(F + D.field_offset, uo + D.field_offset, D.pitch, D.units_x, D.units_y, s));
+  }
+  for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P, c, PH_ASSEMBLY, uo, s, false));
+  for (int d = 0; d < nd; ++d) {
+    const mf_domain_desc& D = dom[d];
+    const float* uod = uo + dint[d].field_offset;
     const float* seed = uout_bar ? uout_bar + D.field_offset : nullptr;
+    if (u_out)
+      MF_HIP(hipMemcpy2DAsync(u_out + D.field_offset, D.pitch * 4, uod, D.pitch * 4, (32 * (size_t)D.units_x + 1) * 4,
+                              32 * (size_t)D.units_y + 1, hipMemcpyDeviceToDevice, s));
     if (J && seed)
-      MF_HIP(launch_grid_dot(seed, uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
+      MF_HIP(launch_grid_dot(seed, uod, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
     else if (J)
-      MF_HIP(launch_interior_sumsq(uo, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
-    // reverse: assembly (the ring of u_out is u0's, so a seed's ring passes
-    // straight to u0_bar), then the sweeps segment by segment
+      MF_HIP(launch_interior_sumsq(uod, D.pitch, D.units_x, D.units_y, part, J, d > 0 ? 1 : 0, s));
+    // the ring of u_out is u0's, so a seed's ring passes straight to u0_bar
+    float* ub = u0_bar + D.field_offset;
     if (seed)
       MF_HIP(launch_assembly_init(seed, ub, D.pitch, D.units_x, D.units_y, s));
     else
       MF_HIP(launch_fill2d(ub, D.pitch, D.units_x, D.units_y, 0.0f, s));
-    for (int c = 3; c >= 0; --c)
-      MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, F, seed ? seed : uo, ub, D.pitch, D.units_x,
-                                   D.units_y, c, targets, seed ? ADJ_SEED : ADJ_SUMSQ, s));
-    for (int i = A.n_ckpt - 1; i >= 0; --i) {
-      const int n_s = std::min(ckpt_every, K - i * ckpt_every);
-      MF_HIP(hipMemcpyAsync(F, ckpt + (size_t)i * A.fsize, ext * 4, hipMemcpyDeviceToDevice, s));
-      for (int k = 0; k < n_s; ++k)
-        for (int c = 0; c < 4; ++c) {
-          MF_HIP(hipMemcpyAsync(states + (size_t)(4 * k + c) * A.fsize, F, ext * 4, hipMemcpyDeviceToDevice, s));
-          MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
-        }
-      for (int k = n_s - 1; k >= 0; --k)
-        for (int c = 3; c >= 0; --c)
-          MF_HIP(launch_adjoint_colour(net, desc->width, whT, ab, states + (size_t)(4 * k + c) * A.fsize,
-                                       nullptr, ub, D.pitch, D.units_x, D.units_y, c, targets, ADJ_SWEEP, s));
-    }
+  }
+  // reverse: the assembly, then the sweeps segment by segment
+  const int w = desc->width;
+  for (int c = 3; c >= 0; --c)
+    MF_HIP(launch_adjoint_colour(net, w, whT, ab, F, lo, uout_bar ? uout_bar : uo, uout_bar ? 0 : lo, u0_bar,
+                                 d_doms, d_q, nd, n_place[c], c, targets, uout_bar ? ADJ_SEED : ADJ_SUMSQ, s));
+  for (int i = A.n_ckpt - 1; i >= 0; --i) {
+    const int n_s = std::min(ckpt_every, K - i * ckpt_every);
+    MF_HIP(hipMemcpyAsync(F, ckpt + (size_t)i * A.fsize, fbytes, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < n_s; ++k)
+      for (int c = 0; c < 4; ++c) {
+        MF_HIP(hipMemcpyAsync(states + (size_t)(4 * k + c) * A.fsize, F, fbytes, hipMemcpyDeviceToDevice, s));
+        MF_TRY(run_colour(ctx, P, c, PH_SWEEP, nullptr, s, false));
+      }
+    for (int k = n_s - 1; k >= 0; --k)
+      for (int c = 3; c >= 0; --c)
+        MF_HIP(launch_adjoint_colour(net, w, whT, ab, states + (size_t)(4 * k + c) * A.fsize, lo, nullptr, 0,
+                                     u0_bar, d_doms, d_q, nd, n_place[c], c, targets, ADJ_SWEEP, s));
   }
   return ok();
 }

@@ -204,7 +204,8 @@ hipError_t launch_grid_dot(const float* w, const float* u, int64_t pitch, int ux
 // output seed is 2 u_out on the interior (ADJ_SUMSQ) or a caller's seed (ADJ_SEED).
 enum { ADJ_SWEEP = 0, ADJ_SUMSQ = 1, ADJ_SEED = 2 };
 hipError_t launch_adjoint_colour(const NetPtrs& net, int width, const float* whT, const AdjointBuffers& ab,
-                                 const float* u_before, const float* u_out, float* ub, int64_t pitch, int ux,
-                                 int uy, int colour, int targets, int kind, hipStream_t s);
+                                 const float* u_before, int64_t before_shift, const float* u_out,
+                                 int64_t out_shift, float* ub, const DomEntry* doms, const int32_t* qbegin, int nd,
+                                 int n_place, int colour, int targets, int kind, hipStream_t s);
 
 }  // namespace mf

@@ -138,3 +138,60 @@ def test_adjoint_batch_domain_k20_against_stored_oracle(ctx):
           f"seeded {es:.3e} (J {Js.item():.6e} vs {float(g['J_seed']):.6e})", flush=True)
     assert e <= 1e-4 and es <= 1e-4
     assert abs(J.item() - float(g["J"])) <= 1e-5 * abs(float(g["J"]))
+
+
+def test_adjoint_whole_batch_k20(ctx):
+    """The 48-domain batch (4..48 units per side, width 256) reversed through
+    its 20 sweeps in one call: the smallest domain's gradient against the
+    stored float64 oracle gradient, and bitwise equal to that domain's own
+    call; J is the sum over the domains."""
+    import os
+    print("case: adjoint 48-domain batch K=20 ckpt=5", flush=True)
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_adjoint.npz"))
+    w = mi.WORKLOADS["C5"]
+    sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    batch = Batch(fields)
+    ub, J = mf_solve_adjoint(ctx, params, batch, None, w["sweeps"], w["ckpt"])
+    d = int(g["domain"])
+    ux, uy = (int(v) for v in sizes[d])
+    ubd, Jd = mf_solve_adjoint(ctx, params, torch.from_numpy(fields[d]).cuda(), (ux, uy), w["sweeps"], w["ckpt"])
+    torch.cuda.synchronize()
+    got = batch.field(d, ub)
+    e = _rel(got.cpu().numpy().astype(np.float64), g["u0_bar"])
+    print(f"batch adjoint domain {d}: rel L2 {e:.3e}", flush=True)
+    assert e <= 1e-4
+    assert torch.equal(got, ubd)
+    assert np.isfinite(J.item()) and J.item() > Jd.item()
+    assert torch.isfinite(ub).all()
+
+
+def test_adjoint_batch_with_gaps(ctx):
+    """A batch whose domains start past the buffer's start and leave other
+    data between them: the domains' gradients and assemblies equal their own
+    calls bitwise; u0_bar and u_out outside the domains are left untouched."""
+    import copy
+    print("case: adjoint batch with gaps", flush=True)
+    sizes, fields = mi.batched_domains(4, 1, 3, 1.0, seed=9)
+    params = torch.from_numpy(mi.random_params(128, seed=4)).cuda()
+    full = Batch(fields)
+    keep = [1, 3]
+    sub = copy.copy(full)
+    sub.units = [full.units[i] for i in keep]
+    sub.offsets = [full.offsets[i] for i in keep]
+    sub.descs = (type(full.descs[0]) * len(keep))(*[full.descs[i] for i in keep])
+    ub = torch.full_like(full.buf, 7.0)
+    uo = torch.full_like(full.buf, -3.0)
+    ub, J = mf_solve_adjoint(ctx, params, sub, None, 3, 2, u_out=uo, u0_bar=ub)
+    total = 0.0
+    for j, i in enumerate(keep):
+        ux, uy = full.units[i]
+        uoi = torch.empty_like(full.field(i))
+        ubi, Ji = mf_solve_adjoint(ctx, params, full.field(i).clone(), (ux, uy), 3, 2, u_out=uoi)
+        torch.cuda.synchronize()
+        assert torch.equal(sub.field(j, ub), ubi), i
+        assert torch.equal(sub.field(j, uo), uoi), i
+        total += Ji.item()
+    for i in (0, 2):
+        assert bool((full.field(i, ub) == 7.0).all()) and bool((full.field(i, uo) == -3.0).all()), i
+    assert abs(J.item() - total) <= 1e-6 * abs(total)
