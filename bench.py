@@ -241,8 +241,8 @@ def c4_section(ctx, args, prec_name):
             cpath = os.path.join(GOLDEN, "c4_cond.npz")
             if os.path.exists(cpath):
                 c = np.load(cpath)
-                ref = {int(k): t["fp64"][list(t["K"]).index(k)] for k in c["K"] if k in t["K"]}
-                spread = {int(k): _rel(c["fp32"][i], ref[int(k)]) for i, k in enumerate(c["K"])
+                ref = {int(k): t["fp64"][list(t["K"]).index(k)] for k in c["K_fp32"] if k in t["K"]}
+                spread = {int(k): _rel(c["fp32"][i], ref[int(k)]) for i, k in enumerate(c["K_fp32"])
                           if int(k) in ref}
             res["parity"]["trajectory"] = trajectory_parity(ctx, params, field, (ux, uy), prec, t["fp64"],
                                                             t["K"], g["skel_j"], g["skel_i"], spread)

@@ -31,8 +31,8 @@ c2_traj.npz -- the 16 x 16-unit workload's skeleton at 8192 sampled points
     rounding at float32 level alone moves the trajectory (its conditioning).
 c4_traj.npz -- 64 x 64 units: the c4 sampled skeleton values after each sweep
     count in TRAJ_K (float64, up to 500 sweeps).
-c4_cond.npz -- 64 x 64 units, the "fp64_perturbed" and "fp32" runs of the
-    same samples up to 50 sweeps.
+c4_cond.npz -- 64 x 64 units, the "fp64_perturbed" run of the same samples
+    up to 50 sweeps (K) and the "fp32" run up to 500 (K_fp32).
 c5_k20.npz -- the 48-domain batch's smallest, median and largest domain at
     its stated 20 sweeps: sampled skeleton after 1, 5, 10, 15 and 20 sweeps
     and the assembly after 20 at sampled points, for the three runs above.
@@ -281,15 +281,18 @@ def c4_traj():
 
 
 def c4_cond():
+    """The "fp64_perturbed" run up to 50 sweeps and the "fp32" run up to the
+    workload's 500, at the c4 sample points."""
     w = mi.WORKLOADS["C4"]
     ux, uy = w["units"]
     field = mi.workload_field("C4")
     params = mi.xavier_params(w["width"], seed=0)
     sj, si = _c4_samples()
-    ks = [k for k in TRAJ_K if k <= 50]
-    out = {"K": np.array(ks, dtype=np.int32), "field_sha": _sha(field), "params_sha": _sha(params)}
+    out = {"field_sha": _sha(field), "params_sha": _sha(params)}
     t0 = time.time()
     for name, solver, dt in _runs(params, w["width"])[1:]:
+        ks = [k for k in TRAJ_K if k <= (50 if name == "fp64_perturbed" else w["sweeps"])]
+        out["K" if name == "fp64_perturbed" else "K_fp32"] = np.array(ks, dtype=np.int32)
         u = torch.from_numpy(field).to(dt)
         rows = []
         for k in range(1, ks[-1] + 1):
