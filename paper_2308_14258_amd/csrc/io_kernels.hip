@@ -118,32 +118,45 @@ __global__ void skel_unpack_kernel(const float* __restrict__ cols, int64_t cpitc
 
 // Gather from the side layout: each of the four edges is one contiguous run
 // (bottom and top in the field's rows, right and left in cols). A workgroup
-// of 128 kSkelPPW threads takes kSkelPPW consecutive placements of its die's
-// range.
+// has kSkelPPW placement slots (128 threads each for the gather, 64 for the
+// scatter) and each thread handles ILP placements, kSkelPPW apart, whose
+// loads it issues together: the kernels are bound by the bytes in flight per
+// CU, and one 4-byte load per thread leaves the HBM pipe mostly idle.
 constexpr int kSkelPPW = 4;
+constexpr int kGatherIlp = 8, kScatterIlp = 4;
 // Placement of slot `sub` of workgroup `blk` (die blk mod 8): each die's
-// workgroups walk its contiguous range kSkelPPW placements at a time.
-__device__ __forceinline__ int64_t xcd_placement_ppw(int64_t blk, int sub, int64_t per_xcd, int64_t q0,
+// workgroups walk its contiguous range `group` placements at a time.
+__device__ __forceinline__ int64_t xcd_placement_ppw(int64_t blk, int sub, int group, int64_t per_xcd, int64_t q0,
                                                      int64_t n_q) {
-  const int64_t q = (blk % kXcds) * per_xcd + (blk / kXcds) * kSkelPPW + sub;
+  const int64_t q = (blk % kXcds) * per_xcd + (blk / kXcds) * group + sub;
   return q < n_q ? q0 + q : -1;
 }
 __global__ __launch_bounds__(kNB * kSkelPPW) void gather_skel_kernel(const float* __restrict__ u, int64_t pitch,
                                                           const float* __restrict__ cols, int64_t cpitch, int ux,
                                                           int colour, int64_t q0, int64_t n_q, int64_t per_xcd,
                                                           float* __restrict__ G) {
-  const int64_t q = xcd_placement_ppw(blockIdx.x, threadIdx.x >> 7, per_xcd, q0, n_q);
-  if (q < 0) return;
-  int a, b;
-  placement_of((int)q, colour, ux, a, b);
   const int k = threadIdx.x & 127, side = k >> 5, m = k & 31;
-  const int64_t r0 = (int64_t)kHalf * b;   // bottom row / first row of the vertical edges
-  float v;
-  if (side == 0) v = u[r0 * pitch + kHalf * a + m];                          // (m, 0)
-  else if (side == 1) v = cols[(int64_t)(a + 2) * cpitch + r0 + m];          // (32, m)
-  else if (side == 2) v = u[(r0 + kS) * pitch + kHalf * a + kS - m];         // (32 - m, 32)
-  else v = cols[(int64_t)a * cpitch + r0 + kS - m];                          // (0, 32 - m)
-  G[q * kNB + k] = v;
+  float v[kGatherIlp];
+  int64_t qs[kGatherIlp];
+  // addresses formed without branches, so that the loads are in flight
+  // together; a slot past the end reads placement q0 and stores nothing
+#pragma unroll
+  for (int i = 0; i < kGatherIlp; ++i) {
+    const int64_t q =
+        xcd_placement_ppw(blockIdx.x, (threadIdx.x >> 7) + i * kSkelPPW, kSkelPPW * kGatherIlp, per_xcd, q0, n_q);
+    qs[i] = q;
+    int a, b;
+    placement_of((int)(q >= 0 ? q : q0), colour, ux, a, b);
+    const int64_t r0 = (int64_t)kHalf * b;    // bottom row / first row of the vertical edges
+    const int mm = side < 2 ? m : kS - m;      // sides 2 and 3 run backwards
+    const bool in_u = (side & 1) == 0;         // (m, 0) and (32 - m, 32) in the field; (32, m), (0, 32 - m) in cols
+    const int64_t off = in_u ? (r0 + (side == 2 ? kS : 0)) * pitch + kHalf * a + mm
+                             : (int64_t)(side == 1 ? a + 2 : a) * cpitch + r0 + mm;
+    v[i] = (in_u ? u : cols)[off];
+  }
+#pragma unroll
+  for (int i = 0; i < kGatherIlp; ++i)
+    if (qs[i] >= 0) G[qs[i] * kNB + k] = v[i];
 }
 
 // CROSS scatter into the side layout: the vertical centre line (targets
@@ -154,21 +167,34 @@ __global__ __launch_bounds__(64 * kSkelPPW) void scatter_skel_kernel(const float
                                                           int64_t pitch, float* __restrict__ cols, int64_t cpitch,
                                                           int ux, int colour, int64_t q0, int64_t n_q,
                                                           int64_t per_xcd) {
-  const int64_t q = xcd_placement_ppw(blockIdx.x, threadIdx.x >> 6, per_xcd, q0, n_q);
-  if (q < 0) return;
-  int a, b;
-  placement_of((int)q, colour, ux, a, b);
   const int t = threadIdx.x & 63;
-  const float* src = pred + q * kCross;
-  float* row = u + (int64_t)(kHalf * b + kHalf) * pitch + kHalf * a;   // row j = 16 b + 16 from i = 16 a
-  if (t < 31) {
-    cols[(int64_t)(a + 1) * cpitch + kHalf * b + 1 + t] = src[t];
-  } else if (t < kCross) {
-    int ti, tj;
-    target_local<0>(t, ti, tj);
-    row[ti] = src[t];
-  } else if (t == kCross) {
-    row[kHalf] = src[kHalf - 1];
+  float v[kScatterIlp];
+  int64_t qs[kScatterIlp];
+  // loads first, without branches (lanes 61..63 and slots past the end read
+  // a valid prediction and store nothing or the centre)
+#pragma unroll
+  for (int i = 0; i < kScatterIlp; ++i) {
+    const int64_t q =
+        xcd_placement_ppw(blockIdx.x, (threadIdx.x >> 6) + i * kSkelPPW, kSkelPPW * kScatterIlp, per_xcd, q0, n_q);
+    qs[i] = q;
+    v[i] = pred[(q >= 0 ? q : q0) * kCross + (t < kCross ? t : kHalf - 1)];
+  }
+#pragma unroll
+  for (int i = 0; i < kScatterIlp; ++i) {
+    const int64_t q = qs[i];
+    if (q < 0) continue;
+    int a, b;
+    placement_of((int)q, colour, ux, a, b);
+    float* row = u + (int64_t)(kHalf * b + kHalf) * pitch + kHalf * a;   // row j = 16 b + 16 from i = 16 a
+    if (t < 31) {
+      cols[(int64_t)(a + 1) * cpitch + kHalf * b + 1 + t] = v[i];
+    } else if (t < kCross) {
+      int ti, tj;
+      target_local<0>(t, ti, tj);
+      row[ti] = v[i];
+    } else if (t == kCross) {
+      row[kHalf] = v[i];   // the centre, target 15, also in the row
+    }
   }
 }
 
@@ -196,8 +222,9 @@ hipError_t launch_gather_skel(const float* u, int64_t pitch, const float* cols, 
                               int64_t n_q, float* G, hipStream_t s) {
   for (int64_t q0 = 0; q0 < n_q; q0 += kIoChunk) {
     const int64_t n = n_q - q0 < kIoChunk ? n_q - q0 : kIoChunk;
-    const int64_t per = (per_xcd_of(n) + kSkelPPW - 1) / kSkelPPW * kSkelPPW;
-    hipLaunchKernelGGL(gather_skel_kernel, dim3((unsigned)(per * kXcds / kSkelPPW)), dim3(kNB * kSkelPPW), 0, s, u,
+    constexpr int group = kSkelPPW * kGatherIlp;
+    const int64_t per = (per_xcd_of(n) + group - 1) / group * group;
+    hipLaunchKernelGGL(gather_skel_kernel, dim3((unsigned)(per * kXcds / group)), dim3(kNB * kSkelPPW), 0, s, u,
                        pitch, cols, skel_cols_pitch(uy), ux, colour, q0, n, per, G);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -209,8 +236,9 @@ hipError_t launch_scatter_skel(const float* pred, float* u, int64_t pitch, float
                                int64_t n_q, hipStream_t s) {
   for (int64_t q0 = 0; q0 < n_q; q0 += kIoChunk) {
     const int64_t n = n_q - q0 < kIoChunk ? n_q - q0 : kIoChunk;
-    const int64_t per = (per_xcd_of(n) + kSkelPPW - 1) / kSkelPPW * kSkelPPW;
-    hipLaunchKernelGGL(scatter_skel_kernel, dim3((unsigned)(per * kXcds / kSkelPPW)), dim3(64 * kSkelPPW), 0, s,
+    constexpr int group = kSkelPPW * kScatterIlp;
+    const int64_t per = (per_xcd_of(n) + group - 1) / group * group;
+    hipLaunchKernelGGL(scatter_skel_kernel, dim3((unsigned)(per * kXcds / group)), dim3(64 * kSkelPPW), 0, s,
                        pred, u, pitch, cols, skel_cols_pitch(uy), ux, colour, q0, n, per);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
