@@ -195,3 +195,27 @@ def test_adjoint_batch_with_gaps(ctx):
     for i in (0, 2):
         assert bool((full.field(i, ub) == 7.0).all()) and bool((full.field(i, uo) == -3.0).all()), i
     assert abs(J.item() - total) <= 1e-6 * abs(total)
+
+
+def test_adjoint_batch_seeded_interior_equals_single(ctx):
+    """A batch with a per-point seed and INTERIOR sweep targets: every
+    domain's u0_bar and u_out equal its own call bitwise, J is the sum."""
+    print("case: adjoint batch, seed, INTERIOR", flush=True)
+    sizes, fields = mi.batched_domains(4, 1, 3, 1.0, seed=5)
+    params = torch.from_numpy(mi.random_params(128, seed=6)).cuda()
+    batch = Batch(fields)
+    seed = torch.from_numpy(np.random.default_rng(8).standard_normal(batch.buf.numel()).astype(np.float32)).cuda()
+    uo = torch.empty_like(batch.buf)
+    ub, J = mf_solve_adjoint(ctx, params, batch, None, 3, 2, MF_INTERIOR, u_out=uo, uout_bar=seed)
+    total = 0.0
+    for i in range(len(fields)):
+        ux, uy = batch.units[i]
+        seed_i = batch.field(i, seed).clone()
+        uoi = torch.empty_like(seed_i)
+        ubi, Ji = mf_solve_adjoint(ctx, params, batch.field(i).clone(), (ux, uy), 3, 2, MF_INTERIOR, u_out=uoi,
+                                   uout_bar=seed_i)
+        torch.cuda.synchronize()
+        assert torch.equal(batch.field(i, ub), ubi), i
+        assert torch.equal(batch.field(i, uo), uoi), i
+        total += Ji.item()
+    assert abs(J.item() - total) <= 1e-5 * max(abs(total), 1.0)
