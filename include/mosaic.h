@@ -57,10 +57,15 @@
  *   projection on the float32 VALU). MF_BF16 rounds the GEMM operands to
  *   bf16 and accumulates in float32 on MFMA: the boundary projection
  *   W1g g (g and W1g rounded to bf16) and the three hidden d x d GEMMs
- *   (weights and the incoming activations rounded to bf16). In both, the
+ *   (weights and the incoming activations rounded to bf16). MF_FP16 does the
+ *   same with IEEE half operands (10 stored mantissa bits against bf16's 7,
+ *   same MFMA rate): the gathered boundary values and every weight must lie
+ *   within +-65504 (larger ones become infinite and the result is not
+ *   finite; the delta test then reports MF_ENONFINITE). In all three, the
  *   field, the gather and scatter, the coordinate term W1x (x, y) + b1 of
  *   the first layer, every bias, tanh, the output layer w5 . h4 + b5 and
- *   the overlap averaging are float32.
+ *   the overlap averaging are float32. sdnet_forward computes the
+ *   projection in float32 in every precision.
  *
  * Memory and streams: every pointer argument marked "device" is device
  * memory owned by the caller; "host" pointers are host memory. The library
@@ -97,7 +102,7 @@ enum {
   MF_EUNSUPPORTED = 7    /* valid request this build does not implement      */
 };
 
-enum { MF_FP32 = 0, MF_BF16 = 1 };                 /* precision           */
+enum { MF_FP32 = 0, MF_BF16 = 1, MF_FP16 = 2 };    /* precision           */
 enum { MF_CROSS = 0, MF_INTERIOR = 1 };             /* target set          */
 enum { MF_MULTIPLICATIVE = 0, MF_ADDITIVE = 1 };    /* sweep mode          */
 enum { MF_TANH = 0, MF_GELU = 1 };                  /* activation          */
@@ -146,20 +151,21 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
 
 /* Tile shape of the colour-phase kernel for one precision: the tile height
  * (rows of (placement, target) pairs per workgroup) is 32 or 64 for MF_FP32
- * and 64, 128 or 256 for MF_BF16. Height 32 in fp32 streams the hidden
+ * and 64, 128 or 256 for MF_BF16 and MF_FP16. Height 32 in fp32 streams the hidden
  * weights from L2; height 64 keeps each wave's slice of them in registers,
  * or streams them when or-ed with MF_TILE_STREAM (fewer registers, two
  * workgroups per CU). For MF_BF16 heights 128 and 256 may be or-ed with
  * MF_TILE_WIDE (each wave then owns 64 output columns instead of 32, halving
- * the LDS reads of the activations), and 256 | MF_TILE_ROWSPLIT selects the
+ * the LDS reads of the activations; not for MF_FP16), and
+ * 256 | MF_TILE_ROWSPLIT selects the
  * row-split tile (each of 8 waves owns 32 rows and every unit; activations
  * stay in registers and the hidden weights stream through LDS); or-ed also
  * with MF_TILE_PERSIST, a batch's row-split phase runs as a persistent grid
  * (one workgroup per CU walking the tiles) instead of one tile per
  * workgroup (single domains ignore the flag). 0 restores
  * the automatic choice: a tuned value from mf_autotune, else a rule on the
- * phase's rows per CU. MF_BF16: 256 | MF_TILE_ROWSPLIT from 256 rows per CU
- * up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
+ * phase's rows per CU. MF_BF16 and MF_FP16: 256 | MF_TILE_ROWSPLIT from
+ * 256 rows per CU up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
  * 64 | MF_TILE_STREAM for a single domain from 128 rows per CU up. */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
@@ -172,7 +178,7 @@ mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
  * descriptors. Candidates: MF_FP32 32, 64, 64 | MF_TILE_STREAM (batches: 32,
  * 64); MF_BF16 64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE,
  * 256 | MF_TILE_ROWSPLIT (batches also 256 | MF_TILE_ROWSPLIT |
- * MF_TILE_PERSIST). The sweeps run on u itself (it advances by
+ * MF_TILE_PERSIST); MF_FP16 the same without the MF_TILE_WIDE shapes. The sweeps run on u itself (it advances by
  * (3 trials + 1) x candidates sweeps); pass a scratch copy to keep the field.
  * rows_out (host, nullable) receives the choice. The tanh network only
  * (MF_EUNSUPPORTED for MF_GELU). Synchronises the stream. */
@@ -231,7 +237,7 @@ mf_status mf_sweep(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params,
  * array of 1 MiB, one per GPU, held until the process ends, into which each
  * call writes the prepared network and the batch table before its kernels
  * read them. That bounds the request: the network at width 256 (about
- * 0.9 MiB in MF_FP32, 0.6 MiB in MF_BF16) plus 56 bytes per domain must
+ * 0.9 MiB in MF_FP32, 0.6 MiB in MF_BF16 or MF_FP16) plus 56 bytes per domain must
  * fit, else MF_ENOMEM with nothing enqueued (about 2,000 domains at width
  * 256 in MF_FP32). No hipMalloc, hipFree or other allocating call is made.
  * All calls on one GPU share its array, so calls that overlap in time on

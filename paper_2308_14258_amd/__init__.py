@@ -4,7 +4,7 @@ hand-written HIP kernels behind a C ABI (include/mosaic.h).
 The Python layer only marshals arguments: torch tensors provide device
 memory and the current stream; every step runs in libmosaic.so.
 """
-from ._lib import (MF_ADDITIVE, MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, MF_MULTIPLICATIVE,  # noqa: F401
+from ._lib import (MF_ADDITIVE, MF_BF16, MF_CROSS, MF_FP16, MF_FP32, MF_INTERIOR, MF_MULTIPLICATIVE,  # noqa: F401
                    MF_GELU, MF_TANH, MF_TILE_PERSIST, MF_TILE_ROWSPLIT, MF_TILE_STREAM, MF_TILE_WIDE,
                    MosaicError, load)
 from .api import (Batch, Context, PhysicsLoss, mf_autotune, mf_colour_placements, mf_gather,  # noqa: F401

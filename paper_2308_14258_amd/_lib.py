@@ -15,7 +15,7 @@ MF_OK, MF_EINVAL, MF_ESHAPE, MF_ENOMEM, MF_EDEVICE, MF_ENONFINITE, MF_ENOTCONVER
     MF_EUNSUPPORTED = range(8)
 STATUS_NAMES = {0: "MF_OK", 1: "MF_EINVAL", 2: "MF_ESHAPE", 3: "MF_ENOMEM", 4: "MF_EDEVICE",
                 5: "MF_ENONFINITE", 6: "MF_ENOTCONVERGED", 7: "MF_EUNSUPPORTED"}
-MF_FP32, MF_BF16 = 0, 1
+MF_FP32, MF_BF16, MF_FP16 = 0, 1, 2
 MF_CROSS, MF_INTERIOR = 0, 1
 MF_MULTIPLICATIVE, MF_ADDITIVE = 0, 1
 MF_TANH = 0

@@ -39,7 +39,7 @@ NetLayout net_layout(int width, int prec, size_t base, int n_in) {
   const size_t d = (size_t)width;
   size_t o = align256(base);
   L.w1gT = o; o = align256(o + (size_t)n_in * d * 4);
-  L.w1gb = o; if (prec == MF_BF16 && n_in == 128) o = align256(o + 128 * d * 2);
+  L.w1gb = o; if (prec != MF_FP32 && n_in == 128) o = align256(o + 128 * d * 2);
   L.w1x = o;  o = align256(o + 2 * d * 4);
   L.b1 = o;   o = align256(o + d * 4);
   L.wh = o;   o = align256(o + 3 * d * d * (prec == MF_FP32 ? 4 : 2));
@@ -188,6 +188,7 @@ static mf_status gelu_limits(const mf_sdnet_desc* d, int prec, int mode) {
 static bool valid_tile_rows(int prec, int rows) {
   if (prec == MF_FP32) return rows == 32 || rows == 64 || rows == (64 | MF_TILE_STREAM);
   if (rows & MF_TILE_STREAM) return false;
+  if (prec == MF_FP16 && (rows & MF_TILE_WIDE)) return false;
   if (rows & MF_TILE_ROWSPLIT)
     return rows == (256 | MF_TILE_ROWSPLIT) || rows == (256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST);
   const int r = rows & ~MF_TILE_WIDE;
@@ -196,7 +197,7 @@ static bool valid_tile_rows(int prec, int rows) {
 }
 
 static mf_status check_prec(int prec) {
-  if (prec != MF_FP32 && prec != MF_BF16) return fail(MF_EINVAL, "precision %d unknown", prec);
+  if (prec != MF_FP32 && prec != MF_BF16 && prec != MF_FP16) return fail(MF_EINVAL, "precision %d unknown", prec);
   return MF_OK;
 }
 
@@ -315,7 +316,7 @@ struct mf_ctx {
   int device;
   int n_cu;
   void* scratch = nullptr;            // this device's static scratch (mf_sweep_noalloc)
-  int force_rows[2] = {0, 0};         // per precision; 0 = automatic
+  int force_rows[3] = {0, 0, 0};      // per precision; 0 = automatic
   std::vector<TuneEntry> tuned;
   hipStream_t gstream = nullptr;     // graph launches (default priority)
   hipEvent_t fork = nullptr, join = nullptr;
@@ -543,9 +544,9 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
         (nd == 1 ? (t.key == 0 && t.ux == dom->units_x && t.uy == dom->units_y) : t.key == key))
       return t.rows;
   const int64_t n_cu = ctx->n_cu;
-  // bf16: the row-split tile from one 256-row tile per CU up; below that the
+  // bf16 and fp16: the row-split tile from one 256-row tile per CU up; below that the
   // 64-row column-split tile spreads the rows over more CUs
-  if (prec == MF_BF16) return rows >= 256 * n_cu ? (256 | MF_TILE_ROWSPLIT) : 64;
+  if (prec != MF_FP32) return rows >= 256 * n_cu ? (256 | MF_TILE_ROWSPLIT) : 64;
   // fp32: 64-row tiles with register weights from one 32-row tile per CU up
   // (a 16 x 16-unit phase, ~0.9 such tiles per CU: 54 us against 61 us with
   // 32-row tiles); below that, 32-row tiles spread the few rows over more CUs.
@@ -842,8 +843,9 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   const int cands_fp32[] = {32, 64, 64 | MF_TILE_STREAM};
   const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE, 256 | MF_TILE_ROWSPLIT,
                             256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
-  const int* cands = prec == MF_FP32 ? cands_fp32 : cands_bf16;
-  const int n_cands = prec == MF_FP32 ? (batch ? 2 : 3) : (batch ? 7 : 6);
+  const int cands_fp16[] = {64, 128, 256, 256 | MF_TILE_ROWSPLIT, 256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
+  const int* cands = prec == MF_FP32 ? cands_fp32 : prec == MF_BF16 ? cands_bf16 : cands_fp16;
+  const int n_cands = prec == MF_FP32 ? (batch ? 2 : 3) : prec == MF_BF16 ? (batch ? 7 : 6) : (batch ? 5 : 4);
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;

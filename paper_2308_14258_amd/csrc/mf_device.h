@@ -22,6 +22,7 @@ constexpr int kInterior = 961;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 // Local (i, j) of boundary sample k (0..127), counter-clockwise from (0, 0).
 __device__ __forceinline__ void boundary_local(int k, int& i, int& j) {
@@ -123,6 +124,10 @@ __device__ __forceinline__ floatx16 mfma32x32x16_bf16(bf16x8 a, bf16x8 b, floatx
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ floatx16 mfma32x32x16_f16(halfx8 a, halfx8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
 // Row of the 32x32 MFMA accumulator held by lane l in register v.
 __device__ __forceinline__ int acc_row(int lane, int v) {
   return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -134,7 +139,13 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
   return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
+// float -> fp16, round to nearest even (v_cvt_pk_f16_f32 for pairs).
+__device__ __forceinline__ uint16_t f16_bits(float f) {
+  return __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void bf16_pair(float a, float b, uint16_t& ha, uint16_t& hb) {
   const bf16x2 p = {(__bf16)a, (__bf16)b};
   const uint32_t u = __builtin_bit_cast(uint32_t, p);

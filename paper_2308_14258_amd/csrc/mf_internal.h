@@ -22,10 +22,10 @@ enum { ACT_TANH = 0, ACT_GELU = 1 };
 struct NetLayout {
   int width = 0, prec = 0;
   size_t w1gT = 0;   // float [128][d]: W1 boundary block, k-major
-  size_t w1gb = 0;   // bf16 W1 boundary block in MFMA operand order (MF_BF16 only)
+  size_t w1gb = 0;   // 16-bit W1 boundary block in MFMA operand order (MF_BF16, MF_FP16)
   size_t w1x = 0;    // float [d][2]: W1 coordinate columns
   size_t b1 = 0;     // float [d]
-  size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32 or bf16)
+  size_t wh = 0;     // 3 hidden matrices, MFMA operand order (fp32, bf16 or fp16)
   size_t bh = 0;     // float [3][d]
   size_t w5 = 0;     // float [d]
   size_t b5 = 0;     // float [2]: b5, b5 + sum(w5)

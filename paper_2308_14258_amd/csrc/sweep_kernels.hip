@@ -53,13 +53,15 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
   for (int64_t idx = tid; n_in == 128 && idx < 128 * (int64_t)d; idx += nthr) {
     const int64_t k = idx / d, n = idx - k * d;
     w1gT[idx] = params[n * 130 + k];
-    if (prec == MF_BF16) {
+    if (prec != MF_FP32) {
+      // 16-bit W1g in MFMA operand order, in the precision of the phase
       // [cb = d/32][kg = 8][lane 64][8]: lane l, element e holds
       // W1[32 cb + (l & 31)][16 kg + 8 (l >> 5) + e]
       const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
       const int64_t rest = idx >> 9;
       const int kg = (int)(rest % 8), cb = (int)(rest / 8);
-      w1gb[idx] = bf16_bits(params[(int64_t)(32 * cb + (lane & 31)) * 130 + 16 * kg + 8 * (lane >> 5) + e]);
+      const float wv = params[(int64_t)(32 * cb + (lane & 31)) * 130 + 16 * kg + 8 * (lane >> 5) + e];
+      w1gb[idx] = prec == MF_FP16 ? f16_bits(wv) : bf16_bits(wv);
     }
   }
   for (int64_t n = tid; n < d; n += nthr) {
@@ -96,7 +98,8 @@ __global__ void prepare_net_kernel(const float* __restrict__ params, int d, int 
       const int kg = (int)(rest % (d / 16)), cb = (int)(rest / (d / 16));
       j = 32 * cb + (lane & 31);
       k = 16 * kg + 8 * (lane >> 5) + e;
-      static_cast<uint16_t*>(wh)[idx] = bf16_bits(params[off_w2 + l * lstride + (int64_t)j * d + k]);
+      const float wv = params[off_w2 + l * lstride + (int64_t)j * d + k];
+      static_cast<uint16_t*>(wh)[idx] = prec == MF_FP16 ? f16_bits(wv) : bf16_bits(wv);
     }
   }
 }
@@ -151,6 +154,7 @@ struct TileArgs {
 
 template <int PREC> struct HType { typedef float T; };
 template <> struct HType<1> { typedef uint16_t T; };
+template <> struct HType<2> { typedef uint16_t T; };
 
 // MFMA on one k group of a d x d layer. The prepared weights are the A
 // operand (rows = output units j) and the activations the B operand (columns
@@ -174,10 +178,41 @@ template <> struct Mma<0> {
 template <> struct Mma<1> {
   typedef bf16x8 T;
   static constexpr int K = 16;
+  static __device__ __forceinline__ floatx16 one(const T& w, const T& h, const floatx16& c) {
+    return mfma32x32x16_bf16(w, h, c);
+  }
   template <int N>
   static __device__ __forceinline__ void run(const T& w, const T (&h)[N], floatx16 (&c)[N]) {
 #pragma unroll
-    for (int n = 0; n < N; ++n) c[n] = mfma32x32x16_bf16(w, h[n], c[n]);
+    for (int n = 0; n < N; ++n) c[n] = one(w, h[n], c[n]);
+  }
+  // two floats -> one register of two operand elements
+  static __device__ __forceinline__ uint32_t pack(float a, float b) {
+    const bf16x2 p = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, p);
+  }
+};
+// fp16 operands: the same layouts and k order as bf16; three more mantissa
+// bits for weights and activations, range +-65504 (activations are k tanh,
+// |k tanh| < 2.9; hidden weights must stay below 65504).
+template <> struct Mma<2> {
+  typedef halfx8 T;
+  static constexpr int K = 16;
+  static __device__ __forceinline__ floatx16 one(const T& w, const T& h, const floatx16& c) {
+    return mfma32x32x16_f16(w, h, c);
+  }
+  template <int N>
+  static __device__ __forceinline__ void run(const T& w, const T (&h)[N], floatx16 (&c)[N]) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) c[n] = one(w, h[n], c[n]);
+  }
+  // The values pass through an opaque move: otherwise the compiler folds the
+  // tanh's last fma into a mixed-precision fma with fp16 output in some tile
+  // forms and not in others, and the tiles would round differently.
+  static __device__ __forceinline__ uint32_t pack(float a, float b) {
+    asm volatile("" : "+v"(a), "+v"(b));
+    const halfx2 p = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, p);
   }
 };
 
@@ -194,8 +229,7 @@ __device__ __forceinline__ void store4(typename HType<PREC>::T* p, float a, floa
   if constexpr (PREC == 0) {
     *reinterpret_cast<floatx4*>(p) = floatx4{a, b, c, d};
   } else {
-    const bf16x2 lo = {(__bf16)a, (__bf16)b}, hi = {(__bf16)c, (__bf16)d};
-    *reinterpret_cast<u32x2*>(p) = u32x2{__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)};
+    *reinterpret_cast<u32x2*>(p) = u32x2{Mma<PREC>::pack(a, b), Mma<PREC>::pack(c, d)};
   }
 }
 
@@ -409,7 +443,7 @@ __device__ __forceinline__ void hidden_and_output(typename HType<PREC>::T* Hs,
 
 template <int D, int R, int TMODE, int PREC, int SRC, int OUT, int CPW = 32, bool WREG = true>
 __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0) {
-  static_assert(CPW == 32 || (CPW == 64 && PREC == 1), "64 columns per wave: bf16 only");
+  static_assert(CPW == 32 || (CPW == 64 && PREC != 0), "64 columns per wave: 16-bit only");
   constexpr int NTH = (D / CPW) * 64;        // one wave per CPW output columns
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = SRC == SRC_GATHER ? (R - 1) / T + 2 : 1;
@@ -499,9 +533,10 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
       gs[idx] = A.u_in[(int64_t)(kHalf * b + bj) * A.pitch + kHalf * a + bi];
     }
     __syncthreads();
-    if constexpr (PREC == 1) {
-      // bf16: W1g G^T on MFMA. A = the tile's boundary vectors (rows p < np,
-      // at most NPMAX <= 8, rounded to bf16), B = the wave's 32-column slice
+    if constexpr (PREC != 0) {
+      // 16-bit: W1g G^T on MFMA in the phase's precision. A = the tile's
+      // boundary vectors (rows p < np, at most NPMAX <= 8, rounded to the
+      // phase's 16-bit type), B = the wave's 32-column slice
       // of W1g in operand order; a lane's accumulator registers 0..3 hold
       // rows 4 (lane >> 5) .. + 3 of its column. The stored projection
       // carries b1 and the factor 2 log2(e) of the tanh.
@@ -517,16 +552,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& A, const int64_t row0)
         for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 #pragma unroll
         for (int kg = 0; kg < 8; ++kg) {
-          bf16x8 a;
+          typedef typename Mma<PREC>::T PT;
+          u32x4 av = u32x4{0u, 0u, 0u, 0u};
           if (arow < np) {
             const floatx4 g0 = *reinterpret_cast<const floatx4*>(&gs[arow * kNB + 16 * kg + 8 * ahalf]);
             const floatx4 g1 = *reinterpret_cast<const floatx4*>(&gs[arow * kNB + 16 * kg + 8 * ahalf + 4]);
-            a = bf16x8{(__bf16)g0[0], (__bf16)g0[1], (__bf16)g0[2], (__bf16)g0[3],
-                       (__bf16)g1[0], (__bf16)g1[1], (__bf16)g1[2], (__bf16)g1[3]};
-          } else {
-            a = bf16x8{};
+            av = u32x4{Mma<PREC>::pack(g0[0], g0[1]), Mma<PREC>::pack(g0[2], g0[3]), Mma<PREC>::pack(g1[0], g1[1]),
+                       Mma<PREC>::pack(g1[2], g1[3])};
           }
-          acc = mfma32x32x16_bf16(a, __builtin_bit_cast(bf16x8, wp[kg * 64]), acc);
+          acc = Mma<PREC>::one(__builtin_bit_cast(PT, av), __builtin_bit_cast(PT, wp[kg * 64]), acc);
         }
         const float bb = net.b1[col];
 #pragma unroll
@@ -623,7 +657,7 @@ struct Shape {
   // waves per SIMD the register budget is sized for (HIP's second launch
   // bound): two 8-wave workgroups per CU, i.e. 128 VGPRs, where the LDS tile
   // allows it
-  static constexpr int MINW = ((PREC == 1 && CPW == 32 && R <= 128) || (PREC == 0 && !WREG)) ? 2 * NTH / 256 : 1;
+  static constexpr int MINW = ((PREC != 0 && CPW == 32 && R <= 128) || (PREC == 0 && !WREG)) ? 2 * NTH / 256 : 1;
 };
 
 // ---------------------------------------------------------------------------
@@ -647,26 +681,26 @@ struct Shape {
 // and 8 + 4 h + 0..3 (v[4..7]) of the group's 16, the operand wants units
 // 8 h + 0..7. One v_permlane32_swap per register pair moves the upper
 // half-wave's first quarter and the lower half-wave's second quarter across.
-__device__ __forceinline__ bf16x8 rs_operand(const float* v) {
-  const bf16x2 p0 = {(__bf16)v[0], (__bf16)v[1]}, p1 = {(__bf16)v[2], (__bf16)v[3]};
-  const bf16x2 q0 = {(__bf16)v[4], (__bf16)v[5]}, q1 = {(__bf16)v[6], (__bf16)v[7]};
-  const auto s0 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, q0),
-                                                   false, false);
-  const auto s1 = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, p1), __builtin_bit_cast(uint32_t, q1),
-                                                   false, false);
+template <int PREC>
+__device__ __forceinline__ typename Mma<PREC>::T rs_operand(const float* v) {
+  const uint32_t p0 = Mma<PREC>::pack(v[0], v[1]), p1 = Mma<PREC>::pack(v[2], v[3]);
+  const uint32_t q0 = Mma<PREC>::pack(v[4], v[5]), q1 = Mma<PREC>::pack(v[6], v[7]);
+  const auto s0 = __builtin_amdgcn_permlane32_swap(p0, q0, false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(p1, q1, false, false);
   // s[0]: lower half-wave keeps its own, upper gets the lower's; s[1] the reverse
-  return __builtin_bit_cast(bf16x8, u32x4{s0[0], s1[0], s0[1], s1[1]});
+  return __builtin_bit_cast(typename Mma<PREC>::T, u32x4{s0[0], s1[0], s0[1], s1[1]});
 }
 
-template <int D_, int PB_>
+template <int D_, int PB_, int PREC_ = 1>
 struct RsShape {
-  static constexpr int D = D_, R = 256, PREC = 1, CPW = 32, PB = PB_;
+  static constexpr int D = D_, R = 256, PREC = PREC_, CPW = 32, PB = PB_;
   static constexpr bool WREG = true, RS = true;
   static constexpr int NTH = 512 / PB, MINW = PB == 1 ? 2 : 1;
 };
 
-template <int D, int TMODE, int OUT, int PB>
+template <int D, int TMODE, int OUT, int PB, int PREC = 1>
 __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
+  typedef typename Mma<PREC>::T OT;   // 16-bit operand vector (bf16 or fp16)
   constexpr int R = 256, NW = 8 / PB, NTH = 64 * NW;
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = (R - 1) / T + 2;
@@ -728,14 +762,14 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 #pragma unroll
     for (int kg = 0; kg < 8; ++kg) {
-      bf16x8 a = bf16x8{};
+      u32x4 av = u32x4{0u, 0u, 0u, 0u};
       if (pn < np) {
         const floatx4 g0 = *reinterpret_cast<const floatx4*>(&gs[pn * kNB + 16 * kg + 8 * hh]);
         const floatx4 g1 = *reinterpret_cast<const floatx4*>(&gs[pn * kNB + 16 * kg + 8 * hh + 4]);
-        a = bf16x8{(__bf16)g0[0], (__bf16)g0[1], (__bf16)g0[2], (__bf16)g0[3],
-                   (__bf16)g1[0], (__bf16)g1[1], (__bf16)g1[2], (__bf16)g1[3]};
+        av = u32x4{Mma<PREC>::pack(g0[0], g0[1]), Mma<PREC>::pack(g0[2], g0[3]), Mma<PREC>::pack(g1[0], g1[1]),
+                   Mma<PREC>::pack(g1[2], g1[3])};
       }
-      acc = mfma32x32x16_bf16(a, __builtin_bit_cast(bf16x8, wp[kg * 64]), acc);
+      acc = Mma<PREC>::one(__builtin_bit_cast(OT, av), __builtin_bit_cast(OT, wp[kg * 64]), acc);
     }
     const float bb = net.b1[col];
 #pragma unroll
@@ -765,11 +799,13 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   }
   __syncthreads();   // projections, constants and the first half layer in LDS
 
-  // -- first layer straight into B-operand registers ---------------------------
-  bf16x8 H[2][PB][NKG];
+  // -- first layer straight into B-operand registers (pairs packed by the
+  // precision's converter) -------------------------------------------------
+  OT H[2][PB][NKG];
 #pragma unroll
   for (int kg = 0; kg < NKG; ++kg) {
     const int u0 = 16 * kg + 8 * hh;   // B operand: lane (point, half h) feeds units 16 kg + 8 h + 0..7
+    u32x4 hb[PB];                      // the operand's four registers, two units each
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
       const floatx4 wx = *reinterpret_cast<const floatx4*>(&wxy[u0 + 4 * g]);
@@ -780,10 +816,12 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
         float v[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = ktanh_exp2(fmaf(y[b], wy[e], fmaf(x[b], wx[e], c[e])));
-#pragma unroll
-        for (int e = 0; e < 4; ++e) H[0][b][kg][4 * g + e] = (__bf16)v[e];
+        hb[b][2 * g] = Mma<PREC>::pack(v[0], v[1]);
+        hb[b][2 * g + 1] = Mma<PREC>::pack(v[2], v[3]);
       }
     }
+#pragma unroll
+    for (int b = 0; b < PB; ++b) H[0][b][kg] = __builtin_bit_cast(OT, hb[b]);
   }
 
   // -- hidden layers: six half-layer steps ------------------------------------
@@ -793,8 +831,8 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const int l = k >> 1, hf = k & 1;
-    bf16x8(&hin)[PB][NKG] = H[l & 1];
-    bf16x8(&hout)[PB][NKG] = H[(l + 1) & 1];
+    OT(&hin)[PB][NKG] = H[l & 1];
+    OT(&hout)[PB][NKG] = H[(l + 1) & 1];
     // the other buffer's half was finished by every wave before the last barrier
     if (k < 5) fetch(k + 1, (k + 1) & 1);
     const u32x4* wb = wbuf[k & 1] + lane;
@@ -804,9 +842,9 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
     // accumulator elements is spread over the block's MFMAs so both pipes
     // stay busy
     constexpr int NI = HOB * NKG, RING = 4, EPK = 16 / NKG;   // epilogue elements per k group and block
-    bf16x8 ar[RING];
+    OT ar[RING];
 #pragma unroll
-    for (int i = 0; i < RING; ++i) ar[i] = __builtin_bit_cast(bf16x8, wb[i * 64]);
+    for (int i = 0; i < RING; ++i) ar[i] = __builtin_bit_cast(OT, wb[i * 64]);
     floatx16 acc[2][PB];
     float ev[PB][16];
     float dsum[PB];
@@ -830,8 +868,8 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
         const int i = j * NKG + kg;
         if (j < HOB) {
 #pragma unroll
-          for (int b = 0; b < PB; ++b) acc[j & 1][b] = mfma32x32x16_bf16(ar[i % RING], hin[b][kg], acc[j & 1][b]);
-          if (i + RING < NI) ar[i % RING] = __builtin_bit_cast(bf16x8, wb[(i + RING) * 64]);
+          for (int b = 0; b < PB; ++b) acc[j & 1][b] = Mma<PREC>::one(ar[i % RING], hin[b][kg], acc[j & 1][b]);
+          if (i + RING < NI) ar[i % RING] = __builtin_bit_cast(OT, wb[(i + RING) * 64]);
         }
         if (j > 0) {
 #pragma unroll
@@ -844,7 +882,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
                 ev[b][e] = ktanh_exp2(c);
                 if ((e & 7) == 7) {
                   const int h2 = e >> 3;
-                  hout[b][2 * obp + h2] = rs_operand(ev[b] + 8 * h2);
+                  hout[b][2 * obp + h2] = rs_operand<PREC>(ev[b] + 8 * h2);
                 }
               } else {
                 dsum[b] = fmaf(w5v[e >> 2][e & 3], rsig_exp2(c), dsum[b]);
@@ -880,7 +918,7 @@ template <class S, int TMODE, int SRC, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
   if constexpr (S::RS) {
     if constexpr (SRC == SRC_GATHER && OUT != OUT_LINEAR)
-      rs_body<S::D, TMODE, OUT, S::PB>(A, (A.block0 + blockIdx.x) * S::R);
+      rs_body<S::D, TMODE, OUT, S::PB, S::PREC>(A, (A.block0 + blockIdx.x) * S::R);
   } else {
     tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
   }
@@ -940,7 +978,7 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB>(A, (t - M.tile_begin[lo]) * S::R);
+    if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB, S::PREC>(A, (t - M.tile_begin[lo]) * S::R);
     else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
   };
   if constexpr (S::RS && !PERSIST) {
@@ -962,7 +1000,8 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
 // Tile shapes by (width, precision, tile code): fp32 32 (streamed weights),
 // 64 (register weights), 64 | MF_TILE_STREAM (streamed); bf16 64, 128, 256,
 // 128 or 256 | MF_TILE_WIDE (64 columns per wave) and 256 | MF_TILE_ROWSPLIT
-// (row-split tile). The caller has validated the code.
+// (row-split tile); fp16 the bf16 codes without MF_TILE_WIDE. The caller has
+// validated the code.
 template <int D, class F>
 static hipError_t with_shape_d(int prec, int code, F&& f) {
   const int r = code & 0xffff;
@@ -972,6 +1011,12 @@ static hipError_t with_shape_d(int prec, int code, F&& f) {
     if (r == 256) return f(Shape<D, 256, 1, 32, true>{});
     if (r == 128) return f(Shape<D, 128, 1, 32, true>{});
     return f(Shape<D, 64, 1, 32, true>{});
+  }
+  if (prec == MF_FP16) {   // the same tiles on fp16 operands (no 64-column forms)
+    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D, 1, 2>{});
+    if (r == 256) return f(Shape<D, 256, 2, 32, true>{});
+    if (r == 128) return f(Shape<D, 128, 2, 32, true>{});
+    return f(Shape<D, 64, 2, 32, true>{});
   }
   if (r == 64) return (code & MF_TILE_STREAM) ? f(Shape<D, 64, 0, 32, false>{}) : f(Shape<D, 64, 0, 32, true>{});
   return f(Shape<D, 32, 0, 32, false>{});

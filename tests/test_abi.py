@@ -128,7 +128,8 @@ def test_sweep_argument_errors(lib):
     assert _sweep(lib, mode=1) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # additive is valid
     assert _sweep(lib, mode=1, colour=2) == MF_EINVAL and b"additive" in lib.mf_last_error()
     assert _sweep(lib, mode=2) == MF_EINVAL
-    assert _sweep(lib, prec=2) == MF_EINVAL
+    assert _sweep(lib, prec=2) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # MF_FP16 is valid
+    assert _sweep(lib, prec=3) == MF_EINVAL and b"precision" in lib.mf_last_error()
     assert _sweep(lib, ws=0) == MF_EINVAL
     assert _sweep(lib, ws=FAKE + 64) == MF_EINVAL
     assert _sweep(lib, ws_bytes=1024) == MF_ENOMEM and b"needed" in lib.mf_last_error()
@@ -272,7 +273,7 @@ def test_sweep_noalloc_argument_errors(lib):
     assert _noalloc(lib, desc=SdnetDesc(64, 4, 128, 0)) == MF_ESHAPE
     assert _noalloc(lib, colour=4) == MF_EINVAL
     assert _noalloc(lib, targets=3) == MF_EINVAL
-    assert _noalloc(lib, prec=2) == MF_EINVAL
+    assert _noalloc(lib, prec=3) == MF_EINVAL
     # the static scratch holds the width-256 fp32 network (924,928 bytes) plus
     # 56 bytes per domain of a batch: 2,207 one-unit domains fit, 2,300 do not
     for n, want in ((2207, MF_EINVAL), (2300, MF_ENOMEM)):

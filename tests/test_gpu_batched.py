@@ -7,7 +7,7 @@ import torch
 
 import mf_inputs as mi
 from oracle import sweep as sw
-from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, Batch, Context
+from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP16, MF_FP32, MF_INTERIOR, Batch, Context
 from paper_2308_14258_amd import mf_solve, mf_sweep
 
 pytestmark = pytest.mark.gpu
@@ -25,7 +25,7 @@ def _fields(seed=7, n=7, lo=1, hi=6):
     return sizes, fields
 
 
-@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16])
+@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16, MF_FP16])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
 def test_batch_equals_one_by_one(ctx, prec, targets):
     print(f"case: batch vs single prec={prec} targets={targets}", flush=True)

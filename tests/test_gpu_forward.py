@@ -6,7 +6,7 @@ import torch
 
 import mf_inputs as mi
 from oracle import sdnet
-from paper_2308_14258_amd import MF_BF16, MF_FP32, Context, sdnet_forward
+from paper_2308_14258_amd import MF_BF16, MF_FP16, MF_FP32, Context, sdnet_forward
 
 pytestmark = pytest.mark.gpu
 
@@ -43,21 +43,22 @@ def test_forward_matches_oracle(ctx, width, shape, per_bc):
     assert _rel(U.cpu().numpy(), want) <= 1e-5
 
 
+@pytest.mark.parametrize("prec,tol", [(MF_BF16, 2e-2), (MF_FP16, 5e-3)])
 @pytest.mark.parametrize("width", [128, 256])
-def test_forward_bf16_error(ctx, width):
-    print(f"case: forward bf16 width={width}", flush=True)
+def test_forward_bf16_error(ctx, width, prec, tol):
+    print(f"case: forward prec {prec} width={width}", flush=True)
     params = mi.xavier_params(width, 0)
     rng = np.random.default_rng(5)
     G = rng.standard_normal((64, 128)).astype(np.float32)
     X = rng.uniform(size=(61, 2)).astype(np.float32)
     U = sdnet_forward(ctx, torch.from_numpy(params).cuda(), torch.from_numpy(G).cuda(),
-                      torch.from_numpy(X).cuda(), MF_BF16)
+                      torch.from_numpy(X).cuda(), prec)
     layers = sdnet.unpack(torch.from_numpy(params.astype(np.float64)), width)
     want = sdnet.forward(layers, torch.from_numpy(G.astype(np.float64)),
                          torch.from_numpy(X.astype(np.float64))).numpy()
     err = _rel(U.cpu().numpy(), want)
-    print(f"forward bf16 width {width}: rel L2 {err:.3e}", flush=True)
-    assert err <= 2e-2
+    print(f"forward prec {prec} width {width}: rel L2 {err:.3e}", flush=True)
+    assert err <= tol
 
 
 def test_forward_empty(ctx):

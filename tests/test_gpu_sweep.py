@@ -3,7 +3,10 @@
 Tolerance: float32 results match the oracle to relative L2 <= 1e-5 over the
 points the run writes (interior skeleton points for CROSS sweeps, every
 interior point for INTERIOR sweeps and for the assembly). BF16 results
-(bf16 hidden GEMMs, float32 everywhere else) are held to <= 2e-2.
+(bf16 projection and hidden GEMMs, float32 everywhere else) are held to
+<= 2e-2. FP16 results (the same GEMMs on IEEE half operands, whose unit
+roundoff 2^-11 = 4.9e-4 is 8x finer) are held to <= 5e-3, ten unit
+roundoffs (measured 5.7e-4 to 1.0e-3).
 """
 import os
 
@@ -13,7 +16,7 @@ import torch
 
 import mf_inputs as mi
 from oracle import fd, sweep as sw
-from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, MF_INTERIOR, MF_TILE_STREAM, Context
+from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP16, MF_FP32, MF_INTERIOR, MF_TILE_STREAM, Context
 from paper_2308_14258_amd import mf_solve, mf_sweep, mf_sweep_operator
 
 pytestmark = pytest.mark.gpu
@@ -279,7 +282,7 @@ def test_bf16_solve_c2_error(ctx):
     assert e_skel <= 2e-2 and e_out <= 2e-2
 
 
-@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2)])
+@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2), (MF_FP16, 5e-3)])
 def test_solve_c4_full_size_golden(ctx, prec, tol):
     """64 x 64 units (2049^2 grid, 16,129 placements), width 256: the
     benchmark's BF16-vs-FP32 workload at full size, in the launch
@@ -327,13 +330,13 @@ def test_solve_c4_full_size_golden(ctx, prec, tol):
         assert err20 <= max(1e-5, 10.0 * e32)
 
 
-@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16])
+@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16, MF_FP16])
 def test_solve_c4_trajectory(ctx, prec):
     """64 x 64 units, width 256, 500 sweeps: the skeleton at 32768 sampled
     points after each stored sweep count against the float64 oracle. Float32
     is held to max(1e-5, 10 x the float32 oracle's spread at that count);
-    BF16 to 2e-2 where that spread is <= 1e-6 (outside the transient) and
-    reported elsewhere; the trajectory maxima are printed."""
+    BF16 to 2e-2 and FP16 to 5e-3 where that spread is <= 1e-6 (outside
+    the transient) and reported elsewhere; the trajectory maxima are printed."""
     print(f"case: C4 trajectory vs golden prec {prec}", flush=True)
     t = np.load(os.path.join(HERE, "golden", "c4_traj.npz"))
     c = np.load(os.path.join(HERE, "golden", "c4_cond.npz"))
@@ -357,7 +360,7 @@ def test_solve_c4_trajectory(ctx, prec):
         if prec == MF_FP32:
             assert e <= max(1e-5, 10.0 * e32), (int(k), e, e32)
         elif e32 <= 1e-6:
-            assert e <= 2e-2, (int(k), e, e32)
+            assert e <= (2e-2 if prec == MF_BF16 else 5e-3), (int(k), e, e32)
     print(f"C4 prec {prec} trajectory max {worst:.3e}", flush=True)
 
 
@@ -426,7 +429,8 @@ def test_graph_replay_sees_new_parameter_values(ctx, prec):
 
 @pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_FP32, 64 | (1 << 17)), (MF_BF16, 64),
                                        (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
-                                       (MF_BF16, 256 | (1 << 16)), (MF_BF16, 256 | (1 << 18))])
+                                       (MF_BF16, 256 | (1 << 16)), (MF_BF16, 256 | (1 << 18)),
+                                       (MF_FP16, 64), (MF_FP16, 128), (MF_FP16, 256), (MF_FP16, 256 | (1 << 18))])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
 def test_every_tile_height(ctx, prec, rows, targets):
     print(f"case: tile rows {rows} prec {prec} targets {targets}", flush=True)
@@ -445,7 +449,7 @@ def test_every_tile_height(ctx, prec, rows, targets):
     m = skel_interior_mask(ny, nx) if targets == MF_CROSS else interior_mask(ny, nx)
     err = rel_l2(u.cpu().numpy(), want.numpy(), m)
     print(f"tile rows {rows} prec {prec} targets {targets}: rel L2 {err:.3e}", flush=True)
-    assert err <= (1e-5 if prec == MF_FP32 else 2e-2)
+    assert err <= {MF_FP32: 1e-5, MF_BF16: 2e-2, MF_FP16: 5e-3}[prec]
     np.testing.assert_array_equal(u.cpu().numpy()[~m], f[~m])
 
 
@@ -500,12 +504,14 @@ def test_additive_solve_c1(ctx):
     assert rel_l2(u_out.cpu().numpy(), uo.numpy(), interior_mask(65, 65)) <= 1e-5
 
 
+@pytest.mark.parametrize("prec,tol", [(MF_BF16, 2e-2), (MF_FP16, 5e-3)])
 @pytest.mark.parametrize("width", [128, 256])
-def test_rowsplit_tile_solve_and_assembly(ctx, width):
-    """The row-split bf16 tile (each wave owns 32 rows, weights streamed
+def test_rowsplit_tile_solve_and_assembly(ctx, width, prec, tol):
+    """The row-split 16-bit tile (each wave owns 32 rows, weights streamed
     through LDS) in a full solve: sweeps and the overlap-averaged assembly
-    against the oracle, and bit for bit against the column-split bf16 tile."""
-    print(f"case: row-split bf16 tile, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
+    against the oracle, and bit for bit against the column-split tile of the
+    same precision."""
+    print(f"case: row-split tile prec {prec}, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
     ux, uy = 5, 4
     params = mi.xavier_params(width, 2)
     f = mi.gp_field(ux, uy, 1.0, seed=6)
@@ -513,20 +519,20 @@ def test_rowsplit_tile_solve_and_assembly(ctx, width):
     for name, rows in (("rowsplit", 256 | (1 << 18)), ("default", 0)):
         u = dev(f)
         u_out = torch.empty_like(u)
-        ctx.tile_rows(MF_BF16, rows)
+        ctx.tile_rows(prec, rows)
         try:
-            mf_solve(ctx, dev(params), u, (ux, uy), 3, prec=MF_BF16, u_out=u_out)
+            mf_solve(ctx, dev(params), u, (ux, uy), 3, prec=prec, u_out=u_out)
             torch.cuda.synchronize()
         finally:
-            ctx.tile_rows(MF_BF16, 0)
+            ctx.tile_rows(prec, 0)
         outs[name] = (u.cpu().numpy(), u_out.cpu().numpy())
     _, want, _, _ = sw.solve(torch.from_numpy(f.astype(np.float64)), ux, uy, oracle_solver(params, width), 3)
     ny, nx = f.shape
     e_or = rel_l2(outs["rowsplit"][1], want.numpy(), interior_mask(ny, nx))
     e_cs = rel_l2(outs["rowsplit"][1], outs["default"][1], interior_mask(ny, nx))
-    print(f"row-split bf16 width {width}: u_out rel L2 vs oracle {e_or:.3e}, vs column-split bf16 {e_cs:.3e}",
+    print(f"row-split prec {prec} width {width}: u_out rel L2 vs oracle {e_or:.3e}, vs column-split {e_cs:.3e}",
           flush=True)
-    assert e_or <= 2e-2
+    assert e_or <= tol
     # same k order in every MFMA, same tanh and output sums: identical results
     np.testing.assert_array_equal(outs["rowsplit"][0], outs["default"][0])
     np.testing.assert_array_equal(outs["rowsplit"][1], outs["default"][1])
