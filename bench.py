@@ -6,8 +6,8 @@ the overlap-averaged assembly, on a 64 x 64-unit domain (2049 x 2049 grid,
 16,129 placements) with a width-256 SDNet (Xavier weights, seed 0) and
 e^x sin y ring data scaled to [0, 1]. The headline value is SDNet point
 evaluations per second over the whole step (sweeps + assembly) in float32;
-the same steps with BF16 hidden GEMMs are reported beside it ("bf16"), each
-with its error against the float64 oracle.
+the same steps with 16-bit GEMM operands are reported beside it ("bf16",
+"fp16"), each with its error against the float64 oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -56,9 +56,10 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # kernel sources hash to the value the counters were taken with; otherwise
 # "traffic" is null. Summary: profiles/tile_kernel_c4_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "8a31a555cb3194c064a7e954a455add67141a98febdb354ce72853818f0861a9",
-    "bytes_per_launch": {"C4:fp32:64|stream": (27768.4 * 2.0 + 4396.5) * 1024,
-                         "C4:bf16:256|rowsplit": (14268.4 * 2.0 + 4312.4) * 1024},
+    "sources_sha256": "a24b2fe5447005a78b9587a0fd35eea29c002883cf43a3b0bb0f0a9267f7c0f0",
+    "bytes_per_launch": {"C4:fp32:64|stream": (27761.9 * 2.0 + 4396.5) * 1024,
+                         "C4:bf16:256|rowsplit": (14266.3 * 2.0 + 4312.4) * 1024,
+                         "C4:fp16:256|rowsplit": (14268.9 * 2.0 + 4312.4) * 1024},
 }
 KERNEL_SOURCES = ("paper_2308_14258_amd/csrc/sweep_kernels.hip",
                   "paper_2308_14258_amd/csrc/mf_device.h")
@@ -160,6 +161,7 @@ def _roofline(prec, width, launches, phase_ms, phase_rows, shape, workload=""):
     fpp = flops_per_point(width, CROSS_T)
     achieved = phase_rows * fpp / (phase_ms * 1e-3) / 1e12
     avg_us = phase_ms * 1e3 / max(launches, 1)
+    # bf16 and fp16 share the dense MFMA peak (2.5 PFLOP/s)
     peak = PEAK_FP32_MFMA_TFLOPS if prec == "fp32" else PEAK_BF16_MFMA_TFLOPS
     key = f"{workload}:{prec}:{shape}"
     traffic = (MEASURED_TRAFFIC["bytes_per_launch"].get(key)
@@ -202,12 +204,12 @@ def c4_section(ctx, args, prec_name):
     the trajectory."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, mf_autotune, mf_solve
+    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP16, MF_FP32, mf_autotune, mf_solve
     w = mi.WORKLOADS["C4"]
     ux, uy = w["units"]
     width = w["width"]
     K = args.sweeps
-    prec = MF_FP32 if prec_name == "fp32" else MF_BF16
+    prec = {"fp32": MF_FP32, "bf16": MF_BF16, "fp16": MF_FP16}[prec_name]
     field = torch.from_numpy(mi.workload_field("C4")).cuda()
     params = torch.from_numpy(mi.xavier_params(width, 0)).cuda()
     # tile shape chosen by the autotuner on a scratch copy (outside the timed region)
@@ -339,7 +341,7 @@ def trained_section(ctx):
     0.05 (checked every 100 sweeps) and the MAE after 2000 sweeps."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_FP32, mf_solve
+    from paper_2308_14258_amd import MF_BF16, MF_FP16, MF_FP32, mf_solve
     from paper_2308_14258_amd.sdnet_training import WEIGHTS_DIR, load_trained
     params, width, cfg, hist = load_trained(os.path.join(WEIGHTS_DIR, "sdnet_laplace_d256.npz"))
     p = torch.from_numpy(params).cuda()
@@ -350,7 +352,7 @@ def trained_section(ctx):
     res = {"network": f"width {width}, tanh, {cfg['epochs']} epochs on {cfg['n_bc']} GP conditions, "
                       f"validation MSE {hist['val_mse'][-1]:.2e}"}
     f4 = mi.gp_field(4, 4, 1.0, seed=31)
-    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16), ("fp16", MF_FP16)):
         u = torch.from_numpy(f4).cuda()
         uo = torch.empty_like(u)
         mf_solve(ctx, p, u, (4, 4), 100, prec=prec, u_out=uo)
@@ -363,7 +365,7 @@ def trained_section(ctx):
         return float(np.mean(np.abs(uo.cpu().numpy()[g["sample_j"], g["sample_i"]] - g["u64_sample"])))
 
     t4 = {}
-    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16)):
+    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16), ("fp16", MF_FP16)):
         u = torch.from_numpy(f64).cuda()
         uo = torch.empty_like(u)
         hit = None
@@ -451,12 +453,16 @@ def main():
     ctx = Context(0)
     fp32, uo32 = c4_section(ctx, args, "fp32")
     print(f"# fp32 64x64: {fp32['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
-    bf16, uo16 = c4_section(ctx, args, "bf16")
-    print(f"# bf16 64x64: {bf16['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
-    d = uo16.double()[1:-1, 1:-1] - uo32.double()[1:-1, 1:-1]
-    bf16["rel_l2_vs_fp32_u_out"] = float(d.norm() / uo32.double()[1:-1, 1:-1].norm())
-    bf16["speedup_over_fp32"] = bf16["value"] / fp32["value"]
-    del uo16, uo32
+    half = {}
+    for name in ("bf16", "fp16"):
+        r, uo = c4_section(ctx, args, name)
+        print(f"# {name} 64x64: {r['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
+        d = uo.double()[1:-1, 1:-1] - uo32.double()[1:-1, 1:-1]
+        r["rel_l2_vs_fp32_u_out"] = float(d.norm() / uo32.double()[1:-1, 1:-1].norm())
+        r["speedup_over_fp32"] = r["value"] / fp32["value"]
+        half[name] = r
+        del uo
+    del uo32
     out = {
         "metric": METRIC,
         "value": fp32["value"],
@@ -478,7 +484,8 @@ def main():
         "step_ms": fp32["step_ms"],
         "roofline": fp32["roofline"],
         "parity": fp32.get("parity"),
-        "bf16": bf16,
+        "bf16": half["bf16"],
+        "fp16": half["fp16"],
     }
     if not args.headline_only:
         out["c2"] = c2_section(ctx, args)
@@ -502,8 +509,9 @@ def main():
             out["achievable_peaks"] = achievable_peaks()
             out["roofline"]["frac_of_achievable"] = (out["roofline"]["achieved"] /
                                                      out["achievable_peaks"]["fp32_tflops"])
-            out["bf16"]["roofline"]["frac_of_achievable"] = (out["bf16"]["roofline"]["achieved"] /
-                                                             out["achievable_peaks"]["bf16_tflops"])
+            for name in ("bf16", "fp16"):
+                out[name]["roofline"]["frac_of_achievable"] = (out[name]["roofline"]["achieved"] /
+                                                               out["achievable_peaks"][name + "_tflops"])
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(mi.workload_field("C4"), mi.xavier_params(width, 0), width,
                                                ux, uy, args.cpu_sample_sweeps)
@@ -568,7 +576,7 @@ def achievable_peaks():
     import torch
     out = {}
     n = 8192
-    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fp16", torch.float16)):
         a = torch.randn(n, n, device="cuda").to(dt)
         b = torch.randn(n, n, device="cuda").to(dt)
         ms = _event_ms(lambda: torch.mm(a, b), 10)
