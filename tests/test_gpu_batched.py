@@ -92,7 +92,7 @@ def test_batch_additive_equals_one_by_one(ctx):
         assert torch.equal(batch.field(i), u), i
 
 
-@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2)])
+@pytest.mark.parametrize("prec,tol", [(MF_FP32, 1e-5), (MF_BF16, 2e-2), (MF_FP16, 5e-3)])
 def test_full_batch_one_sweep_sampled_domains(ctx, prec, tol):
     """The 48-domain batch (4..48 units per side, 138,286 placements), width
     256, in the launch configuration the benchmark uses (one persistent
@@ -127,9 +127,9 @@ def test_full_batch_one_sweep_sampled_domains(ctx, prec, tol):
 # rounding alone causes along the same trajectory: the oracle's algorithm
 # evaluated in float32 on the CPU (the "fp32" run stored with the float64
 # values) differs from float64 by e32(K); the GPU float32 error must stay
-# within max(1e-5, COND_FACTOR * e32(K)). BF16 is held to 2e-2 where the
-# trajectory is well conditioned (e32 <= 1e-6) and its error is reported
-# elsewhere.
+# within max(1e-5, COND_FACTOR * e32(K)). BF16 is held to 2e-2 and FP16 to
+# 5e-3 where the trajectory is well conditioned (e32 <= 1e-6) and their
+# errors are reported elsewhere.
 COND_FACTOR = 10.0
 
 
@@ -137,7 +137,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16])
+@pytest.mark.parametrize("prec", [MF_FP32, MF_BF16, MF_FP16])
 def test_full_batch_k20_sampled_domains(ctx, prec):
     """The 48-domain batch at its stated 20 sweeps, in the benchmark's
     launch configuration: sampled skeleton of the smallest, median and
@@ -172,7 +172,7 @@ def test_full_batch_k20_sampled_domains(ctx, prec):
             if prec == MF_FP32:
                 assert e <= max(1e-5, COND_FACTOR * e32), (k, int(d), e, e32)
             elif e32 <= 1e-6:
-                assert e <= 2e-2, (k, int(d), e, e32)
+                assert e <= (2e-2 if prec == MF_BF16 else 5e-3), (k, int(d), e, e32)
     for n, d in enumerate(g["picks"]):
         uo = batch.field(int(d), out).cpu().numpy().astype(np.float64)
         got = uo[g[f"sample_j{n}"], g[f"sample_i{n}"]]
@@ -184,7 +184,7 @@ def test_full_batch_k20_sampled_domains(ctx, prec):
         if prec == MF_FP32:
             assert e <= max(1e-5, COND_FACTOR * e32), (int(d), e, e32)
         elif e32 <= 1e-6:
-            assert e <= 2e-2, (int(d), e, e32)
+            assert e <= (2e-2 if prec == MF_BF16 else 5e-3), (int(d), e, e32)
 
 
 def test_autotune_on_a_batch_and_the_persistent_row_split_form(ctx):
