@@ -7,7 +7,9 @@ the overlap-averaged assembly, on a 64 x 64-unit domain (2049 x 2049 grid,
 e^x sin y ring data scaled to [0, 1]. The headline value is SDNet point
 evaluations per second over the whole step (sweeps + assembly) in float32;
 the same steps with 16-bit GEMM operands are reported beside it ("bf16",
-"fp16"), each with its error against the float64 oracle.
+"fp16"), each with its error against the float64 oracle, and FP16 sweeps
+held to the float32 iteration by a periodically refreshed correction
+("fp16_mixed").
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -251,6 +253,43 @@ def c4_section(ctx, args, prec_name):
     return res, u_out
 
 
+def c4_mixed_section(ctx, args, refresh=50):
+    """The 64 x 64-unit step with FP16 sweeps held to the float32 iteration
+    by a correction refreshed every `refresh` sweeps (mf_solve_mixed; the
+    refresh sweeps run each phase in float32 and in FP16, the assembly runs
+    in float32): throughput in the step's point evaluations (each refresh
+    evaluates its points twice; that is overhead, not counted) and the error
+    against the oracle at the step's sweep count."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import MF_FP16, mf_solve_mixed
+    w = mi.WORKLOADS["C4"]
+    ux, uy = w["units"]
+    K = args.sweeps
+    field = torch.from_numpy(mi.workload_field("C4")).cuda()
+    params = torch.from_numpy(mi.xavier_params(w["width"], 0)).cuda()
+    u = field.clone()
+    u_out = torch.empty_like(u)
+
+    def step():
+        u.copy_(field)
+        mf_solve_mixed(ctx, params, u, (ux, uy), K, refresh_every=refresh, prec=MF_FP16, u_out=u_out)
+
+    steps = max(args.steps, 5)
+    dt, per, _, _, _ = _timed_steps(ctx, step, steps, 1)
+    evals = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
+    res = {"value": evals * steps / dt, "ms_per_step": dt * 1e3 / steps, "refresh_every": refresh,
+           "step_ms": {"median": float(np.median(per)) * 1e3, "min": min(per) * 1e3, "max": max(per) * 1e3}}
+    gpath = os.path.join(GOLDEN, "c4_fp64.npz")
+    if K == w["sweeps"] and os.path.exists(gpath):
+        g = np.load(gpath)
+        sk = u.cpu().numpy().astype(np.float64)[g["skel_j"], g["skel_i"]]
+        uo = u_out.cpu().numpy().astype(np.float64)[g["sample_j"], g["sample_i"]]
+        res["parity"] = {"rel_l2_skeleton_vs_oracle": _rel(sk, g["skel500"]),
+                         "rel_l2_u_out_vs_oracle": _rel(uo, g["u_out_sample"])}
+    return res
+
+
 def c2_section(ctx, args):
     """16 x 16 units (961 placements), width 256, GP ring data, 200 sweeps +
     assembly, FP32: throughput and error against the oracle, with the
@@ -341,7 +380,7 @@ def trained_section(ctx):
     0.05 (checked every 100 sweeps) and the MAE after 2000 sweeps."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_FP16, MF_FP32, mf_solve
+    from paper_2308_14258_amd import MF_BF16, MF_FP16, MF_FP32, mf_solve, mf_solve_mixed
     from paper_2308_14258_amd.sdnet_training import WEIGHTS_DIR, load_trained
     params, width, cfg, hist = load_trained(os.path.join(WEIGHTS_DIR, "sdnet_laplace_d256.npz"))
     p = torch.from_numpy(params).cuda()
@@ -365,13 +404,22 @@ def trained_section(ctx):
         return float(np.mean(np.abs(uo.cpu().numpy()[g["sample_j"], g["sample_i"]] - g["u64_sample"])))
 
     t4 = {}
-    for name, prec in (("fp32", MF_FP32), ("bf16", MF_BF16), ("fp16", MF_FP16)):
+    # plain sweeps in each precision, and 16-bit sweeps with a float32
+    # correction refreshed every `refresh` sweeps (mf_solve_mixed)
+    runs = (("fp32", MF_FP32, 0), ("bf16", MF_BF16, 0), ("fp16", MF_FP16, 0),
+            ("fp16_mixed_refresh50", MF_FP16, 50), ("bf16_mixed_refresh5", MF_BF16, 5))
+    for name, prec, refresh in runs:
+        def solve(u, n, uo=None):
+            if refresh:
+                mf_solve_mixed(ctx, p, u, (64, 64), n, refresh_every=refresh, prec=prec, u_out=uo)
+            else:
+                mf_solve(ctx, p, u, (64, 64), n, prec=prec, u_out=uo)
         u = torch.from_numpy(f64).cuda()
         uo = torch.empty_like(u)
         hit = None
         curve = {}
         for k in range(100, 2001, 100):
-            mf_solve(ctx, p, u, (64, 64), 100, prec=prec, u_out=uo)
+            solve(u, 100, uo)
             torch.cuda.synchronize()
             curve[k] = mae(uo)
             if hit is None and curve[k] < 0.05:
@@ -379,11 +427,11 @@ def trained_section(ctx):
         r = {"mae_by_sweeps": curve, "sweeps_to_mae_0.05": hit}
         if hit is not None:
             u = torch.from_numpy(f64).cuda()
-            mf_solve(ctx, p, u, (64, 64), 10, prec=prec)
+            solve(u, 10)
             u.copy_(torch.from_numpy(f64).cuda())
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            mf_solve(ctx, p, u, (64, 64), hit, prec=prec, u_out=uo)
+            solve(u, hit, uo)
             torch.cuda.synchronize()
             r["seconds_to_mae_0.05"] = time.perf_counter() - t0
         t4[name] = r
@@ -487,6 +535,10 @@ def main():
         "bf16": half["bf16"],
         "fp16": half["fp16"],
     }
+    mixed = c4_mixed_section(ctx, args)
+    mixed["speedup_over_fp32"] = mixed["value"] / fp32["value"]
+    out["fp16_mixed"] = mixed
+    print(f"# fp16 mixed 64x64: {mixed['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
     if not args.headline_only:
         out["c2"] = c2_section(ctx, args)
         print("# c2 done", file=sys.stderr, flush=True)

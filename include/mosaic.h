@@ -356,6 +356,32 @@ mf_status mf_gather_skel(mf_ctx* ctx, const float* u, const float* cols, const m
 mf_status mf_scatter_skel(mf_ctx* ctx, const float* pred, float* u, float* cols, const mf_domain_desc* dom,
                           int32_t colour, void* stream);
 
+/* Workspace bytes for mf_solve_mixed. */
+mf_status mf_mixed_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
+                           int32_t targets, int32_t prec, size_t* bytes);
+
+/* Alg. 2's sweeps in 16-bit precision (prec MF_BF16 or MF_FP16) held to the
+ * float32 iteration by a correction: every refresh_every-th sweep (the
+ * first included) runs each colour phase in float32 and also, from the
+ * same field state, in 16 bits, and keeps the difference at every target,
+ * corr_c = pred_fp32 - pred_16; the other sweeps run each phase in 16 bits
+ * and add corr_c at its targets. The 16-bit map's rounding error is
+ * systematic and the iteration amplifies systematic errors in its slowest
+ * modes (on large domains a trained network's 16-bit fixed point lies far
+ * from the float32 one); the correction, exact at each refresh and slowly
+ * varying, keeps the fixed point at the float32 one. refresh_every = 1 is
+ * the float32 iteration exactly (bit for bit). max_sweeps sweeps (no delta
+ * test), then, when u_out is not NULL, the float32 assembly as in mf_solve.
+ * The tanh network only; single domains and batches (the correction
+ * kernels take a batch's placements of a colour in one launch). The
+ * workspace holds the three prepared networks (16-bit twice, float32), one
+ * copy of the span the domains occupy in u and four correction fields of
+ * that size. Asynchronous. */
+mf_status mf_solve_mixed(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                         const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
+                         int32_t max_sweeps, int32_t refresh_every, float* u_out, void* ws, size_t ws_bytes,
+                         void* stream);
+
 /* Workspace bytes for mf_solve_adjoint. */
 mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
                              int32_t targets, int32_t K, int32_t ckpt_every, size_t* bytes);

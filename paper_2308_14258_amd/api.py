@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (MF_GELU, MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
+from ._lib import (MF_BF16, MF_GELU, MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
                    check, load)
 
 
@@ -242,6 +242,30 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
                           ctypes.byref(last) if report else None, _ptr(ws), ws.numel(),
                           _stream()), "mf_solve")
     return (done.value, last.value) if report else None
+
+
+def mf_solve_mixed(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int, refresh_every: int = 20,
+                   prec: int = MF_BF16, targets: int = MF_CROSS, u_out=None):
+    """Sweeps in 16 bits (prec MF_BF16 or MF_FP16) with a float32 correction
+    refreshed every refresh_every sweeps, then the float32 assembly into
+    u_out (optional). u is a 2-D field with units (ux, uy), or a Batch."""
+    _need_cuda_f32(params, "params")
+    buf, dom, nd = _field_and_domains(u, units)
+    if u_out is not None:
+        if nd == 1:
+            _need_field(u_out, units)
+            if u_out.stride(0) != u.stride(0):
+                raise ValueError("u_out must have the same pitch as u")
+        elif u_out.numel() != buf.numel():
+            raise ValueError("u_out must match the batch buffer")
+    n = ctypes.c_size_t()
+    lib = load()
+    check(lib.mf_mixed_ws_size(ctypes.byref(desc_of(params)), _dom_arg(dom), nd, targets, prec, ctypes.byref(n)),
+          "mf_mixed_ws_size")
+    ws = ctx.workspace(n.value)
+    check(lib.mf_solve_mixed(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf), _dom_arg(dom), nd,
+                             targets, prec, max_sweeps, refresh_every, _ptr(u_out), _ptr(ws), ws.numel(),
+                             _stream()), "mf_solve_mixed")
 
 
 def mf_solve_adjoint(ctx: Context, params: torch.Tensor, u0, units, K: int, ckpt_every: int = 5,

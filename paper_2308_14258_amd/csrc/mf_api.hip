@@ -219,6 +219,11 @@ static mf_status check_one_domain(const mf_domain_desc* dom, int d) {
 // One domain, or a batch of 2..4096 independent domains in one packed
 // buffer whose element ranges must not overlap (their phases run
 // concurrently).
+// Floats from a domain's first element to one past its last grid point.
+static int64_t field_extent(const mf_domain_desc& d) {
+  return (32LL * d.units_y) * d.pitch + 32LL * d.units_x + 1;
+}
+
 static mf_status check_domain(const mf_domain_desc* dom, int n_domains) {
   if (!dom) return fail(MF_EINVAL, "domain descriptor is NULL");
   if (n_domains < 1 || n_domains > 4096)
@@ -1020,6 +1025,147 @@ mf_status mf_solve(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, 
   return ok();
 }
 
+// ---------------------------------------------------------------------------
+// mf_solve_mixed: 16-bit sweeps with a float32 correction refreshed every
+// `refresh_every` sweeps (the refresh sweep itself runs in float32).
+// ---------------------------------------------------------------------------
+struct MixLayout {
+  SweepLayout l16, l16t, l32;          // each relative to its own sub-workspace
+  size_t o16 = 0, o16t = 0, o32 = 0;   // sub-workspace offsets
+  size_t tmp = 0, corr = 0, table = 0, total = 0;
+  int64_t lo = 0;
+  size_t span = 0;                     // floats per field copy (hi - lo)
+};
+
+static MixLayout mixed_layout(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int prec,
+                              std::vector<mf_domain_desc>* dint) {
+  MixLayout M;
+  int64_t lo = INT64_MAX, hi = 0;
+  for (int i = 0; i < nd; ++i) {
+    lo = std::min<int64_t>(lo, dom[i].field_offset);
+    hi = std::max<int64_t>(hi, dom[i].field_offset + field_extent(dom[i]));
+  }
+  M.lo = lo;
+  M.span = (size_t)(hi - lo);
+  std::vector<mf_domain_desc> di(dom, dom + nd);
+  for (mf_domain_desc& e : di) e.field_offset -= lo;
+  M.l16 = sweep_layout(desc->width, prec, dom, nd, MF_MULTIPLICATIVE);
+  M.l16t = sweep_layout(desc->width, prec, di.data(), nd, MF_MULTIPLICATIVE);
+  M.l32 = sweep_layout(desc->width, MF_FP32, dom, nd, MF_MULTIPLICATIVE);
+  size_t o = 0;
+  M.o16 = o; o = align256(o + M.l16.total);
+  M.o16t = o; o = align256(o + M.l16t.total);
+  M.o32 = o; o = align256(o + M.l32.total);
+  M.tmp = o; o = align256(o + M.span * 4);
+  M.corr = o; o = align256(o + 4 * M.span * 4);
+  M.table = o; o = align256(o + (size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
+  M.total = o;
+  if (dint) *dint = di;
+  return M;
+}
+
+static mf_status mixed_checks(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int targets, int prec) {
+  MF_TRY(check_desc(desc));
+  MF_TRY(need_tanh(desc, "mf_solve_mixed"));
+  MF_TRY(check_domain(dom, nd));
+  if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
+  if (prec != MF_BF16 && prec != MF_FP16) return fail(MF_EINVAL, "mf_solve_mixed: prec must be MF_BF16 or MF_FP16");
+  int64_t n_place = 0;
+  for (int d = 0; d < nd; ++d) n_place += (int64_t)dom[d].units_x * dom[d].units_y;
+  if (n_place > INT32_MAX) return fail(MF_ESHAPE, "batch has too many placements");
+  return MF_OK;
+}
+
+mf_status mf_mixed_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,
+                           int32_t targets, int32_t prec, size_t* bytes) {
+  MF_TRY(check_ptr(bytes, "bytes", 1));
+  *bytes = 0;
+  MF_TRY(mixed_checks(desc, dom, n_domains, targets, prec));
+  *bytes = mixed_layout(desc, dom, n_domains, prec, nullptr).total;
+  return ok();
+}
+
+mf_status mf_solve_mixed(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
+                         const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
+                         int32_t max_sweeps, int32_t refresh_every, float* u_out, void* ws, size_t ws_bytes,
+                         void* stream) {
+  MF_TRY(mixed_checks(desc, dom, n_domains, targets, prec));
+  MF_TRY(check_ptr(params, "params"));
+  MF_TRY(check_ptr(u, "u"));
+  if (max_sweeps < 0) return fail(MF_EINVAL, "max_sweeps %d < 0", max_sweeps);
+  if (refresh_every < 1) return fail(MF_EINVAL, "refresh_every %d < 1", refresh_every);
+  if (u_out) {
+    MF_TRY(check_ptr(u_out, "u_out"));
+    if (u_out == u) return fail(MF_EINVAL, "u_out must not alias u");
+  }
+  std::vector<mf_domain_desc> dint;
+  const MixLayout M = mixed_layout(desc, dom, n_domains, prec, &dint);
+  MF_TRY(check_ws(ws, ws_bytes, M.total));
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  char* b = static_cast<char*>(ws);
+  void* w16 = b + M.o16;
+  void* w16t = b + M.o16t;
+  void* w32 = b + M.o32;
+  float* tmp = reinterpret_cast<float*>(b + M.tmp);
+  float* corr = reinterpret_cast<float*>(b + M.corr);
+  const int nd = n_domains;
+  MF_HIP(prepare_net(desc, params, prec, M.l16.net, w16, s));
+  MF_HIP(prepare_net(desc, params, prec, M.l16t.net, w16t, s));
+  MF_HIP(prepare_net(desc, params, MF_FP32, M.l32.net, w32, s));
+  Plan P16, P16t, P32;
+  MF_TRY(make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, u, dom, nd, w16, M.l16, s, &P16));
+  MF_TRY(make_plan(ctx, desc, prec, targets, MF_MULTIPLICATIVE, tmp, dint.data(), nd, w16t, M.l16t, s, &P16t));
+  MF_TRY(make_plan(ctx, desc, MF_FP32, targets, MF_MULTIPLICATIVE, u, dom, nd, w32, M.l32, s, &P32));
+  // the correction kernels' table: the caller's offsets and per-colour
+  // placement prefixes
+  std::vector<char> host((size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
+  DomEntry* he = reinterpret_cast<DomEntry*>(host.data());
+  int32_t* hq = reinterpret_cast<int32_t*>(host.data() + (size_t)nd * sizeof(DomEntry));
+  int64_t n_place[4] = {0, 0, 0, 0};
+  for (int d = 0; d < nd; ++d) he[d] = DomEntry{dom[d].field_offset, dom[d].pitch, dom[d].units_x, dom[d].units_y};
+  for (int c = 0; c < 4; ++c) {
+    int32_t acc = 0;
+    for (int d = 0; d < nd; ++d) {
+      hq[c * (nd + 1) + d] = acc;
+      acc += (dom[d].units_x - (c & 1)) * (dom[d].units_y - (c >> 1));
+    }
+    hq[c * (nd + 1) + nd] = acc;
+    n_place[c] = acc;
+  }
+  char* tb = b + M.table;
+  MF_HIP(hipMemcpyAsync(tb, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  const DomEntry* d_doms = reinterpret_cast<const DomEntry*>(tb);
+  const int32_t* d_q = reinterpret_cast<const int32_t*>(tb + (size_t)nd * sizeof(DomEntry));
+
+  for (int k = 0; k < max_sweeps; ++k) {
+    const bool refresh = k % refresh_every == 0;
+    for (int c = 0; c < 4; ++c) {
+      if (n_place[c] == 0) continue;
+      const int32_t* qc = d_q + c * (nd + 1);
+      float* cc = corr + (size_t)c * M.span;
+      if (refresh) {
+        // the same field state in both precisions: the 16-bit phase runs on a copy
+        MF_HIP(hipMemcpyAsync(tmp, u + M.lo, M.span * 4, hipMemcpyDeviceToDevice, s));
+        MF_TRY(run_colour(ctx, P32, c, PH_SWEEP, nullptr, s));
+        MF_TRY(run_colour(ctx, P16t, c, PH_SWEEP, nullptr, s, false));
+        MF_HIP(launch_corr_targets(targets, 0, u, tmp, cc, M.lo, d_doms, qc, nd, c, n_place[c], s));
+      } else {
+        MF_TRY(run_colour(ctx, P16, c, PH_SWEEP, nullptr, s));
+        MF_HIP(launch_corr_targets(targets, 1, u, tmp, cc, M.lo, d_doms, qc, nd, c, n_place[c], s));
+      }
+    }
+  }
+  if (u_out) {   // the assembly in float32
+    for (int d = 0; d < nd; ++d)
+      MF_HIP(launch_assembly_init(u + dom[d].field_offset, u_out + dom[d].field_offset, dom[d].pitch,
+                                  dom[d].units_x, dom[d].units_y, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P32, c, PH_ASSEMBLY, u_out, s));
+  }
+  return ok();
+}
+
 mf_status mf_sweep_operator(mf_ctx* ctx, const float* Hop, int64_t hop_rows, int32_t targets,
                             float* u, float* u_out, const mf_domain_desc* dom, int32_t colour,
                             void* stream) {
@@ -1192,10 +1338,6 @@ struct AdjLayout {
   size_t fsize = 0;     // floats per field copy (hi - lo)
   int n_ckpt = 0;
 };
-
-static int64_t field_extent(const mf_domain_desc& d) {
-  return (32LL * d.units_y) * d.pitch + 32LL * d.units_x + 1;
-}
 
 static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, int K, int ckpt_every) {
   AdjLayout A;

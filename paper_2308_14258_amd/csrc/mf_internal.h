@@ -101,6 +101,12 @@ struct DomEntry {
   int32_t ux, uy;   // units
 };
 SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_domains, int mode, int embed_c = 0);
+// Mixed-precision sweeps: at the targets of one colour over a batch (qbegin
+// [nd + 1] placement prefixes of that colour), mode 0: corr = u - tmp, mode
+// 1: u += corr; tmp and corr are indexed by the field index minus lo.
+hipError_t launch_corr_targets(int targets, int mode, float* u, const float* tmp, float* corr, int64_t lo,
+                               const DomEntry* doms, const int32_t* qbegin, int nd, int colour, int64_t n_place,
+                               hipStream_t s);
 hipError_t launch_phase_multi(const NetPtrs& net, int width, int prec, int targets, bool accumulate,
                               int tile_rows, const float* field_in, float* field_out,
                               const DomEntry* doms, const int32_t* tile_begin, int n_domains,

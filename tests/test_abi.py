@@ -323,3 +323,28 @@ def test_gelu_network_descriptor(lib):
     assert lib.mf_adjoint_ws_size(ctypes.byref(g), ctypes.byref(_dom(2, 2)), 1, 0, 2, 1,
                                   ctypes.byref(n)) == MF_EUNSUPPORTED
     assert lib.sdnet_forward_ws_size(ctypes.byref(g), 4, 10, 1, MF_FP32, ctypes.byref(n)) == MF_OK
+
+
+def test_solve_mixed_argument_errors(lib):
+    from paper_2308_14258_amd._lib import MF_FP16
+    d = SdnetDesc(128, 4, 128, 0)
+    dom = _dom()
+    n = ctypes.c_size_t(0)
+
+    def call(prec=MF_BF16, refresh=10, sweeps=5, u_out=None, desc=d, ws=FAKE, ws_bytes=1 << 34):
+        return lib.mf_solve_mixed(None, ctypes.byref(desc), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                                  ctypes.byref(dom), 1, MF_CROSS, prec, sweeps, refresh,
+                                  ctypes.c_void_p(u_out) if u_out else None, ctypes.c_void_p(ws) if ws else None,
+                                  ws_bytes, None)
+    assert call() == MF_EINVAL and b"ctx" in lib.mf_last_error()              # all else valid
+    assert call(prec=MF_FP16) == MF_EINVAL and b"ctx" in lib.mf_last_error()
+    assert call(prec=MF_FP32) == MF_EINVAL and b"MF_BF16 or MF_FP16" in lib.mf_last_error()
+    assert call(refresh=0) == MF_EINVAL and b"refresh_every" in lib.mf_last_error()
+    assert call(sweeps=-1) == MF_EINVAL
+    assert call(u_out=FAKE) == MF_EINVAL and b"alias" in lib.mf_last_error()
+    assert call(ws_bytes=1024) == MF_ENOMEM
+    assert call(desc=SdnetDesc(128, 4, 128, 1, 4)) != MF_OK                    # the GELU network: not supported
+    assert lib.mf_mixed_ws_size(ctypes.byref(d), ctypes.byref(dom), 1, MF_CROSS, MF_BF16, ctypes.byref(n)) == MF_OK
+    # three prepared networks, one field copy and four correction fields
+    nf = 65 * 65
+    assert n.value >= 5 * nf * 4
