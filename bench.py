@@ -756,14 +756,14 @@ def io_measurement(ctx):
 def batched_measurement(ctx):
     """48 independent domains (4..48 units per side, seed 7), width 256, GP
     ring data: 20 sweeps + assembly in one launch per colour for the whole
-    batch, BF16 (the workload's precision) and FP32, each timed over three
+    batch, BF16 (the workload's precision), FP16 and FP32, each timed over three
     steps and checked at its smallest, median and largest domain against
     oracle values along the 20 sweeps; then the FP32 adjoint of
     J = sum u_out^2 through the 20 sweeps with checkpoints every 5, checked
     on the smallest domain against the oracle's gradient."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP32, Batch, mf_autotune, mf_solve, mf_solve_adjoint
+    from paper_2308_14258_amd import MF_BF16, MF_CROSS, MF_FP16, MF_FP32, Batch, mf_autotune, mf_solve, mf_solve_adjoint
     w = mi.WORKLOADS["C5"]
     t0 = time.perf_counter()
     sizes, fields = mi.batched_domains(w["n_domains"], 4, 48, w["length"], w["seed"])
@@ -780,7 +780,7 @@ def batched_measurement(ctx):
            "input_generation_s": gen_s}
     gpath = os.path.join(GOLDEN, "c5_k20.npz")
     g = np.load(gpath) if os.path.exists(gpath) else None
-    for name, prec in (("bf16", MF_BF16), ("fp32", MF_FP32)):
+    for name, prec in (("bf16", MF_BF16), ("fp16", MF_FP16), ("fp32", MF_FP32)):
         # tile shape for the whole domain list from the autotuner (outside the timed region)
         shape = mf_autotune(ctx, params, batch, None, MF_CROSS, prec, trials=1)
 
