@@ -253,17 +253,19 @@ def c4_section(ctx, args, prec_name):
     return res, u_out
 
 
-def c4_mixed_section(ctx, args, refresh=50):
+def c4_mixed_section(ctx, args, refresh=50, assembly_fp16=False):
     """The 64 x 64-unit step with FP16 sweeps held to the float32 iteration
     by a correction refreshed every `refresh` sweeps (mf_solve_mixed; the
     refresh sweeps run each phase in float32 and in FP16, the assembly runs
-    in float32): throughput in the step's point evaluations (each refresh
-    evaluates its points twice; that is overhead, not counted) and the error
-    against the oracle at the step's sweep count."""
+    in float32, or in FP16 with assembly_fp16): throughput in the step's
+    point evaluations (each refresh evaluates its points twice; that is
+    overhead, not counted) and the error against the oracle at the step's
+    sweep count."""
     import torch
     import mf_inputs as mi
-    from paper_2308_14258_amd import MF_FP16, mf_solve_mixed
+    from paper_2308_14258_amd import MF_FP16, MF_FP32, mf_solve_mixed
     w = mi.WORKLOADS["C4"]
+    asm = MF_FP16 if assembly_fp16 else MF_FP32
     ux, uy = w["units"]
     K = args.sweeps
     field = torch.from_numpy(mi.workload_field("C4")).cuda()
@@ -273,12 +275,14 @@ def c4_mixed_section(ctx, args, refresh=50):
 
     def step():
         u.copy_(field)
-        mf_solve_mixed(ctx, params, u, (ux, uy), K, refresh_every=refresh, prec=MF_FP16, u_out=u_out)
+        mf_solve_mixed(ctx, params, u, (ux, uy), K, refresh_every=refresh, prec=MF_FP16, u_out=u_out,
+                       assembly_prec=asm)
 
     steps = max(args.steps, 5)
     dt, per, _, _, _ = _timed_steps(ctx, step, steps, 1)
     evals = K * sweep_points(ux, uy, CROSS_T) + sweep_points(ux, uy, INTERIOR_T)
     res = {"value": evals * steps / dt, "ms_per_step": dt * 1e3 / steps, "refresh_every": refresh,
+           "assembly": "fp16" if assembly_fp16 else "fp32",
            "step_ms": {"median": float(np.median(per)) * 1e3, "min": min(per) * 1e3, "max": max(per) * 1e3}}
     gpath = os.path.join(GOLDEN, "c4_fp64.npz")
     if K == w["sweeps"] and os.path.exists(gpath):
@@ -406,12 +410,15 @@ def trained_section(ctx):
     t4 = {}
     # plain sweeps in each precision, and 16-bit sweeps with a float32
     # correction refreshed every `refresh` sweeps (mf_solve_mixed)
-    runs = (("fp32", MF_FP32, 0), ("bf16", MF_BF16, 0), ("fp16", MF_FP16, 0),
-            ("fp16_mixed_refresh50", MF_FP16, 50), ("bf16_mixed_refresh5", MF_BF16, 5))
-    for name, prec, refresh in runs:
+    # (the assembly in float32, or in the sweeps' precision: asm16)
+    runs = (("fp32", MF_FP32, 0, MF_FP32), ("bf16", MF_BF16, 0, MF_FP32), ("fp16", MF_FP16, 0, MF_FP32),
+            ("fp16_mixed_refresh50", MF_FP16, 50, MF_FP32), ("fp16_mixed_refresh50_asm16", MF_FP16, 50, MF_FP16),
+            ("bf16_mixed_refresh5", MF_BF16, 5, MF_FP32))
+    for name, prec, refresh, asm in runs:
         def solve(u, n, uo=None):
             if refresh:
-                mf_solve_mixed(ctx, p, u, (64, 64), n, refresh_every=refresh, prec=prec, u_out=uo)
+                mf_solve_mixed(ctx, p, u, (64, 64), n, refresh_every=refresh, prec=prec, u_out=uo,
+                               assembly_prec=asm)
             else:
                 mf_solve(ctx, p, u, (64, 64), n, prec=prec, u_out=uo)
         u = torch.from_numpy(f64).cuda()
@@ -538,7 +545,11 @@ def main():
     mixed = c4_mixed_section(ctx, args)
     mixed["speedup_over_fp32"] = mixed["value"] / fp32["value"]
     out["fp16_mixed"] = mixed
-    print(f"# fp16 mixed 64x64: {mixed['value']:.4g} point-evals/s", file=sys.stderr, flush=True)
+    mixed16 = c4_mixed_section(ctx, args, assembly_fp16=True)
+    mixed16["speedup_over_fp32"] = mixed16["value"] / fp32["value"]
+    out["fp16_mixed_asm16"] = mixed16
+    print(f"# fp16 mixed 64x64: {mixed['value']:.4g} point-evals/s, with the FP16 assembly "
+          f"{mixed16['value']:.4g}", file=sys.stderr, flush=True)
     if not args.headline_only:
         out["c2"] = c2_section(ctx, args)
         print("# c2 done", file=sys.stderr, flush=True)

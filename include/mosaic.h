@@ -371,7 +371,10 @@ mf_status mf_mixed_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom,
  * from the float32 one); the correction, exact at each refresh and slowly
  * varying, keeps the fixed point at the float32 one. refresh_every = 1 is
  * the float32 iteration exactly (bit for bit). max_sweeps sweeps (no delta
- * test), then, when u_out is not NULL, the float32 assembly as in mf_solve.
+ * test), then, when u_out is not NULL, the assembly as in mf_solve in
+ * assembly_prec: MF_FP32, or prec itself (one evaluation per point, not
+ * iterated, so its 16-bit rounding is not amplified: on a 64 x 64-unit
+ * domain it moves the FP16 result by 4e-4 and runs 4x faster).
  * The tanh network only; single domains and batches (the correction
  * kernels take a batch's placements of a colour in one launch). The
  * workspace holds the three prepared networks (16-bit twice, float32), one
@@ -379,8 +382,8 @@ mf_status mf_mixed_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom,
  * that size. Asynchronous. */
 mf_status mf_solve_mixed(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
                          const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
-                         int32_t max_sweeps, int32_t refresh_every, float* u_out, void* ws, size_t ws_bytes,
-                         void* stream);
+                         int32_t max_sweeps, int32_t refresh_every, int32_t assembly_prec, float* u_out, void* ws,
+                         size_t ws_bytes, void* stream);
 
 /* Workspace bytes for mf_solve_adjoint. */
 mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int32_t n_domains,

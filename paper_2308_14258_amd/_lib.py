@@ -84,7 +84,8 @@ _SIG = {
     "mf_mixed_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
                                       _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "mf_solve_mixed": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc), _c.c_int32,
-                                    _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P, _P, _c.c_size_t, _P]),
+                                    _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _P, _P,
+                                    _c.c_size_t, _P]),
     "mf_adjoint_ws_size": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(DomainDesc), _c.c_int32,
                                         _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     "mf_solve_adjoint": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.POINTER(DomainDesc),

@@ -245,10 +245,11 @@ def mf_solve(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int,
 
 
 def mf_solve_mixed(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int, refresh_every: int = 20,
-                   prec: int = MF_BF16, targets: int = MF_CROSS, u_out=None):
+                   prec: int = MF_BF16, targets: int = MF_CROSS, u_out=None, assembly_prec: int = MF_FP32):
     """Sweeps in 16 bits (prec MF_BF16 or MF_FP16) with a float32 correction
-    refreshed every refresh_every sweeps, then the float32 assembly into
-    u_out (optional). u is a 2-D field with units (ux, uy), or a Batch."""
+    refreshed every refresh_every sweeps, then the assembly into u_out
+    (optional) in assembly_prec (MF_FP32 or prec). u is a 2-D field with
+    units (ux, uy), or a Batch."""
     _need_cuda_f32(params, "params")
     buf, dom, nd = _field_and_domains(u, units)
     if u_out is not None:
@@ -264,7 +265,8 @@ def mf_solve_mixed(ctx: Context, params: torch.Tensor, u, units, max_sweeps: int
           "mf_mixed_ws_size")
     ws = ctx.workspace(n.value)
     check(lib.mf_solve_mixed(ctx.ptr, ctypes.byref(desc_of(params)), _ptr(params), _ptr(buf), _dom_arg(dom), nd,
-                             targets, prec, max_sweeps, refresh_every, _ptr(u_out), _ptr(ws), ws.numel(),
+                             targets, prec, max_sweeps, refresh_every, assembly_prec, _ptr(u_out), _ptr(ws),
+                             ws.numel(),
                              _stream()), "mf_solve_mixed")
 
 

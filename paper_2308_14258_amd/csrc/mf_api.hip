@@ -1087,9 +1087,11 @@ mf_status mf_mixed_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* dom,
 
 mf_status mf_solve_mixed(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* params, float* u,
                          const mf_domain_desc* dom, int32_t n_domains, int32_t targets, int32_t prec,
-                         int32_t max_sweeps, int32_t refresh_every, float* u_out, void* ws, size_t ws_bytes,
-                         void* stream) {
+                         int32_t max_sweeps, int32_t refresh_every, int32_t assembly_prec, float* u_out, void* ws,
+                         size_t ws_bytes, void* stream) {
   MF_TRY(mixed_checks(desc, dom, n_domains, targets, prec));
+  if (assembly_prec != MF_FP32 && assembly_prec != prec)
+    return fail(MF_EINVAL, "assembly_prec must be MF_FP32 or the sweeps' precision");
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(u, "u"));
   if (max_sweeps < 0) return fail(MF_EINVAL, "max_sweeps %d < 0", max_sweeps);
@@ -1157,11 +1159,12 @@ mf_status mf_solve_mixed(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* pa
       }
     }
   }
-  if (u_out) {   // the assembly in float32
+  if (u_out) {   // the assembly in float32 or in the sweeps' precision
+    const Plan& PA = assembly_prec == MF_FP32 ? P32 : P16;
     for (int d = 0; d < nd; ++d)
       MF_HIP(launch_assembly_init(u + dom[d].field_offset, u_out + dom[d].field_offset, dom[d].pitch,
                                   dom[d].units_x, dom[d].units_y, s));
-    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, P32, c, PH_ASSEMBLY, u_out, s));
+    for (int c = 0; c < 4; ++c) MF_TRY(run_colour(ctx, PA, c, PH_ASSEMBLY, u_out, s));
   }
   return ok();
 }

@@ -331,15 +331,17 @@ def test_solve_mixed_argument_errors(lib):
     dom = _dom()
     n = ctypes.c_size_t(0)
 
-    def call(prec=MF_BF16, refresh=10, sweeps=5, u_out=None, desc=d, ws=FAKE, ws_bytes=1 << 34):
+    def call(prec=MF_BF16, refresh=10, sweeps=5, u_out=None, desc=d, ws=FAKE, ws_bytes=1 << 34, asm=MF_FP32):
         return lib.mf_solve_mixed(None, ctypes.byref(desc), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
-                                  ctypes.byref(dom), 1, MF_CROSS, prec, sweeps, refresh,
+                                  ctypes.byref(dom), 1, MF_CROSS, prec, sweeps, refresh, asm,
                                   ctypes.c_void_p(u_out) if u_out else None, ctypes.c_void_p(ws) if ws else None,
                                   ws_bytes, None)
     assert call() == MF_EINVAL and b"ctx" in lib.mf_last_error()              # all else valid
     assert call(prec=MF_FP16) == MF_EINVAL and b"ctx" in lib.mf_last_error()
     assert call(prec=MF_FP32) == MF_EINVAL and b"MF_BF16 or MF_FP16" in lib.mf_last_error()
     assert call(refresh=0) == MF_EINVAL and b"refresh_every" in lib.mf_last_error()
+    assert call(asm=MF_BF16) == MF_EINVAL and b"ctx" in lib.mf_last_error()    # the sweeps' precision
+    assert call(asm=MF_FP16) == MF_EINVAL and b"assembly_prec" in lib.mf_last_error()
     assert call(sweeps=-1) == MF_EINVAL
     assert call(u_out=FAKE) == MF_EINVAL and b"alias" in lib.mf_last_error()
     assert call(ws_bytes=1024) == MF_ENOMEM
