@@ -159,13 +159,15 @@ mf_status mf_ctx_graphs(mf_ctx* ctx, int32_t enable);
  * the LDS reads of the activations; not for MF_FP16), and
  * 256 | MF_TILE_ROWSPLIT selects the
  * row-split tile (each of 8 waves owns 32 rows and every unit; activations
- * stay in registers and the hidden weights stream through LDS); or-ed also
+ * stay in registers and the hidden weights stream through LDS, one
+ * workgroup per CU), 128 | MF_TILE_ROWSPLIT the same tile with 4 waves (two
+ * workgroups per CU; same results bit for bit); or-ed also
  * with MF_TILE_PERSIST, a batch's row-split phase runs as a persistent grid
- * (one workgroup per CU walking the tiles) instead of one tile per
- * workgroup (single domains ignore the flag). 0 restores
+ * (the workgroups one CU holds, per CU, walking the tiles) instead of one
+ * tile per workgroup (single domains ignore the flag). 0 restores
  * the automatic choice: a tuned value from mf_autotune, else a rule on the
  * phase's rows per CU. MF_BF16 and MF_FP16: 256 | MF_TILE_ROWSPLIT from
- * 256 rows per CU up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
+ * 128 rows per CU up, 64 below. MF_FP32: 32 below 32 rows per CU, 64 from there, and
  * 64 | MF_TILE_STREAM for a single domain from 128 rows per CU up. */
 mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
 
@@ -177,8 +179,8 @@ mf_status mf_ctx_tile_rows(mf_ctx* ctx, int32_t prec, int32_t rows);
  * a single domain is matched by its units, a batch by its list of domain
  * descriptors. Candidates: MF_FP32 32, 64, 64 | MF_TILE_STREAM (batches: 32,
  * 64); MF_BF16 64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE,
- * 256 | MF_TILE_ROWSPLIT (batches also 256 | MF_TILE_ROWSPLIT |
- * MF_TILE_PERSIST); MF_FP16 the same without the MF_TILE_WIDE shapes. The sweeps run on u itself (it advances by
+ * 256 | MF_TILE_ROWSPLIT, 128 | MF_TILE_ROWSPLIT (batches also
+ * 256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST); MF_FP16 the same without the MF_TILE_WIDE shapes. The sweeps run on u itself (it advances by
  * (3 trials + 1) x candidates sweeps); pass a scratch copy to keep the field.
  * rows_out (host, nullable) receives the choice. The tanh network only
  * (MF_EUNSUPPORTED for MF_GELU). Synchronises the stream. */

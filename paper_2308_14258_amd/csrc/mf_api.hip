@@ -190,7 +190,7 @@ static bool valid_tile_rows(int prec, int rows) {
   if (rows & MF_TILE_STREAM) return false;
   if (prec == MF_FP16 && (rows & MF_TILE_WIDE)) return false;
   if (rows & MF_TILE_ROWSPLIT)
-    return rows == (256 | MF_TILE_ROWSPLIT) || rows == (256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST);
+    return (rows & ~MF_TILE_PERSIST) == (256 | MF_TILE_ROWSPLIT) || (rows & ~MF_TILE_PERSIST) == (128 | MF_TILE_ROWSPLIT);
   const int r = rows & ~MF_TILE_WIDE;
   if (rows & MF_TILE_WIDE) return r == 128 || r == 256;
   return r == 64 || r == 128 || r == 256;
@@ -549,9 +549,12 @@ static int tile_rows_for(const mf_ctx* ctx, int width, int prec, int targets, co
         (nd == 1 ? (t.key == 0 && t.ux == dom->units_x && t.uy == dom->units_y) : t.key == key))
       return t.rows;
   const int64_t n_cu = ctx->n_cu;
-  // bf16 and fp16: the row-split tile from one 256-row tile per CU up; below that the
-  // 64-row column-split tile spreads the rows over more CUs
-  if (prec != MF_FP32) return rows >= 256 * n_cu ? (256 | MF_TILE_ROWSPLIT) : 64;
+  // bf16 and fp16: the 256-row row-split tile from half such a tile per CU up
+  // (32 x 32 units, ~0.9 tiles per CU: 32.5 against 42.4 us per phase with
+  // 64-row tiles; 24 x 24 units, ~0.5: 30.5 against 31.2 us); below that the
+  // 64-row column-split tile spreads the rows over more CUs (16 x 16 units:
+  // 17.6 against 30.1 us)
+  if (prec != MF_FP32) return rows >= 128 * n_cu ? (256 | MF_TILE_ROWSPLIT) : 64;
   // fp32: 64-row tiles with register weights from one 32-row tile per CU up
   // (a 16 x 16-unit phase, ~0.9 such tiles per CU: 54 us against 61 us with
   // 32-row tiles); below that, 32-row tiles spread the few rows over more CUs.
@@ -842,15 +845,16 @@ mf_status mf_autotune(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* param
   MF_HIP(hipSetDevice(ctx->device));
   MF_HIP(launch_prepare_net(params, desc->width, prec, L.net, ws, s));
   // Candidates. A batch runs the batched kernel, whose streamed-weight fp32
-  // form spills (not offered); its row-split tile comes in both launch forms
-  // (one tile per workgroup, or a persistent grid).
+  // form spills (not offered); its 256-row row-split tile comes in both
+  // launch forms (one tile per workgroup, or a persistent grid).
   const bool batch = n_domains > 1;
   const int cands_fp32[] = {32, 64, 64 | MF_TILE_STREAM};
   const int cands_bf16[] = {64, 128, 256, 128 | MF_TILE_WIDE, 256 | MF_TILE_WIDE, 256 | MF_TILE_ROWSPLIT,
+                            128 | MF_TILE_ROWSPLIT, 256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
+  const int cands_fp16[] = {64, 128, 256, 256 | MF_TILE_ROWSPLIT, 128 | MF_TILE_ROWSPLIT,
                             256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
-  const int cands_fp16[] = {64, 128, 256, 256 | MF_TILE_ROWSPLIT, 256 | MF_TILE_ROWSPLIT | MF_TILE_PERSIST};
   const int* cands = prec == MF_FP32 ? cands_fp32 : prec == MF_BF16 ? cands_bf16 : cands_fp16;
-  const int n_cands = prec == MF_FP32 ? (batch ? 2 : 3) : prec == MF_BF16 ? (batch ? 7 : 6) : (batch ? 5 : 4);
+  const int n_cands = prec == MF_FP32 ? (batch ? 2 : 3) : prec == MF_BF16 ? (batch ? 8 : 7) : (batch ? 6 : 5);
   const int saved_force = ctx->force_rows[prec];
   const bool saved_timing = ctx->timing;
   ctx->timing = false;

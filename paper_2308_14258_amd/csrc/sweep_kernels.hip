@@ -691,23 +691,30 @@ __device__ __forceinline__ typename Mma<PREC>::T rs_operand(const float* v) {
   return __builtin_bit_cast(typename Mma<PREC>::T, u32x4{s0[0], s1[0], s0[1], s1[1]});
 }
 
-template <int D_, int PB_, int PREC_ = 1>
+template <int D_, int PB_, int PREC_ = 1, int R_ = 256>
 struct RsShape {
-  static constexpr int D = D_, R = 256, PREC = PREC_, CPW = 32, PB = PB_;
+  static constexpr int D = D_, R = R_, PREC = PREC_, CPW = 32, PB = PB_;
   static constexpr bool WREG = true, RS = true;
-  static constexpr int NTH = 512 / PB, MINW = PB == 1 ? 2 : 1;
+  static constexpr int NTH = 2 * R / PB, MINW = PB == 1 ? 2 : 1;
 };
 
-template <int D, int TMODE, int OUT, int PB, int PREC = 1>
+// R = 256: 8 waves, one workgroup per CU (143 KB of LDS at d = 256), the
+// weights in half-layer steps. R = 128: 4 waves and quarter-layer steps
+// (76 KB), so two workgroups share a CU and run out of step with each other:
+// one's gather, projection, first layer and barrier waits overlap the
+// other's MFMAs. Per row the arithmetic is the same in both.
+template <int D, int TMODE, int OUT, int PB, int PREC = 1, int R = 256>
 __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   typedef typename Mma<PREC>::T OT;   // 16-bit operand vector (bf16 or fp16)
-  constexpr int R = 256, NW = 8 / PB, NTH = 64 * NW;
+  constexpr int NW = R / (32 * PB), NTH = 64 * NW;
   constexpr int T = n_targets<TMODE>();
   constexpr int NPMAX = (R - 1) / T + 2;
-  constexpr int NOB = D / 32, NKG = D / 16, HOB = NOB / 2;
-  constexpr int HALF = HOB * NKG * 64;       // 16-byte pieces per half layer
+  constexpr int NOB = D / 32, NKG = D / 16;
+  constexpr int NST = (R == 256 || D == 128) ? 2 : 4;   // weight steps per layer
+  constexpr int HOB = NOB / NST;             // output blocks per step
+  constexpr int HALF = HOB * NKG * 64;       // 16-byte pieces per step
   constexpr int PPT = HALF / NTH;            // pieces per thread
-  static_assert(PPT * NTH == HALF && NPMAX <= 8, "row-split tile");
+  static_assert(PPT * NTH == HALF && HOB * NST == NOB && NPMAX <= 8, "row-split tile");
   __shared__ __align__(16) u32x4 wbuf[2][HALF];
   __shared__ __align__(16) float gs[NPMAX * kNB];
   __shared__ __align__(16) float cs[NPMAX * D];
@@ -719,7 +726,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
   const NetPtrs& net = A.net;
   const u32x4* whp = static_cast<const u32x4*>(net.wh);   // prepared bf16 weights, [ob][kg][lane][8]
 
-  // half layer k (layer k / 2, output blocks HOB (k & 1) ..) into LDS buffer
+  // step k (layer k / NST, output blocks HOB (k % NST) ..) into LDS buffer
   // `buf` with direct global-to-LDS loads (each lane's 16 bytes land at the
   // wave's base + 16 lane), so the copy holds no registers; completion is
   // awaited (vmcnt) before the barrier that publishes the buffer
@@ -824,19 +831,19 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
     for (int b = 0; b < PB; ++b) H[0][b][kg] = __builtin_bit_cast(OT, hb[b]);
   }
 
-  // -- hidden layers: six half-layer steps ------------------------------------
+  // -- hidden layers: 3 NST weight steps --------------------------------------
   float s[PB];
 #pragma unroll
   for (int b = 0; b < PB; ++b) s[b] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int l = k >> 1, hf = k & 1;
+  for (int k = 0; k < 3 * NST; ++k) {
+    const int l = k / NST, hf = k % NST;
     OT(&hin)[PB][NKG] = H[l & 1];
     OT(&hout)[PB][NKG] = H[(l + 1) & 1];
-    // the other buffer's half was finished by every wave before the last barrier
-    if (k < 5) fetch(k + 1, (k + 1) & 1);
+    // the other buffer's step was finished by every wave before the last barrier
+    if (k < 3 * NST - 1) fetch(k + 1, (k + 1) & 1);
     const u32x4* wb = wbuf[k & 1] + lane;
-    // weight operand i of the half step (output block i / NKG, k group
+    // weight operand i of the step (output block i / NKG, k group
     // i % NKG) comes from a ring filled four operands ahead and feeds PB
     // MFMAs; the tanh (or output dot) of the previous output block's 16 PB
     // accumulator elements is spread over the block's MFMAs so both pipes
@@ -896,7 +903,7 @@ __device__ __forceinline__ void rs_body(const TileArgs& A, const int64_t row0) {
         }
       }
     }
-    if (k < 5) {
+    if (k < 3 * NST - 1) {
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
@@ -918,7 +925,7 @@ template <class S, int TMODE, int SRC, int OUT>
 __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel(TileArgs A) {
   if constexpr (S::RS) {
     if constexpr (SRC == SRC_GATHER && OUT != OUT_LINEAR)
-      rs_body<S::D, TMODE, OUT, S::PB, S::PREC>(A, (A.block0 + blockIdx.x) * S::R);
+      rs_body<S::D, TMODE, OUT, S::PB, S::PREC, S::R>(A, (A.block0 + blockIdx.x) * S::R);
   } else {
     tile_body<S::D, S::R, TMODE, S::PREC, SRC, OUT, S::CPW, S::WREG>(A, (A.block0 + blockIdx.x) * S::R);
   }
@@ -978,7 +985,7 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
     A.ux = e.ux;
     A.uy = e.uy;
     A.total_rows = (int64_t)(e.ux - ca) * (e.uy - cb) * T;
-    if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB, S::PREC>(A, (t - M.tile_begin[lo]) * S::R);
+    if constexpr (S::RS) rs_body<S::D, TMODE, OUT, S::PB, S::PREC, S::R>(A, (t - M.tile_begin[lo]) * S::R);
     else tile_body<S::D, S::R, TMODE, S::PREC, SRC_GATHER, OUT, S::CPW, S::WREG>(A, (t - M.tile_begin[lo]) * S::R);
   };
   if constexpr (S::RS && !PERSIST) {
@@ -999,21 +1006,21 @@ __global__ __launch_bounds__(S::NTH, S::MINW) void tile_kernel_multi(MultiArgs M
 
 // Tile shapes by (width, precision, tile code): fp32 32 (streamed weights),
 // 64 (register weights), 64 | MF_TILE_STREAM (streamed); bf16 64, 128, 256,
-// 128 or 256 | MF_TILE_WIDE (64 columns per wave) and 256 | MF_TILE_ROWSPLIT
-// (row-split tile); fp16 the bf16 codes without MF_TILE_WIDE. The caller has
-// validated the code.
+// 128 or 256 | MF_TILE_WIDE (64 columns per wave) and 128 or 256 |
+// MF_TILE_ROWSPLIT (row-split tiles); fp16 the bf16 codes without
+// MF_TILE_WIDE. The caller has validated the code.
 template <int D, class F>
 static hipError_t with_shape_d(int prec, int code, F&& f) {
   const int r = code & 0xffff;
   if (prec == MF_BF16) {
-    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D, 1>{});
+    if (code & MF_TILE_ROWSPLIT) return r == 128 ? f(RsShape<D, 1, 1, 128>{}) : f(RsShape<D, 1>{});
     if (code & MF_TILE_WIDE) return r == 256 ? f(Shape<D, 256, 1, 64, true>{}) : f(Shape<D, 128, 1, 64, true>{});
     if (r == 256) return f(Shape<D, 256, 1, 32, true>{});
     if (r == 128) return f(Shape<D, 128, 1, 32, true>{});
     return f(Shape<D, 64, 1, 32, true>{});
   }
   if (prec == MF_FP16) {   // the same tiles on fp16 operands (no 64-column forms)
-    if (code & MF_TILE_ROWSPLIT) return f(RsShape<D, 1, 2>{});
+    if (code & MF_TILE_ROWSPLIT) return r == 128 ? f(RsShape<D, 1, 2, 128>{}) : f(RsShape<D, 1, 2>{});
     if (r == 256) return f(Shape<D, 256, 2, 32, true>{});
     if (r == 128) return f(Shape<D, 128, 2, 32, true>{});
     return f(Shape<D, 64, 2, 32, true>{});

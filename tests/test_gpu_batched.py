@@ -199,10 +199,11 @@ def test_autotune_on_a_batch_and_the_persistent_row_split_form(ctx):
     rs = 256 | MF_TILE_ROWSPLIT
     scratch = Batch(fields)
     best = mf_autotune(ctx, params, scratch, None, MF_CROSS, MF_BF16, trials=2)
-    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), rs, rs | MF_TILE_PERSIST), best
+    rs128 = 128 | MF_TILE_ROWSPLIT
+    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), rs, rs128, rs | MF_TILE_PERSIST), best
     print(f"batch autotune chose {best:#x}", flush=True)
     outs = {}
-    for code in (rs, rs | MF_TILE_PERSIST, 0):   # 0: the tuned choice
+    for code in (rs, rs | MF_TILE_PERSIST, rs128, rs128 | MF_TILE_PERSIST, 0):   # 0: the tuned choice
         ctx.tile_rows(MF_BF16, code)
         b = Batch(fields)
         o = torch.empty_like(b.buf)
@@ -210,7 +211,8 @@ def test_autotune_on_a_batch_and_the_persistent_row_split_form(ctx):
         torch.cuda.synchronize()
         outs[code] = (b.buf.clone(), o)
     ctx.tile_rows(MF_BF16, 0)
-    assert torch.equal(outs[rs][0], outs[rs | MF_TILE_PERSIST][0])
-    assert torch.equal(outs[rs][1], outs[rs | MF_TILE_PERSIST][1])
-    if best in (rs, rs | MF_TILE_PERSIST):
+    for code in (rs | MF_TILE_PERSIST, rs128, rs128 | MF_TILE_PERSIST):
+        assert torch.equal(outs[rs][0], outs[code][0]), hex(code)
+        assert torch.equal(outs[rs][1], outs[code][1]), hex(code)
+    if best in (rs, rs | MF_TILE_PERSIST, rs128):
         assert torch.equal(outs[0][0], outs[rs][0])

@@ -430,7 +430,8 @@ def test_graph_replay_sees_new_parameter_values(ctx, prec):
 @pytest.mark.parametrize("prec,rows", [(MF_FP32, 32), (MF_FP32, 64), (MF_FP32, 64 | (1 << 17)), (MF_BF16, 64),
                                        (MF_BF16, 128), (MF_BF16, 256), (MF_BF16, 128 | (1 << 16)),
                                        (MF_BF16, 256 | (1 << 16)), (MF_BF16, 256 | (1 << 18)),
-                                       (MF_FP16, 64), (MF_FP16, 128), (MF_FP16, 256), (MF_FP16, 256 | (1 << 18))])
+                                       (MF_BF16, 128 | (1 << 18)), (MF_FP16, 64), (MF_FP16, 128), (MF_FP16, 256),
+                                       (MF_FP16, 256 | (1 << 18)), (MF_FP16, 128 | (1 << 18))])
 @pytest.mark.parametrize("targets", [MF_CROSS, MF_INTERIOR])
 def test_every_tile_height(ctx, prec, rows, targets):
     print(f"case: tile rows {rows} prec {prec} targets {targets}", flush=True)
@@ -460,7 +461,7 @@ def test_autotune_picks_a_candidate_and_is_used(ctx):
     f = mi.gp_field(8, 8, 1.0, seed=2)
     scratch = dev(f)
     best = mf_autotune(ctx, params, scratch, (8, 8), MF_CROSS, MF_BF16, trials=2)
-    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), 256 | (1 << 18))
+    assert best in (64, 128, 256, 128 | (1 << 16), 256 | (1 << 16), 256 | (1 << 18), 128 | (1 << 18))
     a = dev(f)
     mf_solve(ctx, params, a, (8, 8), 5, prec=MF_BF16)
     ctx.tile_rows(MF_BF16, best)
@@ -508,15 +509,15 @@ def test_additive_solve_c1(ctx):
 @pytest.mark.parametrize("width", [128, 256])
 def test_rowsplit_tile_solve_and_assembly(ctx, width, prec, tol):
     """The row-split 16-bit tile (each wave owns 32 rows, weights streamed
-    through LDS) in a full solve: sweeps and the overlap-averaged assembly
-    against the oracle, and bit for bit against the column-split tile of the
-    same precision."""
+    through LDS; 8 waves or 4) in a full solve: sweeps and the overlap-averaged
+    assembly against the oracle, and bit for bit against the column-split tile
+    of the same precision."""
     print(f"case: row-split tile prec {prec}, width {width}, 5x4 units, 3 sweeps + assembly", flush=True)
     ux, uy = 5, 4
     params = mi.xavier_params(width, 2)
     f = mi.gp_field(ux, uy, 1.0, seed=6)
     outs = {}
-    for name, rows in (("rowsplit", 256 | (1 << 18)), ("default", 0)):
+    for name, rows in (("rowsplit", 256 | (1 << 18)), ("rowsplit128", 128 | (1 << 18)), ("default", 0)):
         u = dev(f)
         u_out = torch.empty_like(u)
         ctx.tile_rows(prec, rows)
@@ -534,8 +535,9 @@ def test_rowsplit_tile_solve_and_assembly(ctx, width, prec, tol):
           flush=True)
     assert e_or <= tol
     # same k order in every MFMA, same tanh and output sums: identical results
-    np.testing.assert_array_equal(outs["rowsplit"][0], outs["default"][0])
-    np.testing.assert_array_equal(outs["rowsplit"][1], outs["default"][1])
+    for name in ("rowsplit128", "default"):
+        np.testing.assert_array_equal(outs["rowsplit"][0], outs[name][0])
+        np.testing.assert_array_equal(outs["rowsplit"][1], outs[name][1])
 
 
 @pytest.mark.parametrize("width", [128, 256])
