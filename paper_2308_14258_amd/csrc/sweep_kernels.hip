@@ -210,7 +210,7 @@ template <> struct Mma<2> {
   // tanh's last fma into a mixed-precision fma with fp16 output in some tile
   // forms and not in others, and the tiles would round differently.
   static __device__ __forceinline__ uint32_t pack(float a, float b) {
-    asm volatile("" : "+v"(a), "+v"(b));
+    asm("" : "+v"(a), "+v"(b));
     const halfx2 p = {(_Float16)a, (_Float16)b};
     return __builtin_bit_cast(uint32_t, p);
   }
