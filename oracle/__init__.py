@@ -24,8 +24,10 @@ no blocking, fusion or reordering beyond what the definitions state:
 * ``train``     -- boundary-match + PDE loss (Eq. 3), its gradient, and Adam
   (Alg. 1).
 * ``adjoint``   -- d J / d g through K sweeps and the assembly.
+* ``optim``     -- LAMB, the warm-up + polynomial-decay learning rate and the
+  multi-device scaling rules of the training (Sec. 5.2, "Hyperparameters").
 
 Every function states which passage it follows. Pins that tie the oracle to
 facts outside itself live in ``tests/test_oracle_*.py``.
 """
-from . import adjoint, fd, geometry, sdnet, sdnet_conv, sweep, train  # noqa: F401
+from . import adjoint, fd, geometry, optim, sdnet, sdnet_conv, sweep, train  # noqa: F401
