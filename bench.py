@@ -609,10 +609,47 @@ def train_measurement(ctx, steps):
     dt = time.perf_counter() - t0
     rows = w["n_bc"] * (4 * w["n_colloc"] + 128)
     flops = 3 * (3 * 2.0 * d * d * rows)
-    return {"workload": "C3: 1024 conditions x (128 + 256) points, width 128, Adam",
+    res = {"workload": "C3: 1024 conditions x (128 + 256) points, width 128, Adam",
+           "steps_per_s": steps / dt, "ms_per_step": dt * 1e3 / steps,
+           "gemm_tflops": flops * steps / dt / 1e12,
+           "frac_of_fp32_mfma_peak": flops * steps / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+           "last_loss": [float(x) for x in loss.cpu()]}
+    res["lamb"] = train_lamb_measurement(ctx, steps, G, Xb, Xc, d)
+    return res
+
+
+def train_lamb_measurement(ctx, steps, G, Xb, Xc, d):
+    """The same step with the paper's optimiser (Sec. 5.2): the loss and
+    gradient (sdnet_loss_grad), then LAMB (sdnet_lamb_step) at the
+    schedule's learning rate (peak 1e-3, 0.1% warm-up, linear decay over
+    500 x steps iterations), gradient clipped to norm 1; and the LAMB
+    kernel alone."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import lr_at, lr_schedule, sdnet_lamb_step, sdnet_loss_grad
+    p = torch.from_numpy(mi.xavier_params(d, 0)).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    sched = lr_schedule(1e-3, 500 * steps)
+    hp = dict(weight_decay=0.0, max_grad_norm=1.0, trust_without_decay=True)
+    loss, grad = sdnet_loss_grad(ctx, p, G, Xb, Xc)
+    for k in range(2):
+        sdnet_loss_grad(ctx, p, G, Xb, Xc, loss=loss, grad_out=grad)
+        sdnet_lamb_step(ctx, p, m, v, grad, k + 1, lr=lr_at(sched, k + 1), **hp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sdnet_loss_grad(ctx, p, G, Xb, Xc, loss=loss, grad_out=grad)
+        sdnet_lamb_step(ctx, p, m, v, grad, k + 3, lr=lr_at(sched, k + 3), **hp)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lamb_ms = _event_ms(lambda: sdnet_lamb_step(ctx, p, m, v, grad, 100, lr=1e-4, **hp), 20)
+    n = p.numel()
+    return {"optimizer": "LAMB (trust ratio per tensor, clip 1.0), warm-up + linear decay",
             "steps_per_s": steps / dt, "ms_per_step": dt * 1e3 / steps,
-            "gemm_tflops": flops * steps / dt / 1e12,
-            "frac_of_fp32_mfma_peak": flops * steps / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+            "lamb_kernel_us": lamb_ms * 1e3,
+            # algorithmic bytes: p, m, v, g read once, p, m, v written once
+            "lamb_kernel_gbps": 7 * 4 * n / (lamb_ms * 1e-3) / 1e9,
             "last_loss": [float(x) for x in loss.cpu()]}
 
 

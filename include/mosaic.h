@@ -132,6 +132,35 @@ typedef struct mf_adam {
                                     that 1 - beta is formed before rounding */
 } mf_adam;
 
+/* LAMB (You et al., ICLR 2020), the optimiser of the SDNet training
+ * (Sec. 5.2, "Hyperparameters"). Per step t (from 1) and parameter tensor s:
+ *   g <- g min(1, max_grad_norm / ||g||)   (whole gradient; max_grad_norm 0: off)
+ *   m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2
+ *   u <- (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps) + weight_decay w
+ *   w_s <- w_s - lr r_s u_s,  r_s = ||w_s|| / ||u_s|| (1 if either is 0)
+ * The trust ratio r_s is applied to every tensor when trust_without_decay
+ * is 1 (LAMB as published); when it is 0, only if weight_decay != 0 (with
+ * the paper's weight decay of zero the step is then Adam on the clipped
+ * gradient). */
+typedef struct mf_lamb {
+  double lr, beta1, beta2, eps, weight_decay, max_grad_norm;
+  int32_t trust_without_decay;
+} mf_lamb;
+
+/* Learning rate (Sec. 5.2): linear warm-up over W = ceil(warmup_frac x
+ * total_steps) iterations to max_lr, then polynomial decay with exponent
+ * `power` to end_lr at total_steps:
+ *   lr(t) = max_lr t / W                                     for t <= W,
+ *   lr(t) = end_lr + (max_lr - end_lr) (1 - (t - W) / (total_steps - W))^power
+ *                                                            for W < t < total_steps,
+ *   lr(t) = end_lr                                           from total_steps on. */
+typedef struct mf_lr_schedule {
+  double max_lr, warmup_frac, power, end_lr;
+  int64_t total_steps;
+} mf_lr_schedule;
+
+enum { MF_MAX_SEGMENTS = 64 };                       /* tensors per LAMB step */
+
 typedef struct mf_ctx mf_ctx;
 
 /* Context for one device. mf_ctx_create selects `device`, checks that it is
@@ -490,6 +519,40 @@ mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* p
                           int64_t B, const float* Xd, int64_t nd, int32_t xd_per_bc, const float* Yd,
                           const float* Xc, int64_t nc, float* loss_dev, float* grad_out, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* The tensors of an SDNet's flat parameter vector, each weight matrix and
+ * bias vector on its own, in layout order (the tanh network: W1, b1, W2, b2,
+ * W3, b3, W4, b4, w5, b5; the GELU network: the two convolutions' kernels
+ * and biases first): begin (host, capacity + 1 entries) receives the first
+ * index of every tensor and, last, the parameter count; *n_segments (host)
+ * the number of tensors (also when capacity is too small: MF_ESHAPE). Host
+ * only. */
+mf_status mf_param_segments(const mf_sdnet_desc* desc, int64_t* begin, int32_t capacity, int32_t* n_segments);
+
+/* One LAMB step (see mf_lamb) on device vectors params, m, v (updated in
+ * place) from the gradient grad (device, read only; for Alg. 1 the summed
+ * data and collocation gradient of sdnet_loss_grad, averaged over devices
+ * by the caller's allreduce on more than one). The tensors are given by
+ * seg_begin (host, n_segments + 1 nondecreasing entries, seg_begin[0] = 0,
+ * seg_begin[n_segments] = the vector length), 1 <= n_segments <=
+ * MF_MAX_SEGMENTS; mf_param_segments gives an SDNet's. step counts from 1.
+ * One kernel launch of n_segments workgroups on `stream`, deterministic
+ * (fixed reduction order); no workspace. Asynchronous. */
+mf_status sdnet_lamb_step(mf_ctx* ctx, float* params, float* m, float* v, const float* grad,
+                          const int64_t* seg_begin, int32_t n_segments, int64_t step, const mf_lamb* hp,
+                          void* stream);
+
+/* The schedule's learning rate at iteration step (from 1) into *lr (host).
+ * MF_EINVAL for step < 1, total_steps < 1, warmup_frac outside [0, 1],
+ * max_lr or end_lr < 0, power <= 0. Host only. */
+mf_status mf_lr_at(const mf_lr_schedule* sched, int64_t step, double* lr);
+
+/* The rules for a batch batch_factor times larger (k devices, each with
+ * the one-device batch; Sec. 5.2): max_lr times sqrt(batch_factor), the
+ * warm-up fraction times batch_factor (at most 1); the other fields are
+ * copied (the caller sets total_steps for its epochs). batch_factor > 0.
+ * Host only. */
+mf_status mf_lr_schedule_scaled(const mf_lr_schedule* base, double batch_factor, mf_lr_schedule* out);
 
 #ifdef __cplusplus
 }

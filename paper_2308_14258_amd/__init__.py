@@ -10,4 +10,5 @@ from ._lib import (MF_ADDITIVE, MF_BF16, MF_CROSS, MF_FP16, MF_FP32, MF_INTERIOR
 from .api import (Batch, Context, PhysicsLoss, mf_autotune, mf_colour_placements, mf_gather,  # noqa: F401
                   mf_scatter, mf_solve, mf_solve_adjoint, mf_solve_mixed, mf_sweep, mf_sweep_noalloc, mf_sweep_operator, mf_target_coords,
                   physics_loss, sdnet_forward, sdnet_loss_grad, sdnet_train_step, SkeletonCols,
-                  mf_skeleton_pack, mf_skeleton_unpack, mf_gather_skel, mf_scatter_skel)
+                  mf_skeleton_pack, mf_skeleton_unpack, mf_gather_skel, mf_scatter_skel, param_segments,
+                  sdnet_lamb_step, lr_schedule, lr_at, lr_schedule_scaled)

@@ -44,6 +44,20 @@ class Adam(ctypes.Structure):
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
+class Lamb(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("weight_decay", ctypes.c_double),
+                ("max_grad_norm", ctypes.c_double), ("trust_without_decay", ctypes.c_int32)]
+
+
+class LrSchedule(ctypes.Structure):
+    _fields_ = [("max_lr", ctypes.c_double), ("warmup_frac", ctypes.c_double), ("power", ctypes.c_double),
+                ("end_lr", ctypes.c_double), ("total_steps", ctypes.c_int64)]
+
+
+MF_MAX_SEGMENTS = 64
+
+
 _c = ctypes
 _P = ctypes.c_void_p
 _F = ctypes.POINTER(ctypes.c_float)
@@ -102,6 +116,12 @@ _SIG = {
                                       _P, _c.c_int64, _P, _P, _P, _c.c_size_t, _P]),
     "sdnet_loss_grad": (_c.c_int32, [_P, _c.POINTER(SdnetDesc), _P, _P, _c.c_int64, _P, _c.c_int64,
                                      _c.c_int32, _P, _P, _c.c_int64, _P, _P, _P, _c.c_size_t, _P]),
+    "mf_param_segments": (_c.c_int32, [_c.POINTER(SdnetDesc), _c.POINTER(_c.c_int64), _c.c_int32,
+                                       _c.POINTER(_c.c_int32)]),
+    "sdnet_lamb_step": (_c.c_int32, [_P, _P, _P, _P, _P, _c.POINTER(_c.c_int64), _c.c_int32, _c.c_int64,
+                                     _c.POINTER(Lamb), _P]),
+    "mf_lr_at": (_c.c_int32, [_c.POINTER(LrSchedule), _c.c_int64, _c.POINTER(_c.c_double)]),
+    "mf_lr_schedule_scaled": (_c.c_int32, [_c.POINTER(LrSchedule), _c.c_double, _c.POINTER(LrSchedule)]),
 }
 
 _lib = None

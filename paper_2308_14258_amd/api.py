@@ -12,8 +12,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (MF_BF16, MF_GELU, MF_CROSS, MF_FP32, MF_MULTIPLICATIVE, MF_TANH, Adam, DomainDesc, SdnetDesc,
-                   check, load)
+from ._lib import (MF_BF16, MF_GELU, MF_CROSS, MF_FP32, MF_MAX_SEGMENTS, MF_MULTIPLICATIVE, MF_TANH, Adam,
+                   DomainDesc, Lamb, LrSchedule, SdnetDesc, check, load)
 
 
 def _gelu_count(d: int, C: int) -> int:
@@ -506,6 +506,61 @@ def sdnet_loss_grad(ctx: Context, params: torch.Tensor, G: torch.Tensor, Xd: tor
                                  _ptr(grad_out), _ptr(ws), ws.numel(), _stream()),
           "sdnet_loss_grad")
     return loss, grad_out
+
+
+def param_segments(desc_or_params) -> list:
+    """Tensor boundaries of an SDNet's flat parameter vector (C entry point
+    mf_param_segments): the first index of W1, b1, W2, ..., w5, b5 (the GELU
+    network's two convolutions first) and, last, the parameter count."""
+    d = desc_or_params if isinstance(desc_or_params, SdnetDesc) else desc_of(desc_or_params)
+    begin = (ctypes.c_int64 * (MF_MAX_SEGMENTS + 1))()
+    n = ctypes.c_int32()
+    check(load().mf_param_segments(ctypes.byref(d), begin, MF_MAX_SEGMENTS, ctypes.byref(n)), "mf_param_segments")
+    return list(begin[:n.value + 1])
+
+
+def sdnet_lamb_step(ctx: Context, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor,
+                    step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-6,
+                    weight_decay: float = 0.0, max_grad_norm: float = 0.0, trust_without_decay: bool = True,
+                    segments=None) -> None:
+    """One LAMB step on params, m and v in place from grad (C entry point
+    sdnet_lamb_step). segments: tensor boundaries (default: the SDNet layout
+    of params, param_segments)."""
+    for t, name in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
+        _need_cuda_f32(t, name)
+        if t.numel() != params.numel() or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {params.numel()} elements")
+    seg = param_segments(params) if segments is None else [int(x) for x in segments]
+    if seg[-1] != params.numel():
+        raise ValueError("segments must end at the parameter count")
+    arr = (ctypes.c_int64 * len(seg))(*seg)
+    hp = Lamb(lr, beta1, beta2, eps, weight_decay, max_grad_norm, 1 if trust_without_decay else 0)
+    check(load().sdnet_lamb_step(ctx.ptr, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), arr, len(seg) - 1, step,
+                                 ctypes.byref(hp), _stream()), "sdnet_lamb_step")
+
+
+def lr_schedule(max_lr: float, total_steps: int, warmup_frac: float = 0.001, power: float = 1.0,
+                end_lr: float = 0.0) -> LrSchedule:
+    """Linear warm-up then polynomial decay (the paper's defaults: 0.1%
+    warm-up, exponent 1, decay to 0)."""
+    return LrSchedule(max_lr, warmup_frac, power, end_lr, total_steps)
+
+
+def lr_at(sched: LrSchedule, step: int) -> float:
+    """The schedule's learning rate at iteration step (from 1; C entry point
+    mf_lr_at)."""
+    lr = ctypes.c_double()
+    check(load().mf_lr_at(ctypes.byref(sched), step, ctypes.byref(lr)), "mf_lr_at")
+    return lr.value
+
+
+def lr_schedule_scaled(sched: LrSchedule, batch_factor: float) -> LrSchedule:
+    """Peak learning rate times sqrt(k) and warm-up fraction times k for a
+    batch k times larger (C entry point mf_lr_schedule_scaled)."""
+    out = LrSchedule()
+    check(load().mf_lr_schedule_scaled(ctypes.byref(sched), batch_factor, ctypes.byref(out)),
+          "mf_lr_schedule_scaled")
+    return out
 
 
 class PhysicsLoss(torch.autograd.Function):

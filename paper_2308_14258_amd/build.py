@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmosaic.so")
 SOURCES = ["mf_api.hip", "sweep_kernels.hip", "train_kernels.hip", "adjoint_kernels.hip", "io_kernels.hip",
-           "embed_kernels.hip", "mixed_kernels.hip"]
+           "embed_kernels.hip", "mixed_kernels.hip", "optim_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

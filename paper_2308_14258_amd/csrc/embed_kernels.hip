@@ -17,8 +17,6 @@
 
 namespace mf {
 
-constexpr int kConvK = 5;
-
 // Transposed embedding block of W1 ([E][d], coalesced over the output unit)
 // from the flat parameters (W1 of shape d x (E + 2) at offset w1_off).
 __global__ void prepare_w1eT_kernel(const float* __restrict__ params, int64_t w1_off, int d, int E,

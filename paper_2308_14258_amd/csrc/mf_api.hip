@@ -1692,4 +1692,103 @@ mf_status sdnet_loss_grad(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* p
                           xd_per_bc, Yd, Xc, nc, loss_dev, grad_out, ws, ws_bytes, stream);
 }
 
+mf_status mf_param_segments(const mf_sdnet_desc* desc, int64_t* begin, int32_t capacity, int32_t* n_segments) {
+  MF_TRY(check_desc(desc));
+  if (!begin || !n_segments) return fail(MF_EINVAL, "begin or n_segments is NULL");
+  const int64_t d = desc->width;
+  int64_t sizes[16];
+  int n = 0;
+  int64_t in1 = desc->n_boundary;
+  if (is_gelu(desc)) {   // conv 1 -> C and conv C -> C, kernel 5, each with its bias
+    const int64_t C = desc->embed_channels;
+    sizes[n++] = C * kConvK;
+    sizes[n++] = C;
+    sizes[n++] = C * C * kConvK;
+    sizes[n++] = C;
+    in1 = C * desc->n_boundary;
+  }
+  sizes[n++] = d * (in1 + 2);
+  sizes[n++] = d;
+  for (int l = 0; l < 3; ++l) {
+    sizes[n++] = d * d;
+    sizes[n++] = d;
+  }
+  sizes[n++] = d;
+  sizes[n++] = 1;
+  *n_segments = n;
+  if (capacity < n) return fail(MF_ESHAPE, "capacity %d < %d tensors", capacity, n);
+  begin[0] = 0;
+  for (int i = 0; i < n; ++i) begin[i + 1] = begin[i] + sizes[i];
+  if (begin[n] != mf_param_count(desc)) return fail(MF_EINVAL, "tensor table does not cover the parameters");
+  return ok();
+}
+
+mf_status sdnet_lamb_step(mf_ctx* ctx, float* params, float* m, float* v, const float* grad,
+                          const int64_t* seg_begin, int32_t n_segments, int64_t step, const mf_lamb* hp,
+                          void* stream) {
+  MF_TRY(check_ptr(params, "params"));
+  MF_TRY(check_ptr(m, "m"));
+  MF_TRY(check_ptr(v, "v"));
+  MF_TRY(check_ptr(grad, "grad"));
+  if (!seg_begin) return fail(MF_EINVAL, "seg_begin is NULL");
+  if (n_segments < 1 || n_segments > MF_MAX_SEGMENTS)
+    return fail(MF_EINVAL, "n_segments %d not in 1..%d", n_segments, (int)MF_MAX_SEGMENTS);
+  if (seg_begin[0] != 0) return fail(MF_EINVAL, "seg_begin[0] must be 0");
+  for (int i = 0; i < n_segments; ++i)
+    if (seg_begin[i + 1] < seg_begin[i]) return fail(MF_EINVAL, "seg_begin decreases at %d", i + 1);
+  if (seg_begin[n_segments] < 1) return fail(MF_EINVAL, "no parameters");
+  if (!hp) return fail(MF_EINVAL, "lamb hyperparameters are NULL");
+  if (step < 1) return fail(MF_EINVAL, "step %lld < 1 (LAMB counts from 1)", (long long)step);
+  if (!(hp->lr >= 0.0) || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) ||
+      !(hp->eps >= 0.0) || !(hp->weight_decay >= 0.0) || !(hp->max_grad_norm >= 0.0))
+    return fail(MF_EINVAL, "lamb hyperparameters out of range");
+  if (hp->trust_without_decay != 0 && hp->trust_without_decay != 1)
+    return fail(MF_EINVAL, "trust_without_decay %d is not 0 or 1", hp->trust_without_decay);
+  if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
+  LambSegments S;
+  S.n = n_segments;
+  for (int i = 0; i <= n_segments; ++i) S.begin[i] = seg_begin[i];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MF_HIP(hipSetDevice(ctx->device));
+  MF_HIP(launch_lamb(params, m, v, grad, S, hp->lr, hp->beta1, hp->beta2, hp->eps, hp->weight_decay,
+                     hp->max_grad_norm, hp->trust_without_decay == 1 || hp->weight_decay != 0.0, step, s));
+  return ok();
+}
+
+static mf_status check_schedule(const mf_lr_schedule* sc) {
+  if (!sc) return fail(MF_EINVAL, "schedule is NULL");
+  if (sc->total_steps < 1) return fail(MF_EINVAL, "total_steps %lld < 1", (long long)sc->total_steps);
+  if (!(sc->warmup_frac >= 0.0 && sc->warmup_frac <= 1.0)) return fail(MF_EINVAL, "warmup_frac not in [0, 1]");
+  if (!(sc->max_lr >= 0.0) || !(sc->end_lr >= 0.0)) return fail(MF_EINVAL, "learning rates must be >= 0");
+  if (!(sc->power > 0.0)) return fail(MF_EINVAL, "power must be > 0");
+  return MF_OK;
+}
+
+mf_status mf_lr_at(const mf_lr_schedule* sc, int64_t step, double* lr) {
+  MF_TRY(check_schedule(sc));
+  if (!lr) return fail(MF_EINVAL, "lr is NULL");
+  if (step < 1) return fail(MF_EINVAL, "step %lld < 1", (long long)step);
+  const int64_t T = sc->total_steps;
+  const int64_t W = (int64_t)ceil(sc->warmup_frac * (double)T);
+  if (step <= W) {
+    *lr = sc->max_lr * (double)step / (double)W;
+  } else if (step >= T) {
+    *lr = sc->end_lr;
+  } else {
+    const double frac = 1.0 - (double)(step - W) / (double)(T - W);
+    *lr = sc->end_lr + (sc->max_lr - sc->end_lr) * pow(frac, sc->power);
+  }
+  return ok();
+}
+
+mf_status mf_lr_schedule_scaled(const mf_lr_schedule* base, double batch_factor, mf_lr_schedule* out) {
+  MF_TRY(check_schedule(base));
+  if (!out) return fail(MF_EINVAL, "out is NULL");
+  if (!(batch_factor > 0.0)) return fail(MF_EINVAL, "batch_factor must be > 0");
+  *out = *base;
+  out->max_lr = base->max_lr * sqrt(batch_factor);
+  out->warmup_frac = std::min(1.0, base->warmup_frac * batch_factor);
+  return ok();
+}
+
 }  // extern "C"

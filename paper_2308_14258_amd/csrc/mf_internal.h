@@ -151,6 +151,20 @@ hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, co
                              hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
                        double b2, double eps, int64_t step, hipStream_t s);
+// optim_kernels.hip: LAMB, one workgroup per parameter tensor. The tensor
+// table travels by value (at most MF_MAX_SEGMENTS tensors); begin[n] is the
+// parameter count.
+struct LambSegments {
+  int64_t begin[MF_MAX_SEGMENTS + 1];
+  int n;
+};
+struct LambParams {
+  float lr, b1, omb1, b2, omb2, eps, wd, bc1, bc2, max_grad_norm;
+  int trust;
+};
+hipError_t launch_lamb(float* p, float* m, float* v, const float* g, const LambSegments& S, double lr, double b1,
+                       double b2, double eps, double wd, double max_grad_norm, bool trust, int64_t step,
+                       hipStream_t s);
 hipError_t launch_forward_derivs(const NetPtrs& net, int width, int act, const float* C, const float* X,
                                  int x_per_bc, int64_t n_bc, int64_t n_pts, float* Z0, float* Z1,
                                  float* U, float* dU, float* lapU, hipStream_t s);
@@ -160,6 +174,7 @@ hipError_t launch_value_forward_act(const NetPtrs& net, int width, int act, cons
 // embed_kernels.hip: the convolutional-embedding GELU network (activation
 // MF_GELU). Its prepared network uses NetLayout with n_in = 128 C: w1gT holds
 // the transposed embedding block of W1 ([128 C][d]).
+constexpr int kConvK = 5;   // embedding convolutions' kernel width
 int64_t embed_param_offset(int C);
 hipError_t launch_prepare_w1eT(const float* params, int width, int C, float* w1eT, hipStream_t s);
 hipError_t launch_embed_project(const float* params, int width, int C, const NetPtrs& net, const float* G,

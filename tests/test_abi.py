@@ -350,3 +350,70 @@ def test_solve_mixed_argument_errors(lib):
     # three prepared networks, one field copy and four correction fields
     nf = 65 * 65
     assert n.value >= 5 * nf * 4
+
+
+def test_param_segments_match_the_oracle_layouts(lib):
+    """mf_param_segments (host) gives the tensors of the oracle's layouts."""
+    from oracle import optim
+    n = ctypes.c_int32()
+    for desc, want in ((SdnetDesc(128, 4, 128, 0), optim.tanh_segments(128)),
+                       (SdnetDesc(256, 4, 128, 0), optim.tanh_segments(256)),
+                       (SdnetDesc(128, 4, 128, 1, 4), optim.conv_segments(128, 4))):
+        begin = (ctypes.c_int64 * 65)()
+        assert lib.mf_param_segments(ctypes.byref(desc), begin, 64, ctypes.byref(n)) == MF_OK
+        assert list(begin[:n.value + 1]) == want
+        assert begin[n.value] == lib.mf_param_count(ctypes.byref(desc))
+    begin = (ctypes.c_int64 * 5)()
+    assert lib.mf_param_segments(ctypes.byref(SdnetDesc(128, 4, 128, 0)), begin, 4, ctypes.byref(n)) == MF_ESHAPE
+    assert n.value == 10
+
+
+def test_lr_schedule_matches_the_oracle(lib):
+    """mf_lr_at / mf_lr_schedule_scaled (host) against the oracle's
+    schedule, over warm-up, decay and the end, for several settings."""
+    from oracle import optim
+    lr = ctypes.c_double()
+    for T, frac, lr0, power, end in ((50000, 0.001, 1e-3, 1.0, 0.0), (400, 0.05, 2e-3, 2.0, 1e-5),
+                                     (10, 0.0, 1e-3, 1.0, 0.0), (7, 1.0, 1e-3, 0.5, 0.0)):
+        sc = _lib.LrSchedule(lr0, frac, power, end, T)
+        for step in sorted({1, 2, 3, 5, 9, 10, 11, 49, 50, 51, 100, 200, 399, 400, 401, T - 1, T, T + 1, 25000}):
+            if step < 1:
+                continue
+            assert lib.mf_lr_at(ctypes.byref(sc), step, ctypes.byref(lr)) == MF_OK
+            assert lr.value == pytest.approx(optim.lr_at(step, T, lr0, frac, power, end), rel=1e-12, abs=1e-300)
+    out = _lib.LrSchedule()
+    sc = _lib.LrSchedule(1e-3, 0.001, 1.0, 0.0, 50000)
+    for k in (1.0, 2.0, 8.0, 2000.0):
+        assert lib.mf_lr_schedule_scaled(ctypes.byref(sc), k, ctypes.byref(out)) == MF_OK
+        want_lr, want_frac = optim.scaled_schedule(1e-3, 0.001, k)
+        assert out.max_lr == pytest.approx(want_lr, rel=1e-15) and out.warmup_frac == pytest.approx(want_frac)
+        assert out.total_steps == 50000 and out.power == 1.0
+    assert lib.mf_lr_at(ctypes.byref(sc), 0, ctypes.byref(lr)) == MF_EINVAL
+    bad = _lib.LrSchedule(1e-3, 1.5, 1.0, 0.0, 100)
+    assert lib.mf_lr_at(ctypes.byref(bad), 1, ctypes.byref(lr)) == MF_EINVAL
+    bad = _lib.LrSchedule(1e-3, 0.1, 0.0, 0.0, 100)
+    assert lib.mf_lr_at(ctypes.byref(bad), 1, ctypes.byref(lr)) == MF_EINVAL
+    assert lib.mf_lr_schedule_scaled(ctypes.byref(sc), 0.0, ctypes.byref(out)) == MF_EINVAL
+
+
+def test_lamb_step_argument_errors(lib):
+    FAKE = 1 << 40
+    hp = _lib.Lamb(1e-3, 0.9, 0.999, 1e-6, 0.0, 1.0, 1)
+
+    def call(seg=(0, 10, 20), n=None, step=1, h=hp, ptr=FAKE):
+        arr = (ctypes.c_int64 * len(seg))(*seg)
+        return lib.sdnet_lamb_step(None, ctypes.c_void_p(ptr), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                                   ctypes.c_void_p(FAKE), arr, len(seg) - 1 if n is None else n, step,
+                                   ctypes.byref(h), None)
+    assert call() == MF_EINVAL and b"ctx" in lib.mf_last_error()              # all else valid
+    assert call(seg=(1, 10)) == MF_EINVAL and b"seg_begin[0]" in lib.mf_last_error()
+    assert call(seg=(0, 10, 5)) == MF_EINVAL and b"decreases" in lib.mf_last_error()
+    assert call(seg=(0, 0)) == MF_EINVAL and b"no parameters" in lib.mf_last_error()
+    assert call(seg=(0, 0, 7)) == MF_EINVAL and b"ctx" in lib.mf_last_error()   # empty tensors are allowed
+    assert call(n=0) == MF_EINVAL and b"n_segments" in lib.mf_last_error()
+    assert call(seg=tuple(range(66)), n=65) == MF_EINVAL and b"n_segments" in lib.mf_last_error()
+    assert call(step=0) == MF_EINVAL
+    assert call(ptr=0) == MF_EINVAL and b"params" in lib.mf_last_error()
+    assert call(h=_lib.Lamb(1e-3, 1.0, 0.999, 1e-6, 0.0, 0.0, 1)) == MF_EINVAL
+    assert call(h=_lib.Lamb(1e-3, 0.9, 0.999, 1e-6, -1.0, 0.0, 1)) == MF_EINVAL
+    assert call(h=_lib.Lamb(1e-3, 0.9, 0.999, 1e-6, 0.0, 0.0, 2)) == MF_EINVAL
