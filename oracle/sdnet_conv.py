@@ -124,15 +124,20 @@ def forward_concat(params, G: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     return mlp_from_first(I @ W1.T + b1, layers)
 
 
-def derivatives(params, G: torch.Tensor, X: torch.Tensor):
-    """(u, u_x, u_y, Laplacian u) at per-condition points X [B, n, 2]."""
+def derivatives(params, G: torch.Tensor, X: torch.Tensor, create_graph: bool = False):
+    """(u, u_x, u_y, Laplacian u) at per-condition points X [B, n, 2]; with
+    create_graph the results stay differentiable in the parameters (for the
+    PDE loss's gradient)."""
     X = X.detach().clone().requires_grad_(True)
     u = forward(params, G, X)
     (gx,) = torch.autograd.grad(u.sum(), X, create_graph=True)
     ux, uy = gx[..., 0], gx[..., 1]
     (gxx,) = torch.autograd.grad(ux.sum(), X, create_graph=True)
-    (gyy,) = torch.autograd.grad(uy.sum(), X)
-    return u.detach(), ux.detach(), uy.detach(), (gxx[..., 0] + gyy[..., 1]).detach()
+    (gyy,) = torch.autograd.grad(uy.sum(), X, create_graph=create_graph)
+    lap = gxx[..., 0] + gyy[..., 1]
+    if not create_graph:
+        return u.detach(), ux.detach(), uy.detach(), lap.detach()
+    return u, ux, uy, lap
 
 
 def solver(theta: torch.Tensor, width: int, channels: int):

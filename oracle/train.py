@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import torch
 
-from . import sdnet
+from . import sdnet, sdnet_conv
 
 
 def losses(theta: torch.Tensor, width: int, G: torch.Tensor, Xd: torch.Tensor,
@@ -47,6 +47,27 @@ def gradient(theta: torch.Tensor, width: int, G, Xd, Xc, Yd=None):
     """Returns (L_data, L_pde, grad_data, grad_pde) in float64."""
     th = theta.detach().clone().requires_grad_(True)
     l_data, l_pde = losses(th, width, G, Xd, Xc, Yd)
+    (g_data,) = torch.autograd.grad(l_data, th)
+    (g_pde,) = torch.autograd.grad(l_pde, th)
+    return l_data.item(), l_pde.item(), g_data, g_pde
+
+
+def losses_conv(theta: torch.Tensor, width: int, channels: int, G: torch.Tensor, Xd: torch.Tensor,
+                Xc: torch.Tensor, Yd: torch.Tensor | None = None):
+    """(L_data, L_pde) of ``losses`` for the paper's network (``sdnet_conv``:
+    convolutional boundary embedding and GELU layers, Sec. 3.1)."""
+    params = sdnet_conv.unpack(theta, width, channels)
+    u_d = sdnet_conv.forward(params, G, Xd)
+    l_data = torch.mean((u_d - (G if Yd is None else Yd)) ** 2)
+    _, _, _, lap = sdnet_conv.derivatives(params, G, Xc, create_graph=True)
+    l_pde = torch.mean(lap ** 2)
+    return l_data, l_pde
+
+
+def gradient_conv(theta: torch.Tensor, width: int, channels: int, G, Xd, Xc, Yd=None):
+    """Returns (L_data, L_pde, grad_data, grad_pde) of ``losses_conv``."""
+    th = theta.detach().clone().requires_grad_(True)
+    l_data, l_pde = losses_conv(th, width, channels, G, Xd, Xc, Yd)
     (g_data,) = torch.autograd.grad(l_data, th)
     (g_pde,) = torch.autograd.grad(l_pde, th)
     return l_data.item(), l_pde.item(), g_data, g_pde

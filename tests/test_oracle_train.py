@@ -191,3 +191,47 @@ def test_boundary_match_is_the_data_term_with_targets_g():
     a = train.losses(th, D, G, Xb, Xc)
     b = train.losses(th, D, G, Xb.expand(3, 128, 2), Xc, G)
     assert a[0].item() == b[0].item() and a[1].item() == b[1].item()
+
+
+def test_conv_network_losses_hand_computed_constant_network():
+    """The paper's network (convolutional embedding, GELU) with only b5
+    non-zero: GELU(0) = 0 in every layer, so u = b5 everywhere and the
+    Laplacian vanishes; with boundary data 1 and 3 and b5 = 0.5 the data
+    loss is, by hand, ((0.5 - 1)^2 + (0.5 - 3)^2) / 2 = 3.25."""
+    from oracle import sdnet_conv
+    d, C = 16, 2
+    th = torch.zeros(sdnet_conv.param_count(d, C), dtype=torch.float64)
+    th[-1] = 0.5
+    G = torch.cat([torch.full((1, 128), 1.0), torch.full((1, 128), 3.0)]).double()
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes())
+    Xc = torch.from_numpy(mi.collocation_points(2, 5, seed=4).astype(np.float64))
+    l_data, l_pde = train.losses_conv(th, d, C, G, Xb, Xc)
+    assert l_data.item() == pytest.approx(3.25, rel=1e-15)
+    assert l_pde.item() == 0.0
+
+
+def test_conv_network_gradient_matches_finite_differences():
+    """gradient_conv (autograd through the embedding, the GELU layers and
+    the Laplacian) against float64 central differences of losses_conv in
+    random directions, width 16, 2 channels, 3 conditions x 6 points."""
+    from oracle import sdnet_conv
+    d, C = 16, 2
+    rng = np.random.default_rng(5)
+    th = torch.from_numpy(rng.standard_normal(sdnet_conv.param_count(d, C)) * 0.3)
+    G = torch.from_numpy(mi.gp_perimeter_batch(3, 0.5, seed=8).astype(np.float64))
+    Xb = torch.from_numpy(mi.unit_perimeter_nodes()[::16].copy())
+    Gb = G[:, ::16].contiguous()
+    Xc = torch.from_numpy(mi.collocation_points(3, 6, seed=9).astype(np.float64))
+    ld, lp, gd, gp = train.gradient_conv(th, d, C, G, Xb, Xc, Yd=Gb)
+    grad = gd + gp
+
+    def L(t):
+        a, b = train.losses_conv(t, d, C, G, Xb, Xc, Yd=Gb)
+        return (a + b).item()
+    h = 1e-5
+    for _ in range(12):
+        v = torch.from_numpy(rng.standard_normal(th.numel()))
+        v /= torch.linalg.vector_norm(v)
+        fd = (L(th + h * v) - L(th - h * v)) / (2 * h)
+        an = torch.dot(grad, v).item()
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * grad.norm().item())
