@@ -85,6 +85,119 @@ __global__ __launch_bounds__(256) void embed_project_kernel(const float* __restr
   }
 }
 
+// Reverse of the embedding for the training gradient. One workgroup per
+// condition b recomputes p1 = conv1(g) + bc1, h1 = GELU(p1) and
+// p2 = conv2(h1) + bc2 in LDS. MODE 0 writes e = GELU(p2) ([B][128 C], the
+// first layer's input columns). MODE 1 takes the first layer's
+// per-condition sums of the pre-activation adjoint from the two passes,
+// c = c0[b] + c1[b], forms e_bar = W1e^T c, then p2_bar = e_bar GELU'(p2),
+// the second convolution's kernel and bias gradients, h1_bar (the circular
+// convolution transposed), p1_bar = h1_bar GELU'(p1) and the first
+// convolution's gradients, into part[b][0 .. 10 C + 5 C^2) in the order of
+// the parameters. Every sum runs in a fixed order.
+template <int MODE>
+__global__ __launch_bounds__(256) void embed_grad_kernel(const float* __restrict__ conv, int C,
+                                                         const float* __restrict__ w1, int d,
+                                                         const float* __restrict__ G, const float* __restrict__ c0,
+                                                         const float* __restrict__ c1, float* __restrict__ e_out,
+                                                         float* __restrict__ part) {
+  extern __shared__ float sm[];   // g [128] | p1, h1, p2, v [C][128] each | c [d]
+  const int E = C * kNB;
+  float* g = sm;
+  float* p1 = g + kNB;
+  float* h1 = p1 + E;
+  float* p2 = h1 + E;
+  float* v = p2 + E;
+  float* cs = v + E;
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < kNB) g[tid] = G[b * kNB + tid];
+  __syncthreads();
+  const float* w1c = conv;
+  const float* b1c = w1c + C * kConvK;
+  const float* w2c = b1c + C;
+  const float* b2c = w2c + C * C * kConvK;
+  for (int idx = tid; idx < E; idx += 256) {
+    const int o = idx >> 7, k = idx & 127;
+    float acc = b1c[o];
+#pragma unroll
+    for (int t = 0; t < kConvK; ++t) acc = fmaf(w1c[o * kConvK + t], g[(k + t - 2) & 127], acc);
+    p1[idx] = acc;
+    h1[idx] = gelu_f32(acc);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < E; idx += 256) {
+    const int o = idx >> 7, k = idx & 127;
+    float acc = b2c[o];
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int t = 0; t < kConvK; ++t) acc = fmaf(w2c[(o * C + i) * kConvK + t], h1[i * kNB + ((k + t - 2) & 127)], acc);
+    p2[idx] = acc;
+  }
+  __syncthreads();
+  if constexpr (MODE == 0) {
+    for (int idx = tid; idx < E; idx += 256) e_out[b * E + idx] = gelu_f32(p2[idx]);
+    return;
+  }
+  for (int j = tid; j < d; j += 256) cs[j] = c0[b * d + j] + c1[b * d + j];
+  __syncthreads();
+  for (int idx = tid; idx < E; idx += 256) {   // p2_bar = (W1e^T c) GELU'(p2)
+    float eb = 0.0f;
+    for (int j = 0; j < d; ++j) eb = fmaf(w1[(int64_t)j * (E + 2) + idx], cs[j], eb);
+    float z, d1, d2;
+    gelu_rules(p2[idx], z, d1, d2);
+    v[idx] = eb * d1;
+  }
+  __syncthreads();
+  float* P = part + b * (int64_t)(2 * C + C * kConvK + C * C * kConvK);
+  float* P2 = P + C * kConvK + C;   // the second convolution's kernel, then its bias
+  for (int q = tid; q < C * C * kConvK; q += 256) {
+    const int o = q / (C * kConvK), i = (q / kConvK) % C, t = q % kConvK;
+    float acc = 0.0f;
+    for (int k = 0; k < kNB; ++k) acc = fmaf(v[o * kNB + k], h1[i * kNB + ((k + t - 2) & 127)], acc);
+    P2[q] = acc;
+  }
+  for (int o = tid; o < C; o += 256) {
+    float acc = 0.0f;
+    for (int k = 0; k < kNB; ++k) acc += v[o * kNB + k];
+    P2[C * C * kConvK + o] = acc;
+  }
+  for (int idx = tid; idx < E; idx += 256) {   // p1_bar = h1_bar GELU'(p1), into p2's space
+    const int i = idx >> 7, m = idx & 127;
+    float hb = 0.0f;
+    for (int o = 0; o < C; ++o)
+#pragma unroll
+      for (int t = 0; t < kConvK; ++t) hb = fmaf(w2c[(o * C + i) * kConvK + t], v[o * kNB + ((m - t + 2) & 127)], hb);
+    float z, d1, d2;
+    gelu_rules(p1[idx], z, d1, d2);
+    p2[idx] = hb * d1;
+  }
+  __syncthreads();
+  for (int q = tid; q < C * kConvK; q += 256) {
+    const int o = q / kConvK, t = q % kConvK;
+    float acc = 0.0f;
+    for (int k = 0; k < kNB; ++k) acc = fmaf(p2[o * kNB + k], g[(k + t - 2) & 127], acc);
+    P[q] = acc;
+  }
+  for (int o = tid; o < C; o += 256) {
+    float acc = 0.0f;
+    for (int k = 0; k < kNB; ++k) acc += p2[o * kNB + k];
+    P[C * kConvK + o] = acc;
+  }
+}
+
+hipError_t launch_embed_grad(const float* params, int width, int C, int64_t off_w1, const float* G, int64_t B,
+                             const float* c0, const float* c1, float* e_out, float* part, hipStream_t s) {
+  const size_t lds = (size_t)(kNB + 4 * C * kNB + width) * 4;
+  if (e_out)
+    hipLaunchKernelGGL((embed_grad_kernel<0>), dim3((unsigned)B), dim3(256), lds, s, params, C, params + off_w1,
+                       width, G, c0, c1, e_out, part);
+  else
+    hipLaunchKernelGGL((embed_grad_kernel<1>), dim3((unsigned)B), dim3(256), lds, s, params, C, params + off_w1,
+                       width, G, c0, c1, e_out, part);
+  return hipGetLastError();
+}
+
 // Output layer on value rows Z [n_rows][D]: u = w5 . z + b5, one wave per
 // row. MODE 0: U[r0 + r] = u. MODE 1: the field at target t of placement
 // q0 + r / T of the colour takes u. MODE 2: u_out there += u / cover count.

@@ -90,25 +90,34 @@ SweepLayout sweep_layout(int width, int prec, const mf_domain_desc* dom, int n_d
   return S;
 }
 
-TrainLayout train_layout(int width, int64_t B, int64_t nd, int64_t nc) {
+TrainLayout train_layout(const mf_sdnet_desc* desc, int64_t B, int64_t nd, int64_t nc) {
   TrainLayout T;
-  T.net = net_layout(width, MF_FP32, 0);
+  const int width = desc->width;
+  const bool gelu = desc->activation == MF_GELU;
+  const int C = gelu ? desc->embed_channels : 0;
+  T.net = net_layout(width, MF_FP32, 0, gelu ? 128 * C : 128);
   const size_t d = (size_t)width;
   const size_t SR = (size_t)std::max<int64_t>(4 * B * nc, B * nd);   // stream rows
   const size_t chunks = kBwdGroups;   // weight-gradient partials: one per reverse-kernel workgroup
-  const size_t P = (size_t)(d * 130 + d + 3 * (d * d + d) + d + 1);
+  const size_t P = (size_t)mf_param_count(desc);
   size_t o = T.net.end;
   T.whT = o; o = align256(o + 3 * d * d * 4);
   T.C = o;   o = align256(o + (size_t)B * d * 4);
   for (int l = 0; l < 4; ++l) { T.Z[l] = o; o = align256(o + SR * d * 4); }
-  // Sv[0] (layer 1) is never stored: its a_x, a_y, a_L are W1x and 0 for every row
-  for (int l = 1; l < 4; ++l) { T.Sv[l] = o; o = align256(o + SR * d * 4); }
+  // tanh: Sv[0] (layer 1) is never stored, its a_x, a_y, a_L being W1x and 0
+  // for every row; GELU keeps layer 1's pre-activations there
+  for (int l = gelu ? 0 : 1; l < 4; ++l) { T.Sv[l] = o; o = align256(o + SR * d * 4); }
   for (int l = 0; l < 2; ++l) { T.Ab[l] = o; o = align256(o + SR * d * 4); }
-  T.wpart = o; o = align256(o + chunks * d * d * 4);
+  const size_t l1parts = (size_t)kL1MaxChunks * d * ((gelu ? 128 * C : 128) + 3);
+  T.wpart = o; o = align256(o + std::max(chunks * d * d, l1parts) * 4);
   T.bpart = o; o = align256(o + chunks * d * 4);
   for (int l = 0; l < 2; ++l) { T.opart[l] = o; o = align256(o + (size_t)kOutWaves * (d + 2) * 4); }
   for (int l = 0; l < 2; ++l) { T.l1[l] = o; o = align256(o + 3 * (size_t)B * d * 4); }
   T.grad = o; o = align256(o + P * 4);
+  if (gelu) {
+    T.emb = o;   o = align256(o + (size_t)B * 128 * C * 4);
+    T.cpart = o; o = align256(o + (size_t)B * embed_param_offset(C) * 4);
+  }
   T.total = o;
   return T;
 }
@@ -119,7 +128,7 @@ TrainBuffers train_buffers(const TrainLayout& L, void* ws) {
   t.C = reinterpret_cast<float*>(b + L.C);
   for (int l = 0; l < 4; ++l) {
     t.Z[l] = reinterpret_cast<float*>(b + L.Z[l]);
-    t.Sv[l] = l == 0 ? nullptr : reinterpret_cast<float*>(b + L.Sv[l]);
+    t.Sv[l] = L.Sv[l] == 0 ? nullptr : reinterpret_cast<float*>(b + L.Sv[l]);
   }
   for (int l = 0; l < 2; ++l) {
     t.Ab[l] = reinterpret_cast<float*>(b + L.Ab[l]);
@@ -129,6 +138,8 @@ TrainBuffers train_buffers(const TrainLayout& L, void* ws) {
   t.wpart = reinterpret_cast<float*>(b + L.wpart);
   t.bpart = reinterpret_cast<float*>(b + L.bpart);
   t.grad = reinterpret_cast<float*>(b + L.grad);
+  t.emb = L.emb ? reinterpret_cast<float*>(b + L.emb) : nullptr;
+  t.cpart = L.cpart ? reinterpret_cast<float*>(b + L.cpart) : nullptr;
   return t;
 }
 
@@ -1434,7 +1445,7 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
   MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, A.net, ws, s));
   const NetPtrs net = net_ptrs(A.net, ws);
   float* whT = reinterpret_cast<float*>(b + A.whT);
-  MF_HIP(launch_prepare_wT(params, desc->width, whT, s));
+  MF_HIP(launch_prepare_wT(params, (int64_t)desc->width * (desc->n_boundary + 2) + desc->width, desc->width, whT, s));
   AdjointBuffers ab;
   ab.X_cross = reinterpret_cast<float*>(b + A.X_cross);
   ab.X_interior = reinterpret_cast<float*>(b + A.X_interior);
@@ -1629,9 +1640,8 @@ mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nd, 
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(check_desc(desc));
-  MF_TRY(need_tanh(desc, "sdnet training"));
   MF_TRY(train_sizes(B, nd, nc));
-  *bytes = train_layout(desc->width, B, nd, nc).total;
+  *bytes = train_layout(desc, B, nd, nc).total;
   return ok();
 }
 
@@ -1640,7 +1650,6 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
                            int64_t nd, int32_t xd_per_bc, const float* Yd, const float* Xc, int64_t nc,
                            float* loss_dev, float* grad_out, void* ws, size_t ws_bytes, void* stream) {
   MF_TRY(check_desc(desc));
-  MF_TRY(need_tanh(desc, "sdnet_train_step"));
   MF_TRY(train_sizes(B, nd, nc));
   MF_TRY(check_ptr(params, "params"));
   MF_TRY(check_ptr(G, "G"));
@@ -1664,18 +1673,27 @@ mf_status sdnet_train_step(mf_ctx* ctx, const mf_sdnet_desc* desc, float* params
         !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) || !(hp->eps > 0.0))
       return fail(MF_EINVAL, "adam hyperparameters out of range");
   }
-  const TrainLayout L = train_layout(desc->width, B, nd, nc);
+  const TrainLayout L = train_layout(desc, B, nd, nc);
   MF_TRY(check_ws(ws, ws_bytes, L.total));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
-  MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, L.net, ws, s));
+  MF_HIP(prepare_net(desc, params, MF_FP32, L.net, ws, s));
   const NetPtrs net = net_ptrs(L.net, ws);
+  // where the tensors sit: [convolutions] | W1 | b1 | W2 | b2 | W3 | b3 | W4 | b4 | w5 | b5
+  TrainNet tn;
+  tn.params = params;
+  tn.channels = is_gelu(desc) ? desc->embed_channels : 0;
+  tn.n_in = is_gelu(desc) ? 128 * desc->embed_channels : desc->n_boundary;
+  const int64_t d = desc->width;
+  tn.off_w1 = is_gelu(desc) ? embed_param_offset(desc->embed_channels) : 0;
+  tn.off_w2 = tn.off_w1 + d * (tn.n_in + 2) + d;
+  tn.off_w5 = tn.off_w2 + 3 * (d * d + d);
   float* whT = reinterpret_cast<float*>(static_cast<char*>(ws) + L.whT);
-  MF_HIP(launch_prepare_wT(params, desc->width, whT, s));
+  MF_HIP(launch_prepare_wT(params, tn.off_w2, desc->width, whT, s));
   const TrainBuffers tb = train_buffers(L, ws);
   float* grad = grad_out ? grad_out : tb.grad;
-  MF_HIP(launch_train_grad(net, desc->width, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss_dev, s));
+  MF_HIP(launch_train_grad(tn, net, desc->width, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss_dev, s));
   if (!grad_out)
     MF_HIP(launch_adam(params, m, v, grad, mf_param_count(desc), hp->lr, hp->beta1, hp->beta2, hp->eps,
                        step, s));

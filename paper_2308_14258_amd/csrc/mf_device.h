@@ -101,6 +101,17 @@ __device__ __forceinline__ void gelu_rules(float a, float& z, float& d1, float& 
   d2 = phi * (2.0f - a * a);
 }
 
+// The first three derivatives of GELU: Phi + a phi, phi (2 - a^2) and
+// phi a (a^2 - 4) (from phi' = -a phi), for the reverse Taylor rules.
+__device__ __forceinline__ void gelu_d123(float a, float& d1, float& d2, float& d3) {
+  const float Phi = 0.5f * (1.0f + erff(a * 0.70710678118654752f));
+  const float phi = 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.72134752044448170f * a * a);
+  const float a2 = a * a;
+  d1 = fmaf(a, phi, Phi);
+  d2 = phi * (2.0f - a2);
+  d3 = phi * a * (a2 - 4.0f);
+}
+
 // Cheaper tanh for activations that are rounded to bf16 next:
 // tanh x = 1 - 2 / (1 + exp(2x)); absolute error a few float32 ulps of 1.
 __device__ __forceinline__ float tanh_fast(float x) {

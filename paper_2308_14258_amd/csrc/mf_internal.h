@@ -123,6 +123,9 @@ hipError_t launch_forward_rows(const NetPtrs& net, int width, int prec, const fl
 // Upper bound of the fused reverse kernel's persistent grid = number of
 // weight-gradient partials in the training workspace.
 constexpr int kBwdGroups = 512;
+// Chunks of conditions of the first-layer gradient (at most); its partials
+// (kL1MaxChunks x d x (input columns + 3)) share the weight-gradient buffer.
+constexpr int kL1MaxChunks = 256;
 constexpr int kOutWaves = 2048;    // waves of the output-layer kernel: one partial each
 
 struct TrainBuffers {
@@ -135,19 +138,30 @@ struct TrainBuffers {
   float* opart[2];   // [kOutWaves][d+2] output-layer partials (data, collocation)
   float* l1[2];      // [3][B][d] first-layer sums (data, collocation)
   float* grad;       // [P] gradient (used when the caller gives none)
+  float* emb;        // GELU network: [B][128 C] embeddings
+  float* cpart;      // GELU network: [B][10 C + 5 C^2] convolution-gradient partials
+};
+// Where the parameters of the network being trained sit in the flat vector.
+struct TrainNet {
+  const float* params;   // flat parameters (the embedding's convolutions are read from here)
+  int channels;          // 0: tanh network; C: the convolutional-embedding GELU network
+  int n_in;              // first-layer input columns: 128, or 128 C
+  int64_t off_w1;        // W1 (d x (n_in + 2)); also the count of the convolutions' parameters
+  int64_t off_w2;        // the first hidden weight matrix
+  int64_t off_w5;        // the output weights
 };
 struct TrainLayout {
   NetLayout net;
   size_t whT = 0, C = 0, Z[4] = {0, 0, 0, 0}, Sv[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
-  size_t wpart = 0, bpart = 0, opart[2] = {0, 0}, l1[2] = {0, 0}, grad = 0, total = 0;
+  size_t wpart = 0, bpart = 0, opart[2] = {0, 0}, l1[2] = {0, 0}, grad = 0, emb = 0, cpart = 0, total = 0;
 };
-TrainLayout train_layout(int width, int64_t B, int64_t nd, int64_t nc);
+TrainLayout train_layout(const mf_sdnet_desc* desc, int64_t B, int64_t nd, int64_t nc);
 TrainBuffers train_buffers(const TrainLayout& L, void* ws);
 
-hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStream_t s);
-hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
-                             const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
-                             const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
+hipError_t launch_prepare_wT(const float* params, int64_t off_w2, int width, float* whT, hipStream_t s);
+hipError_t launch_train_grad(const TrainNet& tn, const NetPtrs& net, int width, const float* whT,
+                             const TrainBuffers& tb, const float* G, int64_t B, const float* Xd, int64_t nd,
+                             int xd_per_bc, const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
                              hipStream_t s);
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,
                        double b2, double eps, int64_t step, hipStream_t s);
@@ -177,6 +191,8 @@ hipError_t launch_value_forward_act(const NetPtrs& net, int width, int act, cons
 constexpr int kConvK = 5;   // embedding convolutions' kernel width
 int64_t embed_param_offset(int C);
 hipError_t launch_prepare_w1eT(const float* params, int width, int C, float* w1eT, hipStream_t s);
+hipError_t launch_embed_grad(const float* params, int width, int C, int64_t off_w1, const float* G, int64_t B,
+                             const float* c0, const float* c1, float* e_out, float* part, hipStream_t s);
 hipError_t launch_embed_project(const float* params, int width, int C, const NetPtrs& net, const float* G,
                                 int64_t n_bc, const float* u, int64_t pitch, int ux, int colour, int q0,
                                 float* Cout, hipStream_t s);

@@ -37,8 +37,7 @@ namespace mf {
 // ---------------------------------------------------------------------------
 // W^T of each hidden layer in MFMA operand order (for h-adjoint = ab W).
 // ---------------------------------------------------------------------------
-__global__ void prepare_wT_kernel(const float* __restrict__ params, int d, float* __restrict__ whT) {
-  const int64_t off_w2 = (int64_t)d * 130 + d;
+__global__ void prepare_wT_kernel(const float* __restrict__ params, int64_t off_w2, int d, float* __restrict__ whT) {
   const int64_t lstride = (int64_t)d * d + d;
   const int64_t dd = (int64_t)d * d;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 3 * dd;
@@ -64,7 +63,7 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
                                                          const float* __restrict__ X, int x_per_bc,
                                                          int64_t rows_per_bc, int64_t n_rows,
                                                          const float* __restrict__ w1x,
-                                                         float* __restrict__ Z) {
+                                                         float* __restrict__ Z, float* __restrict__ A1) {
   const int64_t n = n_rows * D;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -79,9 +78,11 @@ __global__ __launch_bounds__(256) void fwd_layer1_kernel(const float* __restrict
       gelu_rules(a, z, d1, d2);
       if constexpr (S == 1) {
         Z[r * D + j] = z;
+        if (A1) A1[r * D + j] = a;
       } else {
         const int64_t o = 4 * r * D + j;
         Z[o] = z;
+        if (A1) A1[o] = a;   // the value row of the saved streams (a_x, a_y, a_L are W1x and 0)
         Z[o + D] = d1 * wx;
         Z[o + 2 * D] = d1 * wy;
         Z[o + 3 * D] = d2 * (wx * wx + wy * wy);
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
           }
           Out[o + 3 * D] = fmaf(d2, ax * ax + ay * ay, d1 * aL);
           if (Sv_out) {
+            Sv_out[o] = a;   // GELU's rules need the pre-activation, not z
             Sv_out[o + D] = ax;
             Sv_out[o + 2 * D] = ay;
             Sv_out[o + 3 * D] = aL;
@@ -207,7 +209,9 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
           if (row >= n_srows) continue;
           const int64_t o = row * D + j;
           if constexpr (MODE == 0) {
-            Out[o] = ACT == ACT_GELU ? gelu_f32(acc[rb][4 * m + e] + bj) : tanh_f32(acc[rb][4 * m + e] + bj);
+            const float a = acc[rb][4 * m + e] + bj;
+            Out[o] = ACT == ACT_GELU ? gelu_f32(a) : tanh_f32(a);
+            if (ACT == ACT_GELU && Sv_out) Sv_out[o] = a;
           } else {
             const float z = Sv_in[o];
             Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
 // when Sv_in is null (the previous layer is the first one, whose stream
 // derivatives do not depend on the row), a_x = W1x[j][0], a_y = W1x[j][1],
 // a_L = 0 (L1: the previous layer is the first one).
-template <int D, int S, int LDH, bool L1>
+template <int D, int S, int LDH, bool L1, int ACT = ACT_TANH>
 __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t row0, int j, int h,
                                              const float* HH, const float* __restrict__ Sv_in,
                                              const float* __restrict__ w1x, float* __restrict__ Out,
@@ -260,11 +264,22 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
       if constexpr (S == 4) {
         if (sr >= n_srows) continue;
         const int64_t o = sr * D + j;
-        const float z = HH[lr * LDH + j];
         const float ax = L1 ? ax1 : Sv_in[o + D], ay = L1 ? ay1 : Sv_in[o + 2 * D];
         const float aL = L1 ? 0.0f : Sv_in[o + 3 * D];
         const float zb = acc[rb][4 * m], zbx = acc[rb][4 * m + 1];
         const float zby = acc[rb][4 * m + 2], zbL = acc[rb][4 * m + 3];
+        if constexpr (ACT == ACT_GELU) {
+          // f1, f2, f3: GELU's first three derivatives at the saved pre-activation
+          float f1, f2, f3;
+          gelu_d123(Sv_in[o], f1, f2, f3);
+          const float q = ax * ax + ay * ay;
+          Out[o] = f1 * zb + f2 * (ax * zbx + ay * zby) + zbL * (f2 * aL + f3 * q);
+          Out[o + D] = f1 * zbx + 2.0f * f2 * ax * zbL;
+          Out[o + 2 * D] = f1 * zby + 2.0f * f2 * ay * zbL;
+          Out[o + 3 * D] = f1 * zbL;
+          continue;
+        }
+        const float z = HH[lr * LDH + j];
         const float s = 1.0f - z * z, q = ax * ax + ay * ay;
         Out[o] = s * zb - 2.0f * z * s * (ax * zbx + ay * zby) -
                  zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
@@ -276,8 +291,14 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
         for (int e = 0; e < 4; ++e) {
           const int64_t row = sr + e;
           if (row >= n_srows) continue;
-          const float z = HH[(lr + e) * LDH + j];
-          Out[row * D + j] = (1.0f - z * z) * acc[rb][4 * m + e];
+          if constexpr (ACT == ACT_GELU) {
+            float f1, f2, f3;
+            gelu_d123(Sv_in[row * D + j], f1, f2, f3);
+            Out[row * D + j] = f1 * acc[rb][4 * m + e];
+          } else {
+            const float z = HH[(lr + e) * LDH + j];
+            Out[row * D + j] = (1.0f - z * z) * acc[rb][4 * m + e];
+          }
         }
       }
     }
@@ -285,7 +306,7 @@ __device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[2], int64_t r
 }
 
 // Register budget for two 8-wave workgroups per CU (four waves per SIMD).
-template <int D, int S, bool L1>
+template <int D, int S, bool L1, int ACT = ACT_TANH>
 __global__ __launch_bounds__(4 * D, 4) void taylor_bwd_split_kernel(const float* __restrict__ Ab,
                                                            const float* __restrict__ H,
                                                            const floatx4* __restrict__ wsw,
@@ -341,7 +362,7 @@ __global__ __launch_bounds__(4 * D, 4) void taylor_bwd_split_kernel(const float*
       fetch(Ab, rt, t + gridDim.x);
       floatx16 acc[RB];
       mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
-      bwd_epilogue<D, S, LDH, L1>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
+      bwd_epilogue<D, S, LDH, L1, ACT>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
       __syncthreads();   // the next tile overwrites the LDS
     }
   } else {
@@ -386,7 +407,7 @@ __global__ __launch_bounds__(4 * D, 4) void taylor_bwd_split_kernel(const float*
 // Width 256: one role per wave (both products in turn); the role-split
 // form above would need more than the 128 VGPRs a 1024-thread workgroup
 // allows.
-template <int D, int S, bool L1>
+template <int D, int S, bool L1, int ACT = ACT_TANH>
 __global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __restrict__ Ab,
                                                            const float* __restrict__ H,
                                                            const floatx4* __restrict__ wsw,
@@ -439,7 +460,7 @@ __global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __re
     // (i) input adjoint and reverse rules
     floatx16 acc[RB];
     mfma_layer_f32<D, RB, LDH>(HA, wsw + (size_t)wave * (D / 8) * 64 + lane, acc, lane);
-    bwd_epilogue<D, S, LDH, L1>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
+    bwd_epilogue<D, S, LDH, L1, ACT>(acc, row0, j, h, HH, Sv_in, w1x, Out, n_srows);
     // (ii) weight gradient over the tile's rows: lane feeds row 8 g + 4 h + e
     // at MFMA step e to both operands
 #pragma unroll 2
@@ -471,7 +492,7 @@ __global__ __launch_bounds__(2 * D) void taylor_bwd_seq_kernel(const float* __re
 // Writes ab_4 = reverse tanh rules of zb_4 = w5 ub, and per-wave partial
 // sums of the w5 / b5 gradient and of the squared residual.
 // ---------------------------------------------------------------------------
-template <int D, int S>
+template <int D, int S, int ACT = ACT_TANH>
 __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restrict__ Z4,
                                                           const float* __restrict__ Sv4,
                                                           const float* __restrict__ w5,
@@ -508,9 +529,19 @@ __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restric
       for (int t = 0; t < NJ; ++t) {
         const int j = lane + 64 * t;
         gw5[t] = fmaf(ubL, zL[t], gw5[t]);
-        const float z = Z4[o + j], ax = Sv4[o + D + j], ay = Sv4[o + 2 * D + j];
+        const float ax = Sv4[o + D + j], ay = Sv4[o + 2 * D + j];
         const float aL = Sv4[o + 3 * D + j];
         const float zbL = w5r[t] * ubL;
+        if constexpr (ACT == ACT_GELU) {   // only z_L carries an adjoint here
+          float f1, f2, f3;
+          gelu_d123(Sv4[o + j], f1, f2, f3);
+          Ab[o + j] = zbL * (f2 * aL + f3 * (ax * ax + ay * ay));
+          Ab[o + D + j] = 2.0f * f2 * ax * zbL;
+          Ab[o + 2 * D + j] = 2.0f * f2 * ay * zbL;
+          Ab[o + 3 * D + j] = f1 * zbL;
+          continue;
+        }
+        const float z = Z4[o + j];
         const float s = 1.0f - z * z, q = ax * ax + ay * ay;
         Ab[o + j] = -zbL * (2.0f * z * s * aL + 2.0f * s * (1.0f - 3.0f * z * z) * q);
         Ab[o + D + j] = s * (-4.0f * z * ax * zbL);
@@ -534,7 +565,13 @@ __global__ __launch_bounds__(256) void output_loss_kernel(const float* __restric
 #pragma unroll
       for (int t = 0; t < NJ; ++t) {
         gw5[t] = fmaf(ub, zv[t], gw5[t]);
-        Ab[o + lane + 64 * t] = (1.0f - zv[t] * zv[t]) * w5r[t] * ub;
+        if constexpr (ACT == ACT_GELU) {
+          float f1, f2, f3;
+          gelu_d123(Sv4[o + lane + 64 * t], f1, f2, f3);
+          Ab[o + lane + 64 * t] = f1 * w5r[t] * ub;
+        } else {
+          Ab[o + lane + 64 * t] = (1.0f - zv[t] * zv[t]) * w5r[t] * ub;
+        }
       }
     }
   }
@@ -636,17 +673,21 @@ __global__ __launch_bounds__(kL1Groups * D) void layer1_reduce_kernel(const floa
 // chunk ch (L consecutive ones, staged through LDS 64 at a time, ascending)
 // for rows j in [8 g, 8 g + 8) into part[ch][j][0..130] (128 W1g columns,
 // then x, y, bias); layer1_sum_kernel adds the chunk partials in chunk order.
-constexpr int kL1Rows = 8, kL1Chunk = 64, kL1MaxChunks = 256, kL1Cols = 131;
+constexpr int kL1Rows = 8, kL1Chunk = 64;   // kL1MaxChunks: mf_internal.h
 
+// The first layer's input columns are the boundary vector (ncols = 128) or,
+// for the convolutional network, the embedding (ncols = 128 C); blockIdx.z
+// takes 128 of them, and a partial row holds ncols + 3 values.
 template <int D>
 __global__ __launch_bounds__(256) void layer1_part_kernel(const float* __restrict__ l1a,
                                                           const float* __restrict__ l1b,
-                                                          const float* __restrict__ G, int64_t B, int64_t L,
-                                                          float* __restrict__ part) {
+                                                          const float* __restrict__ G, int ncols, int64_t B,
+                                                          int64_t L, float* __restrict__ part) {
   __shared__ float gs[kL1Chunk][128];
   __shared__ float ls[3][kL1Chunk][kL1Rows];   // c, cx, cy of the rows
   const int j0 = blockIdx.x * kL1Rows;
   const int64_t ch = blockIdx.y;
+  const int col0 = 128 * blockIdx.z, pw = ncols + 3;
   const int64_t b_begin = ch * L, b_end = std::min<int64_t>(B, b_begin + L);
   const int k = threadIdx.x & 127, js = threadIdx.x >> 7;   // rows j0 + js + 2 i, i < 4
   float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -655,7 +696,7 @@ __global__ __launch_bounds__(256) void layer1_part_kernel(const float* __restric
     const int nb = (int)std::min<int64_t>(kL1Chunk, b_end - b0);
     for (int idx = threadIdx.x; idx < kL1Chunk * 128; idx += 256) {
       const int bb = idx >> 7, kk = idx & 127;
-      gs[bb][kk] = bb < nb ? G[(b0 + bb) * 128 + kk] : 0.0f;
+      gs[bb][kk] = bb < nb ? G[(b0 + bb) * ncols + col0 + kk] : 0.0f;
     }
     for (int idx = threadIdx.x; idx < 3 * kL1Chunk * kL1Rows; idx += 256) {
       const int t = idx / (kL1Chunk * kL1Rows), r = idx - t * (kL1Chunk * kL1Rows);
@@ -669,32 +710,35 @@ __global__ __launch_bounds__(256) void layer1_part_kernel(const float* __restric
 #pragma unroll
       for (int i = 0; i < 4; ++i) acc[i] = fmaf(ls[0][bb][js + 2 * i], g, acc[i]);
     }
-    if (threadIdx.x < 3 * kL1Rows) {
+    if (blockIdx.z == 0 && threadIdx.x < 3 * kL1Rows) {
       const int t = threadIdx.x / kL1Rows, jj = threadIdx.x - t * kL1Rows;
       const int src = t == 2 ? 0 : t + 1;   // x <- cx, y <- cy, bias <- c
       for (int bb = 0; bb < nb; ++bb) sacc += ls[src][bb][jj];
     }
     __syncthreads();
   }
-  float* pp = part + (ch * D + j0) * kL1Cols;
+  float* pp = part + (ch * D + j0) * pw;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) pp[(js + 2 * i) * kL1Cols + k] = acc[i];
-  if (threadIdx.x < 3 * kL1Rows) {
+  for (int i = 0; i < 4; ++i) pp[(js + 2 * i) * pw + col0 + k] = acc[i];
+  if (blockIdx.z == 0 && threadIdx.x < 3 * kL1Rows) {
     const int t = threadIdx.x / kL1Rows, jj = threadIdx.x - t * kL1Rows;
-    pp[jj * kL1Cols + 128 + t] = sacc;
+    pp[jj * pw + ncols + t] = sacc;
   }
 }
 
+// W1 (D rows of ncols + 2: the input columns, then x and y) at w1_off, b1
+// after it.
 template <int D>
-__global__ __launch_bounds__(256) void layer1_sum_kernel(const float* __restrict__ part, int n_chunks,
-                                                         float* __restrict__ grad) {
+__global__ __launch_bounds__(256) void layer1_sum_kernel(const float* __restrict__ part, int n_chunks, int ncols,
+                                                         int64_t w1_off, float* __restrict__ grad) {
+  const int pw = ncols + 3;
   const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= D * kL1Cols) return;
-  const int j = idx / kL1Cols, c = idx - j * kL1Cols;
+  if (idx >= D * pw) return;
+  const int j = idx / pw, c = idx - j * pw;
   float v = 0.0f;
-  for (int ch = 0; ch < n_chunks; ++ch) v += part[(int64_t)ch * D * kL1Cols + idx];
-  if (c < 130) grad[(int64_t)j * 130 + c] = v;   // W1g columns, then W1x x and y
-  else grad[(int64_t)D * 130 + j] = v;           // b1
+  for (int ch = 0; ch < n_chunks; ++ch) v += part[(int64_t)ch * D * pw + idx];
+  if (c < ncols + 2) grad[w1_off + (int64_t)j * (ncols + 2) + c] = v;   // W1 input columns, then x and y
+  else grad[w1_off + (int64_t)D * (ncols + 2) + j] = v;                 // b1
 }
 
 // Output-layer gradient and the two losses from the per-wave partials:
@@ -703,12 +747,11 @@ __global__ __launch_bounds__(256) void layer1_sum_kernel(const float* __restrict
 template <int D>
 __global__ __launch_bounds__(256) void output_grad_kernel(const float* __restrict__ op_data,
                                                           const float* __restrict__ op_col,
-                                                          float inv_data, float inv_col,
+                                                          float inv_data, float inv_col, int64_t off_w5,
                                                           float* __restrict__ grad,
                                                           float* __restrict__ loss) {
   constexpr int EPB = 256 / kReduceGroups;
   __shared__ float sh[2][kReduceGroups][EPB];
-  const int64_t off_w5 = (int64_t)D * 130 + D + 3 * ((int64_t)D * D + D);
   const int e = threadIdx.x % EPB, g = threadIdx.x / EPB;
   const int j = blockIdx.x * EPB + e;
   float s0 = 0.0f, s1 = 0.0f;
@@ -821,10 +864,10 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
   const int64_t n_srows = S * n_rows;
   if (S == 4)
     hipLaunchKernelGGL((fwd_layer1_kernel<D, 4, ACT>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
-                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], ACT == ACT_GELU ? Sv[0] : nullptr);
   else
     hipLaunchKernelGGL((fwd_layer1_kernel<D, 1, ACT>), dim3(grid_for(n_rows * D, 256)), dim3(256), 0, s, C,
-                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0]);
+                       X, x_per_bc, rows_per_bc, n_rows, net.w1x, Z[0], ACT == ACT_GELU ? Sv[0] : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const unsigned blocks = gemm_grid((n_srows + 63) / 64);
@@ -835,35 +878,34 @@ static hipError_t run_taylor_forward(const NetPtrs& net, const float* C, const f
                          net.bh + l * D, nullptr, Z[l + 1], Sv[l + 1], n_srows, (skip_last_xy && l == 2) ? 1 : 0);
     else
       hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 0, ACT>), dim3(blocks), dim3(2 * D), 0, s, Z[l], w,
-                         net.bh + l * D, nullptr, Z[l + 1], nullptr, n_srows, 0);
+                         net.bh + l * D, nullptr, Z[l + 1], ACT == ACT_GELU ? Sv[l + 1] : nullptr, n_srows, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-template <int D>
-static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuffers& tb,
+template <int D, int ACT>
+static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuffers& tb, int64_t off_w2,
                            const float* C, const float* X, int x_per_bc, int64_t rows_per_bc,
                            int64_t B, int S, const float* target, float* grad, float* opart,
                            float* l1out, bool accumulate, hipStream_t s) {
   const int64_t n_rows = B * rows_per_bc;
   const int64_t n_srows = S * n_rows;
   float* const* Z = tb.Z;
-  float* const* Sv = (S == 4) ? tb.Sv : tb.Z;   // value-only rows: saved z = Z
-  hipError_t e = run_taylor_forward<D>(net, C, X, x_per_bc, rows_per_bc, n_rows, S, Z,
-                                       (S == 4) ? tb.Sv : tb.Z, true, s);
+  // value-only rows keep z in Z for tanh; GELU saves its pre-activations
+  float* const* Sv = (S == 4 || ACT == ACT_GELU) ? tb.Sv : tb.Z;
+  hipError_t e = run_taylor_forward<D, ACT>(net, C, X, x_per_bc, rows_per_bc, n_rows, S, Z, Sv, true, s);
   if (e != hipSuccess) return e;
   const float inv_n = 1.0f / (float)n_rows;
   if (S == 4)
-    hipLaunchKernelGGL((output_loss_kernel<D, 4>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
+    hipLaunchKernelGGL((output_loss_kernel<D, 4, ACT>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
                        net.w5, net.b5, target, n_rows, inv_n, tb.Ab[0], opart);
   else
-    hipLaunchKernelGGL((output_loss_kernel<D, 1>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
+    hipLaunchKernelGGL((output_loss_kernel<D, 1, ACT>), dim3(kOutWaves / 4), dim3(256), 0, s, Z[3], Sv[3],
                        net.w5, net.b5, target, n_rows, inv_n, tb.Ab[0], opart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
 
-  const int64_t off_w2 = (int64_t)D * 130 + D;
   const int64_t lstride = (int64_t)D * D + D;
   const int64_t n_tiles = (n_srows + 63) / 64;
   const int64_t groups = std::min<int64_t>(n_tiles, kBwdGroups);
@@ -872,28 +914,29 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
     float* Ab = tb.Ab[cur];
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
     // layer 1's stream derivatives are W1x and 0 for every row: not stored
+    // (GELU keeps layer 1's pre-activations in Sv[0])
     const bool l1 = S == 4 && l == 0;
-    const float* svl = l1 ? nullptr : Sv[l];
+    const float* svl = (l1 && ACT != ACT_GELU) ? nullptr : Sv[l];
     float* out = tb.Ab[cur ^ 1];
     if constexpr (D <= 128) {
       if (l1)
-        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, true>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, true, ACT>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else if (S == 4)
-        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, false>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 4, false, ACT>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else
-        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 1, false>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_split_kernel<D, 1, false, ACT>), dim3((unsigned)groups), dim3(4 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
     } else {
       if (l1)
-        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, true>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, true, ACT>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else if (S == 4)
-        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, false>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 4, false, ACT>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
       else
-        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 1, false>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
+        hipLaunchKernelGGL((taylor_bwd_seq_kernel<D, 1, false, ACT>), dim3((unsigned)groups), dim3(2 * D), 0, s, Ab,
                            Z[l], wT, svl, net.w1x, out, n_srows, tb.wpart, tb.bpart);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -914,49 +957,74 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
   return hipGetLastError();
 }
 
-hipError_t launch_prepare_wT(const float* params, int width, float* whT, hipStream_t s) {
-  hipLaunchKernelGGL(prepare_wT_kernel, dim3(256), dim3(256), 0, s, params, width, whT);
+hipError_t launch_prepare_wT(const float* params, int64_t off_w2, int width, float* whT, hipStream_t s) {
+  hipLaunchKernelGGL(prepare_wT_kernel, dim3(256), dim3(256), 0, s, params, off_w2, width, whT);
   return hipGetLastError();
 }
 
-template <int D>
-static hipError_t train_step_d(const NetPtrs& net, const float* whT, const TrainBuffers& tb,
+template <int D, int ACT>
+static hipError_t train_step_d(const TrainNet& tn, const NetPtrs& net, const float* whT, const TrainBuffers& tb,
                                const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
                                const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
                                hipStream_t s) {
-  hipError_t e = launch_projection(net, D, G, B, tb.C, s);
+  hipError_t e = ACT == ACT_GELU
+                     ? launch_embed_project(tn.params, D, tn.channels, net, G, B, nullptr, 0, 0, 0, 0, tb.C, s)
+                     : launch_projection(net, D, G, B, tb.C, s);
   if (e != hipSuccess) return e;
   // Alg. 1 step 1: data points, value stream only; the targets are Yd, or
   // the boundary vector itself (boundary match at the 128 perimeter nodes).
-  e = run_pass<D>(net, whT, tb, tb.C, Xd, xd_per_bc, nd, B, 1, Yd ? Yd : G, grad, tb.opart[0], tb.l1[0],
-                  false, s);
+  e = run_pass<D, ACT>(net, whT, tb, tn.off_w2, tb.C, Xd, xd_per_bc, nd, B, 1, Yd ? Yd : G, grad, tb.opart[0],
+                       tb.l1[0], false, s);
   if (e != hipSuccess) return e;
   // Alg. 1 step 2: collocation points, four streams; accumulate.
-  e = run_pass<D>(net, whT, tb, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true, s);
+  e = run_pass<D, ACT>(net, whT, tb, tn.off_w2, tb.C, Xc, 1, nc, B, 4, nullptr, grad, tb.opart[1], tb.l1[1], true,
+                       s);
   if (e != hipSuccess) return e;
-  // first-layer gradient; the weight-gradient partials (already reduced into
-  // grad by both passes) hold its chunk partials
+  // first-layer gradient over its input columns (the boundary vector, or the
+  // embedding, recomputed per condition); the weight-gradient partials
+  // (already reduced into grad by both passes) hold its chunk partials
+  const float* cols = G;
+  if (ACT == ACT_GELU) {
+    e = launch_embed_grad(tn.params, D, tn.channels, tn.off_w1, G, B, nullptr, nullptr, tb.emb, nullptr, s);
+    if (e != hipSuccess) return e;
+    cols = tb.emb;
+  }
   const int64_t L = std::max<int64_t>(kL1Chunk, ((B + kL1MaxChunks - 1) / kL1MaxChunks + kL1Chunk - 1) /
                                                     kL1Chunk * kL1Chunk);
   const int n_chunks = (int)((B + L - 1) / L);
-  hipLaunchKernelGGL((layer1_part_kernel<D>), dim3(D / kL1Rows, n_chunks), dim3(256), 0, s, tb.l1[0], tb.l1[1], G,
-                     B, L, tb.wpart);
+  hipLaunchKernelGGL((layer1_part_kernel<D>), dim3(D / kL1Rows, n_chunks, tn.n_in / 128), dim3(256), 0, s, tb.l1[0],
+                     tb.l1[1], cols, tn.n_in, B, L, tb.wpart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((layer1_sum_kernel<D>), dim3((D * kL1Cols + 255) / 256), dim3(256), 0, s, tb.wpart, n_chunks,
-                     grad);
+  hipLaunchKernelGGL((layer1_sum_kernel<D>), dim3((D * (tn.n_in + 3) + 255) / 256), dim3(256), 0, s, tb.wpart,
+                     n_chunks, tn.n_in, tn.off_w1, grad);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ACT == ACT_GELU) {   // the embedding's convolutions, from the first layer's per-condition sums
+    e = launch_embed_grad(tn.params, D, tn.channels, tn.off_w1, G, B, tb.l1[0], tb.l1[1], nullptr, tb.cpart, s);
+    if (e != hipSuccess) return e;
+    const int64_t n_conv = tn.off_w1;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(n_conv, 256 / kReduceGroups)), dim3(256), 0, s, tb.cpart,
+                       B, n_conv, n_conv, grad, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((output_grad_kernel<D>), dim3((D + 2 + 256 / kReduceGroups - 1) / (256 / kReduceGroups)),
                      dim3(256), 0, s, tb.opart[0], tb.opart[1],
-                     1.0f / (float)(B * nd), 1.0f / (float)(B * nc), grad, loss);
+                     1.0f / (float)(B * nd), 1.0f / (float)(B * nc), tn.off_w5, grad, loss);
   return hipGetLastError();
 }
 
-hipError_t launch_train_grad(const NetPtrs& net, int width, const float* whT, const TrainBuffers& tb,
-                             const float* G, int64_t B, const float* Xd, int64_t nd, int xd_per_bc,
-                             const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
+hipError_t launch_train_grad(const TrainNet& tn, const NetPtrs& net, int width, const float* whT,
+                             const TrainBuffers& tb, const float* G, int64_t B, const float* Xd, int64_t nd,
+                             int xd_per_bc, const float* Yd, const float* Xc, int64_t nc, float* grad, float* loss,
                              hipStream_t s) {
-  return width == 256 ? train_step_d<256>(net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss, s)
-                      : train_step_d<128>(net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad, loss, s);
+  if (tn.channels > 0)
+    return width == 256 ? train_step_d<256, ACT_GELU>(tn, net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad,
+                                                      loss, s)
+                        : train_step_d<128, ACT_GELU>(tn, net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad,
+                                                      loss, s);
+  return width == 256 ? train_step_d<256, ACT_TANH>(tn, net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad,
+                                                    loss, s)
+                      : train_step_d<128, ACT_TANH>(tn, net, whT, tb, G, B, Xd, nd, xd_per_bc, Yd, Xc, nc, grad,
+                                                    loss, s);
 }
 
 hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, double lr, double b1,

@@ -300,7 +300,7 @@ def test_fault_inject_spec_parsing(lib):
 
 def test_gelu_network_descriptor(lib):
     """The convolutional-embedding GELU network: parameter count, descriptor
-    checks, and the forms it does not run."""
+    checks, the forms it does not run, and its training workspace."""
     from paper_2308_14258_amd._lib import MF_EUNSUPPORTED
     import mf_inputs as mi
     for d in (128, 256):
@@ -319,7 +319,10 @@ def test_gelu_network_descriptor(lib):
                                  ctypes.byref(n)) == MF_EUNSUPPORTED
     assert lib.mf_workspace_size(ctypes.byref(g), ctypes.byref(_dom(16, 16)), 1, MF_FP32, 0, 1,
                                  ctypes.byref(n)) == MF_EUNSUPPORTED
-    assert lib.sdnet_train_ws_size(ctypes.byref(g), 4, 128, 8, ctypes.byref(n)) == MF_EUNSUPPORTED
+    assert lib.sdnet_train_ws_size(ctypes.byref(g), 4, 128, 8, ctypes.byref(n)) == MF_OK   # trains too
+    t = ctypes.c_size_t()
+    assert lib.sdnet_train_ws_size(ctypes.byref(SdnetDesc(256, 4, 128, 0)), 4, 128, 8, ctypes.byref(t)) == MF_OK
+    assert n.value > t.value   # layer 1's saved pre-activations, the embeddings and convolution partials
     assert lib.mf_adjoint_ws_size(ctypes.byref(g), ctypes.byref(_dom(2, 2)), 1, 0, 2, 1,
                                   ctypes.byref(n)) == MF_EUNSUPPORTED
     assert lib.sdnet_forward_ws_size(ctypes.byref(g), 4, 10, 1, MF_FP32, ctypes.byref(n)) == MF_OK

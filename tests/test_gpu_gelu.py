@@ -1,8 +1,9 @@
 """GPU parity of the paper's SDNet architecture (convolutional boundary
 embedding, input-split first layer, GELU layers; Sec. 3.1, Fig. 3) through
-the C ABI: sdnet_forward's value, gradient and Laplacian, and the sweep and
-solve with it, against the float64 oracle (oracle/sdnet_conv.py). Bars as
-for the tanh network: float32 relative L2 <= 1e-5 (Laplacian 1e-4)."""
+the C ABI: sdnet_forward's value, gradient and Laplacian, the sweep and
+solve with it, and its training gradient (Alg. 1) and Adam steps, against
+the float64 oracle (oracle/sdnet_conv.py, oracle/train.py). Bars as for the
+tanh network: float32 relative L2 <= 1e-5 (Laplacian 1e-4, gradient 1e-4)."""
 import numpy as np
 import pytest
 import torch
@@ -127,10 +128,79 @@ def test_unsupported_forms_are_refused(ctx):
     with pytest.raises(MosaicError) as e:
         mf_sweep(ctx, p, u, (2, 2), prec=MF_BF16)
     assert e.value.status == MF_EUNSUPPORTED
-    G = torch.from_numpy(mi.gp_perimeter_batch(2, 0.5, seed=53)).cuda()
-    Xb = torch.from_numpy(mi.unit_perimeter_nodes().astype(np.float32)).cuda()
-    Xc = torch.from_numpy(mi.collocation_points(2, 4, seed=54)).cuda()
-    z = torch.zeros_like(p)
-    with pytest.raises(MosaicError) as e:
-        sdnet_train_step(ctx, p, z, z.clone(), 1, G, Xb, Xc)
-    assert e.value.status == MF_EUNSUPPORTED
+
+
+def _t64(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float64))
+
+
+@pytest.mark.parametrize("width,targets", [(128, "boundary"), (256, "boundary"), (128, "per_condition")])
+def test_training_gradient_matches_the_oracle(ctx, width, targets):
+    """Alg. 1 for the paper's network (sdnet_loss_grad): the data pass and the
+    collocation pass with the GELU Taylor rules forward and backward, the
+    first layer's gradient over the embedding, and the reverse through the
+    two circular convolutions, against float64 autograd of the oracle's loss
+    (oracle/train.py losses_conv): the losses to 1e-5 and the gradient to
+    relative 1e-4, also tensor by tensor (convolutions included) to 1e-3."""
+    print(f"case: GELU training gradient width={width} targets={targets}", flush=True)
+    from oracle import optim, train
+    from paper_2308_14258_amd import sdnet_loss_grad
+    th = _params(width, 61)
+    B, nc = 6, 24
+    G = mi.gp_perimeter_batch(B, 0.5, seed=62)
+    Xc = mi.collocation_points(B, nc, seed=63)
+    if targets == "boundary":
+        Xd, Yd = mi.unit_perimeter_nodes().astype(np.float32), None
+    else:
+        Xd = mi.collocation_points(B, 40, seed=64)
+        Yd = np.random.default_rng(65).uniform(size=(B, 40)).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    loss, grad = sdnet_loss_grad(ctx, d(th), d(G), d(Xd), d(Xc), Yd=None if Yd is None else d(Yd))
+    torch.cuda.synchronize()
+    ld, lp, gd, gp = train.gradient_conv(_t64(th), width, C, _t64(G), _t64(Xd), _t64(Xc),
+                                         None if Yd is None else _t64(Yd))
+    want = (gd + gp).numpy()
+    got = grad.cpu().numpy().astype(np.float64)
+    L = loss.cpu().numpy().astype(np.float64)
+    err = _rel(got, want)
+    seg = optim.conv_segments(width, C)
+    per = [_rel(got[a:b], want[a:b]) for a, b in zip(seg[:-1], seg[1:]) if np.linalg.norm(want[a:b]) > 0]
+    print(f"GELU training width {width} ({targets}): loss {L[:2]} vs {ld:.6e} {lp:.6e}; gradient rel L2 "
+          f"{err:.2e}, worst tensor {max(per):.2e}", flush=True)
+    assert abs(L[0] - ld) <= 1e-5 * abs(ld) and abs(L[1] - lp) <= 1e-5 * abs(lp)
+    assert err <= 1e-4
+    assert max(per) <= 1e-3
+
+
+def test_training_steps_track_the_oracle(ctx):
+    """Twenty Alg. 1 + Adam steps of the paper's network (sdnet_train_step)
+    against the same steps in float64: the loss curves agree to relative
+    1e-3 and the loss falls."""
+    print("case: GELU training, width 128, 4 x 12, 20 Adam steps", flush=True)
+    from oracle import train
+    width, B, nc, steps = 128, 4, 12, 20
+    th = _params(width, 71)
+    G = mi.gp_perimeter_batch(B, 0.5, seed=72)
+    Xc = mi.collocation_points(B, nc, seed=73)
+    Xb = mi.unit_perimeter_nodes().astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    p = d(th)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    Gd, Xbd, Xcd = d(G), d(Xb), d(Xc)
+    curve = []
+    for t in range(1, steps + 1):
+        curve.append(sdnet_train_step(ctx, p, m, v, t, Gd, Xbd, Xcd, lr=1e-3).clone())
+    got = torch.stack(curve).cpu().numpy().astype(np.float64)[:, :2]
+    x = _t64(th)
+    mo, vo = torch.zeros_like(x), torch.zeros_like(x)
+    want = []
+    for t in range(1, steps + 1):
+        ld, lp, gd, gp = train.gradient_conv(x, width, C, _t64(G), _t64(Xb), _t64(Xc))
+        x, mo, vo = train.adam_update(x, mo, vo, gd + gp, t)
+        want.append((ld, lp))
+    want = np.array(want)
+    rel = np.abs(got - want) / np.abs(want)
+    print(f"GELU Adam curve: max rel diff {rel.max():.3e}; total {got[0].sum():.4e} -> {got[-1].sum():.4e}",
+          flush=True)
+    assert rel.max() <= 1e-3
+    assert got[-1].sum() < got[0].sum()
