@@ -615,7 +615,30 @@ def train_measurement(ctx, steps):
            "frac_of_fp32_mfma_peak": flops * steps / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
            "last_loss": [float(x) for x in loss.cpu()]}
     res["lamb"] = train_lamb_measurement(ctx, steps, G, Xb, Xc, d)
+    res["gelu_conv_sdnet"] = train_gelu_measurement(ctx, steps, G, Xb, Xc, d)
     return res
+
+
+def train_gelu_measurement(ctx, steps, G, Xb, Xc, d, C=4):
+    """The same training step (Alg. 1 + Adam, same conditions and points) for
+    the paper's network: the convolutional embedding (C channels) and GELU
+    layers at the same width."""
+    import torch
+    import mf_inputs as mi
+    from paper_2308_14258_amd import sdnet_train_step
+    p = torch.from_numpy(mi.xavier_conv_params(d, C, 0, bias_scale=0.1)).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    for k in range(2):
+        sdnet_train_step(ctx, p, m, v, k + 1, G, Xb, Xc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        loss = sdnet_train_step(ctx, p, m, v, k + 3, G, Xb, Xc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"network": f"conv embedding (C={C}) + GELU, width {d}", "steps_per_s": steps / dt,
+            "ms_per_step": dt * 1e3 / steps, "last_loss": [float(x) for x in loss.cpu()]}
 
 
 def train_lamb_measurement(ctx, steps, G, Xb, Xc, d):

@@ -51,8 +51,11 @@
  *   condition), plus W1x (x, y) per point. The MF_GELU network runs in
  *   MF_FP32 through mf_sweep / mf_solve (multiplicative; a placement's
  *   embedding and projection once per phase, then the value stream through
- *   MFMA GEMMs with a GELU epilogue) and sdnet_forward (with its gradient
- *   and Laplacian); the other entry points return MF_EUNSUPPORTED for it.
+ *   MFMA GEMMs with a GELU epilogue), sdnet_forward (with its gradient
+ *   and Laplacian) and the training entry points (sdnet_train_step,
+ *   sdnet_loss_grad; the GELU Taylor rules forward and in reverse, and the
+ *   reverse through the convolutions); the other entry points return
+ *   MF_EUNSUPPORTED for it.
  * Precision: MF_FP32 computes every GEMM with float32 MFMA (the boundary
  *   projection on the float32 VALU). MF_BF16 rounds the GEMM operands to
  *   bf16 and accumulates in float32 on MFMA: the boundary projection
@@ -480,7 +483,8 @@ mf_status sdnet_forward(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* par
  * nd data points and nc collocation points per condition. */
 mf_status sdnet_train_ws_size(const mf_sdnet_desc* desc, int64_t B, int64_t nd, int64_t nc, size_t* bytes);
 
-/* One physics-informed training iteration (Alg. 1 on one device, then Adam):
+/* One physics-informed training iteration (Alg. 1 on one device, then Adam),
+ * for either network (MF_TANH, or MF_GELU with its convolutional embedding):
  *   L_data = mean_{b,k} (N(Xd_{b,k}, G_b) - Yd_{b,k})^2   (data term)
  *   L_pde  = mean_{b,j} (Laplacian N(Xc_{b,j}, G_b))^2     (Eq. 3)
  * The data term is the paper's mean squared error against known solution
