@@ -443,6 +443,28 @@ def trained_section(ctx):
             r["seconds_to_mae_0.05"] = time.perf_counter() - t0
         t4[name] = r
     res["table4_64x64_units"] = t4
+    # the paper's network (convolutional embedding, GELU), trained the same way
+    gw = os.path.join(WEIGHTS_DIR, "sdnet_laplace_gelu_c4_d256.npz")
+    if os.path.exists(gw):
+        gparams, gwidth, gcfg, ghist = load_trained(gw)
+        gp = torch.from_numpy(gparams).cuda()
+        u = torch.from_numpy(f4).cuda()
+        uo = torch.empty_like(u)
+        mf_solve(ctx, gp, u, (4, 4), 100, u_out=uo)
+        torch.cuda.synchronize()
+        r = {"network": f"width {gwidth}, conv embedding C={gcfg['channels']} + GELU, {gcfg['epochs']} epochs, "
+                        f"validation MSE {ghist['val_mse'][-1]:.2e}",
+             "fig1_4x4_units_100_sweeps_mae_fp32": float(
+                 np.abs(uo.cpu().numpy().astype(np.float64) - g["u4"])[1:-1, 1:-1].mean())}
+        u = torch.from_numpy(f64).cuda()
+        uo = torch.empty_like(u)
+        curve = {}
+        for k in range(100, 2001, 100):
+            mf_solve(ctx, gp, u, (64, 64), 100, u_out=uo)
+            torch.cuda.synchronize()
+            curve[k] = mae(uo)
+        r["table4_64x64_mae_by_sweeps_fp32"] = curve
+        res["papers_network"] = r
     return res
 
 

@@ -19,8 +19,11 @@ conditions against their exact solutions (mean squared error).
 
     python -m paper_2308_14258_amd.sdnet_training --width 256 --epochs 500 --out weights.npz
 
-The weights file holds the flat float32 parameter vector in the library's
-layout, the width, the training configuration and the loss history.
+With --channels C (1..8) the network is the paper's (Sec. 3.1): a circular
+convolutional embedding of the boundary with C channels and GELU layers;
+without it, the tanh network. The weights file holds the flat float32
+parameter vector in the library's layout, the width, the training
+configuration and the loss history.
 """
 from __future__ import annotations
 
@@ -56,7 +59,7 @@ def grid_nodes(cells: int = 32) -> np.ndarray:
 
 
 def train(width: int = 256, n_bc: int = 20480, n_data: int = 128, n_colloc: int = 128, batch: int = 512,
-          epochs: int = 500, lr: float = 1e-3, seed: int = 0, val_every: int = 25, log=print):
+          epochs: int = 500, lr: float = 1e-3, seed: int = 0, val_every: int = 25, log=print, channels: int = 0):
     """Returns (params [float32 numpy], history dict)."""
     import torch
 
@@ -75,7 +78,8 @@ def train(width: int = 256, n_bc: int = 20480, n_data: int = 128, n_colloc: int 
          (("G", G[:n_tr]), ("Xd", Xd[:n_tr]), ("Yd", Yd[:n_tr]), ("Xc", Xc[:n_tr]), ("Gv", Gv), ("Uv", Uv),
           ("Xv", grid_nodes()))}
     ctx = Context(0)
-    p = torch.from_numpy(mi.xavier_params(width, seed)).to(dev)
+    init = mi.xavier_conv_params(width, channels, seed) if channels else mi.xavier_params(width, seed)
+    p = torch.from_numpy(init).to(dev)
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
     loss = torch.empty(3, device=dev)
@@ -139,11 +143,13 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--val-every", type=int, default=25)
+    ap.add_argument("--channels", type=int, default=0, help="embedding channels (0: the tanh network)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    cfg = {k: getattr(a, k) for k in ("width", "n_bc", "n_data", "n_colloc", "batch", "epochs", "lr", "seed")}
+    cfg = {k: getattr(a, k) for k in ("width", "n_bc", "n_data", "n_colloc", "batch", "epochs", "lr", "seed",
+                                      "channels")}
     params, hist = train(a.width, a.n_bc, a.n_data, a.n_colloc, a.batch, a.epochs, a.lr, a.seed, a.val_every,
-                         log=lambda s: print(s, flush=True))
+                         log=lambda s: print(s, flush=True), channels=a.channels)
     save(a.out, params, a.width, cfg, hist)
     print(json.dumps({"out": a.out, "val_mse": hist["val_mse"][-1], "train_s": hist["train_s"]}), flush=True)
 
