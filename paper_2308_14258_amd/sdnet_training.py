@@ -19,6 +19,11 @@ conditions against their exact solutions (mean squared error).
 
     python -m paper_2308_14258_amd.sdnet_training --width 256 --epochs 500 --out weights.npz
 
+With --optimizer lamb each iteration is ``sdnet_loss_grad`` (the same Alg. 1
+passes) followed by ``sdnet_lamb_step`` (LAMB with the per-tensor trust
+ratio and the gradient clipped to norm 1, the optimiser the paper names for
+large batches) at the library's schedule (``lr_at``).
+
 With --channels C (1..8) the network is the paper's (Sec. 3.1): a circular
 convolutional embedding of the boundary with C channels and GELU layers;
 without it, the tanh network. The weights file holds the flat float32
@@ -59,12 +64,14 @@ def grid_nodes(cells: int = 32) -> np.ndarray:
 
 
 def train(width: int = 256, n_bc: int = 20480, n_data: int = 128, n_colloc: int = 128, batch: int = 512,
-          epochs: int = 500, lr: float = 1e-3, seed: int = 0, val_every: int = 25, log=print, channels: int = 0):
+          epochs: int = 500, lr: float = 1e-3, seed: int = 0, val_every: int = 25, log=print, channels: int = 0,
+          optimizer: str = "adam"):
     """Returns (params [float32 numpy], history dict)."""
     import torch
 
     import mf_inputs as mi
-    from paper_2308_14258_amd import Context, sdnet_forward, sdnet_train_step
+    from paper_2308_14258_amd import (Context, lr_at as sched_lr, lr_schedule, sdnet_forward, sdnet_lamb_step,
+                                      sdnet_loss_grad, sdnet_train_step)
 
     t0 = time.perf_counter()
     G, Xd, Yd, Xc, hyper = mi.training_set(n_bc, n_data, n_colloc, seed)
@@ -86,6 +93,8 @@ def train(width: int = 256, n_bc: int = 20480, n_data: int = 128, n_colloc: int 
     steps_per_epoch = n_tr // batch
     total = steps_per_epoch * epochs
     hist = {"epoch": [], "loss_data": [], "loss_pde": [], "val_mse": [], "seconds": []}
+    grad = torch.empty_like(p)
+    sched = lr_schedule(lr, total, warmup_frac=1e-3)
 
     def validate():
         U = sdnet_forward(ctx, p, d["Gv"], d["Xv"])
@@ -98,8 +107,13 @@ def train(width: int = 256, n_bc: int = 20480, n_data: int = 128, n_colloc: int 
         for s in range(steps_per_epoch):
             it += 1
             sl = slice(s * batch, (s + 1) * batch)
-            sdnet_train_step(ctx, p, m, v, it, d["G"][sl], d["Xd"][sl], d["Xc"][sl], lr=lr_at(it, total, lr),
-                             loss=loss, Yd=d["Yd"][sl])
+            if optimizer == "lamb":
+                sdnet_loss_grad(ctx, p, d["G"][sl], d["Xd"][sl], d["Xc"][sl], loss=loss, grad_out=grad,
+                                Yd=d["Yd"][sl])
+                sdnet_lamb_step(ctx, p, m, v, grad, it, lr=sched_lr(sched, it), max_grad_norm=1.0)
+            else:
+                sdnet_train_step(ctx, p, m, v, it, d["G"][sl], d["Xd"][sl], d["Xc"][sl], lr=lr_at(it, total, lr),
+                                 loss=loss, Yd=d["Yd"][sl])
             acc += loss
         if ep % val_every == 0 or ep == epochs or ep == 1:
             acc = (acc / steps_per_epoch).cpu().numpy()
@@ -144,12 +158,13 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--val-every", type=int, default=25)
     ap.add_argument("--channels", type=int, default=0, help="embedding channels (0: the tanh network)")
+    ap.add_argument("--optimizer", choices=["adam", "lamb"], default="adam")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     cfg = {k: getattr(a, k) for k in ("width", "n_bc", "n_data", "n_colloc", "batch", "epochs", "lr", "seed",
-                                      "channels")}
+                                      "channels", "optimizer")}
     params, hist = train(a.width, a.n_bc, a.n_data, a.n_colloc, a.batch, a.epochs, a.lr, a.seed, a.val_every,
-                         log=lambda s: print(s, flush=True), channels=a.channels)
+                         log=lambda s: print(s, flush=True), channels=a.channels, optimizer=a.optimizer)
     save(a.out, params, a.width, cfg, hist)
     print(json.dumps({"out": a.out, "val_mse": hist["val_mse"][-1], "train_s": hist["train_s"]}), flush=True)
 
