@@ -125,6 +125,22 @@ __global__ void adjoint_seed_kernel(const float* __restrict__ Z4, const float* _
   }
 }
 
+// The same seed through the GELU network's last layer: GELU'(a4) w5[j] ubp[r]
+// with a4 the saved pre-activations.
+template <int D>
+__global__ void adjoint_seed_gelu_kernel(const float* __restrict__ A4, const float* __restrict__ w5,
+                                         const float* __restrict__ ubp, int64_t n_rows, float* __restrict__ Ab) {
+  const int64_t n = n_rows * D;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / D;
+    const int j = (int)(idx - r * D);
+    float f1, f2, f3;
+    gelu_d123(A4[idx], f1, f2, f3);
+    Ab[idx] = f1 * w5[j] * ubp[r];
+  }
+}
+
 // gb[q][k] = sum_j W1g[j][k] c[q][j] with W1g^T stored k-major (w1gT[k][j]).
 template <int D>
 __global__ __launch_bounds__(128) void boundary_adjoint_kernel(const float* __restrict__ w1gT,
@@ -297,17 +313,37 @@ static hipError_t adjoint_colour_d(const NetPtrs& net, const float* whT, const A
     hipLaunchKernelGGL(gather_boundaries_kernel, dim3(grid_of((int64_t)nq * kNB, 256)), dim3(256), 0, s,
                        u_before, before_shift, dd, colour, q0, nq, ab.G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_projection(net, D, ab.G, nq, ab.C, s)) != hipSuccess) return e;
-    if ((e = launch_value_forward(net, D, ab.C, X, T, nq, ab.Z, s)) != hipSuccess) return e;
+    const bool gelu = ab.channels > 0;
+    if (gelu) {
+      if ((e = launch_embed_project(ab.params, D, ab.channels, net, ab.G, nq, nullptr, 0, 0, 0, 0, ab.C, s)) !=
+          hipSuccess)
+        return e;
+      if ((e = launch_value_forward_gelu_saved(net, D, ab.C, X, T, nq, ab.Z, ab.Sv, s)) != hipSuccess) return e;
+    } else {
+      if ((e = launch_projection(net, D, ab.G, nq, ab.C, s)) != hipSuccess) return e;
+      if ((e = launch_value_forward(net, D, ab.C, X, T, nq, ab.Z, s)) != hipSuccess) return e;
+    }
     // 3. reverse pass to the first-layer pre-activation adjoints
-    hipLaunchKernelGGL((adjoint_seed_kernel<D>), dim3(grid_of(n_rows * D, 256)), dim3(256), 0, s, ab.Z[3],
-                       net.w5, ab.ubp, n_rows, ab.Ab[0]);
+    if (gelu)
+      hipLaunchKernelGGL((adjoint_seed_gelu_kernel<D>), dim3(grid_of(n_rows * D, 256)), dim3(256), 0, s, ab.Sv[3],
+                         net.w5, ab.ubp, n_rows, ab.Ab[0]);
+    else
+      hipLaunchKernelGGL((adjoint_seed_kernel<D>), dim3(grid_of(n_rows * D, 256)), dim3(256), 0, s, ab.Z[3],
+                         net.w5, ab.ubp, n_rows, ab.Ab[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_value_backward(whT, D, ab.Z, ab.Ab, n_rows, X, nq, T, ab.csum, s)) != hipSuccess)
+    if ((e = launch_value_backward(whT, D, ab.Z, gelu ? ab.Sv : nullptr, ab.Ab, n_rows, X, nq, T, ab.csum, s)) !=
+        hipSuccess)
       return e;
-    // 4. boundary adjoints, scattered in four sub-colours
-    hipLaunchKernelGGL((boundary_adjoint_kernel<D>), dim3(nq), dim3(128), 0, s, net.w1gT, ab.csum, nq, ab.gb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 4. boundary adjoints (through the embedding for the GELU network),
+    // scattered in four sub-colours
+    if (gelu) {
+      if ((e = launch_embed_input_adjoint(ab.params, net, D, ab.channels, ab.G, ab.csum, nq, ab.gb, s)) !=
+          hipSuccess)
+        return e;
+    } else {
+      hipLaunchKernelGGL((boundary_adjoint_kernel<D>), dim3(nq), dim3(128), 0, s, net.w1gT, ab.csum, nq, ab.gb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (int sub = 0; sub < 4; ++sub) {
       hipLaunchKernelGGL(boundary_scatter_add_kernel, dim3(nq), dim3(128), 0, s, ub, dd, colour, q0, nq, sub,
                          ab.gb);

@@ -186,6 +186,88 @@ __global__ __launch_bounds__(256) void embed_grad_kernel(const float* __restrict
   }
 }
 
+// Boundary adjoint of the GELU network for the sweep's adjoint: per placement
+// q (one workgroup), c = the first layer's pre-activation adjoint sum over
+// the placement's targets, e_bar = W1e^T c (w1eT: the transposed block,
+// [E][d]), then back through the two convolutions as in embed_grad_kernel,
+// ending at the boundary values: g_bar[m] = sum_o sum_t Wc1[o][t]
+// p1_bar[o][(m - t + 2) mod 128].
+__global__ __launch_bounds__(256) void embed_input_adjoint_kernel(const float* __restrict__ conv, int C,
+                                                                  const float* __restrict__ w1eT, int d,
+                                                                  const float* __restrict__ G,
+                                                                  const float* __restrict__ c,
+                                                                  float* __restrict__ gb) {
+  extern __shared__ float sm[];   // g [128] | p1, h1, p2, v [C][128] each | c [d]
+  const int E = C * kNB;
+  float* g = sm;
+  float* p1 = g + kNB;
+  float* h1 = p1 + E;
+  float* p2 = h1 + E;
+  float* v = p2 + E;
+  float* cs = v + E;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < kNB) g[tid] = G[q * kNB + tid];
+  for (int j = tid; j < d; j += 256) cs[j] = c[q * d + j];
+  __syncthreads();
+  const float* w1c = conv;
+  const float* b1c = w1c + C * kConvK;
+  const float* w2c = b1c + C;
+  const float* b2c = w2c + C * C * kConvK;
+  for (int idx = tid; idx < E; idx += 256) {
+    const int o = idx >> 7, k = idx & 127;
+    float acc = b1c[o];
+#pragma unroll
+    for (int t = 0; t < kConvK; ++t) acc = fmaf(w1c[o * kConvK + t], g[(k + t - 2) & 127], acc);
+    p1[idx] = acc;
+    h1[idx] = gelu_f32(acc);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < E; idx += 256) {
+    const int o = idx >> 7, k = idx & 127;
+    float acc = b2c[o];
+    for (int i = 0; i < C; ++i)
+#pragma unroll
+      for (int t = 0; t < kConvK; ++t) acc = fmaf(w2c[(o * C + i) * kConvK + t], h1[i * kNB + ((k + t - 2) & 127)], acc);
+    p2[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < E; idx += 256) {   // p2_bar = (W1e^T c) GELU'(p2)
+    float eb = 0.0f;
+    for (int j = 0; j < d; ++j) eb = fmaf(w1eT[(int64_t)idx * d + j], cs[j], eb);
+    float z, d1, d2;
+    gelu_rules(p2[idx], z, d1, d2);
+    v[idx] = eb * d1;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < E; idx += 256) {   // p1_bar = h1_bar GELU'(p1), into p2's space
+    const int i = idx >> 7, m = idx & 127;
+    float hb = 0.0f;
+    for (int o = 0; o < C; ++o)
+#pragma unroll
+      for (int t = 0; t < kConvK; ++t) hb = fmaf(w2c[(o * C + i) * kConvK + t], v[o * kNB + ((m - t + 2) & 127)], hb);
+    float z, d1, d2;
+    gelu_rules(p1[idx], z, d1, d2);
+    p2[idx] = hb * d1;
+  }
+  __syncthreads();
+  if (tid < kNB) {
+    float acc = 0.0f;
+    for (int o = 0; o < C; ++o)
+#pragma unroll
+      for (int t = 0; t < kConvK; ++t) acc = fmaf(w1c[o * kConvK + t], p2[o * kNB + ((tid - t + 2) & 127)], acc);
+    gb[q * kNB + tid] = acc;
+  }
+}
+
+hipError_t launch_embed_input_adjoint(const float* params, const NetPtrs& net, int width, int C, const float* G,
+                                      const float* c, int n_q, float* gb, hipStream_t s) {
+  const size_t lds = (size_t)(kNB + 4 * C * kNB + width) * 4;
+  hipLaunchKernelGGL(embed_input_adjoint_kernel, dim3((unsigned)n_q), dim3(256), lds, s, params, C, net.w1gT, width,
+                     G, c, gb);
+  return hipGetLastError();
+}
+
 hipError_t launch_embed_grad(const float* params, int width, int C, int64_t off_w1, const float* G, int64_t B,
                              const float* c0, const float* c1, float* e_out, float* part, hipStream_t s) {
   const size_t lds = (size_t)(kNB + 4 * C * kNB + width) * 4;

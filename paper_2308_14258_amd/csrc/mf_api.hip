@@ -1350,16 +1350,20 @@ static constexpr int64_t kAdjRows = 262144;   // (placement, target) rows per ch
 // its own offset minus lo, so that one copy moves every domain of the batch.
 struct AdjLayout {
   NetLayout net;
-  size_t whT = 0, X_cross = 0, X_interior = 0, G = 0, C = 0, ubp = 0, Z[4] = {0, 0, 0, 0}, Ab[2] = {0, 0};
+  size_t whT = 0, X_cross = 0, X_interior = 0, G = 0, C = 0, ubp = 0, Z[4] = {0, 0, 0, 0}, Ab[2] = {0, 0}, Sv[4] = {0, 0, 0, 0};
   size_t csum = 0, gb = 0, part = 0, ftable = 0, atable = 0, field = 0, ckpt = 0, states = 0, uout = 0, total = 0;
+  size_t gC = 0, gX = 0, gZ[2] = {0, 0};   // the GELU network's forward phases (as in the sweep workspace)
   int64_t lo = 0;       // first float of the span
   size_t fsize = 0;     // floats per field copy (hi - lo)
   int n_ckpt = 0;
 };
 
-static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, int K, int ckpt_every) {
+static AdjLayout adjoint_layout(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int K,
+                                int ckpt_every) {
   AdjLayout A;
-  A.net = net_layout(width, MF_FP32, 0);
+  const int width = desc->width;
+  const bool gelu = is_gelu(desc);
+  A.net = net_layout(width, MF_FP32, 0, gelu ? 128 * desc->embed_channels : 128);
   const size_t d = (size_t)width;
   const size_t max_q = (size_t)(kAdjRows / 61);
   int64_t lo = INT64_MAX, hi = 0;
@@ -1379,6 +1383,8 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
   A.ubp = o; o = align256(o + (size_t)kAdjRows * 4);
   for (int l = 0; l < 4; ++l) { A.Z[l] = o; o = align256(o + (size_t)kAdjRows * d * 4); }
   for (int l = 0; l < 2; ++l) { A.Ab[l] = o; o = align256(o + (size_t)kAdjRows * d * 4); }
+  if (gelu)   // the GELU network's saved pre-activations
+    for (int l = 0; l < 4; ++l) { A.Sv[l] = o; o = align256(o + (size_t)kAdjRows * d * 4); }
   A.csum = o; o = align256(o + 3 * max_q * d * 4);
   A.gb = o; o = align256(o + max_q * 128 * 4);
   A.part = o; o = align256(o + 1024 * 4);
@@ -1386,6 +1392,11 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
   // adjoint's: DomEntry [nd] + placement prefixes [4][nd + 1]
   A.ftable = o; o = align256(o + (size_t)nd * sizeof(DomEntry) + 2 * 4 * ((size_t)nd + 1) * 4);
   A.atable = o; o = align256(o + (size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
+  if (gelu) {   // the forward solve's GELU phase chunks, sized as in sweep_layout
+    A.gC = o; o = align256(o + (size_t)(kGeluRows / 61) * width * 4);
+    A.gX = o; o = align256(o + (61 + 961) * 2 * 4);
+    for (int l = 0; l < 2; ++l) { A.gZ[l] = o; o = align256(o + (size_t)kGeluRows * width * 4); }
+  }
   A.field = o; o = align256(o + A.fsize * 4);
   A.ckpt = o; o = align256(o + (size_t)A.n_ckpt * A.fsize * 4);
   A.states = o; o = align256(o + 4 * (size_t)ckpt_every * A.fsize * 4);
@@ -1397,7 +1408,6 @@ static AdjLayout adjoint_layout(int width, const mf_domain_desc* dom, int nd, in
 static mf_status adjoint_checks(const mf_sdnet_desc* desc, const mf_domain_desc* dom, int nd, int targets,
                                 int K, int ckpt_every) {
   MF_TRY(check_desc(desc));
-  MF_TRY(need_tanh(desc, "mf_solve_adjoint"));
   MF_TRY(check_domain(dom, nd));
   if (targets != MF_CROSS && targets != MF_INTERIOR) return fail(MF_EINVAL, "targets %d unknown", targets);
   if (K < 0) return fail(MF_EINVAL, "K %d < 0", K);
@@ -1413,7 +1423,7 @@ mf_status mf_adjoint_ws_size(const mf_sdnet_desc* desc, const mf_domain_desc* do
   MF_TRY(check_ptr(bytes, "bytes", 1));
   *bytes = 0;
   MF_TRY(adjoint_checks(desc, dom, n_domains, targets, K, ckpt_every));
-  *bytes = adjoint_layout(desc->width, dom, n_domains, K, ckpt_every).total;
+  *bytes = adjoint_layout(desc, dom, n_domains, K, ckpt_every).total;
   return ok();
 }
 
@@ -1435,18 +1445,26 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
     return fail(MF_EINVAL, "u0, u_out and u0_bar must be distinct buffers");
   if (uout_bar && (uout_bar == u0_bar || uout_bar == u_out))
     return fail(MF_EINVAL, "uout_bar must not alias u0_bar or u_out");
-  const AdjLayout A = adjoint_layout(desc->width, dom, n_domains, K, ckpt_every);
+  const AdjLayout A = adjoint_layout(desc, dom, n_domains, K, ckpt_every);
   MF_TRY(check_ws(ws, ws_bytes, A.total));
   if (!ctx) return fail(MF_EINVAL, "ctx is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MF_HIP(hipSetDevice(ctx->device));
   char* b = static_cast<char*>(ws);
   const int nd = n_domains;
-  MF_HIP(launch_prepare_net(params, desc->width, MF_FP32, A.net, ws, s));
+  MF_HIP(prepare_net(desc, params, MF_FP32, A.net, ws, s));
   const NetPtrs net = net_ptrs(A.net, ws);
   float* whT = reinterpret_cast<float*>(b + A.whT);
-  MF_HIP(launch_prepare_wT(params, (int64_t)desc->width * (desc->n_boundary + 2) + desc->width, desc->width, whT, s));
+  const bool gelu = is_gelu(desc);
+  const int64_t n_in = gelu ? 128 * (int64_t)desc->embed_channels : desc->n_boundary;
+  const int64_t off_w2 = (gelu ? embed_param_offset(desc->embed_channels) : 0) + desc->width * (n_in + 2) + desc->width;
+  MF_HIP(launch_prepare_wT(params, off_w2, desc->width, whT, s));
   AdjointBuffers ab;
+  if (gelu) {
+    ab.params = params;
+    ab.channels = desc->embed_channels;
+    for (int l = 0; l < 4; ++l) ab.Sv[l] = reinterpret_cast<float*>(b + A.Sv[l]);
+  }
   ab.X_cross = reinterpret_cast<float*>(b + A.X_cross);
   ab.X_interior = reinterpret_cast<float*>(b + A.X_interior);
   ab.G = reinterpret_cast<float*>(b + A.G);
@@ -1472,8 +1490,13 @@ mf_status mf_solve_adjoint(mf_ctx* ctx, const mf_sdnet_desc* desc, const float* 
   SweepLayout SL;
   SL.net = A.net;
   SL.table = A.ftable;
+  SL.gC = A.gC;
+  SL.gX = A.gX;
+  SL.gZ[0] = A.gZ[0];
+  SL.gZ[1] = A.gZ[1];
   Plan P;
   MF_TRY(make_plan(ctx, desc, MF_FP32, targets, MF_MULTIPLICATIVE, F, dint.data(), nd, ws, SL, s, &P));
+  P.params = params;   // the GELU network's phases read its convolutions from here
   // the adjoint's table: caller offsets and per-colour placement prefixes
   std::vector<char> host((size_t)nd * sizeof(DomEntry) + 4 * ((size_t)nd + 1) * 4);
   DomEntry* he = reinterpret_cast<DomEntry*>(host.data());

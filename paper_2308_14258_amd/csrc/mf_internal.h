@@ -211,12 +211,21 @@ struct AdjointBuffers {
   float* csum;        // [3][max_q][d] first-layer sums
   float* gb;          // [max_q][128] boundary adjoints
   int64_t max_rows;
+  // the GELU network (channels > 0): its parameters (for the embedding) and
+  // each layer's saved pre-activations [max_rows][d]
+  const float* params = nullptr;
+  int channels = 0;
+  float* Sv[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
                                 int64_t n_bc, float* const Z[4], hipStream_t s);
-hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Ab[2],
-                                 int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
-                                 hipStream_t s);
+hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Sv[4],
+                                 float* const Ab[2], int64_t n_rows, const float* X, int64_t n_bc, int64_t T,
+                                 float* csum, hipStream_t s);
+hipError_t launch_value_forward_gelu_saved(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
+                                           int64_t n_bc, float* const Z[4], float* const Sv[4], hipStream_t s);
+hipError_t launch_embed_input_adjoint(const float* params, const NetPtrs& net, int width, int C, const float* G,
+                                      const float* c, int n_q, float* gb, hipStream_t s);
 // io_kernels.hip: one colour's boundary gather and target scatter
 hipError_t launch_gather_colour(const float* u, int64_t pitch, int ux, int colour, int64_t n_q, float* G,
                                 hipStream_t s);

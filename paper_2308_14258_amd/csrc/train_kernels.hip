@@ -124,7 +124,6 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
                                                             float* __restrict__ Sv_out,
                                                             int64_t n_srows, int skip_xy) {
   static_assert(MODE == 0 || S == 1, "four-stream backward: taylor_bwd_*_kernel");
-  static_assert(MODE == 0 || ACT == ACT_TANH, "value backward: tanh only");
   constexpr int R = 64, RB = 2, LDH = D + 4, NTH = 2 * D;
   constexpr int PER = R * D / 4 / NTH;       // float4 of the input tile per thread
   __shared__ __align__(16) float Hs[R * LDH];
@@ -213,8 +212,14 @@ __global__ __launch_bounds__(2 * D, 4) void taylor_gemm_kernel(const float* __re
             Out[o] = ACT == ACT_GELU ? gelu_f32(a) : tanh_f32(a);
             if (ACT == ACT_GELU && Sv_out) Sv_out[o] = a;
           } else {
-            const float z = Sv_in[o];
-            Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
+            if constexpr (ACT == ACT_GELU) {   // Sv_in: the layer's pre-activations
+              float f1, f2, f3;
+              gelu_d123(Sv_in[o], f1, f2, f3);
+              Out[o] = f1 * acc[rb][4 * m + e];
+            } else {                           // Sv_in: the layer's outputs z
+              const float z = Sv_in[o];
+              Out[o] = (1.0f - z * z) * acc[rb][4 * m + e];
+            }
           }
         }
       }
@@ -1036,6 +1041,15 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, 
   return hipGetLastError();
 }
 
+// The GELU network's value stream saving each layer's pre-activations in Sv
+// (for its reverse pass): first layer from C [n_bc][D] and shared points
+// X [T][2], then the three hidden layers.
+hipError_t launch_value_forward_gelu_saved(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
+                                           int64_t n_bc, float* const Z[4], float* const Sv[4], hipStream_t s) {
+  return width == 256 ? run_taylor_forward<256, ACT_GELU>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, false, s)
+                      : run_taylor_forward<128, ACT_GELU>(net, C, X, 0, T, n_bc * T, 1, Z, Sv, false, s);
+}
+
 // Value stream only: first layer from C [n_bc][D] and shared points X [T][2],
 // then the three hidden layers; Z[l] receives layer l+1's activations.
 hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, const float* X, int64_t T,
@@ -1048,14 +1062,19 @@ hipError_t launch_value_forward(const NetPtrs& net, int width, const float* C, c
 // Value-stream reverse pass from ab4 in Ab[0] down to ab1, then per-condition
 // sums c[b][j] = sum_t ab1 (first of the three [n_bc][D] blocks of csum).
 template <int D>
-static hipError_t value_backward_d(const float* whT, float* const Z[4], float* const Ab[2], int64_t n_rows,
-                                   const float* X, int64_t n_bc, int64_t T, float* csum, hipStream_t s) {
+static hipError_t value_backward_d(const float* whT, float* const Z[4], float* const Sv[4], float* const Ab[2],
+                                   int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
+                                   hipStream_t s) {
   int cur = 0;
   const unsigned blocks = gemm_grid((n_rows + 63) / 64);
   for (int l = 2; l >= 0; --l) {
     const floatx4* wT = reinterpret_cast<const floatx4*>(whT) + (size_t)l * D * D / 4;
-    hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT, nullptr,
-                       Z[l], Ab[cur ^ 1], nullptr, n_rows, 0);
+    if (Sv)   // GELU: the reverse rule needs the saved pre-activations
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1, ACT_GELU>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT,
+                         nullptr, Sv[l], Ab[cur ^ 1], nullptr, n_rows, 0);
+    else
+      hipLaunchKernelGGL((taylor_gemm_kernel<D, 1, 1>), dim3(blocks), dim3(2 * D), 0, s, Ab[cur], wT, nullptr,
+                         Z[l], Ab[cur ^ 1], nullptr, n_rows, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur ^= 1;
@@ -1065,11 +1084,11 @@ static hipError_t value_backward_d(const float* whT, float* const Z[4], float* c
   return hipGetLastError();
 }
 
-hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Ab[2],
-                                 int64_t n_rows, const float* X, int64_t n_bc, int64_t T, float* csum,
-                                 hipStream_t s) {
-  return width == 256 ? value_backward_d<256>(whT, Z, Ab, n_rows, X, n_bc, T, csum, s)
-                      : value_backward_d<128>(whT, Z, Ab, n_rows, X, n_bc, T, csum, s);
+hipError_t launch_value_backward(const float* whT, int width, float* const Z[4], float* const Sv[4],
+                                 float* const Ab[2], int64_t n_rows, const float* X, int64_t n_bc, int64_t T,
+                                 float* csum, hipStream_t s) {
+  return width == 256 ? value_backward_d<256>(whT, Z, Sv, Ab, n_rows, X, n_bc, T, csum, s)
+                      : value_backward_d<128>(whT, Z, Sv, Ab, n_rows, X, n_bc, T, csum, s);
 }
 
 // Value stream of either activation, rows_per_bc points per condition (X

@@ -204,3 +204,27 @@ def test_training_steps_track_the_oracle(ctx):
           flush=True)
     assert rel.max() <= 1e-3
     assert got[-1].sum() < got[0].sum()
+
+
+@pytest.mark.parametrize("units,K,ce,targets", [((2, 2), 3, 2, "cross"), ((3, 2), 2, 1, "interior")])
+def test_adjoint_matches_the_oracle(ctx, units, K, ce, targets):
+    """mf_solve_adjoint for the paper's network (recomputed forward with the
+    GELU rules, reverse value stream, and the boundary adjoint back through
+    W1e and the two circular convolutions) against float64 autograd through
+    the oracle's sweeps with the same network: relative 1e-4, J to 1e-5."""
+    print(f"case: GELU adjoint units={units} K={K} ckpt={ce} targets={targets}", flush=True)
+    from oracle import adjoint
+    from paper_2308_14258_amd import MF_CROSS, mf_solve_adjoint
+    ux, uy = units
+    th = _params(128, 81)
+    f = mi.gp_field(ux, uy, 0.6, seed=82)
+    tg = MF_CROSS if targets == "cross" else MF_INTERIOR
+    u0 = torch.from_numpy(f).cuda()
+    ub, J = mf_solve_adjoint(ctx, torch.from_numpy(th).cuda(), u0, units, K, ce, tg)
+    torch.cuda.synchronize()
+    solver = sc.solver(torch.from_numpy(th.astype(np.float64)), 128, C)
+    Jo, go = adjoint.solve_adjoint(torch.from_numpy(f.astype(np.float64)), ux, uy, solver, K, targets)
+    err = _rel(ub.cpu().numpy(), go.numpy())
+    print(f"GELU adjoint rel L2 {err:.3e}, J {J.item():.6e} vs {Jo:.6e}", flush=True)
+    assert err <= 1e-4
+    assert abs(J.item() - Jo) <= 1e-5 * abs(Jo)
