@@ -52,10 +52,11 @@
  *   MF_FP32 through mf_sweep / mf_solve (multiplicative; a placement's
  *   embedding and projection once per phase, then the value stream through
  *   MFMA GEMMs with a GELU epilogue), sdnet_forward (with its gradient
- *   and Laplacian) and the training entry points (sdnet_train_step,
+ *   and Laplacian), the training entry points (sdnet_train_step,
  *   sdnet_loss_grad; the GELU Taylor rules forward and in reverse, and the
- *   reverse through the convolutions); the other entry points return
- *   MF_EUNSUPPORTED for it.
+ *   reverse through the convolutions) and mf_solve_adjoint; the autotuner,
+ *   the 16-bit precisions, additive sweeps, mf_solve_mixed and
+ *   mf_sweep_noalloc return MF_EUNSUPPORTED for it.
  * Precision: MF_FP32 computes every GEMM with float32 MFMA (the boundary
  *   projection on the float32 VALU). MF_BF16 rounds the GEMM operands to
  *   bf16 and accumulates in float32 on MFMA: the boundary projection
