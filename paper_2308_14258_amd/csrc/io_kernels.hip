@@ -118,12 +118,12 @@ __global__ void skel_unpack_kernel(const float* __restrict__ cols, int64_t cpitc
 
 // Gather from the side layout: each of the four edges is one contiguous run
 // (bottom and top in the field's rows, right and left in cols). A workgroup
-// has kSkelPPW placement slots (128 threads each for the gather, 64 for the
-// scatter) and each thread handles ILP placements, kSkelPPW apart, whose
-// loads it issues together: the kernels are bound by the bytes in flight per
-// CU, and one 4-byte load per thread leaves the HBM pipe mostly idle.
-constexpr int kSkelPPW = 4;
-constexpr int kGatherIlp = 8, kScatterIlp = 4;
+// has PPW placement slots (128 threads each for the gather, 64 for the
+// scatter) and each thread handles ILP placements, PPW apart, whose loads it
+// issues together: the kernels are bound by the bytes in flight per CU, and
+// one 4-byte load per thread leaves the HBM pipe mostly idle.
+constexpr int kSkelPPW = 4, kGatherIlp = 8;
+constexpr int kScatterPPW = 4, kScatterIlp = 4;
 // Placement of slot `sub` of workgroup `blk` (die blk mod 8): each die's
 // workgroups walk its contiguous range `group` placements at a time.
 __device__ __forceinline__ int64_t xcd_placement_ppw(int64_t blk, int sub, int group, int64_t per_xcd, int64_t q0,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kNB * kSkelPPW) void gather_skel_kernel(const float
 // CROSS scatter into the side layout: the vertical centre line (targets
 // 0..30, j = 1..31) into cols, the horizontal one (targets 31..60) into the
 // field's row, and the centre (target 15) into that row as well.
-__global__ __launch_bounds__(64 * kSkelPPW) void scatter_skel_kernel(const float* __restrict__ pred,
+__global__ __launch_bounds__(64 * kScatterPPW) void scatter_skel_kernel(const float* __restrict__ pred,
                                                           float* __restrict__ u,
                                                           int64_t pitch, float* __restrict__ cols, int64_t cpitch,
                                                           int ux, int colour, int64_t q0, int64_t n_q,
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(64 * kSkelPPW) void scatter_skel_kernel(const float
 #pragma unroll
   for (int i = 0; i < kScatterIlp; ++i) {
     const int64_t q =
-        xcd_placement_ppw(blockIdx.x, (threadIdx.x >> 6) + i * kSkelPPW, kSkelPPW * kScatterIlp, per_xcd, q0, n_q);
+        xcd_placement_ppw(blockIdx.x, (threadIdx.x >> 6) + i * kScatterPPW, kScatterPPW * kScatterIlp, per_xcd, q0,
+                          n_q);
     qs[i] = q;
     v[i] = pred[(q >= 0 ? q : q0) * kCross + (t < kCross ? t : kHalf - 1)];
   }
@@ -236,9 +237,9 @@ hipError_t launch_scatter_skel(const float* pred, float* u, int64_t pitch, float
                                int64_t n_q, hipStream_t s) {
   for (int64_t q0 = 0; q0 < n_q; q0 += kIoChunk) {
     const int64_t n = n_q - q0 < kIoChunk ? n_q - q0 : kIoChunk;
-    constexpr int group = kSkelPPW * kScatterIlp;
+    constexpr int group = kScatterPPW * kScatterIlp;
     const int64_t per = (per_xcd_of(n) + group - 1) / group * group;
-    hipLaunchKernelGGL(scatter_skel_kernel, dim3((unsigned)(per * kXcds / group)), dim3(64 * kSkelPPW), 0, s,
+    hipLaunchKernelGGL(scatter_skel_kernel, dim3((unsigned)(per * kXcds / group)), dim3(64 * kScatterPPW), 0, s,
                        pred, u, pitch, cols, skel_cols_pitch(uy), ux, colour, q0, n, per);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
