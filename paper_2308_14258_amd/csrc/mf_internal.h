@@ -173,7 +173,8 @@ struct LambSegments {
   int n;
 };
 struct LambParams {
-  float lr, b1, omb1, b2, omb2, eps, wd, bc1, bc2, max_grad_norm;
+  // ibc1 = 1 / (1 - beta1^t), ibc2 = 1 / (1 - beta2^t): the bias corrections
+  float lr, b1, omb1, b2, omb2, eps, wd, ibc1, ibc2, max_grad_norm;
   int trust;
 };
 hipError_t launch_lamb(float* p, float* m, float* v, const float* g, const LambSegments& S, double lr, double b1,
