@@ -948,8 +948,8 @@ static hipError_t run_pass(const NetPtrs& net, const float* whT, const TrainBuff
     float* gW = grad + off_w2 + l * lstride;
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for((int64_t)D * D, 256 / kReduceGroups)), dim3(256), 0, s,
                        tb.wpart, groups, (int64_t)D * D, (int64_t)D * D, gW, accumulate ? 1 : 0);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, tb.bpart, groups, (int64_t)D,
-                       (int64_t)D, gW + (int64_t)D * D, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(D, 256 / kReduceGroups)), dim3(256), 0, s, tb.bpart,
+                       groups, (int64_t)D, (int64_t)D, gW + (int64_t)D * D, accumulate ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
